@@ -1,0 +1,243 @@
+/*
+ * cemppi.h -- C ABI of the MI355X CE-MPPI replan library (libcemppi.so).
+ *
+ * One call of ce_mppi_replan runs one iteration of clustering-embedded MPPI
+ * (Liu, Chang, Chen, "Clustering-Embedded Model Predictive Path Integral
+ * Control", Alg. 1) for one planner on the GPU:
+ *   noise -> rollouts with cost and collision -> pruning -> reference point
+ *   and features -> DBSCAN -> cluster selection -> within-cluster update ->
+ *   shift.
+ *
+ * Conventions (all entry points):
+ *  - Every call returns a ce_status; no C++ exception crosses the ABI.  The
+ *    text of the last error of the calling thread is available from
+ *    ce_mppi_last_error().
+ *  - Pointers documented as "device" must point to device memory of the
+ *    planner's GPU (e.g. a torch tensor's data_ptr()); "host" pointers to
+ *    host memory.  The caller owns every buffer it passes in.
+ *  - Arrays are dense, row-major, single precision unless stated.
+ *  - Work is enqueued on the HIP stream passed as `stream` (a hipStream_t; 0
+ *    is the null stream) and is asynchronous: outputs are valid once that
+ *    stream has been synchronised.
+ *  - A planner owns its device state (nominal control sequence, obstacle
+ *    history, step counter, scratch), all allocated in ce_mppi_create.
+ *    ce_mppi_replan allocates nothing.  A planner must not have two calls in
+ *    flight on different streams at once; different planners are independent.
+ */
+#ifndef CEMPPI_H
+#define CEMPPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CE_MPPI_ABI_VERSION 1u
+#define CE_MPPI_MAX_CTRL 6        /* m                                          */
+#define CE_MPPI_MAX_OBSTACLES 64  /* n_obs per planner                          */
+#define CE_MPPI_MAX_HORIZON 63    /* N: the N+1 states of a rollout share a wave */
+#define CE_MPPI_MAX_HISTORY 16    /* H                                          */
+#define CE_MPPI_MAX_SAMPLES 65536 /* K                                          */
+#define CE_MPPI_MAX_SPHERES 16    /* arm link spheres                           */
+
+typedef int32_t ce_status;
+enum {
+  CE_OK = 0,
+  CE_EINVAL = 1,       /* invalid argument or configuration                    */
+  CE_ENOMEM = 2,       /* device allocation failed                             */
+  CE_EDEVICE = 3,      /* HIP runtime error or no usable GPU                   */
+  CE_EUNSUPPORTED = 4, /* valid request this build does not support            */
+  CE_EBUSY = 5         /* resource in use (e.g. server full)                   */
+};
+
+/* f(.) of Sec. II-A: the differential-drive robot of Sec. III-A (state
+ * (x, y, theta), control (v, omega), task space (x, y)) and a six-joint serial
+ * arm driven by joint velocities as in Sec. III-C (state (q, qdot) in R^12,
+ * control qdot command in R^6, task space = end-effector position). */
+enum { CE_DYN_UNICYCLE = 0, CE_DYN_ARM6 = 1 };
+/* selection rule of Alg. 1: minimum mean cost (static) or most opposite to
+ * the estimated obstacle motion (dynamic), Sec. II-B.3 */
+enum { CE_SCENE_STATIC = 0, CE_SCENE_DYNAMIC = 1 };
+/* point averaged into the collision-derived reference point, Sec. II-B.2:
+ * terminal position (the paper's Eq. (11)) or first-contact position */
+enum { CE_REF_TERMINAL = 0, CE_REF_FIRST_CONTACT = 1 };
+/* branch of Alg. 1 taken by a replan */
+enum { CE_BRANCH_CLUSTER = 0, CE_BRANCH_FALLBACK = 1, CE_BRANCH_ALL_COLLIDE = 2 };
+
+/* ce_mppi_info.status bits (data-dependent conditions, not errors) */
+#define CE_STATUS_FALLBACK 1u    /* no colliding rollout: plain MPPI over all K      */
+#define CE_STATUS_ALL_COLLIDE 2u /* every rollout collides: plain MPPI over all K    */
+#define CE_STATUS_NO_CLUSTER 4u  /* DBSCAN found no cluster: update over all of V    */
+#define CE_STATUS_DYN_STATIC 8u  /* dynamic rule impossible (H'<2 or slow obstacle)  */
+#define CE_STATUS_NONFINITE 16u  /* non-finite x_t or obstacle: replan was a no-op   */
+
+/* Planner configuration: the "Require" line of Alg. 1.  Fill with
+ * ce_mppi_config_init() and override fields. */
+typedef struct ce_mppi_config {
+  uint32_t abi_version;      /* CE_MPPI_ABI_VERSION                                     */
+  int32_t dynamics;          /* CE_DYN_*                                                */
+  int32_t horizon;           /* N, 1..CE_MPPI_MAX_HORIZON                               */
+  int32_t num_samples;       /* K, 1..CE_MPPI_MAX_SAMPLES                               */
+  float dt;                  /* integration step and observation interval (> 0)        */
+  float lambda;              /* temperature of Eq. (6) / Eq. (19), > 0                  */
+  float noise_chol[36];      /* L, m x m row-major lower triangular, Sigma = L L^T      */
+  float u_min[6], u_max[6];  /* control bounds; -INF/+INF disable the clamp             */
+  float dbscan_eps;          /* DBSCAN radius (closed ball), > 0                        */
+  int32_t dbscan_min_pts;    /* DBSCAN minPts, the point itself included, >= 1          */
+  float norm_eps;            /* epsilon of the normalisations of Eq. (13),(15)-(17)     */
+  int32_t scene_mode;        /* CE_SCENE_*                                              */
+  int32_t history_len;       /* H of Eq. (17), 1..CE_MPPI_MAX_HISTORY (>=2 if dynamic)  */
+  float v_obs_min;           /* obstacle speed below which the static rule is used      */
+  int32_t ref_mode;          /* CE_REF_*                                                */
+  int32_t max_obstacles;     /* capacity, 0..CE_MPPI_MAX_OBSTACLES                      */
+  float robot_radius;        /* unicycle body radius (0 = point robot)                  */
+  float goal[6];             /* unicycle: goal state x_f; arm: end-effector target p_g  */
+  float Q[6];                /* unicycle: diag state weight; arm: Q[0] = position weight */
+  float R[6];                /* diag control weight                                     */
+  float Qf[6];               /* unicycle: diag terminal weight; arm: Qf[0]              */
+  float dh[6][4];            /* arm: per joint (a, d, alpha, theta offset), standard DH */
+  int32_t n_link_spheres;    /* arm: collision spheres along the link chain, <= 16      */
+  float link_sphere_radius;  /* arm                                                     */
+  float q_limit[6];          /* arm: joint-limit penalty threshold |q_i|                */
+  float w_limit;             /* arm: joint-limit penalty weight                         */
+  uint64_t seed;             /* Philox key                                              */
+  uint32_t stream_id;        /* Philox counter word 3 (e.g. the planner id)             */
+  int32_t device;            /* HIP device ordinal                                      */
+  uint32_t flags;            /* reserved, 0                                             */
+} ce_mppi_config;
+
+/* Per-replan diagnostics, written on the device. */
+typedef struct ce_mppi_info {
+  int32_t branch;          /* CE_BRANCH_*                                     */
+  int32_t n_collide;       /* |C^col|                                         */
+  int32_t n_feasible;      /* |V|                                             */
+  int32_t n_ref;           /* rollouts averaged into the reference point      */
+  int32_t n_clusters;      /* M                                               */
+  int32_t selected;        /* c*, -1 if none                                  */
+  int32_t selected_size;   /* |C_{c*}|                                        */
+  int32_t closest;         /* o*, -1 without obstacles                        */
+  int32_t rule;            /* CE_SCENE_* actually applied                     */
+  int32_t history_used;    /* H' = min(H, observations available)            */
+  uint32_t status;         /* CE_STATUS_* bits                                */
+  uint32_t step;           /* Philox step word used by this replan           */
+  float margin;            /* second-best minus best selection key (INF if M<2) */
+  float s_min;             /* minimum cost over the update set                */
+  float ref_point[3];      /* collision-derived reference point              */
+  float v_obs[3];          /* obstacle velocity estimate, Eq. (17)           */
+  float v_obs_hat[3];      /* normalised                                     */
+  float weight_sum;        /* sum of exp(-(S - s_min)/lambda) over the set   */
+} ce_mppi_info;
+
+typedef struct ce_mppi_planner ce_mppi_planner;
+
+/* Fill *cfg with defaults for the given dynamics (the unit-sized unicycle or
+ * arm problem, static rule, no obstacles).  Returns CE_EINVAL for an unknown
+ * dynamics or a NULL cfg. */
+ce_status ce_mppi_config_init(ce_mppi_config* cfg, int32_t dynamics);
+
+/* Validate *cfg and create a planner on cfg->device: allocates every device
+ * buffer, sets the nominal sequence U to zero, empties the obstacle history
+ * and sets the step counter to 0.  Errors: CE_EINVAL (bad config; see the
+ * limits above), CE_ENOMEM, CE_EDEVICE. */
+ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out);
+
+/* One replan, Alg. 1.
+ *   x_t       device, [n] current state (n = 3 unicycle, 12 arm)
+ *   obstacles device, [n_obs][p+1] rows (centre..., radius), p = 2 or 3;
+ *             may be NULL when n_obs == 0.  Their centres are pushed into the
+ *             planner's history (the {o_{t-h}} of Eq. (17)); a change of n_obs
+ *             empties the history first.
+ *   u_out     device, [m] control to apply (u_t after the update)
+ *   U_out     device, [N][m] updated sequence before the shift, or NULL
+ *   info      device, one ce_mppi_info, or NULL
+ * The planner keeps the shifted warm start (last control repeated) and
+ * increments its step counter.  A non-finite x_t or obstacle value makes the
+ * call a no-op apart from u_out = U[0] and info.status.  Errors: CE_EINVAL
+ * (NULL planner/x_t/u_out, n_obs outside 0..max_obstacles), CE_EDEVICE. */
+ce_status ce_mppi_replan(ce_mppi_planner* planner, const float* x_t, const float* obstacles,
+                         int32_t n_obs, float* u_out, float* U_out, ce_mppi_info* info,
+                         void* stream);
+
+/* Release every resource of the planner.  NULL-safe.  The caller must have
+ * synchronised the streams the planner was used on. */
+void ce_mppi_destroy(ce_mppi_planner* planner);
+
+/* ---- planner state ---- */
+
+/* Copy U ([N][m], device) into / out of the planner (asynchronous on stream). */
+ce_status ce_mppi_set_nominal(ce_mppi_planner* planner, const float* U, void* stream);
+ce_status ce_mppi_get_nominal(const ce_mppi_planner* planner, float* U, void* stream);
+/* Empty the obstacle history. */
+ce_status ce_mppi_reset_history(ce_mppi_planner* planner, void* stream);
+/* Set the step counter (the Philox step word of the next replan). */
+ce_status ce_mppi_set_step(ce_mppi_planner* planner, uint64_t step, void* stream);
+/* Checkpoint: size in bytes of the serialised state (U, history, counters). */
+ce_status ce_mppi_state_size(const ce_mppi_planner* planner, size_t* bytes);
+/* Serialise the state into host memory `buf` of state_size bytes; synchronises
+ * the stream. */
+ce_status ce_mppi_get_state(const ce_mppi_planner* planner, void* buf, size_t bytes, void* stream);
+/* Restore a state produced by ce_mppi_get_state of a planner with the same
+ * configuration; synchronises the stream. */
+ce_status ce_mppi_set_state(ce_mppi_planner* planner, const void* buf, size_t bytes, void* stream);
+
+/* ---- diagnostics: internal buffers of the last replan ---- */
+enum {
+  CE_DBG_COST = 0,       /* float [K]            S of Eq. (5)                      */
+  CE_DBG_COLLIDE = 1,    /* int32 [K]            collision indicator               */
+  CE_DBG_FIRST_OBS = 2,  /* int32 [K]            lowest obstacle at first contact  */
+  CE_DBG_P_TERM = 3,     /* float [K][p]         p(x_{t+N})                        */
+  CE_DBG_P_FIRST = 4,    /* float [K][p]         p at first contact                */
+  CE_DBG_EPS = 5,        /* float [K][N][m]      applied perturbation              */
+  CE_DBG_V_IDX = 6,      /* int32 [|V|]          feasible rollouts, ascending      */
+  CE_DBG_Z = 7,          /* float [|V|][p]       feature of Eq. (13)               */
+  CE_DBG_G = 8,          /* float [|V|][p]       direction of Eq. (15)             */
+  CE_DBG_NCOUNT = 9,     /* int32 [|V|]          eps-neighbour counts              */
+  CE_DBG_LABEL = 10,     /* int32 [|V|]          cluster label, -1 noise           */
+  CE_DBG_CLUSTER_COST = 11, /* float [M]         mean cost per cluster             */
+  CE_DBG_CLUSTER_DIR = 12,  /* float [M][p]      normalised mean direction Eq.(16) */
+  CE_DBG_CLUSTER_SIZE = 13, /* int32 [M]                                           */
+  CE_DBG_COUNT_ = 14
+};
+/* Copy the named buffer into device memory dst of `bytes` bytes (at most the
+ * buffer's full capacity is copied; rows beyond |V| or M are unspecified). */
+ce_status ce_mppi_debug_get(const ce_mppi_planner* planner, int32_t which, void* dst, size_t bytes,
+                            void* stream);
+
+/* ---- stage entry points (the same kernels on caller-supplied inputs) ---- */
+
+/* Philox noise of the planner's configuration for rollouts 0..K-1 at `step`:
+ * words  device uint32 [K][B][4], B = ceil(N*m/4) (may be NULL)
+ * gauss  device float  [K][N][m] standard normals (may be NULL). */
+ce_status ce_mppi_stage_noise(ce_mppi_planner* planner, uint32_t step, uint32_t* words, float* gauss,
+                              void* stream);
+
+/* Everything after the rollouts (Alg. 1 from [Pruning] on) applied to
+ * rollout records supplied by the caller instead of the planner's rollout
+ * kernel; the planner state (U, history, step) is used and advanced exactly
+ * as by ce_mppi_replan.
+ *   S [K], collide int32 [K], first_obs int32 [K], p_term [K][p],
+ *   p_first [K][p], eps [K][N][m]: device. */
+ce_status ce_mppi_replan_from_rollouts(ce_mppi_planner* planner, const float* x_t,
+                                       const float* obstacles, int32_t n_obs, const float* S,
+                                       const int32_t* collide, const int32_t* first_obs,
+                                       const float* p_term, const float* p_first, const float* eps,
+                                       float* u_out, float* U_out, ce_mppi_info* info,
+                                       void* stream);
+
+/* DBSCAN of the planner's kernels on V caller-supplied features z (device,
+ * [V][p]) with the planner's eps/minPts; V <= K.  Outputs (device, [V]):
+ * ncount (may be NULL), label; n_clusters (device int32, may be NULL). */
+ce_status ce_mppi_stage_dbscan(ce_mppi_planner* planner, const float* z, int32_t V, int32_t* ncount,
+                               int32_t* label, int32_t* n_clusters, void* stream);
+
+/* ---- errors ---- */
+const char* ce_mppi_status_string(ce_status status);
+/* Message of the last failed call on this thread ("" if none). */
+const char* ce_mppi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CEMPPI_H */

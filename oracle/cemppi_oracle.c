@@ -538,61 +538,16 @@ static int32_t all_finite(const double* a, size_t n) {
   return 1;
 }
 
-int32_t orc_replan(const orc_problem* P, const double* x_t, const double* U, const double* obs,
-                   int32_t n_obs, const double* hist, int32_t h_avail, uint32_t step, orc_out* out) {
+/* Alg. 1 from [Pruning] on, given the rollout records (cost, collision
+ * indicator, first obstacle hit, terminal and first-contact points, applied
+ * perturbations). */
+static void post_rollouts(const orc_problem* P, const double* x_t, const double* U, const double* obs,
+                          int32_t n_obs, const double* hist, int32_t h_avail, const double* S,
+                          const int32_t* col, const int32_t* fo, const double* pT, const double* pF,
+                          const double* E, orc_out* out) {
   int32_t n, m, p;
-  if (orc_dims(P->dynamics, &n, &m, &p) != 0) return -1;
+  orc_dims(P->dynamics, &n, &m, &p);
   const int32_t N = P->N, K = P->K, NM = P->N * m;
-  if (N < 1 || K < 1 || !(P->lambda > 0.0) || n_obs < 0 || n_obs > ORC_MAX_OBS) return -1;
-
-  out->branch = ORC_BRANCH_FALLBACK;
-  out->n_col = out->n_feas = out->n_ref = out->n_clusters = 0;
-  out->selected = -1;
-  out->selected_size = 0;
-  out->closest = -1;
-  out->rule = ORC_STATIC;
-  out->h_used = 0;
-  out->status = 0;
-  out->margin = INFINITY;
-  out->s_min = 0.0;
-  for (int i = 0; i < 3; ++i) out->ref_point[i] = out->v_obs[i] = out->v_obs_hat[i] = 0.0;
-
-  /* non-finite input: no update, no shift */
-  if (!all_finite(x_t, (size_t)n) || !all_finite(obs, (size_t)n_obs * (p + 1))) {
-    out->status = ORC_ST_NONFINITE;
-    if (out->U_new) memcpy(out->U_new, U, sizeof(double) * (size_t)NM);
-    if (out->U_next) memcpy(out->U_next, U, sizeof(double) * (size_t)NM);
-    if (out->u_out) memcpy(out->u_out, U, sizeof(double) * (size_t)m);
-    return 0;
-  }
-
-  double* S = (double*)malloc(sizeof(double) * (size_t)K);
-  int32_t* col = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
-  int32_t* fo = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
-  double* pT = (double*)malloc(sizeof(double) * (size_t)K * p);
-  double* pF = (double*)malloc(sizeof(double) * (size_t)K * p);
-  double* E = (double*)malloc(sizeof(double) * (size_t)K * NM);
-  double* eps = (double*)malloc(sizeof(double) * (size_t)NM);
-  double* ut = (double*)malloc(sizeof(double) * (size_t)NM);
-
-  /* [Rollouts] Alg. 1: sample, perturb (Eq. (3)), simulate (Eq. (4)),
-   * cost (Eq. (5)), collision indicator. */
-  for (int32_t k = 0; k < K; ++k) {
-    orc_rollout_noise(P, step, k, NULL, eps);
-    for (int32_t j = 0; j < N; ++j)
-      for (int32_t i = 0; i < m; ++i) {
-        double u = U[j * m + i] + eps[j * m + i];
-        if (u < P->u_min[i]) u = P->u_min[i];
-        if (u > P->u_max[i]) u = P->u_max[i];
-        ut[j * m + i] = u;
-        E[(size_t)k * NM + j * m + i] = u - U[j * m + i];
-      }
-    double clear;
-    orc_simulate(P, x_t, ut, obs, n_obs, NULL, &S[k], &col[k], &fo[k], pT + (size_t)k * p,
-                 pF + (size_t)k * p, &clear);
-    if (out->clearance) out->clearance[k] = clear;
-  }
-
   /* [Pruning] Eq. (9)-(10) */
   int32_t* Vi = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
   int32_t nV = 0, nC = 0;
@@ -770,23 +725,85 @@ int32_t orc_replan(const orc_problem* P, const double* x_t, const double* U, con
     }
   }
 
-  if (out->S) memcpy(out->S, S, sizeof(double) * (size_t)K);
-  if (out->col) memcpy(out->col, col, sizeof(int32_t) * (size_t)K);
-  if (out->first_obs) memcpy(out->first_obs, fo, sizeof(int32_t) * (size_t)K);
-  if (out->p_term) memcpy(out->p_term, pT, sizeof(double) * (size_t)K * p);
-  if (out->p_first) memcpy(out->p_first, pF, sizeof(double) * (size_t)K * p);
-  if (out->eps_eff) memcpy(out->eps_eff, E, sizeof(double) * (size_t)K * NM);
   if (out->v_idx) memcpy(out->v_idx, Vi, sizeof(int32_t) * (size_t)nV);
   if (out->z && z) memcpy(out->z, z, sizeof(double) * (size_t)nV * p);
   if (out->g && g) memcpy(out->g, g, sizeof(double) * (size_t)nV * p);
   if (out->label && lab) memcpy(out->label, lab, sizeof(int32_t) * (size_t)nV);
-
   free(Un);
   free(z);
   free(g);
   free(lab);
   free(set);
   free(Vi);
+}
+
+static void init_out(orc_out* out) {
+  out->branch = ORC_BRANCH_FALLBACK;
+  out->n_col = out->n_feas = out->n_ref = out->n_clusters = 0;
+  out->selected = -1;
+  out->selected_size = 0;
+  out->closest = -1;
+  out->rule = ORC_STATIC;
+  out->h_used = 0;
+  out->status = 0;
+  out->margin = INFINITY;
+  out->s_min = 0.0;
+  for (int i = 0; i < 3; ++i) out->ref_point[i] = out->v_obs[i] = out->v_obs_hat[i] = 0.0;
+}
+
+int32_t orc_replan(const orc_problem* P, const double* x_t, const double* U, const double* obs,
+                   int32_t n_obs, const double* hist, int32_t h_avail, uint32_t step, orc_out* out) {
+  int32_t n, m, p;
+  if (orc_dims(P->dynamics, &n, &m, &p) != 0) return -1;
+  const int32_t N = P->N, K = P->K, NM = P->N * m;
+  if (N < 1 || K < 1 || !(P->lambda > 0.0) || n_obs < 0 || n_obs > ORC_MAX_OBS) return -1;
+
+  init_out(out);
+
+  /* non-finite input: no update, no shift */
+  if (!all_finite(x_t, (size_t)n) || !all_finite(obs, (size_t)n_obs * (p + 1))) {
+    out->status = ORC_ST_NONFINITE;
+    if (out->U_new) memcpy(out->U_new, U, sizeof(double) * (size_t)NM);
+    if (out->U_next) memcpy(out->U_next, U, sizeof(double) * (size_t)NM);
+    if (out->u_out) memcpy(out->u_out, U, sizeof(double) * (size_t)m);
+    return 0;
+  }
+
+  double* S = (double*)malloc(sizeof(double) * (size_t)K);
+  int32_t* col = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
+  int32_t* fo = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
+  double* pT = (double*)malloc(sizeof(double) * (size_t)K * p);
+  double* pF = (double*)malloc(sizeof(double) * (size_t)K * p);
+  double* E = (double*)malloc(sizeof(double) * (size_t)K * NM);
+  double* eps = (double*)malloc(sizeof(double) * (size_t)NM);
+  double* ut = (double*)malloc(sizeof(double) * (size_t)NM);
+
+  /* [Rollouts] Alg. 1: sample, perturb (Eq. (3)), simulate (Eq. (4)),
+   * cost (Eq. (5)), collision indicator. */
+  for (int32_t k = 0; k < K; ++k) {
+    orc_rollout_noise(P, step, k, NULL, eps);
+    for (int32_t j = 0; j < N; ++j)
+      for (int32_t i = 0; i < m; ++i) {
+        double u = U[j * m + i] + eps[j * m + i];
+        if (u < P->u_min[i]) u = P->u_min[i];
+        if (u > P->u_max[i]) u = P->u_max[i];
+        ut[j * m + i] = u;
+        E[(size_t)k * NM + j * m + i] = u - U[j * m + i];
+      }
+    double clear;
+    orc_simulate(P, x_t, ut, obs, n_obs, NULL, &S[k], &col[k], &fo[k], pT + (size_t)k * p,
+                 pF + (size_t)k * p, &clear);
+    if (out->clearance) out->clearance[k] = clear;
+  }
+
+  post_rollouts(P, x_t, U, obs, n_obs, hist, h_avail, S, col, fo, pT, pF, E, out);
+  if (out->S) memcpy(out->S, S, sizeof(double) * (size_t)K);
+  if (out->col) memcpy(out->col, col, sizeof(int32_t) * (size_t)K);
+  if (out->first_obs) memcpy(out->first_obs, fo, sizeof(int32_t) * (size_t)K);
+  if (out->p_term) memcpy(out->p_term, pT, sizeof(double) * (size_t)K * p);
+  if (out->p_first) memcpy(out->p_first, pF, sizeof(double) * (size_t)K * p);
+  if (out->eps_eff) memcpy(out->eps_eff, E, sizeof(double) * (size_t)K * NM);
+
   free(S);
   free(col);
   free(fo);
@@ -795,5 +812,19 @@ int32_t orc_replan(const orc_problem* P, const double* x_t, const double* U, con
   free(E);
   free(eps);
   free(ut);
+  return 0;
+}
+
+int32_t orc_replan_from_rollouts(const orc_problem* P, const double* x_t, const double* U,
+                                 const double* obs, int32_t n_obs, const double* hist,
+                                 int32_t h_avail, const double* S, const int32_t* col,
+                                 const int32_t* first_obs, const double* p_term,
+                                 const double* p_first, const double* eps_eff, orc_out* out) {
+  int32_t n, m, p;
+  if (orc_dims(P->dynamics, &n, &m, &p) != 0) return -1;
+  if (P->N < 1 || P->K < 1 || !(P->lambda > 0.0) || n_obs < 0 || n_obs > ORC_MAX_OBS) return -1;
+  init_out(out);
+  post_rollouts(P, x_t, U, obs, n_obs, hist, h_avail, S, col, first_obs, p_term, p_first, eps_eff,
+                out);
   return 0;
 }

@@ -150,6 +150,15 @@ void orc_weighted_update(int32_t n_set, const int32_t* set, const double* S, con
 int32_t orc_replan(const orc_problem* P, const double* x_t, const double* U, const double* obs,
                    int32_t n_obs, const double* hist, int32_t h_avail, uint32_t step, orc_out* out);
 
+/* Alg. 1 from [Pruning] on, applied to given rollout records (S [K],
+ * col [K], first_obs [K], p_term [K][p], p_first [K][p], eps_eff [K][N][m]);
+ * per-rollout outputs of `out` are not written. */
+int32_t orc_replan_from_rollouts(const orc_problem* P, const double* x_t, const double* U,
+                                 const double* obs, int32_t n_obs, const double* hist,
+                                 int32_t h_avail, const double* S, const int32_t* col,
+                                 const int32_t* first_obs, const double* p_term,
+                                 const double* p_first, const double* eps_eff, orc_out* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -155,6 +155,11 @@ def load():
         _p(OrcProblem), _f64p, _f64p, _f64p, C.c_int32, _f64p, C.c_int32, C.c_uint32, _p(OrcOut),
     ]
     lib.orc_replan.restype = C.c_int32
+    lib.orc_replan_from_rollouts.argtypes = [
+        _p(OrcProblem), _f64p, _f64p, _f64p, C.c_int32, _f64p, C.c_int32, _f64p, _i32p, _i32p,
+        _f64p, _f64p, _f64p, _p(OrcOut),
+    ]
+    lib.orc_replan_from_rollouts.restype = C.c_int32
     _lib = lib
     return lib
 
@@ -339,9 +344,11 @@ def weighted_update(set_idx, S, eps_eff, lam, U):
 
 
 # ---------------------------------------------------------------- full replan
-def replan(spec, x_t, U, obs, hist=None, step: int = 0, c_cap: int = 4096):
+def replan(spec, x_t, U, obs, hist=None, step: int = 0, c_cap: int = 4096, rollouts=None):
     """Run Alg. 1 once.  obs [n_obs][p+1]; hist [h_avail][n_obs][p] newest
-    first (defaults to the current positions alone).  Returns a dict."""
+    first (defaults to the current positions alone).  With ``rollouts`` (a
+    dict of S, col, first_obs, p_term, p_first, eps_eff) the rollout stage is
+    skipped and those records are used.  Returns a dict."""
     lib = load()
     P = make_problem(spec)
     n, m, p = dims(P.dynamics)
@@ -367,8 +374,18 @@ def replan(spec, x_t, U, obs, hist=None, step: int = 0, c_cap: int = 4096):
     o.c_cap = c_cap
     obs_flat = np.ascontiguousarray(obs.ravel()) if n_obs else np.zeros(1)
     hist_flat = np.ascontiguousarray(hist.ravel()) if hist.size else np.zeros(1)
-    rc = lib.orc_replan(C.byref(P), _f64(x_t), _f64(U).ravel(), obs_flat, n_obs, hist_flat, h_avail,
-                        int(step) & 0xFFFFFFFF, C.byref(o))
+    if rollouts is None:
+        rc = lib.orc_replan(C.byref(P), _f64(x_t), _f64(U).ravel(), obs_flat, n_obs, hist_flat,
+                            h_avail, int(step) & 0xFFFFFFFF, C.byref(o))
+    else:
+        ro = rollouts
+        rc = lib.orc_replan_from_rollouts(
+            C.byref(P), _f64(x_t), _f64(U).ravel(), obs_flat, n_obs, hist_flat, h_avail,
+            _f64(ro["S"]), np.ascontiguousarray(ro["col"], dtype=np.int32),
+            np.ascontiguousarray(ro["first_obs"], dtype=np.int32), _f64(ro["p_term"]).ravel(),
+            _f64(ro["p_first"]).ravel(), _f64(ro["eps_eff"]).ravel(), C.byref(o))
+        for name in ("S", "col", "first_obs", "p_term", "p_first", "eps_eff"):
+            r[name] = np.asarray(ro[name]).copy()
     if rc != 0:
         raise ValueError("oracle rejected the problem")
     nV = o.n_feas

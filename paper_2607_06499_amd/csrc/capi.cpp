@@ -1,0 +1,607 @@
+// capi.cpp -- the C ABI of libcemppi.so (declared in include/cemppi.h):
+// validation, the per-planner device arena and the launch sequence of one
+// replan.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cemppi.h"
+#include "device.hpp"
+
+namespace cemppi {
+hipError_t launch_rollout(const Cfg& c, const Bufs& b, const float* x_t, const float* obs, int n_obs,
+                          hipStream_t s);
+hipError_t launch_reduce_records(const Cfg& c, const Bufs& b, const float* x_t, const float* obs,
+                                 int n_obs, hipStream_t s);
+hipError_t launch_stage_noise(const Cfg& c, uint32_t step, uint32_t* words, float* gauss,
+                              hipStream_t s);
+hipError_t launch_post_rollout(const Cfg& c, const Bufs& b, float* u_out, float* U_out, void* info,
+                               hipStream_t s);
+hipError_t launch_stage_dbscan(const Cfg& c, const Bufs& b, const float* z, int V, int* ncount,
+                               int* label, int* mout, hipStream_t s);
+}  // namespace cemppi
+
+using namespace cemppi;
+
+static_assert(sizeof(ce_mppi_info) == 4 * (12 + 2 + 10), "ce_mppi_info layout");
+
+struct ce_mppi_planner {
+  ce_mppi_config cfg;
+  Cfg c;
+  Bufs b;
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  size_t cap_K = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+ce_status fail(ce_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+ce_status hip_fail(hipError_t e, const char* what) {
+  return fail(CE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool finite(float x) { return std::isfinite(x); }
+
+// Arena carving: every buffer 256-byte aligned.
+struct Carver {
+  size_t off = 0;
+  template <class T>
+  size_t take(size_t count) {
+    const size_t o = off;
+    off += ((count * sizeof(T) + 255) / 256) * 256;
+    return o;
+  }
+};
+
+void dims(int dyn, int& n, int& m, int& p) {
+  if (dyn == CE_DYN_UNICYCLE) {
+    n = 3; m = 2; p = 2;
+  } else {
+    n = 12; m = 6; p = 3;
+  }
+}
+
+ce_status validate(const ce_mppi_config* c) {
+  if (!c) return fail(CE_EINVAL, "config is NULL");
+  if (c->abi_version != CE_MPPI_ABI_VERSION) return fail(CE_EINVAL, "abi_version mismatch");
+  if (c->dynamics != CE_DYN_UNICYCLE && c->dynamics != CE_DYN_ARM6)
+    return fail(CE_EINVAL, "unknown dynamics");
+  if (c->horizon < 1 || c->horizon > CE_MPPI_MAX_HORIZON)
+    return fail(CE_EINVAL, "horizon out of range 1..63");
+  if (c->num_samples < 1 || c->num_samples > CE_MPPI_MAX_SAMPLES)
+    return fail(CE_EINVAL, "num_samples out of range 1..65536");
+  if (!(c->dt > 0.f) || !finite(c->dt)) return fail(CE_EINVAL, "dt must be finite and > 0");
+  if (!(c->lambda > 0.f) || !finite(c->lambda)) return fail(CE_EINVAL, "lambda must be finite and > 0");
+  if (!(c->dbscan_eps > 0.f) || !finite(c->dbscan_eps)) return fail(CE_EINVAL, "dbscan_eps must be > 0");
+  if (c->dbscan_min_pts < 1) return fail(CE_EINVAL, "dbscan_min_pts must be >= 1");
+  if (!(c->norm_eps >= 0.f) || !finite(c->norm_eps)) return fail(CE_EINVAL, "norm_eps must be >= 0");
+  if (c->scene_mode != CE_SCENE_STATIC && c->scene_mode != CE_SCENE_DYNAMIC)
+    return fail(CE_EINVAL, "unknown scene_mode");
+  if (c->history_len < 1 || c->history_len > CE_MPPI_MAX_HISTORY)
+    return fail(CE_EINVAL, "history_len out of range 1..16");
+  if (c->scene_mode == CE_SCENE_DYNAMIC && c->history_len < 2)
+    return fail(CE_EINVAL, "dynamic scenes need history_len >= 2");
+  if (!(c->v_obs_min >= 0.f)) return fail(CE_EINVAL, "v_obs_min must be >= 0");
+  if (c->ref_mode != CE_REF_TERMINAL && c->ref_mode != CE_REF_FIRST_CONTACT)
+    return fail(CE_EINVAL, "unknown ref_mode");
+  if (c->max_obstacles < 0 || c->max_obstacles > CE_MPPI_MAX_OBSTACLES)
+    return fail(CE_EINVAL, "max_obstacles out of range 0..64");
+  if (!(c->robot_radius >= 0.f) || !finite(c->robot_radius))
+    return fail(CE_EINVAL, "robot_radius must be finite and >= 0");
+  int n, m, p;
+  dims(c->dynamics, n, m, p);
+  for (int i = 0; i < 36; ++i)
+    if (!finite(c->noise_chol[i])) return fail(CE_EINVAL, "noise_chol must be finite");
+  for (int i = 0; i < m; ++i) {
+    if (std::isnan(c->u_min[i]) || std::isnan(c->u_max[i]) || c->u_min[i] > c->u_max[i])
+      return fail(CE_EINVAL, "control bounds must satisfy u_min <= u_max");
+    if (!finite(c->goal[i]) || !finite(c->Q[i]) || !finite(c->R[i]) || !finite(c->Qf[i]))
+      return fail(CE_EINVAL, "cost parameters must be finite");
+  }
+  if (c->dynamics == CE_DYN_ARM6) {
+    if (c->n_link_spheres < 1 || c->n_link_spheres > CE_MPPI_MAX_SPHERES)
+      return fail(CE_EINVAL, "n_link_spheres out of range 1..16");
+    if (!(c->link_sphere_radius >= 0.f) || !finite(c->link_sphere_radius))
+      return fail(CE_EINVAL, "link_sphere_radius must be finite and >= 0");
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 4; ++j)
+        if (!finite(c->dh[i][j])) return fail(CE_EINVAL, "dh must be finite");
+    double total = 0.0;
+    for (int i = 0; i < 6; ++i) total += std::hypot((double)c->dh[i][0], (double)c->dh[i][1]);
+    if (!(total > 0.0)) return fail(CE_EINVAL, "arm has zero length");
+  }
+  return CE_OK;
+}
+
+void build_cfg(const ce_mppi_config* u, Cfg& c) {
+  std::memset(&c, 0, sizeof(c));
+  c.dyn = u->dynamics;
+  dims(c.dyn, c.n, c.m, c.p);
+  c.N = u->horizon;
+  c.K = u->num_samples;
+  c.NM = c.N * c.m;
+  c.B = (c.NM + 3) / 4;
+  c.seg = (c.dyn == CE_DYN_UNICYCLE && c.N + 1 <= 32) ? 32 : 64;
+  c.rpb = 4 * (64 / c.seg);
+  c.nblk_roll = (c.K + c.rpb - 1) / c.rpb;
+  c.dt = u->dt;
+  c.lambda = u->lambda;
+  c.norm_eps = u->norm_eps;
+  for (int i = 0; i < 36; ++i) c.L[i] = u->noise_chol[i];
+  for (int i = 0; i < 6; ++i) {
+    c.umin[i] = u->u_min[i];
+    c.umax[i] = u->u_max[i];
+    c.goal[i] = u->goal[i];
+    c.Q[i] = u->Q[i];
+    c.R[i] = u->R[i];
+    c.Qf[i] = u->Qf[i];
+    c.qlim[i] = u->q_limit[i];
+  }
+  const float e = u->dbscan_eps;
+  c.eps2 = e * e;
+  c.min_pts = u->dbscan_min_pts;
+  c.scene_mode = u->scene_mode;
+  c.H = u->history_len;
+  c.v_obs_min = u->v_obs_min;
+  c.ref_mode = u->ref_mode;
+  c.max_obs = u->max_obstacles;
+  c.robot_r = u->robot_radius;
+  c.wlim = u->w_limit;
+  if (c.dyn == CE_DYN_ARM6) {
+    double seg[6], total = 0.0;
+    for (int i = 0; i < 6; ++i) {
+      const double a = u->dh[i][0], d = u->dh[i][1], al = u->dh[i][2];
+      c.dh_a[i] = u->dh[i][0];
+      c.dh_d[i] = u->dh[i][1];
+      c.dh_ca[i] = (float)std::cos(al);
+      c.dh_sa[i] = (float)std::sin(al);
+      c.dh_off[i] = u->dh[i][3];
+      seg[i] = std::sqrt(a * a + d * d);
+      total += seg[i];
+    }
+    c.ns = u->n_link_spheres;
+    c.rs = u->link_sphere_radius;
+    // sphere s sits at arc length (s + 1/2)/ns of the frame-origin polyline;
+    // segment lengths sqrt(a^2 + d^2) do not depend on the joint angles
+    for (int s = 0; s < c.ns; ++s) {
+      const double target = ((double)s + 0.5) / (double)c.ns * total;
+      int i = 0;
+      double start = 0.0;
+      while (i < 5 && start + seg[i] < target) {
+        start += seg[i];
+        ++i;
+      }
+      c.sph_seg[s] = i;
+      c.sph_t[s] = seg[i] > 0.0 ? (float)((target - start) / seg[i]) : 0.f;
+    }
+  }
+  c.seed_lo = (uint32_t)(u->seed & 0xffffffffu);
+  c.seed_hi = (uint32_t)(u->seed >> 32);
+  c.stream_id = u->stream_id;
+  c.ntile = (c.K + kTile - 1) / kTile;
+  c.nblk_upd = (c.K + kUpdChunk - 1) / kUpdChunk;
+  c.mcap = c.K;
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+ce_status ce_mppi_config_init(ce_mppi_config* cfg, int32_t dynamics) {
+  if (!cfg) return fail(CE_EINVAL, "config is NULL");
+  if (dynamics != CE_DYN_UNICYCLE && dynamics != CE_DYN_ARM6) return fail(CE_EINVAL, "unknown dynamics");
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->abi_version = CE_MPPI_ABI_VERSION;
+  cfg->dynamics = dynamics;
+  cfg->horizon = 30;
+  cfg->num_samples = 1024;
+  cfg->dt = 0.1f;
+  cfg->lambda = 1.0f;
+  int n, m, p;
+  dims(dynamics, n, m, p);
+  for (int i = 0; i < m; ++i) cfg->noise_chol[i * m + i] = 0.5f;
+  for (int i = 0; i < 6; ++i) {
+    cfg->u_min[i] = -INFINITY;
+    cfg->u_max[i] = INFINITY;
+    cfg->q_limit[i] = 3.14159265f;
+  }
+  cfg->dbscan_eps = 0.3f;
+  cfg->dbscan_min_pts = 10;
+  cfg->norm_eps = 1e-6f;
+  cfg->scene_mode = CE_SCENE_STATIC;
+  cfg->history_len = 5;
+  cfg->v_obs_min = 1e-3f;
+  cfg->ref_mode = CE_REF_TERMINAL;
+  cfg->max_obstacles = CE_MPPI_MAX_OBSTACLES;
+  cfg->n_link_spheres = 8;
+  cfg->link_sphere_radius = 0.05f;
+  cfg->w_limit = 100.0f;
+  cfg->seed = 1;
+  return CE_OK;
+}
+
+ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
+  if (!out) return fail(CE_EINVAL, "out is NULL");
+  *out = nullptr;
+  ce_status st = validate(cfg);
+  if (st != CE_OK) return st;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return fail(CE_EDEVICE, "no HIP device available");
+  if (cfg->device < 0 || cfg->device >= ndev) return fail(CE_EINVAL, "device ordinal out of range");
+  DeviceGuard guard(cfg->device);
+
+  ce_mppi_planner* P = new (std::nothrow) ce_mppi_planner();
+  if (!P) return fail(CE_ENOMEM, "host allocation failed");
+  P->cfg = *cfg;
+  build_cfg(cfg, P->c);
+  const Cfg& c = P->c;
+  const size_t K = (size_t)c.K, NM = (size_t)c.NM, p = (size_t)c.p;
+  const size_t zs = c.p == 2 ? 2 : 4;
+  const size_t nw = (K + 63) / 64 + 1;
+  const size_t hist = (size_t)c.H * (size_t)(c.max_obs > 0 ? c.max_obs : 1) * p;
+  Carver cv;
+  const size_t o_ctrl = cv.take<Ctrl>(1);
+  const size_t o_U = cv.take<float>(NM), o_Unew = cv.take<float>(NM), o_hist = cv.take<float>(hist);
+  const size_t o_S = cv.take<float>(K), o_col = cv.take<int>(K), o_first = cv.take<int>(K);
+  const size_t o_pT = cv.take<float>(K * p), o_pF = cv.take<float>(K * p), o_g = cv.take<float>(K * p);
+  const size_t o_eps = cv.take<float>(K * NM);
+  const size_t o_part = cv.take<float>((size_t)c.nblk_roll * kPart);
+  const size_t o_foff = cv.take<int>((size_t)c.nblk_roll);
+  const size_t o_vidx = cv.take<int>(K), o_z = cv.take<float>(K * zs), o_gv = cv.take<float>(K * zs);
+  const size_t o_Sv = cv.take<float>(K);
+  const size_t o_nc = cv.take<int>(K), o_mcn = cv.take<int>(K), o_root = cv.take<int>(K);
+  const size_t o_rid = cv.take<int>(K), o_lab = cv.take<int>(K);
+  const size_t o_rm = cv.take<unsigned long long>(nw), o_woff = cv.take<int>(nw);
+  const size_t o_tslot = cv.take<unsigned long long>((size_t)c.ntile * c.ntile * kMaxTrees);
+  const size_t o_tcl = cv.take<int>(kMaxTrees), o_troot = cv.take<int>(kMaxTrees);
+  const size_t o_ccost = cv.take<float>((size_t)c.mcap), o_cdir = cv.take<float>((size_t)c.mcap * 4);
+  const size_t o_csize = cv.take<int>((size_t)c.mcap), o_csmin = cv.take<float>((size_t)c.mcap);
+  const size_t o_upart = cv.take<float>((size_t)c.nblk_upd * (NM + 1));
+  P->arena_bytes = cv.off;
+  e = hipMalloc(&P->arena, P->arena_bytes);
+  if (e != hipSuccess) {
+    delete P;
+    return fail(CE_ENOMEM, std::string("hipMalloc of the planner arena failed: ") + hipGetErrorString(e));
+  }
+  char* base = static_cast<char*>(P->arena);
+  Bufs& b = P->b;
+  b.ctrl = reinterpret_cast<Ctrl*>(base + o_ctrl);
+  b.U = reinterpret_cast<float*>(base + o_U);
+  b.Unew = reinterpret_cast<float*>(base + o_Unew);
+  b.hist = reinterpret_cast<float*>(base + o_hist);
+  b.S = reinterpret_cast<float*>(base + o_S);
+  b.col = reinterpret_cast<int*>(base + o_col);
+  b.first = reinterpret_cast<int*>(base + o_first);
+  b.pT = reinterpret_cast<float*>(base + o_pT);
+  b.pF = reinterpret_cast<float*>(base + o_pF);
+  b.g = reinterpret_cast<float*>(base + o_g);
+  b.eps = reinterpret_cast<float*>(base + o_eps);
+  b.part = reinterpret_cast<float*>(base + o_part);
+  b.feas_off = reinterpret_cast<int*>(base + o_foff);
+  b.vidx = reinterpret_cast<int*>(base + o_vidx);
+  b.z = reinterpret_cast<float*>(base + o_z);
+  b.gv = reinterpret_cast<float*>(base + o_gv);
+  b.Sv = reinterpret_cast<float*>(base + o_Sv);
+  b.ncount = reinterpret_cast<int*>(base + o_nc);
+  b.mcn = reinterpret_cast<int*>(base + o_mcn);
+  b.root = reinterpret_cast<int*>(base + o_root);
+  b.rid = reinterpret_cast<int*>(base + o_rid);
+  b.label = reinterpret_cast<int*>(base + o_lab);
+  b.rootmask = reinterpret_cast<unsigned long long*>(base + o_rm);
+  b.woff = reinterpret_cast<int*>(base + o_woff);
+  b.tslot = reinterpret_cast<unsigned long long*>(base + o_tslot);
+  b.tree_cluster = reinterpret_cast<int*>(base + o_tcl);
+  b.tree_root = reinterpret_cast<int*>(base + o_troot);
+  b.c_cost = reinterpret_cast<float*>(base + o_ccost);
+  b.c_dir = reinterpret_cast<float*>(base + o_cdir);
+  b.c_size = reinterpret_cast<int*>(base + o_csize);
+  b.c_smin = reinterpret_cast<float*>(base + o_csmin);
+  b.upart = reinterpret_cast<float*>(base + o_upart);
+  e = hipMemset(P->arena, 0, P->arena_bytes);
+  if (e == hipSuccess) {
+    Ctrl init;
+    std::memset(&init, 0, sizeof(init));
+    init.hist_head = c.H - 1;
+    init.hist_nobs = -1;
+    e = hipMemcpy(b.ctrl, &init, sizeof(init), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(P->arena);
+    delete P;
+    return hip_fail(e, "planner initialisation");
+  }
+  P->cap_K = K;
+  *out = P;
+  return CE_OK;
+}
+
+void ce_mppi_destroy(ce_mppi_planner* P) {
+  if (!P) return;
+  {
+    DeviceGuard guard(P->cfg.device);
+    if (P->arena) (void)hipFree(P->arena);
+  }
+  delete P;
+}
+
+ce_status ce_mppi_replan(ce_mppi_planner* P, const float* x_t, const float* obstacles, int32_t n_obs,
+                         float* u_out, float* U_out, ce_mppi_info* info, void* stream) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  if (!x_t || !u_out) return fail(CE_EINVAL, "x_t and u_out must not be NULL");
+  if (n_obs < 0 || n_obs > P->c.max_obs) return fail(CE_EINVAL, "n_obs outside 0..max_obstacles");
+  if (n_obs > 0 && !obstacles) return fail(CE_EINVAL, "obstacles is NULL with n_obs > 0");
+  DeviceGuard guard(P->cfg.device);
+  hipError_t e = launch_rollout(P->c, P->b, x_t, obstacles, n_obs, S(stream));
+  if (e == hipSuccess) e = launch_post_rollout(P->c, P->b, u_out, U_out, info, S(stream));
+  if (e != hipSuccess) return hip_fail(e, "replan launch");
+  return CE_OK;
+}
+
+ce_status ce_mppi_replan_from_rollouts(ce_mppi_planner* P, const float* x_t, const float* obstacles,
+                                       int32_t n_obs, const float* S_in, const int32_t* collide,
+                                       const int32_t* first_obs, const float* p_term,
+                                       const float* p_first, const float* eps, float* u_out,
+                                       float* U_out, ce_mppi_info* info, void* stream) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  if (!x_t || !u_out || !S_in || !collide || !first_obs || !p_term || !p_first || !eps)
+    return fail(CE_EINVAL, "NULL input or output");
+  if (n_obs < 0 || n_obs > P->c.max_obs) return fail(CE_EINVAL, "n_obs outside 0..max_obstacles");
+  if (n_obs > 0 && !obstacles) return fail(CE_EINVAL, "obstacles is NULL with n_obs > 0");
+  DeviceGuard guard(P->cfg.device);
+  const Cfg& c = P->c;
+  const Bufs& b = P->b;
+  const size_t K = (size_t)c.K;
+  hipStream_t s = S(stream);
+  hipError_t e = hipMemcpyAsync(b.S, S_in, K * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b.col, collide, K * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b.first, first_obs, K * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b.pT, p_term, K * c.p * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b.pF, p_first, K * c.p * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b.eps, eps, K * c.NM * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = launch_reduce_records(c, b, x_t, obstacles, n_obs, s);
+  if (e == hipSuccess) e = launch_post_rollout(c, b, u_out, U_out, info, s);
+  if (e != hipSuccess) return hip_fail(e, "replan_from_rollouts");
+  return CE_OK;
+}
+
+ce_status ce_mppi_stage_dbscan(ce_mppi_planner* P, const float* z, int32_t V, int32_t* ncount,
+                               int32_t* label, int32_t* n_clusters, void* stream) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  if (V < 0 || (size_t)V > P->cap_K) return fail(CE_EINVAL, "V outside 0..K");
+  if (V > 0 && (!z || !label)) return fail(CE_EINVAL, "z and label must not be NULL");
+  DeviceGuard guard(P->cfg.device);
+  const Cfg& c = P->c;
+  const Bufs& b = P->b;
+  hipStream_t s = S(stream);
+  hipError_t e = hipSuccess;
+  const float* zin = z;
+  if (V > 0 && c.p == 3) {
+    // caller layout [V][3] -> internal float4 rows
+    e = hipMemcpy2DAsync(b.gv, 16, z, 12, 12, V, hipMemcpyDeviceToDevice, s);
+    zin = b.gv;
+  }
+  if (e == hipSuccess) e = launch_stage_dbscan(c, b, zin, V, ncount, label, n_clusters, s);
+  if (e != hipSuccess) return hip_fail(e, "stage_dbscan");
+  return CE_OK;
+}
+
+ce_status ce_mppi_stage_noise(ce_mppi_planner* P, uint32_t step, uint32_t* words, float* gauss,
+                              void* stream) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  DeviceGuard guard(P->cfg.device);
+  hipError_t e = launch_stage_noise(P->c, step, words, gauss, S(stream));
+  if (e != hipSuccess) return hip_fail(e, "stage_noise");
+  return CE_OK;
+}
+
+ce_status ce_mppi_set_nominal(ce_mppi_planner* P, const float* U, void* stream) {
+  if (!P || !U) return fail(CE_EINVAL, "NULL argument");
+  DeviceGuard guard(P->cfg.device);
+  hipError_t e = hipMemcpyAsync(P->b.U, U, (size_t)P->c.NM * 4, hipMemcpyDeviceToDevice, S(stream));
+  if (e != hipSuccess) return hip_fail(e, "set_nominal");
+  return CE_OK;
+}
+
+ce_status ce_mppi_get_nominal(const ce_mppi_planner* P, float* U, void* stream) {
+  if (!P || !U) return fail(CE_EINVAL, "NULL argument");
+  DeviceGuard guard(P->cfg.device);
+  hipError_t e = hipMemcpyAsync(U, P->b.U, (size_t)P->c.NM * 4, hipMemcpyDeviceToDevice, S(stream));
+  if (e != hipSuccess) return hip_fail(e, "get_nominal");
+  return CE_OK;
+}
+
+namespace {
+// persistent part of the control block
+struct Persist {
+  uint32_t step_lo, step_hi;
+  int32_t hist_head, hist_count, hist_nobs;
+};
+static_assert(offsetof(Ctrl, step_lo) == 0 && offsetof(Ctrl, hist_nobs) == 16, "Ctrl prefix");
+
+struct StateHeader {
+  uint32_t magic, abi, dyn, N, m, p, H, max_obs;
+};
+constexpr uint32_t kStateMagic = 0x43454d50u;  // "CEMP"
+
+ce_status write_persist(ce_mppi_planner* P, const Persist& ps, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(P->b.ctrl, &ps, sizeof(ps), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "control block update");
+  return CE_OK;
+}
+
+ce_status read_persist(const ce_mppi_planner* P, Persist& ps, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(&ps, P->b.ctrl, sizeof(ps), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "control block read");
+  return CE_OK;
+}
+
+size_t hist_floats(const Cfg& c) {
+  return (size_t)c.H * (size_t)(c.max_obs > 0 ? c.max_obs : 1) * (size_t)c.p;
+}
+}  // namespace
+
+ce_status ce_mppi_reset_history(ce_mppi_planner* P, void* stream) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  DeviceGuard guard(P->cfg.device);
+  Persist ps;
+  ce_status st = read_persist(P, ps, S(stream));
+  if (st != CE_OK) return st;
+  ps.hist_head = P->c.H - 1;
+  ps.hist_count = 0;
+  ps.hist_nobs = -1;
+  return write_persist(P, ps, S(stream));
+}
+
+ce_status ce_mppi_set_step(ce_mppi_planner* P, uint64_t step, void* stream) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  DeviceGuard guard(P->cfg.device);
+  Persist ps;
+  ce_status st = read_persist(P, ps, S(stream));
+  if (st != CE_OK) return st;
+  ps.step_lo = (uint32_t)(step & 0xffffffffu);
+  ps.step_hi = (uint32_t)(step >> 32);
+  return write_persist(P, ps, S(stream));
+}
+
+ce_status ce_mppi_state_size(const ce_mppi_planner* P, size_t* bytes) {
+  if (!P || !bytes) return fail(CE_EINVAL, "NULL argument");
+  *bytes = sizeof(StateHeader) + sizeof(Persist) + (size_t)P->c.NM * 4 + hist_floats(P->c) * 4;
+  return CE_OK;
+}
+
+ce_status ce_mppi_get_state(const ce_mppi_planner* P, void* buf, size_t bytes, void* stream) {
+  size_t need = 0;
+  ce_status st = ce_mppi_state_size(P, &need);
+  if (st != CE_OK) return st;
+  if (!buf || bytes < need) return fail(CE_EINVAL, "state buffer too small");
+  DeviceGuard guard(P->cfg.device);
+  char* out = static_cast<char*>(buf);
+  StateHeader h{kStateMagic, CE_MPPI_ABI_VERSION, (uint32_t)P->c.dyn, (uint32_t)P->c.N,
+                (uint32_t)P->c.m, (uint32_t)P->c.p, (uint32_t)P->c.H, (uint32_t)P->c.max_obs};
+  std::memcpy(out, &h, sizeof(h));
+  Persist ps;
+  st = read_persist(P, ps, S(stream));
+  if (st != CE_OK) return st;
+  std::memcpy(out + sizeof(h), &ps, sizeof(ps));
+  char* p = out + sizeof(h) + sizeof(ps);
+  hipError_t e = hipMemcpyAsync(p, P->b.U, (size_t)P->c.NM * 4, hipMemcpyDeviceToHost, S(stream));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p + (size_t)P->c.NM * 4, P->b.hist, hist_floats(P->c) * 4,
+                       hipMemcpyDeviceToHost, S(stream));
+  if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
+  if (e != hipSuccess) return hip_fail(e, "get_state");
+  return CE_OK;
+}
+
+ce_status ce_mppi_set_state(ce_mppi_planner* P, const void* buf, size_t bytes, void* stream) {
+  size_t need = 0;
+  ce_status st = ce_mppi_state_size(P, &need);
+  if (st != CE_OK) return st;
+  if (!buf || bytes < need) return fail(CE_EINVAL, "state buffer too small");
+  const char* in = static_cast<const char*>(buf);
+  StateHeader h;
+  std::memcpy(&h, in, sizeof(h));
+  if (h.magic != kStateMagic || h.abi != CE_MPPI_ABI_VERSION || h.dyn != (uint32_t)P->c.dyn ||
+      h.N != (uint32_t)P->c.N || h.m != (uint32_t)P->c.m || h.p != (uint32_t)P->c.p ||
+      h.H != (uint32_t)P->c.H || h.max_obs != (uint32_t)P->c.max_obs)
+    return fail(CE_EINVAL, "state was saved by a planner with a different configuration");
+  DeviceGuard guard(P->cfg.device);
+  Persist ps;
+  std::memcpy(&ps, in + sizeof(h), sizeof(ps));
+  const char* p = in + sizeof(h) + sizeof(ps);
+  hipError_t e = hipMemcpyAsync(P->b.U, p, (size_t)P->c.NM * 4, hipMemcpyHostToDevice, S(stream));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(P->b.hist, p + (size_t)P->c.NM * 4, hist_floats(P->c) * 4,
+                       hipMemcpyHostToDevice, S(stream));
+  if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
+  if (e != hipSuccess) return hip_fail(e, "set_state");
+  return write_persist(P, ps, S(stream));
+}
+
+ce_status ce_mppi_debug_get(const ce_mppi_planner* P, int32_t which, void* dst, size_t bytes,
+                            void* stream) {
+  if (!P || !dst) return fail(CE_EINVAL, "NULL argument");
+  DeviceGuard guard(P->cfg.device);
+  const Cfg& c = P->c;
+  const Bufs& b = P->b;
+  const size_t K = (size_t)c.K, p = (size_t)c.p;
+  const void* src = nullptr;
+  size_t cap = 0;
+  size_t rows = 0, src_pitch = 0;  // strided float4 rows (p = 3 features)
+  switch (which) {
+    case CE_DBG_COST: src = b.S; cap = K * 4; break;
+    case CE_DBG_COLLIDE: src = b.col; cap = K * 4; break;
+    case CE_DBG_FIRST_OBS: src = b.first; cap = K * 4; break;
+    case CE_DBG_P_TERM: src = b.pT; cap = K * p * 4; break;
+    case CE_DBG_P_FIRST: src = b.pF; cap = K * p * 4; break;
+    case CE_DBG_EPS: src = b.eps; cap = K * (size_t)c.NM * 4; break;
+    case CE_DBG_V_IDX: src = b.vidx; cap = K * 4; break;
+    case CE_DBG_Z: src = b.z; cap = K * p * 4; if (p == 3) { rows = K; src_pitch = 16; } break;
+    case CE_DBG_G: src = b.gv; cap = K * p * 4; if (p == 3) { rows = K; src_pitch = 16; } break;
+    case CE_DBG_NCOUNT: src = b.ncount; cap = K * 4; break;
+    case CE_DBG_LABEL: src = b.label; cap = K * 4; break;
+    case CE_DBG_CLUSTER_COST: src = b.c_cost; cap = (size_t)c.mcap * 4; break;
+    case CE_DBG_CLUSTER_DIR: src = b.c_dir; cap = (size_t)c.mcap * p * 4; rows = c.mcap; src_pitch = 16; break;
+    case CE_DBG_CLUSTER_SIZE: src = b.c_size; cap = (size_t)c.mcap * 4; break;
+    default: return fail(CE_EINVAL, "unknown debug buffer");
+  }
+  const size_t n = bytes < cap ? bytes : cap;
+  hipError_t e;
+  if (src_pitch) {
+    const size_t row_bytes = p * 4;
+    const size_t nrows = n / row_bytes < rows ? n / row_bytes : rows;
+    e = nrows ? hipMemcpy2DAsync(dst, row_bytes, src, src_pitch, row_bytes, nrows,
+                                 hipMemcpyDeviceToDevice, S(stream))
+              : hipSuccess;
+  } else {
+    e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, S(stream));
+  }
+  if (e != hipSuccess) return hip_fail(e, "debug_get");
+  return CE_OK;
+}
+
+const char* ce_mppi_status_string(ce_status s) {
+  switch (s) {
+    case CE_OK: return "ok";
+    case CE_EINVAL: return "invalid argument";
+    case CE_ENOMEM: return "out of device memory";
+    case CE_EDEVICE: return "device error";
+    case CE_EUNSUPPORTED: return "unsupported";
+    case CE_EBUSY: return "busy";
+    default: return "unknown status";
+  }
+}
+
+const char* ce_mppi_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

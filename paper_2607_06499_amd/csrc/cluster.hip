@@ -1,0 +1,874 @@
+// cluster.hip -- everything after the rollouts: pruning and stable compaction
+// of the feasible set with the features of Eq. (12)-(13), DBSCAN
+// (Sec. II-B.2), cluster statistics and selection (Alg. 1 [Cluster stats] /
+// [Selection], Eq. (14)-(18)) and the path-integral update with the shift
+// (Eq. (6)-(7), Eq. (19)-(20), Alg. 1 [Execute]).
+//
+// No kernel here communicates between its own workgroups: every reduction
+// that several blocks need is recomputed by each of them from the previous
+// kernel's outputs in a fixed order (so results are deterministic), and the
+// work that needs a single view runs in a one-block kernel.
+//
+// DBSCAN plan (exact, deterministic; V = number of feasible rollouts):
+//  1. count   tiled all-pairs eps-neighbour count -> core flags
+//  2. mcn     tiled all-pairs lowest-index core neighbour; for a core point it
+//             is its hook target, for a non-core point it is exactly the
+//             border rule (join the cluster of the lowest-index core neighbour)
+//  3. roots   follow the hooks (indices strictly decrease) to a tree root;
+//             trees are numbered by root index
+//  4. trees   tiled pass over core-core neighbour pairs of different trees;
+//             each tile writes the tree adjacency bits it saw to its own slot
+//  5. tree CC connected components of the (small) tree graph; the cluster of
+//             a component is ranked by its lowest root index, which is the
+//             lowest core index of the cluster
+// With more than 64 trees, steps 4-5 are replaced by an exact
+// single-workgroup union-find over the core graph.
+#include "device.hpp"
+
+namespace cemppi {
+
+template <int P>
+struct ZVec;
+template <>
+struct ZVec<2> {
+  using T = float2;
+  static __device__ __forceinline__ T far() { return make_float2(1e30f, 1e30f); }
+  static __device__ __forceinline__ float d2(T a, T b) { return dist2_2(a.x, a.y, b.x, b.y); }
+};
+template <>
+struct ZVec<3> {
+  using T = float4;
+  static __device__ __forceinline__ T far() { return make_float4(1e30f, 1e30f, 1e30f, 0.f); }
+  static __device__ __forceinline__ float d2(T a, T b) { return dist2_3(a.x, a.y, a.z, b.x, b.y, b.z); }
+};
+
+__device__ __forceinline__ bool is_min_field(int f) { return f == P_SMIN_ALL || f == P_SMIN_FEAS; }
+
+// ---------------------------------------------------------------------------
+// Reduction of the rollout blocks' partial records (256-thread blocks):
+// thread t owns records t, t+256, ... (coalesced), then a fixed tree.  Also
+// returns the number of feasible rollouts in records [0, upto).
+__device__ void reduce_partials(const Cfg& c, const Bufs& b, int upto, float* s_tot, int* s_before) {
+  __shared__ float s_red[kPart + 1][256];
+  const int tid = threadIdx.x;
+  float acc[kPart + 1];
+#pragma unroll
+  for (int f = 0; f < kPart; ++f) acc[f] = is_min_field(f) ? INFINITY : 0.f;
+  acc[kPart] = 0.f;
+  const float4* rows = reinterpret_cast<const float4*>(b.part);
+  for (int i = tid; i < c.nblk_roll; i += 256) {
+    const float4 x = rows[3 * i], y = rows[3 * i + 1], z = rows[3 * i + 2];
+    const float v[kPart] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w, z.x, z.y, z.z, z.w};
+#pragma unroll
+    for (int f = 0; f < kPart; ++f) acc[f] = is_min_field(f) ? fminf(acc[f], v[f]) : acc[f] + v[f];
+    if (i < upto) acc[kPart] += v[P_NFEAS];
+  }
+#pragma unroll
+  for (int f = 0; f <= kPart; ++f) s_red[f][tid] = acc[f];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+#pragma unroll
+      for (int f = 0; f <= kPart; ++f)
+        s_red[f][tid] = (f < kPart && is_min_field(f)) ? fminf(s_red[f][tid], s_red[f][tid + w])
+                                                        : s_red[f][tid] + s_red[f][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid <= kPart) s_tot[tid] = s_red[tid][0];
+  if (tid == 0) *s_before = (int)s_red[kPart][0];
+  __syncthreads();
+}
+
+// Branch of Alg. 1 and the reference point of Eq. (11) from the totals.
+struct Totals {
+  int branch, ncol, nfeas, nref;
+  uint32_t status;
+  float ref[3];
+};
+__device__ __forceinline__ Totals decide(const Cfg& c, const float* tot, int bad) {
+  Totals t;
+  t.ncol = (int)tot[P_NCOL];
+  t.nfeas = (int)tot[P_NFEAS];
+  const int na = (int)tot[P_NREF];
+  if (bad) {
+    t.branch = 1;
+    t.status = 16u;
+  } else if (t.ncol == 0) {
+    t.branch = 1;
+    t.status = 1u;
+  } else if (t.nfeas == 0) {
+    t.branch = 2;
+    t.status = 2u;
+  } else {
+    t.branch = 0;
+    t.status = 0u;
+  }
+  // the rollouts whose first contact is o*, or every colliding rollout
+  const bool useA = na > 0;
+  const float cnt = useA ? (float)na : (float)t.ncol;
+  for (int i = 0; i < 3; ++i) {
+    const float sum = useA ? tot[P_SUM_REF + i] : tot[P_SUM_COL + i];
+    t.ref[i] = (t.branch == 0 && i < c.p) ? sum / cnt : 0.f;
+  }
+  t.nref = t.branch == 0 ? (useA ? na : t.ncol) : 0;
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Pruning (Eq. (9)-(10)), reference point (Eq. (11)), stable compaction of V
+// in ascending rollout order, features z (Eq. (13)) and the DBSCAN arrays.
+// Block 0 publishes the totals.
+template <int P>
+__global__ __launch_bounds__(256) void k_compact(Cfg c, Bufs b) {
+  using ZT = typename ZVec<P>::T;
+  __shared__ float s_tot[kPart + 1];
+  __shared__ int s_before;
+  const int blk0 = (blockIdx.x * 256) / c.rpb;
+  reduce_partials(c, b, blk0, s_tot, &s_before);
+  const int bad = b.ctrl->nonfinite;
+  const Totals T = decide(c, s_tot, bad);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctrl* ct = b.ctrl;
+    ct->n_col = T.ncol;
+    ct->n_feas = T.nfeas;
+    ct->n_ref = T.nref;
+    ct->branch = T.branch;
+    ct->status = T.status;
+    ct->smin_all = s_tot[P_SMIN_ALL];
+    ct->smin_feas = s_tot[P_SMIN_FEAS];
+    ct->M = 0;
+    ct->sel = -1;
+    for (int i = 0; i < 3; ++i) ct->ref[i] = T.ref[i];
+  }
+  if (T.branch != 0) return;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int feas = (k < c.K) ? !b.col[k] : 0;
+  int tot;
+  const int local = block_excl_scan<256>(feas, &tot);
+  if (!feas) return;
+  const int rank = s_before + local;
+  float d[3] = {0.f, 0.f, 0.f}, g[3] = {0.f, 0.f, 0.f};
+  for (int i = 0; i < P; ++i) {
+    d[i] = b.pT[(size_t)k * P + i] - T.ref[i];
+    g[i] = b.g[(size_t)k * P + i];
+  }
+  const float nd = sqrtf(__builtin_fmaf(d[2], d[2], __builtin_fmaf(d[1], d[1], d[0] * d[0])));
+  const float den = nd + c.norm_eps;
+  ZT zz, gg;
+  if constexpr (P == 2) {
+    zz = make_float2(d[0] / den, d[1] / den);
+    gg = make_float2(g[0], g[1]);
+  } else {
+    zz = make_float4(d[0] / den, d[1] / den, d[2] / den, 0.f);
+    gg = make_float4(g[0], g[1], g[2], 0.f);
+  }
+  reinterpret_cast<ZT*>(b.z)[rank] = zz;
+  reinterpret_cast<ZT*>(b.gv)[rank] = gg;
+  b.vidx[rank] = k;
+  b.Sv[rank] = b.S[k];
+  b.ncount[rank] = 0;
+  b.mcn[rank] = kInt32Max;
+  b.root[rank] = -1;
+  b.label[rank] = -1;
+}
+
+// per-point DBSCAN state for a stage call on caller features
+__global__ void k_init_points(Bufs b, int V) {
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= V) return;
+  b.ncount[a] = 0;
+  b.mcn[a] = kInt32Max;
+  b.root[a] = -1;
+  b.label[a] = -1;
+}
+
+// number of points DBSCAN runs on: caller features (stage) or the feasible set
+__device__ __forceinline__ int dbscan_V(const Bufs& b, const float* zin, int Vin) {
+  return zin ? Vin : (b.ctrl->branch == 0 ? b.ctrl->n_feas : 0);
+}
+
+// ---------------------------------------------------------------------------
+// 1. neighbour counts: block (I, J) counts, for each row point of tile I, its
+// neighbours among the column points of tile J (closed ball, itself included).
+template <int P>
+__global__ __launch_bounds__(kTile) void k_count(Cfg c, Bufs b, const float* __restrict__ zin,
+                                                 int Vin) {
+  using ZT = typename ZVec<P>::T;
+  __shared__ ZT s_z[kTile];
+  const int V = dbscan_V(b, zin, Vin);
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I * kTile >= V || J * kTile >= V) return;
+  const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
+  const int l = J * kTile + threadIdx.x;
+  s_z[threadIdx.x] = l < V ? z[l] : ZVec<P>::far();
+  const int k = I * kTile + threadIdx.x;
+  const ZT zk = k < V ? z[k] : ZVec<P>::far();
+  __syncthreads();
+  const float r2 = c.eps2;
+  const int ncol = min(kTile, V - J * kTile);
+  int cnt = 0;
+  for (int t = 0; t < ncol; ++t) cnt += ZVec<P>::d2(zk, s_z[t]) <= r2 ? 1 : 0;
+  if (k < V && cnt) atomicAdd(&b.ncount[k], cnt);
+}
+
+// 2. lowest-index core neighbour of every point (core points include
+// themselves).
+template <int P>
+__global__ __launch_bounds__(kTile) void k_mcn(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  using ZT = typename ZVec<P>::T;
+  __shared__ ZT s_z[kTile];
+  const int V = dbscan_V(b, zin, Vin);
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I * kTile >= V || J * kTile >= V) return;
+  const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
+  const int l = J * kTile + threadIdx.x;
+  // non-core columns are parked far away: they can never be a neighbour here
+  s_z[threadIdx.x] = (l < V && b.ncount[l] >= c.min_pts) ? z[l] : ZVec<P>::far();
+  const int k = I * kTile + threadIdx.x;
+  const ZT zk = k < V ? z[k] : ZVec<P>::far();
+  __syncthreads();
+  if (k >= V) return;
+  const float r2 = c.eps2;
+  const int ncol = min(kTile, V - J * kTile);
+  int m = kInt32Max;
+  for (int t = 0; t < ncol; ++t) {
+    const bool h = ZVec<P>::d2(zk, s_z[t]) <= r2;
+    m = (h && m == kInt32Max) ? J * kTile + t : m;
+  }
+  if (m != kInt32Max) atomicMin(&b.mcn[k], m);
+}
+
+// 3. roots: follow the hook chain of each core point (indices decrease, so the
+// walk ends at a point that hooks to itself); root flags go into 64-bit words.
+__global__ __launch_bounds__(256) void k_roots(Cfg c, Bufs b, const float* zin, int Vin) {
+  const int V = dbscan_V(b, zin, Vin);
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x * 256 >= V) return;
+  bool isroot = false;
+  if (a < V) {
+    if (b.ncount[a] >= c.min_pts) {
+      int r = b.mcn[a];
+      while (true) {
+        const int n = b.mcn[r];
+        if (n == r) break;
+        r = n;
+      }
+      b.root[a] = r;
+      isroot = (r == a);
+    } else {
+      b.root[a] = -1;
+    }
+  }
+  const unsigned long long m = __ballot(isroot);
+  if ((threadIdx.x & 63) == 0 && a < V) b.rootmask[a >> 6] = m;
+}
+
+// Tree numbering: exclusive prefix of root counts over the root-flag words,
+// computed by each block that needs it into LDS; returns the number of trees.
+template <int NT>
+__device__ int tree_prefix(const Bufs& b, int V, int* s_woff) {
+  const int nwords = (V + 63) >> 6;
+  const int per = (nwords + NT - 1) / NT;
+  const int lo = min((int)threadIdx.x * per, nwords), hi = min(lo + per, nwords);
+  int mine = 0;
+  for (int i = lo; i < hi; ++i) mine += __popcll(b.rootmask[i]);
+  int tot;
+  int off = block_excl_scan<NT>(mine, &tot);
+  for (int i = lo; i < hi; ++i) {
+    s_woff[i] = off;
+    off += __popcll(b.rootmask[i]);
+  }
+  __syncthreads();
+  return tot;
+}
+
+__device__ __forceinline__ int tree_id(const unsigned long long* rootmask, const int* woff, int r) {
+  const int w = r >> 6, bit = r & 63;
+  const unsigned long long below = bit ? (rootmask[w] & ((1ull << bit) - 1ull)) : 0ull;
+  return woff[w] + __popcll(below);
+}
+
+constexpr int kMaxWords = (65536 + 63) / 64;
+
+// 4. tree adjacency: for every core-core neighbour pair (row k, column l) of
+// different trees set bit tree(l) in the row of tree(k); the tile's rows go
+// to its own slot (no cross-block atomics).
+template <int P>
+__global__ __launch_bounds__(kTile) void k_tree_adj(Cfg c, Bufs b, const float* __restrict__ zin,
+                                                    int Vin, int ntile) {
+  using ZT = typename ZVec<P>::T;
+  __shared__ ZT s_z[kTile];
+  __shared__ int s_t[kTile];
+  __shared__ int s_woff[kMaxWords];
+  __shared__ unsigned long long s_adj[kMaxTrees];
+  const int V = dbscan_V(b, zin, Vin);
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I * kTile >= V || J * kTile >= V) return;
+  const int R = tree_prefix<kTile>(b, V, s_woff);
+  if (R < 2 || R > kMaxTrees) return;
+  if (threadIdx.x < kMaxTrees) s_adj[threadIdx.x] = 0ull;
+  const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
+  const int l = J * kTile + threadIdx.x;
+  int tl = -1;
+  if (l < V && b.ncount[l] >= c.min_pts) tl = tree_id(b.rootmask, s_woff, b.root[l]);
+  s_z[threadIdx.x] = tl >= 0 ? z[l] : ZVec<P>::far();
+  s_t[threadIdx.x] = tl >= 0 ? tl : 0;
+  const int k = I * kTile + threadIdx.x;
+  int tk = -1;
+  if (k < V && b.ncount[k] >= c.min_pts) tk = tree_id(b.rootmask, s_woff, b.root[k]);
+  const ZT zk = tk >= 0 ? z[k] : ZVec<P>::far();
+  __syncthreads();
+  if (tk >= 0) {
+    const float r2 = c.eps2;
+    const int ncol = min(kTile, V - J * kTile);
+    unsigned long long mask = 0ull;
+    for (int t = 0; t < ncol; ++t) {
+      const bool h = ZVec<P>::d2(zk, s_z[t]) <= r2;
+      mask |= h ? (1ull << s_t[t]) : 0ull;
+    }
+    mask &= ~(1ull << tk);
+    if (mask) atomicOr(&s_adj[tk], mask);
+  }
+  __syncthreads();
+  if (threadIdx.x < R) b.tslot[((size_t)I * ntile + J) * kMaxTrees + threadIdx.x] = s_adj[threadIdx.x];
+}
+
+// 5. connected components of the tree graph and canonical cluster numbers
+// (one 1024-thread block), or the exact fallback for more than 64 trees.
+template <int P>
+__device__ void uf_fallback(const Cfg& c, const Bufs& b, const float* zin, int V) {
+  // single-workgroup union-find over core-core neighbour pairs.  root[]
+  // already holds the hook forest of step 3 (each core points to a lower-index
+  // core of its own component, roots point to themselves): a valid starting
+  // forest.  Hooks always go to the smaller root, so the final root of a
+  // component is its lowest core index.
+  using ZT = typename ZVec<P>::T;
+  const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
+  int* parent = b.root;
+  const float r2 = c.eps2;
+  auto find = [&](int x) {
+    while (true) {
+      const int p = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (p == x) return x;
+      x = p;
+    }
+  };
+  for (int a = threadIdx.x; a < V; a += blockDim.x) {
+    if (b.ncount[a] < c.min_pts) continue;
+    const ZT za = z[a];
+    for (int l = a + 1; l < V; ++l) {
+      if (b.ncount[l] < c.min_pts) continue;
+      if (!(ZVec<P>::d2(za, z[l]) <= r2)) continue;
+      int x = a, y = l;
+      while (true) {
+        x = find(x);
+        y = find(y);
+        if (x == y) break;
+        if (x > y) {
+          const int t = x;
+          x = y;
+          y = t;
+        }
+        int expected = y;
+        if (__hip_atomic_compare_exchange_strong(&parent[y], &expected, x, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+          break;
+        y = expected;
+      }
+    }
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < V; a += blockDim.x)
+    if (b.ncount[a] >= c.min_pts) parent[a] = find(a);
+  __syncthreads();
+}
+
+template <int P>
+__global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const float* __restrict__ zin,
+                                                         int Vin, int ntile, int* mout) {
+  __shared__ int s_woff[kMaxWords];
+  __shared__ unsigned long long s_adj[kMaxTrees];
+  __shared__ unsigned long long s_part[kFinThreads / kWave][kMaxTrees];
+  const int V = dbscan_V(b, zin, Vin);
+  const int R = V > 0 ? tree_prefix<kFinThreads>(b, V, s_woff) : 0;
+  const int nwords = (V + 63) >> 6;
+  for (int i = threadIdx.x; i < nwords; i += kFinThreads) b.woff[i] = s_woff[i];
+  if (threadIdx.x == 0) {
+    b.ctrl->n_trees = R;
+    b.ctrl->tree_overflow = R > kMaxTrees ? 1 : 0;
+  }
+  if (R <= 1) {
+    if (threadIdx.x == 0) {
+      if (R == 1) b.tree_cluster[0] = 0;
+      b.ctrl->M = R;
+      if (mout) *mout = R;
+    }
+    return;
+  }
+  if (R <= kMaxTrees) {
+    // OR the tile slots: wave w takes tiles w, w+16, ...; lane = tree row
+    const int nt = (V + kTile - 1) / kTile;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    unsigned long long acc = 0ull;
+    if (lane < R) {
+      for (int t = w; t < nt * nt; t += kFinThreads / kWave) {
+        const int I = t / nt, J = t % nt;
+        acc |= b.tslot[((size_t)I * ntile + J) * kMaxTrees + lane];
+      }
+    }
+    s_part[w][lane] = acc;
+    __syncthreads();
+    if (threadIdx.x < kMaxTrees) {
+      unsigned long long a = 0ull;
+      for (int i = 0; i < kFinThreads / kWave; ++i) a |= s_part[i][threadIdx.x];
+      s_adj[threadIdx.x] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x >= kWave) return;
+    const int r = threadIdx.x;
+    // make the relation symmetric, then close it transitively
+    unsigned long long reach = r < R ? (s_adj[r] | (1ull << r)) : 0ull;
+    for (int t = 0; t < R; ++t)
+      if ((s_adj[t] >> r) & 1ull) reach |= 1ull << t;
+    if (r >= R) reach = 0ull;
+    for (int it = 0; it < 64; ++it) {
+      unsigned long long nr = reach;
+      for (int t = 0; t < R; ++t) {
+        const unsigned long long rt = __shfl(reach, t, kWave);
+        if ((reach >> t) & 1ull) nr |= rt;
+      }
+      const bool changed = __ballot(nr != reach) != 0ull;
+      reach = nr;
+      if (!changed) break;
+    }
+    const int cmin = r < R ? __ffsll((long long)reach) - 1 : kInt32Max;
+    const unsigned long long heads = __ballot(r < R && cmin == r);
+    if (r < R) {
+      const unsigned long long below = cmin ? (heads & ((1ull << cmin) - 1ull)) : 0ull;
+      b.tree_cluster[r] = __popcll(below);
+    }
+    if (r == 0) {
+      b.ctrl->M = __popcll(heads);
+      if (mout) *mout = __popcll(heads);
+    }
+    return;
+  }
+  // exact fallback
+  uf_fallback<P>(c, b, zin, V);
+  // clusters = components ranked by their root (lowest core index); the
+  // cluster number of each root is parked in label[root] for k_label
+  int base = 0;
+  for (int a0 = 0; a0 < V; a0 += kFinThreads) {
+    const int a = a0 + threadIdx.x;
+    const int isr = (a < V && b.ncount[a] >= c.min_pts && b.root[a] == a) ? 1 : 0;
+    int tot;
+    const int ex = block_excl_scan<kFinThreads>(isr, &tot);
+    if (isr) b.label[a] = base + ex;
+    base += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    b.ctrl->M = base;
+    if (mout) *mout = base;
+  }
+}
+
+// final labels: core -> cluster of its tree / component; border -> cluster of
+// its lowest-index core neighbour; noise -> -1.  In the fallback, label[] of
+// a root holds its cluster number (written by k_tree_cc); a root's own thread
+// rewrites the same value, so every read of it is stable.
+__global__ __launch_bounds__(256) void k_label(Cfg c, Bufs b, const float* zin, int Vin,
+                                               int* lab_out, int* cnt_out) {
+  const int V = dbscan_V(b, zin, Vin);
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= V) return;
+  const bool overflow = b.ctrl->tree_overflow != 0;
+  const int R = b.ctrl->n_trees;
+  int x = -1;
+  if (b.ncount[a] >= c.min_pts) x = a;
+  else if (b.mcn[a] != kInt32Max) x = b.mcn[a];
+  int lab = -1;
+  if (x >= 0) {
+    const int r = b.root[x];
+    if (overflow) lab = b.label[r];
+    else lab = R == 1 ? 0 : b.tree_cluster[tree_id(b.rootmask, b.woff, r)];
+  }
+  b.label[a] = lab;
+  if (lab_out) lab_out[a] = lab;
+  if (cnt_out) cnt_out[a] = b.ncount[a];
+}
+
+// ---------------------------------------------------------------------------
+// Cluster statistics with fixed-order block reductions: count, mean cost
+// (Alg. 1 [Cluster stats]), normalised mean direction (Eq. (16)), minimum
+// cost.  Block b handles clusters b, b + gridDim.x, ...
+template <int P>
+__global__ __launch_bounds__(256) void k_stats(Cfg c, Bufs b) {
+  using ZT = typename ZVec<P>::T;
+  __shared__ float s_r[6][256];
+  const Ctrl* ct = b.ctrl;
+  const int branch = ct->branch;
+  const int V = branch == 0 ? ct->n_feas : 0;
+  const int M = branch == 0 ? ct->M : 0;
+  const ZT* gv = reinterpret_cast<const ZT*>(b.gv);
+  for (int cl = blockIdx.x; cl < M; cl += gridDim.x) {
+    float n = 0.f, sS = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, mn = INFINITY;
+    for (int a = threadIdx.x; a < V; a += 256) {
+      if (b.label[a] != cl) continue;
+      const float S = b.Sv[a];
+      const ZT g = gv[a];
+      n += 1.f;
+      sS += S;
+      g0 += g.x;
+      g1 += g.y;
+      if constexpr (P == 3) g2 += g.z;
+      mn = fminf(mn, S);
+    }
+    s_r[0][threadIdx.x] = n;
+    s_r[1][threadIdx.x] = sS;
+    s_r[2][threadIdx.x] = g0;
+    s_r[3][threadIdx.x] = g1;
+    s_r[4][threadIdx.x] = g2;
+    s_r[5][threadIdx.x] = mn;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        for (int f = 0; f < 5; ++f) s_r[f][threadIdx.x] += s_r[f][threadIdx.x + w];
+        s_r[5][threadIdx.x] = fminf(s_r[5][threadIdx.x], s_r[5][threadIdx.x + w]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const float cnt = s_r[0][0];
+      const float vx = s_r[2][0] / cnt, vy = s_r[3][0] / cnt, vz = s_r[4][0] / cnt;
+      const float nv = sqrtf(__builtin_fmaf(vz, vz, __builtin_fmaf(vy, vy, vx * vx))) + c.norm_eps;
+      b.c_size[cl] = (int)cnt;
+      b.c_cost[cl] = s_r[1][0] / cnt;
+      b.c_dir[4 * cl] = vx / nv;
+      b.c_dir[4 * cl + 1] = vy / nv;
+      b.c_dir[4 * cl + 2] = P == 3 ? vz / nv : 0.f;
+      b.c_smin[cl] = s_r[5][0];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Selection (Eq. (14), or Eq. (17)-(18) for the dynamic rule), computed the
+// same way by every update block: each thread scans a strided subset of the
+// clusters keeping its best and second-best key, then a fixed tree merges
+// them (ties go to the lowest cluster number).
+struct Sel {
+  int sel, rule, h_used;
+  uint32_t status_add;
+  float margin, v[3], vh[3];
+};
+
+__device__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
+  __shared__ float s_k1[kUpdThreads], s_k2[kUpdThreads];
+  __shared__ int s_i1[kUpdThreads];
+  __shared__ Sel s_sel;
+  const Ctrl* ct = b.ctrl;
+  if (threadIdx.x == 0) {
+    Sel s;
+    s.sel = -1;
+    s.rule = 0;
+    s.h_used = 0;
+    s.status_add = 0u;
+    s.margin = INFINITY;
+    for (int i = 0; i < 3; ++i) s.v[i] = s.vh[i] = 0.f;
+    if (M == 0) {
+      s.status_add = 4u;  // no cluster: update over all of V
+    } else if (c.scene_mode == 1) {
+      const int hc = ct->hist_count;
+      const int Hp = hc < c.H ? hc : c.H;
+      s.h_used = Hp;
+      const int o = ct->closest;
+      if (Hp >= 2 && o >= 0) {
+        // Eq. (17): the mean of H'-1 finite differences telescopes to
+        // (o_t - o_{t-H'+1}) / ((H'-1) dt)
+        const int h0 = ct->hist_head;
+        const int h1 = (h0 - (Hp - 1) + 2 * c.H) % c.H;
+        for (int i = 0; i < c.p; ++i) {
+          const float a = b.hist[((size_t)h0 * c.max_obs + o) * c.p + i];
+          const float z0 = b.hist[((size_t)h1 * c.max_obs + o) * c.p + i];
+          s.v[i] = (a - z0) / ((float)(Hp - 1) * c.dt);
+        }
+      }
+      const float nv =
+          sqrtf(__builtin_fmaf(s.v[2], s.v[2], __builtin_fmaf(s.v[1], s.v[1], s.v[0] * s.v[0])));
+      for (int i = 0; i < 3; ++i) s.vh[i] = s.v[i] / (nv + c.norm_eps);
+      if (Hp >= 2 && !(nv < c.v_obs_min)) s.rule = 1;
+      else s.status_add = 8u;
+    }
+    s_sel = s;
+  }
+  __syncthreads();
+  Sel s = s_sel;
+  if (M == 0) return s;
+  float k1 = INFINITY, k2 = INFINITY;
+  int i1 = kInt32Max;
+  for (int cl = threadIdx.x; cl < M; cl += kUpdThreads) {
+    float key;
+    if (s.rule == 0) key = b.c_cost[cl];
+    else key = b.c_dir[4 * cl] * s.vh[0] + b.c_dir[4 * cl + 1] * s.vh[1] + b.c_dir[4 * cl + 2] * s.vh[2];
+    if (key < k1) {  // clusters are visited in increasing order: strict < keeps the lowest
+      k2 = k1;
+      k1 = key;
+      i1 = cl;
+    } else if (key < k2) {
+      k2 = key;
+    }
+  }
+  s_k1[threadIdx.x] = k1;
+  s_k2[threadIdx.x] = k2;
+  s_i1[threadIdx.x] = i1;
+  __syncthreads();
+  for (int w = kUpdThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const float a1 = s_k1[threadIdx.x], a2 = s_k2[threadIdx.x];
+      const float b1 = s_k1[threadIdx.x + w], b2 = s_k2[threadIdx.x + w];
+      const int ai = s_i1[threadIdx.x], bi = s_i1[threadIdx.x + w];
+      const bool takeb = b1 < a1 || (b1 == a1 && bi < ai);
+      s_k1[threadIdx.x] = takeb ? b1 : a1;
+      s_i1[threadIdx.x] = takeb ? bi : ai;
+      s_k2[threadIdx.x] = fminf(fminf(a2, b2), takeb ? a1 : b1);
+    }
+    __syncthreads();
+  }
+  s.sel = s_i1[0];
+  s.margin = M > 1 ? s_k2[0] - s_k1[0] : INFINITY;
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Update partials, Eq. (19)-(20) (Eq. (6)-(7) on the fallback branches):
+// block b takes kUpdChunk candidates (16 per wave); lane = element of the
+// [N][m] sequence; the four waves' sums are combined in a fixed order.
+__global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
+  __shared__ float s_w[kUpdChunk];
+  __shared__ int s_k[kUpdChunk];
+  __shared__ float s_acc[kUpdThreads / kWave][kWave];
+  const Ctrl* ct = b.ctrl;
+  const int branch = ct->branch;
+  const bool bad = ct->nonfinite != 0;
+  const int NM = c.NM;
+  const bool over_all = branch != 0;
+  const int M = branch == 0 ? ct->M : 0;
+  Sel s;
+  if (branch == 0) {
+    s = select_cluster(c, b, M);
+  } else {
+    s.sel = -1;
+    s.rule = 0;
+    s.h_used = 0;
+    s.status_add = 0u;
+    s.margin = INFINITY;
+    for (int i = 0; i < 3; ++i) s.v[i] = s.vh[i] = 0.f;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && branch == 0) {
+    Ctrl* cw = b.ctrl;
+    cw->sel = s.sel;
+    cw->rule = s.rule;
+    cw->h_used = s.h_used;
+    cw->margin = s.margin;
+    cw->status = ct->status | s.status_add;
+    for (int i = 0; i < 3; ++i) {
+      cw->v_obs[i] = s.v[i];
+      cw->v_hat[i] = s.vh[i];
+    }
+    cw->sel_size = s.sel >= 0 ? b.c_size[s.sel] : 0;
+  }
+  const int ncand = over_all ? c.K : ct->n_feas;
+  const int sel = s.sel;
+  const float smin = over_all ? ct->smin_all : (sel >= 0 ? b.c_smin[sel] : ct->smin_feas);
+  const float inv_l = 1.0f / c.lambda;
+  const int a0 = blockIdx.x * kUpdChunk;
+  if (threadIdx.x < kUpdChunk) {
+    const int a = a0 + threadIdx.x;
+    float w = 0.f;
+    int k = 0;
+    if (!bad && a < ncand) {
+      if (over_all) {
+        k = a;
+        w = expf(-(b.S[a] - smin) * inv_l);
+      } else if (sel < 0 || b.label[a] == sel) {
+        k = b.vidx[a];
+        w = expf(-(b.Sv[a] - smin) * inv_l);
+      }
+    }
+    s_w[threadIdx.x] = w;
+    s_k[threadIdx.x] = k;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  constexpr int PER = kUpdChunk / (kUpdThreads / kWave);
+  float* part = b.upart + (size_t)blockIdx.x * (NM + 1);
+  for (int e0 = 0; e0 < NM + 1; e0 += kWave) {
+    const int e = e0 + lane;
+    float acc = 0.f;
+    if (e < NM) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int ci = wv * PER + i;
+        acc += s_w[ci] * b.eps[(size_t)s_k[ci] * NM + e];
+      }
+    } else if (e == NM) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) acc += s_w[wv * PER + i];
+    }
+    s_acc[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && e <= NM) part[e] = ((s_acc[0][lane] + s_acc[1][lane]) + s_acc[2][lane]) + s_acc[3][lane];
+    __syncthreads();
+  }
+}
+
+// Final combination (one block): sum of the update partials in a fixed order,
+// U_new = U + sum / sum(w), outputs, shift (last control repeated), step
+// counter and the info record.
+__global__ __launch_bounds__(kFinThreads) void k_finish(Cfg c, Bufs b, float* __restrict__ u_out,
+                                                        float* __restrict__ U_out, void* info_out) {
+  __shared__ float s_sum[kFinThreads];
+  __shared__ float s_tot[kMaxNM + 1];
+  const Ctrl* ct = b.ctrl;
+  const bool bad = ct->nonfinite != 0;
+  const int NM = c.NM, W = NM + 1;
+  const int nb = c.nblk_upd;
+  // G threads per element, each summing a strided subset of the partials
+  const int G = kFinThreads / W > 0 ? kFinThreads / W : 1;
+  const int EP = kFinThreads / G;  // elements per pass
+  for (int e0 = 0; e0 < W; e0 += EP) {
+    const int el = threadIdx.x / G, g = threadIdx.x % G;
+    const int e = e0 + el;
+    float acc = 0.f;
+    if (el < EP && e < W) {
+#pragma unroll 8
+      for (int i = g; i < nb; i += G) acc += b.upart[(size_t)i * W + e];
+    }
+    s_sum[threadIdx.x] = acc;
+    __syncthreads();
+    if (g == 0 && el < EP && e < W) {
+      float t = 0.f;
+      for (int j = 0; j < G; ++j) t += s_sum[threadIdx.x + j];
+      s_tot[e] = t;
+    }
+    __syncthreads();
+  }
+  const float wsum = s_tot[NM];
+  for (int e = threadIdx.x; e < NM; e += kFinThreads) {
+    const float u = b.U[e];
+    const float un = bad ? u : u + s_tot[e] / wsum;
+    if (U_out) U_out[e] = un;
+    b.Unew[e] = un;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NM; e += kFinThreads) {
+    const int j = e / c.m, i = e % c.m;
+    if (j == 0 && u_out) u_out[i] = b.Unew[e];
+    if (!bad) {
+      const int src = j + 1 < c.N ? j + 1 : c.N - 1;
+      b.U[e] = b.Unew[src * c.m + i];
+    }
+  }
+  if (threadIdx.x == 0) {
+    Ctrl* cw = b.ctrl;
+    const int branch = cw->branch;
+    const bool cl = branch == 0;
+    const bool hasM = cl && cw->M > 0;
+    const float smin = !cl ? cw->smin_all : (hasM ? b.c_smin[cw->sel] : cw->smin_feas);
+    cw->wsum = wsum;
+    if (!bad) {
+      const uint32_t lo = cw->step_lo + 1u;
+      if (lo == 0u) cw->step_hi += 1u;
+      cw->step_lo = lo;
+    }
+    if (info_out) {
+      struct Info {
+        int32_t branch, n_collide, n_feasible, n_ref, n_clusters, selected, selected_size, closest,
+            rule, history_used;
+        uint32_t status, step;
+        float margin, s_min, ref_point[3], v_obs[3], v_obs_hat[3], weight_sum;
+      };
+      Info* inf = reinterpret_cast<Info*>(info_out);
+      inf->branch = branch;
+      inf->n_collide = bad ? 0 : cw->n_col;
+      inf->n_feasible = bad ? 0 : cw->n_feas;
+      inf->n_ref = cl ? cw->n_ref : 0;
+      inf->n_clusters = cl ? cw->M : 0;
+      inf->selected = hasM ? cw->sel : -1;
+      inf->selected_size = hasM ? cw->sel_size : 0;
+      inf->closest = cw->closest;
+      inf->rule = hasM ? cw->rule : 0;
+      inf->history_used = hasM ? cw->h_used : 0;
+      inf->status = cw->status;
+      inf->step = cw->step_used;
+      inf->margin = hasM ? cw->margin : INFINITY;
+      inf->s_min = smin;
+      for (int i = 0; i < 3; ++i) {
+        inf->ref_point[i] = cl ? cw->ref[i] : 0.f;
+        inf->v_obs[i] = hasM ? cw->v_obs[i] : 0.f;
+        inf->v_obs_hat[i] = hasM ? cw->v_hat[i] : 0.f;
+      }
+      inf->weight_sum = wsum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+template <int P>
+static hipError_t launch_dbscan_p(const Cfg& c, const Bufs& b, const float* zin, int Vin, int ntile,
+                                  int* lab_out, int* cnt_out, int* mout, hipStream_t s) {
+  dim3 tiles(ntile, ntile), tb(kTile);
+  const int nr = (ntile * kTile + 255) / 256;
+  hipLaunchKernelGGL(k_count<P>, tiles, tb, 0, s, c, b, zin, Vin);
+  hipLaunchKernelGGL(k_mcn<P>, tiles, tb, 0, s, c, b, zin, Vin);
+  hipLaunchKernelGGL(k_roots, dim3(nr), dim3(256), 0, s, c, b, zin, Vin);
+  hipLaunchKernelGGL(k_tree_adj<P>, tiles, tb, 0, s, c, b, zin, Vin, ntile);
+  hipLaunchKernelGGL(k_tree_cc<P>, dim3(1), dim3(kFinThreads), 0, s, c, b, zin, Vin, ntile, mout);
+  hipLaunchKernelGGL(k_label, dim3(nr), dim3(256), 0, s, c, b, zin, Vin, lab_out, cnt_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_post_rollout(const Cfg& c, const Bufs& b, float* u_out, float* U_out, void* info,
+                               hipStream_t s) {
+  const int nk = (c.K + 255) / 256;
+  hipError_t e;
+  if (c.p == 2) {
+    hipLaunchKernelGGL(k_compact<2>, dim3(nk), dim3(256), 0, s, c, b);
+    e = launch_dbscan_p<2>(c, b, nullptr, 0, c.ntile, nullptr, nullptr, nullptr, s);
+    hipLaunchKernelGGL(k_stats<2>, dim3(64), dim3(256), 0, s, c, b);
+  } else {
+    hipLaunchKernelGGL(k_compact<3>, dim3(nk), dim3(256), 0, s, c, b);
+    e = launch_dbscan_p<3>(c, b, nullptr, 0, c.ntile, nullptr, nullptr, nullptr, s);
+    hipLaunchKernelGGL(k_stats<3>, dim3(64), dim3(256), 0, s, c, b);
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_update, dim3(c.nblk_upd), dim3(kUpdThreads), 0, s, c, b);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinThreads), 0, s, c, b, u_out, U_out, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_dbscan(const Cfg& c, const Bufs& b, const float* z, int V, int* ncount,
+                               int* label, int* mout, hipStream_t s) {
+  // the stage runs on caller features: initialise the per-point arrays.  A
+  // non-null feature pointer marks stage mode in the kernels.
+  if (z == nullptr) z = b.z;
+  if (V == 0) {
+    // no points: only the cluster count (0) is produced
+    if (c.p == 2)
+      hipLaunchKernelGGL(k_tree_cc<2>, dim3(1), dim3(kFinThreads), 0, s, c, b, z, 0, 1, mout);
+    else
+      hipLaunchKernelGGL(k_tree_cc<3>, dim3(1), dim3(kFinThreads), 0, s, c, b, z, 0, 1, mout);
+    return hipGetLastError();
+  }
+  const int ntile = (V + kTile - 1) / kTile;
+  hipLaunchKernelGGL(k_init_points, dim3((V + 255) / 256), dim3(256), 0, s, b, V);
+  if (c.p == 2) return launch_dbscan_p<2>(c, b, z, V, ntile, label, ncount, mout, s);
+  return launch_dbscan_p<3>(c, b, z, V, ntile, label, ncount, mout, s);
+}
+
+}  // namespace cemppi

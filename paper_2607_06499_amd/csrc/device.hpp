@@ -1,0 +1,256 @@
+// device.hpp -- data layout and device primitives of the CE-MPPI replan
+// kernels for gfx950 (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cemppi {
+
+constexpr int kMaxCtrl = 6;
+constexpr int kMaxObs = 64;
+constexpr int kMaxHorizon = 63;
+constexpr int kMaxHistory = 16;
+constexpr int kMaxSpheres = 16;
+constexpr int kMaxNM = kMaxHorizon * kMaxCtrl;
+constexpr int kWave = 64;
+
+// rollout kernel: 256 threads = 4 waves; a wave holds one rollout (64-lane
+// segment) or two (32-lane segments) when N + 1 <= 32.
+constexpr int kRollThreads = 256;
+// per-block partial record of the rollout reduction (floats)
+constexpr int kPart = 12;
+enum PartField {
+  P_NCOL = 0, P_NREF = 1, P_NFEAS = 2, P_SMIN_ALL = 3, P_SMIN_FEAS = 4,
+  P_SUM_REF = 5,   // 3 floats: sum over colliding rollouts that hit o*
+  P_SUM_COL = 8,   // 3 floats: sum over every colliding rollout
+};
+
+// DBSCAN tiles: kTile rows (one per thread) x kTile columns (staged in LDS)
+constexpr int kTile = 128;
+// update kernel: candidates per block (16 per wave) and threads; the
+// single-block finisher
+constexpr int kUpdChunk = 64;
+constexpr int kUpdThreads = 256;
+constexpr int kFinThreads = 1024;
+// tree graph handled by the fast path
+constexpr int kMaxTrees = 64;
+
+constexpr int kInt32Max = 0x7fffffff;
+
+// Device control block of one planner: per-replan decisions shared between
+// kernels plus the persistent counters.
+struct Ctrl {
+  // persistent
+  uint32_t step_lo, step_hi;
+  int32_t hist_head, hist_count, hist_nobs;
+  // per replan
+  int32_t n_obs, nonfinite, closest;
+  int32_t n_col, n_feas, n_ref, branch;
+  float p0[3];
+  float ref[3];
+  float smin_all, smin_feas;
+  int32_t n_trees, tree_overflow, M;
+  int32_t sel, sel_size, rule, h_used;
+  float margin, smin_sel, wsum;
+  float v_obs[3], v_hat[3];
+  uint32_t status;
+  uint32_t step_used;
+};
+
+// Scalar configuration (kernel argument).
+struct Cfg {
+  int dyn, N, K, m, n, p, NM, B;
+  int seg, rpb, nblk_roll;
+  float dt, lambda, norm_eps;
+  float L[36];
+  float umin[6], umax[6];
+  float eps2;
+  int min_pts;
+  int scene_mode, H;
+  float v_obs_min;
+  int ref_mode, max_obs;
+  float robot_r;
+  float goal[6], Q[6], R[6], Qf[6];
+  float dh_a[6], dh_d[6], dh_ca[6], dh_sa[6], dh_off[6];
+  int ns;
+  float rs;
+  int sph_seg[kMaxSpheres];
+  float sph_t[kMaxSpheres];
+  float qlim[6], wlim;
+  uint32_t seed_lo, seed_hi, stream_id;
+  int ntile;       // ceil(K / kTile)
+  int nblk_upd;    // update kernel blocks
+  int mcap;        // cluster capacity
+};
+
+// Device buffers of one planner (kernel argument).
+struct Bufs {
+  Ctrl* ctrl;
+  float* U;        // [N][m] nominal sequence
+  float* hist;     // [H][max_obs][p] ring of obstacle centres
+  // per rollout
+  float* S;        // [K]
+  int* col;        // [K]
+  int* first;      // [K]
+  float* pT;       // [K][p]
+  float* pF;       // [K][p]
+  float* g;        // [K][p]
+  float* eps;      // [K][N][m]
+  float* part;     // [nblk_roll][kPart]
+  int* feas_off;   // [nblk_roll] exclusive prefix of feasible counts
+  // compacted feasible set
+  int* vidx;       // [K]
+  float* z;        // [K][zs] zs = 2 (p = 2) or 4 (p = 3)
+  float* gv;       // [K][zs]
+  float* Sv;       // [K]
+  // DBSCAN
+  int* ncount;     // [K]
+  int* mcn;        // [K] lowest-index core neighbour (kInt32Max if none)
+  int* root;       // [K] tree root (core points), -1 otherwise
+  int* rid;        // [K] compacted tree id of each root point
+  unsigned long long* tslot;    // [ntile*ntile][kMaxTrees] tree adjacency per DBSCAN tile
+  int* tree_cluster;            // [kMaxTrees] cluster of each tree
+  int* tree_root;               // [kMaxTrees] root point of each tree
+  int* label;      // [K]
+  unsigned long long* rootmask;  // [ceil(K/64)] root flags
+  int* woff;                     // [ceil(K/64)] roots before each word
+  // cluster statistics
+  float* c_cost;   // [mcap] mean cost
+  float* c_dir;    // [mcap][4] normalised mean direction
+  int* c_size;     // [mcap]
+  float* c_smin;   // [mcap]
+  // update partials
+  float* upart;    // [nblk_upd][NM + 1]
+  float* Unew;     // [N][m] updated sequence before the shift
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, key bumped by
+// the Weyl constants between rounds.
+__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// open-interval uniform (2*(w>>9)+1) * 2^-24, exact in FP32
+__device__ __forceinline__ float u01(uint32_t w) {
+  return (float)(((w >> 9) << 1) | 1u) * 5.9604644775390625e-8f;
+}
+
+// Box-Muller pair
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& ga, float& gb) {
+  const float r = sqrtf(-2.0f * logf(u01(wa)));
+  float s, c;
+  sincospif(2.0f * u01(wb), &s, &c);
+  ga = r * c;
+  gb = r * s;
+}
+
+// Standard normals g[0..m) of step j of rollout k (elements j*m .. j*m+m-1 of
+// the flattened sequence; pair q uses words (0,1) or (2,3) of block q/2).
+__device__ __forceinline__ void step_gaussians(const Cfg& c, uint32_t step, int k, int j, float* g) {
+  const int q0 = (j * c.m) >> 1;
+  const int nq = c.m >> 1;
+  int cached = -1;
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  for (int q = 0; q < nq; ++q) {
+    const int b = (q0 + q) >> 1;
+    if (b != cached) {
+      philox((uint32_t)b, (uint32_t)k, step, c.stream_id, c.seed_lo, c.seed_hi, w);
+      cached = b;
+    }
+    const int h = (q0 + q) & 1;
+    box_muller(w[2 * h], w[2 * h + 1], g[2 * q], g[2 * q + 1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Segmented wave primitives (segments of SEG lanes; every lane participates).
+template <int SEG>
+__device__ __forceinline__ float seg_incl_scan(float v, int j) {
+#pragma unroll
+  for (int d = 1; d < SEG; d <<= 1) {
+    const float t = __shfl_up(v, (unsigned)d, SEG);
+    if (j >= d) v += t;
+  }
+  return v;
+}
+
+template <int SEG>
+__device__ __forceinline__ float seg_excl_scan(float v, int j) {
+  const float inc = seg_incl_scan<SEG>(v, j);
+  const float t = __shfl_up(inc, 1u, SEG);
+  return j == 0 ? 0.0f : t;
+}
+
+// butterfly sum: every lane of the segment ends with the bitwise same value
+template <int SEG>
+__device__ __forceinline__ float seg_sum(float v) {
+#pragma unroll
+  for (int d = SEG >> 1; d > 0; d >>= 1) v += __shfl_xor(v, d, SEG);
+  return v;
+}
+
+__device__ __forceinline__ float sq(float x) { return x * x; }
+
+// squared distance with a fixed operation order, shared by every decision
+// that compares a distance to a radius: d_i = a_i - b_i,
+// s = fma(d_{p-1}, d_{p-1}, ... fma(d_1, d_1, d_0 * d_0))
+__device__ __forceinline__ float dist2_2(float ax, float ay, float bx, float by) {
+  const float dx = ax - bx, dy = ay - by;
+  return __builtin_fmaf(dy, dy, dx * dx);
+}
+__device__ __forceinline__ float dist2_3(float ax, float ay, float az, float bx, float by, float bz) {
+  const float dx = ax - bx, dy = ay - by, dz = az - bz;
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
+// agent-scope atomics for data shared between workgroups inside one kernel
+__device__ __forceinline__ int ld_acquire(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// block-wide (blockDim.x == NT) exclusive scan of one int per thread;
+// returns the exclusive prefix and writes the total.
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+  __shared__ int s_w[NT / kWave];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int t = __shfl_up(inc, (unsigned)d, kWave);
+    if (lane >= d) inc += t;
+  }
+  if (lane == kWave - 1) s_w[w] = inc;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / kWave; ++i) {
+    if (i < w) base += s_w[i];
+    tot += s_w[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
+}
+
+}  // namespace cemppi

@@ -1,0 +1,540 @@
+// rollout.hip -- noise, forward simulation, cost and collision of every
+// rollout (Alg. 1 [Rollouts], Eq. (3)-(5), Sec. II-B.1).  Each block also
+// leaves a partial record (counts and sums for pruning and the reference
+// point of Eq. (9)-(11)); the next kernel reduces those records.
+//
+// Layout: one rollout per 64-lane segment of a wavefront (two per wave when
+// the N+1 states fit in 32 lanes).  Lane j of a segment owns control u_j and
+// state x_j: the noise of a step is drawn in its lane, the linear parts of the
+// dynamics are prefix sums across lanes (the heading of the unicycle, the joint
+// angles of the arm), and every lane evaluates its own stage cost, collision
+// test and (arm) forward kinematics.  The serial N-step recursion of Eq. (4)
+// thus becomes log2(N) shuffle steps and all work of a step runs in parallel.
+#include "device.hpp"
+
+namespace cemppi {
+
+// ---------------------------------------------------------------------------
+// shared prologue: obstacles into LDS, finiteness, closest obstacle o*.
+struct ObsLds {
+  float x[kMaxObs], y[kMaxObs], z[kMaxObs], r[kMaxObs], R2[kMaxObs];
+};
+
+// Arm forward kinematics: origins P0..P6 of the standard DH chain
+// (A_i = Rz(q_i + off_i) Tz(d_i) Tx(a_i) Rx(alpha_i)); P6 is p_ee(q).
+__device__ __forceinline__ void arm_origins(const Cfg& c, const float* q, float P[7][3]) {
+  float r00 = 1.f, r01 = 0.f, r02 = 0.f, r10 = 0.f, r11 = 1.f, r12 = 0.f, r20 = 0.f, r21 = 0.f,
+        r22 = 1.f;
+  float tx = 0.f, ty = 0.f, tz = 0.f;
+  P[0][0] = P[0][1] = P[0][2] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    float st, ct;
+    sincosf(q[i] + c.dh_off[i], &st, &ct);
+    const float ca = c.dh_ca[i], sa = c.dh_sa[i], a = c.dh_a[i], d = c.dh_d[i];
+    // translation of frame i in frame i-1: (a cos th, a sin th, d)
+    const float lx = a * ct, ly = a * st, lz = d;
+    tx += r00 * lx + r01 * ly + r02 * lz;
+    ty += r10 * lx + r11 * ly + r12 * lz;
+    tz += r20 * lx + r21 * ly + r22 * lz;
+    // rotation Rz(th) Rx(alpha)
+    const float a00 = ct, a01 = -st * ca, a02 = st * sa;
+    const float a10 = st, a11 = ct * ca, a12 = -ct * sa;
+    const float a21 = sa, a22 = ca;
+    const float n00 = r00 * a00 + r01 * a10, n01 = r00 * a01 + r01 * a11 + r02 * a21,
+                n02 = r00 * a02 + r01 * a12 + r02 * a22;
+    const float n10 = r10 * a00 + r11 * a10, n11 = r10 * a01 + r11 * a11 + r12 * a21,
+                n12 = r10 * a02 + r11 * a12 + r12 * a22;
+    const float n20 = r20 * a00 + r21 * a10, n21 = r20 * a01 + r21 * a11 + r22 * a21,
+                n22 = r20 * a02 + r21 * a12 + r22 * a22;
+    r00 = n00; r01 = n01; r02 = n02;
+    r10 = n10; r11 = n11; r12 = n12;
+    r20 = n20; r21 = n21; r22 = n22;
+    P[i + 1][0] = tx;
+    P[i + 1][1] = ty;
+    P[i + 1][2] = tz;
+  }
+}
+
+__device__ __forceinline__ void sphere_centre(const Cfg& c, const float P[7][3], int s, float& x,
+                                              float& y, float& zz) {
+  // seg and t are compile-time-unknown: select the segment end points
+  const int sg = c.sph_seg[s];
+  float ax = 0.f, ay = 0.f, az = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    if (i == sg) {
+      ax = P[i][0]; ay = P[i][1]; az = P[i][2];
+      bx = P[i + 1][0]; by = P[i + 1][1]; bz = P[i + 1][2];
+    }
+  }
+  const float t = c.sph_t[s];
+  x = ax + t * (bx - ax);
+  y = ay + t * (by - ay);
+  zz = az + t * (bz - az);
+}
+
+__device__ __forceinline__ float limit_penalty(const Cfg& c, const float* q) {
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const float e = fabsf(q[i]) - c.qlim[i];
+    s += e > 0.f ? e * e : 0.f;
+  }
+  return c.wlim * s;
+}
+
+// Prologue run by every block: stages the obstacles, checks the inputs and
+// computes o* (smallest surface clearance, ties to the lowest index) and
+// p(x_t).  Returns through LDS: s_bad, s_closest, s_p0.
+template <int DYN>
+__device__ void prologue(const Cfg& c, const float* __restrict__ x_t, const float* __restrict__ obs,
+                         int n_obs, ObsLds& L, int& s_bad, int& s_closest, float* s_p0) {
+  const int tid = threadIdx.x;
+  const int P = DYN == 0 ? 2 : 3;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  if (tid < n_obs) {
+    const float* o = obs + tid * (P + 1);
+    float ok = 1.f;
+    for (int i = 0; i <= P; ++i) ok = isfinite(o[i]) ? ok : 0.f;
+    if (ok == 0.f) atomicOr(&s_bad, 1);
+    L.x[tid] = o[0];
+    L.y[tid] = o[1];
+    L.z[tid] = DYN == 0 ? 0.f : o[2];
+    L.r[tid] = o[P];
+    const float R = (DYN == 0 ? c.robot_r : c.rs) + o[P];
+    L.R2[tid] = R * R;
+  }
+  if (tid < c.n && !isfinite(x_t[tid])) atomicOr(&s_bad, 1);
+  __syncthreads();
+  if (tid < kWave) {
+    float cl = INFINITY;
+    int idx = kInt32Max;
+    if (DYN == 0) {
+      const float x0 = x_t[0], y0 = x_t[1];
+      if (tid == 0) {
+        s_p0[0] = x0;
+        s_p0[1] = y0;
+        s_p0[2] = 0.f;
+      }
+      if (tid < n_obs) {
+        cl = sqrtf(dist2_2(x0, y0, L.x[tid], L.y[tid])) - L.r[tid];
+        idx = tid;
+      }
+    } else {
+      float q[6], Pm[7][3];
+      for (int i = 0; i < 6; ++i) q[i] = x_t[i];
+      arm_origins(c, q, Pm);
+      if (tid == 0) {
+        s_p0[0] = Pm[6][0];
+        s_p0[1] = Pm[6][1];
+        s_p0[2] = Pm[6][2];
+      }
+      if (tid < n_obs) {
+        for (int s = 0; s < c.ns; ++s) {
+          float sx, sy, sz;
+          sphere_centre(c, Pm, s, sx, sy, sz);
+          const float v = sqrtf(dist2_3(sx, sy, sz, L.x[tid], L.y[tid], L.z[tid])) - L.r[tid];
+          cl = v < cl ? v : cl;
+        }
+        idx = tid;
+      }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      const float oc = __shfl_xor(cl, d, kWave);
+      const int oi = __shfl_xor(idx, d, kWave);
+      if (oc < cl || (oc == cl && oi < idx)) {
+        cl = oc;
+        idx = oi;
+      }
+    }
+    if (tid == 0) s_closest = n_obs > 0 ? idx : -1;
+  }
+  __syncthreads();
+}
+
+// Block 0: push the observation into the history ring and publish the
+// per-replan facts of the prologue.
+__device__ void publish(const Cfg& c, const Bufs& b, const float* __restrict__ obs, int n_obs,
+                        int bad, int closest, const float* p0, uint32_t step) {
+  Ctrl* ct = b.ctrl;
+  __shared__ int s_nh;
+  if (threadIdx.x == 0) {
+    int head = ct->hist_head;
+    s_nh = (head + 1) % c.H;
+  }
+  __syncthreads();
+  const int nh = s_nh;
+  if (!bad) {
+    for (int t = threadIdx.x; t < n_obs * c.p; t += blockDim.x) {
+      const int i = t / c.p, d = t % c.p;
+      b.hist[((size_t)nh * c.max_obs + i) * c.p + d] = obs[i * (c.p + 1) + d];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!bad) {
+      const int count = ct->hist_nobs == n_obs ? ct->hist_count : 0;
+      ct->hist_head = nh;
+      ct->hist_count = count + 1 < c.H ? count + 1 : c.H;
+      ct->hist_nobs = n_obs;
+    }
+    ct->n_obs = n_obs;
+    ct->nonfinite = bad;
+    ct->closest = closest;
+    ct->p0[0] = p0[0];
+    ct->p0[1] = p0[1];
+    ct->p0[2] = p0[2];
+    ct->step_used = step;
+  }
+}
+
+// Per-rollout contribution to the block partial record.
+__device__ __forceinline__ void rollout_contrib(float* rec, bool active, int col, int first,
+                                                int closest, float S, const float* src, int P) {
+  for (int i = 0; i < kPart; ++i) rec[i] = 0.f;
+  rec[P_SMIN_ALL] = INFINITY;
+  rec[P_SMIN_FEAS] = INFINITY;
+  if (!active) return;
+  rec[P_SMIN_ALL] = S;
+  if (col) {
+    rec[P_NCOL] = 1.f;
+    const bool inA = first == closest;
+    rec[P_NREF] = inA ? 1.f : 0.f;
+    for (int i = 0; i < P; ++i) {
+      rec[P_SUM_COL + i] = src[i];
+      rec[P_SUM_REF + i] = inA ? src[i] : 0.f;
+    }
+  } else {
+    rec[P_NFEAS] = 1.f;
+    rec[P_SMIN_FEAS] = S;
+  }
+}
+
+// Sum the per-rollout records of this block (fixed order) into part[block].
+__device__ __forceinline__ void write_block_partial(const Bufs& b, float (*recs)[kPart], int rpb) {
+  __syncthreads();
+  if (threadIdx.x < kPart) {
+    const int f = threadIdx.x;
+    float acc = (f == P_SMIN_ALL || f == P_SMIN_FEAS) ? INFINITY : 0.f;
+    for (int r = 0; r < rpb; ++r) {
+      const float v = recs[r][f];
+      acc = (f == P_SMIN_ALL || f == P_SMIN_FEAS) ? fminf(acc, v) : acc + v;
+    }
+    b.part[(size_t)blockIdx.x * kPart + f] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Unicycle rollouts (Sec. III-A): state (x, y, theta), control (v, omega).
+template <int SEG>
+__global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b,
+                                                                   const float* __restrict__ x_t,
+                                                                   const float* __restrict__ obs,
+                                                                   int n_obs) {
+  __shared__ ObsLds L;
+  __shared__ int s_bad, s_closest;
+  __shared__ float s_p0[3];
+  __shared__ float s_rec[8][kPart];
+  prologue<0>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
+  const uint32_t step = b.ctrl->step_lo;
+  const int bad = s_bad, closest = s_closest;
+  if (blockIdx.x == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
+
+  constexpr int SPW = kWave / SEG;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int j = lane & (SEG - 1), sgi = lane / SEG;
+  const int kloc = wave * SPW + sgi;
+  const int k = blockIdx.x * (4 * SPW) + kloc;
+  const int N = c.N;
+  const bool act = (k < c.K) && !bad;
+  const float dt = c.dt;
+  const float x0 = x_t[0], y0 = x_t[1], th0 = x_t[2];
+
+  // noise, perturbation and clamp (Eq. (3)); applied perturbation kept
+  float uv = 0.f, uw = 0.f;
+  if (act && j < N) {
+    float g[2];
+    step_gaussians(c, step, k, j, g);
+    const float e0 = c.L[0] * g[0];
+    const float e1 = c.L[2] * g[0] + c.L[3] * g[1];
+    const float n0 = b.U[j * 2], n1 = b.U[j * 2 + 1];
+    const float t0 = n0 + e0, t1 = n1 + e1;
+    uv = fminf(fmaxf(t0, c.umin[0]), c.umax[0]);
+    uw = fminf(fmaxf(t1, c.umin[1]), c.umax[1]);
+    const float a0 = uv == t0 ? e0 : uv - n0;
+    const float a1 = uw == t1 ? e1 : uw - n1;
+    float2* ep = reinterpret_cast<float2*>(b.eps + ((size_t)k * N + j) * 2);
+    *ep = make_float2(a0, a1);
+  }
+  // forward simulation, Eq. (4)/(21): heading and position are prefix sums
+  const float th = th0 + seg_excl_scan<SEG>(uw * dt, j);
+  float sn, cs;
+  sincosf(th, &sn, &cs);
+  const float px = x0 + seg_excl_scan<SEG>(uv * cs * dt, j);
+  const float py = y0 + seg_excl_scan<SEG>(uv * sn * dt, j);
+
+  // cost, Eq. (5): stage terms in lanes 0..N-1, terminal term in lane N
+  float l = 0.f;
+  if (act && j < N) {
+    l = c.Q[0] * sq(px - c.goal[0]) + c.Q[1] * sq(py - c.goal[1]) + c.Q[2] * sq(th - c.goal[2]) +
+        c.R[0] * uv * uv + c.R[1] * uw * uw;
+  } else if (act && j == N) {
+    l = c.Qf[0] * sq(px - c.goal[0]) + c.Qf[1] * sq(py - c.goal[1]) + c.Qf[2] * sq(th - c.goal[2]);
+  }
+  const float S = seg_sum<SEG>(l);
+
+  // collision of states 1..N against the frozen obstacles: lowest index hit
+  int hit = kInt32Max;
+  if (act && j >= 1 && j <= N) {
+    for (int i = 0; i < n_obs; ++i) {
+      const bool h = dist2_2(px, py, L.x[i], L.y[i]) <= L.R2[i];
+      hit = (h && hit == kInt32Max) ? i : hit;
+    }
+  }
+  const unsigned long long segmask = SEG == 64 ? ~0ull : (0xffffffffull << (sgi * 32));
+  const unsigned long long hm = __ballot(hit != kInt32Max) & segmask;
+  const int col = hm != 0ull;
+  const int fl = col ? __ffsll((long long)hm) - 1 : lane;
+  const int f = __shfl(hit, fl, kWave);
+  const float pfx = __shfl(px, fl, kWave), pfy = __shfl(py, fl, kWave);
+  const int ln = sgi * SEG + (N < SEG ? N : SEG - 1);
+  const float ptx = __shfl(px, ln, kWave), pty = __shfl(py, ln, kWave);
+
+  float src[2];
+  src[0] = c.ref_mode == 1 ? pfx : ptx;
+  src[1] = c.ref_mode == 1 ? pfy : pty;
+  if (j == 0) {
+    if (act) {
+      b.S[k] = S;
+      b.col[k] = col;
+      b.first[k] = col ? f : -1;
+      b.pT[2 * k] = ptx;
+      b.pT[2 * k + 1] = pty;
+      b.pF[2 * k] = col ? pfx : 0.f;
+      b.pF[2 * k + 1] = col ? pfy : 0.f;
+      // unit terminal displacement, Eq. (15)
+      const float ex = ptx - x0, ey = pty - y0;
+      const float den = sqrtf(__builtin_fmaf(ey, ey, ex * ex)) + c.norm_eps;
+      b.g[2 * k] = ex / den;
+      b.g[2 * k + 1] = ey / den;
+    }
+    rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 2);
+  }
+  write_block_partial(b, s_rec, 4 * SPW);
+}
+
+// ---------------------------------------------------------------------------
+// Six-joint arm rollouts (Sec. III-C): joint-velocity control, q_{j+1} =
+// q_j + u_j dt; end-effector cost, joint-limit penalty, link spheres against
+// obstacle spheres.
+__global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b,
+                                                              const float* __restrict__ x_t,
+                                                              const float* __restrict__ obs,
+                                                              int n_obs) {
+  constexpr int SEG = 64;
+  __shared__ ObsLds L;
+  __shared__ int s_bad, s_closest;
+  __shared__ float s_p0[3];
+  __shared__ float s_rec[8][kPart];
+  prologue<1>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
+  const uint32_t step = b.ctrl->step_lo;
+  const int bad = s_bad, closest = s_closest;
+  if (blockIdx.x == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int j = lane;
+  const int kloc = wave;
+  const int k = blockIdx.x * 4 + kloc;
+  const int N = c.N;
+  const bool act = (k < c.K) && !bad;
+  const float dt = c.dt;
+
+  float u[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) u[i] = 0.f;
+  if (act && j < N) {
+    float g[6];
+    step_gaussians(c, step, k, j, g);
+    float a[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      float e = 0.f;
+#pragma unroll
+      for (int cc = 0; cc < 6; ++cc)
+        if (cc <= i) e += c.L[i * 6 + cc] * g[cc];
+      const float n0 = b.U[j * 6 + i];
+      const float t = n0 + e;
+      u[i] = fminf(fmaxf(t, c.umin[i]), c.umax[i]);
+      a[i] = u[i] == t ? e : u[i] - n0;
+    }
+    float2* ep = reinterpret_cast<float2*>(b.eps + ((size_t)k * N + j) * 6);
+    ep[0] = make_float2(a[0], a[1]);
+    ep[1] = make_float2(a[2], a[3]);
+    ep[2] = make_float2(a[4], a[5]);
+  }
+  float q[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) q[i] = x_t[i] + seg_excl_scan<SEG>(u[i] * dt, j);
+  float P[7][3];
+  arm_origins(c, q, P);
+  const float ex = P[6][0], ey = P[6][1], ez = P[6][2];
+  float l = 0.f;
+  const float d2g = sq(ex - c.goal[0]) + sq(ey - c.goal[1]) + sq(ez - c.goal[2]);
+  if (act && j < N) {
+    float r = 0.f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) r += c.R[i] * u[i] * u[i];
+    l = c.Q[0] * d2g + limit_penalty(c, q) + r;
+  } else if (act && j == N) {
+    l = c.Qf[0] * d2g + limit_penalty(c, q);
+  }
+  const float S = seg_sum<SEG>(l);
+
+  int hit = kInt32Max;
+  if (act && j >= 1 && j <= N) {
+    for (int s = 0; s < c.ns; ++s) {
+      float sx, sy, sz;
+      sphere_centre(c, P, s, sx, sy, sz);
+      for (int i = 0; i < n_obs; ++i) {
+        const bool h = dist2_3(sx, sy, sz, L.x[i], L.y[i], L.z[i]) <= L.R2[i];
+        hit = (h && i < hit) ? i : hit;
+      }
+    }
+  }
+  const unsigned long long hm = __ballot(hit != kInt32Max);
+  const int col = hm != 0ull;
+  const int fl = col ? __ffsll((long long)hm) - 1 : lane;
+  const int f = __shfl(hit, fl, kWave);
+  const float pfx = __shfl(ex, fl, kWave), pfy = __shfl(ey, fl, kWave), pfz = __shfl(ez, fl, kWave);
+  const int ln = N;
+  const float ptx = __shfl(ex, ln, kWave), pty = __shfl(ey, ln, kWave), ptz = __shfl(ez, ln, kWave);
+
+  float src[3];
+  src[0] = c.ref_mode == 1 ? pfx : ptx;
+  src[1] = c.ref_mode == 1 ? pfy : pty;
+  src[2] = c.ref_mode == 1 ? pfz : ptz;
+  if (j == 0) {
+    if (act) {
+      b.S[k] = S;
+      b.col[k] = col;
+      b.first[k] = col ? f : -1;
+      b.pT[3 * k] = ptx;
+      b.pT[3 * k + 1] = pty;
+      b.pT[3 * k + 2] = ptz;
+      b.pF[3 * k] = col ? pfx : 0.f;
+      b.pF[3 * k + 1] = col ? pfy : 0.f;
+      b.pF[3 * k + 2] = col ? pfz : 0.f;
+      const float dx = ptx - s_p0[0], dy = pty - s_p0[1], dz = ptz - s_p0[2];
+      const float den = sqrtf(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))) + c.norm_eps;
+      b.g[3 * k] = dx / den;
+      b.g[3 * k + 1] = dy / den;
+      b.g[3 * k + 2] = dz / den;
+    }
+    rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 3);
+  }
+  write_block_partial(b, s_rec, 4);
+}
+
+// ---------------------------------------------------------------------------
+// The same reduction on rollout records already in the planner buffers
+// (records supplied by the caller): grid = nblk_roll blocks of rpb rollouts.
+template <int DYN>
+__global__ __launch_bounds__(kRollThreads) void k_reduce_records(Cfg c, Bufs b,
+                                                                 const float* __restrict__ x_t,
+                                                                 const float* __restrict__ obs,
+                                                                 int n_obs) {
+  __shared__ ObsLds L;
+  __shared__ int s_bad, s_closest;
+  __shared__ float s_p0[3];
+  __shared__ float s_rec[8][kPart];
+  prologue<DYN>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
+  const uint32_t step = b.ctrl->step_lo;
+  const int bad = s_bad, closest = s_closest;
+  if (blockIdx.x == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
+  const int P = DYN == 0 ? 2 : 3;
+  if (threadIdx.x < c.rpb) {
+    const int k = blockIdx.x * c.rpb + threadIdx.x;
+    const bool act = k < c.K && !bad;
+    int col = 0, f = -1;
+    float S = 0.f, src[3] = {0.f, 0.f, 0.f};
+    if (act) {
+      col = b.col[k];
+      f = b.first[k];
+      S = b.S[k];
+      const float* sp = c.ref_mode == 1 ? b.pF : b.pT;
+      for (int i = 0; i < P; ++i) src[i] = sp[(size_t)k * P + i];
+      // Eq. (15) from the supplied terminal point
+      float e[3] = {0.f, 0.f, 0.f};
+      for (int i = 0; i < P; ++i) e[i] = b.pT[(size_t)k * P + i] - s_p0[i];
+      const float den =
+          sqrtf(__builtin_fmaf(e[2], e[2], __builtin_fmaf(e[1], e[1], e[0] * e[0]))) + c.norm_eps;
+      for (int i = 0; i < P; ++i) b.g[(size_t)k * P + i] = e[i] / den;
+    }
+    rollout_contrib(s_rec[threadIdx.x], act, col, f, closest, S, src, P);
+  }
+  write_block_partial(b, s_rec, c.rpb);
+}
+
+// Philox words and standard normals of every rollout (stage entry point):
+// one thread per (rollout, counter block).
+__global__ void k_stage_noise(Cfg c, uint32_t step, uint32_t* __restrict__ words,
+                              float* __restrict__ gauss) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= c.K * c.B) return;
+  const int k = t / c.B, bl = t % c.B;
+  uint32_t w[4];
+  philox((uint32_t)bl, (uint32_t)k, step, c.stream_id, c.seed_lo, c.seed_hi, w);
+  if (words) {
+    uint4* wp = reinterpret_cast<uint4*>(words) + t;
+    *wp = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  if (gauss) {
+    for (int h = 0; h < 2; ++h) {
+      const int e = 4 * bl + 2 * h;
+      if (e >= c.NM) break;
+      float ga, gb;
+      box_muller(w[2 * h], w[2 * h + 1], ga, gb);
+      gauss[(size_t)k * c.NM + e] = ga;
+      if (e + 1 < c.NM) gauss[(size_t)k * c.NM + e + 1] = gb;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+hipError_t launch_rollout(const Cfg& c, const Bufs& b, const float* x_t, const float* obs, int n_obs,
+                          hipStream_t s) {
+  dim3 grid(c.nblk_roll), block(kRollThreads);
+  if (c.dyn == 0) {
+    if (c.seg == 32)
+      hipLaunchKernelGGL(k_rollout_unicycle<32>, grid, block, 0, s, c, b, x_t, obs, n_obs);
+    else
+      hipLaunchKernelGGL(k_rollout_unicycle<64>, grid, block, 0, s, c, b, x_t, obs, n_obs);
+  } else {
+    hipLaunchKernelGGL(k_rollout_arm, grid, block, 0, s, c, b, x_t, obs, n_obs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_records(const Cfg& c, const Bufs& b, const float* x_t, const float* obs,
+                                 int n_obs, hipStream_t s) {
+  dim3 grid(c.nblk_roll), block(kRollThreads);
+  if (c.dyn == 0)
+    hipLaunchKernelGGL(k_reduce_records<0>, grid, block, 0, s, c, b, x_t, obs, n_obs);
+  else
+    hipLaunchKernelGGL(k_reduce_records<1>, grid, block, 0, s, c, b, x_t, obs, n_obs);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_noise(const Cfg& c, uint32_t step, uint32_t* words, float* gauss,
+                              hipStream_t s) {
+  const int total = c.K * c.B;
+  dim3 grid((total + 255) / 256), block(256);
+  hipLaunchKernelGGL(k_stage_noise, grid, block, 0, s, c, step, words, gauss);
+  return hipGetLastError();
+}
+
+}  // namespace cemppi

@@ -171,7 +171,7 @@ def _place_circles(rng, n, lo, hi, rmin, rmax, avoid, margin, speed=None):
         centres.append(c)
         radii.append(r)
         if speed is None:
-            vels.append(np.zeros_like(c))
+            vels.append(np.zeros_like(c, dtype=float))
         else:
             s = rng.uniform(*speed)
             if len(lo) == 2:
@@ -180,7 +180,9 @@ def _place_circles(rng, n, lo, hi, rmin, rmax, avoid, margin, speed=None):
             else:
                 d = rng.normal(size=3)
                 vels.append(s * d / np.linalg.norm(d))
-    return np.array(centres), np.array(radii), np.array(vels)
+    dim = len(lo)
+    return (np.array(centres, dtype=float).reshape(-1, dim), np.array(radii, dtype=float),
+            np.array(vels, dtype=float).reshape(-1, dim))
 
 
 def _unicycle_spec(**kw) -> PlannerSpec:

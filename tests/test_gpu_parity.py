@@ -1,0 +1,342 @@
+"""GPU parity: the HIP replan path (through the C-ABI) against the FP64
+oracle on the same seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_06499_amd import workloads as W
+from tests import harness as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not H.gpu_ok():
+        pytest.skip("no GPU")
+    from paper_2607_06499_amd import binding
+
+    binding.load()
+
+
+def _planner(spec):
+    from paper_2607_06499_amd import binding as B
+
+    return B.Planner(spec)
+
+
+def _set_U(pl, U):
+    pl.set_nominal(H.to_dev(np.asarray(U, np.float32)))
+
+
+# ------------------------------------------------------------------ noise
+@pytest.mark.parametrize("dyn,N,K,step,seed", [(W.UNICYCLE, 23, 301, 7, 5), (W.ARM6, 13, 97, 123456, 2**40 + 3),
+                                               (W.UNICYCLE, 1, 5, 0, 0)])
+def test_noise_words_bit_exact(dyn, N, K, step, seed):
+    spec = W.PlannerSpec(dynamics=dyn, horizon=N, num_samples=K, seed=seed, stream_id=11,
+                         noise_chol=W.diag_chol([1.0] * 6, 2 if dyn == 0 else 6),
+                         dh=W.arm_dh([0.2] * 6)).rounded()
+    pl = _planner(spec)
+    words, gauss = pl.stage_noise(step)
+    words = words.cpu().numpy().view(np.uint32)
+    gauss = gauss.cpu().numpy()
+    m = spec.m
+    for k in range(K):
+        ref = oracle.noise_words(spec, step, k).reshape(-1, 4)
+        assert np.array_equal(words[k], ref), k
+        g, _ = oracle.rollout_noise(spec, step, k)
+        err = np.abs(gauss[k] - g) / np.maximum(np.abs(g), 1.0)
+        assert err.max() <= H.GAUSS_TOL, (k, err.max())
+    assert gauss.shape == (K, N, m)
+
+
+# ------------------------------------------------------------------ rollouts
+def _compare_rollouts(r, o, spec, check_eps=True):
+    """Rollout records: costs, trajectories end points, collision flags."""
+    bnd = o["clearance"] <= H.BOUNDARY
+    ok = ~bnd
+    perr = H.rel_err(r["p_term"], o["p_term"]).max()
+    serr = H.rel_err(r["S"], o["S"]).max()
+    flips = int(np.sum(r["col"][bnd] != o["col"][bnd]))
+    print(f"rollouts: K={spec.num_samples} max p_term err {perr:.2e} max S err {serr:.2e} "
+          f"boundary {int(bnd.sum())} flipped {flips}")
+    assert np.array_equal(r["col"][ok], o["col"][ok])
+    both = ok & (o["col"] == 1)
+    assert np.array_equal(r["first_obs"][both], o["first_obs"][both])
+    assert H.rel_err(r["S"], o["S"]).max() <= H.TRAJ_RTOL
+    assert H.rel_err(r["p_term"], o["p_term"]).max() <= H.TRAJ_RTOL
+    if both.any():
+        assert H.rel_err(r["p_first"][both], o["p_first"][both]).max() <= H.TRAJ_RTOL
+    if check_eps:
+        e = np.abs(r["eps_eff"] - o["eps_eff"]) / np.maximum(np.abs(o["eps_eff"]), 1.0)
+        assert e.max() <= 1e-5
+    return bnd
+
+
+SCENES = [
+    ("random_uni", lambda: W.random_scene(1, num_samples=1000, horizon=30, n_obs=7)),
+    ("random_uni_noclamp", lambda: W.random_scene(2, num_samples=777, horizon=50, n_obs=12, clamp=False)),
+    ("random_uni_short", lambda: W.random_scene(3, num_samples=513, horizon=9, n_obs=3)),
+    ("config1_probe", lambda: W.config1_probe(1)),
+    ("config2_probe", lambda: W.config2_probe(2, num_samples=2048)),
+    ("random_arm", lambda: W.random_scene(4, dynamics=W.ARM6, num_samples=600, horizon=20, n_obs=10)),
+    ("random_arm_noclamp", lambda: W.random_scene(5, dynamics=W.ARM6, num_samples=301, horizon=32,
+                                                  n_obs=16, clamp=False)),
+]
+
+
+@pytest.mark.parametrize("name,make", SCENES, ids=[s[0] for s in SCENES])
+def test_rollouts_match_oracle(name, make):
+    s = make()
+    pl = _planner(s.spec)
+    _set_U(pl, s.U0)
+    r = H.gpu_replan(pl, s.x0, s.obstacles)
+    o = oracle.replan(s.spec, s.x0, s.U0, s.obstacles)
+    _compare_rollouts(r, o, s.spec)
+
+
+# ------------------------------------------------------------------ stages after the rollouts
+def _fp32_records(o):
+    return {k: np.asarray(o[k], np.float32 if o[k].dtype == np.float64 else np.int32)
+            for k in ("S", "col", "first_obs", "p_term", "p_first", "eps_eff")}
+
+
+def _check_post(r, o, spec, exact_labels=True):
+    inf = r["info"]
+    assert inf["branch"] == o["branch"]
+    assert inf["status"] == o["status"], (inf["status"], o["status"])
+    if o["branch"] != 0:
+        return
+    assert inf["n_collide"] == o["n_col"] and inf["n_feasible"] == o["n_feas"]
+    assert inf["n_ref"] == o["n_ref"]
+    assert inf["closest"] == o["closest"]
+    assert np.array_equal(r["v_idx"], o["v_idx"])
+    assert H.rel_err(inf["ref_point"][: spec.p], o["ref_point"]).max() <= 1e-5
+    assert np.abs(r["z"] - o["z"]).max() <= 2e-5
+    assert np.abs(r["g"] - o["g"]).max() <= 2e-5
+    pts, npairs = H.flagged_pairs(o["z"], float(np.float32(spec.dbscan_eps)))
+    if npairs == 0 and exact_labels:
+        assert np.array_equal(r["ncount"], o["ncount"])
+        assert np.array_equal(r["label"], o["label"])
+        assert inf["n_clusters"] == o["n_clusters"]
+    if inf["n_clusters"] != o["n_clusters"] or not np.array_equal(r["label"], o["label"]):
+        return npairs
+    M = o["n_clusters"]
+    if M:
+        assert np.array_equal(r["c_size"], o["c_size"])
+        assert H.rel_err(r["c_mean_cost"], o["c_mean_cost"]).max() <= 1e-5
+        assert np.abs(r["c_dir"] - o["c_dir"]).max() <= 2e-5
+        near_tie = np.isfinite(o["margin"]) and abs(o["margin"]) <= 1e-4 * max(1.0, abs(
+            o["c_mean_cost"][o["selected"]] if o["rule"] == 0 else 1.0))
+        if not near_tie:
+            assert inf["selected"] == o["selected"]
+            assert inf["rule"] == o["rule"]
+    return npairs
+
+
+POST = [
+    ("config1_probe", lambda: W.config1_probe(1)),
+    ("config1_probe_s3", lambda: W.config1_probe(3)),
+    ("config2_probe", lambda: W.config2_probe(2, num_samples=3000)),
+    ("random_uni", lambda: W.random_scene(7, num_samples=1500, horizon=40, n_obs=8)),
+    ("random_uni_first_contact", lambda: W.random_scene(8, num_samples=900, horizon=30, n_obs=8,
+                                                        ref_mode=W.REF_FIRST_CONTACT)),
+    ("random_arm", lambda: W.random_scene(9, dynamics=W.ARM6, num_samples=800, horizon=16, n_obs=12)),
+]
+
+
+@pytest.mark.parametrize("name,make", POST, ids=[s[0] for s in POST])
+def test_post_rollout_stages_on_oracle_records(name, make):
+    s = make()
+    o_full = oracle.replan(s.spec, s.x0, s.U0, s.obstacles)
+    rec = _fp32_records(o_full)
+    o = oracle.replan(s.spec, s.x0, s.U0, s.obstacles, rollouts=rec)
+    pl = _planner(s.spec)
+    _set_U(pl, s.U0)
+    x = H.to_dev(s.x0)
+    obs = H.to_dev(s.obstacles)
+    t = {k: H.to_dev(v) for k, v in rec.items()}
+    u, U, _ = pl.replan_from_rollouts(x, obs, t["S"], t["col"], t["first_obs"], t["p_term"],
+                                      t["p_first"], t["eps_eff"])
+    H.torch_mod().cuda.synchronize()
+    info = pl.info()
+    r = H.collect(pl, info)
+    _check_post(r, o, s.spec)
+    # update on identical costs and labels: FP32 weights and sums
+    scale = max(1.0, float(np.abs(rec["eps_eff"]).max()))
+    assert np.abs(U.cpu().numpy() - o["U_new"]).max() <= 1e-4 * scale
+    assert np.abs(u.cpu().numpy() - o["u_out"]).max() <= 1e-4 * scale
+    assert np.allclose(pl.get_nominal().cpu().numpy(), o["U_next"], atol=1e-4 * scale)
+
+
+# ------------------------------------------------------------------ DBSCAN alone, bit-exact
+def _dbscan_cases():
+    cases = []
+    for name, make in POST:
+        s = make()
+        o = oracle.replan(s.spec, s.x0, s.U0, s.obstacles)
+        if o["branch"] == 0 and o["n_feas"] > 0:
+            cases.append((name, np.asarray(o["z"], np.float32), s.spec))
+    rng = np.random.default_rng(0)
+    # many small separated groups: more than 64 trees (exercises the fallback)
+    ang = np.repeat(np.arange(90) * 2 * math.pi / 90, 12) + rng.normal(0, 0.004, 90 * 12)
+    z = np.stack([np.cos(ang), np.sin(ang)], 1).astype(np.float32)
+    cases.append(("90_groups", z, W.PlannerSpec(num_samples=2000, dbscan_eps=0.03, dbscan_min_pts=5)))
+    # duplicates and exact-radius pairs
+    z = np.zeros((300, 2), np.float32)
+    z[100:200, 0] = np.float32(0.3)
+    z[200:] = rng.normal(size=(100, 2)).astype(np.float32)
+    cases.append(("dups", z, W.PlannerSpec(num_samples=512, dbscan_eps=0.3, dbscan_min_pts=50)))
+    # 3-D features, ragged size
+    v = rng.normal(size=(1111, 3))
+    v[:500] += 3 * np.array([1, 0, 0])
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    cases.append(("sphere3d", v.astype(np.float32),
+                  W.PlannerSpec(dynamics=W.ARM6, num_samples=1200, dbscan_eps=0.35, dbscan_min_pts=16,
+                                dh=W.arm_dh([0.2] * 6))))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(9))
+def test_stage_dbscan_bit_exact(case):
+    cases = _dbscan_cases()
+    if case >= len(cases):
+        pytest.skip("no such case")
+    name, z, spec = cases[case]
+    spec = spec.rounded()
+    pl = _planner(spec)
+    lab, cnt, M = pl.stage_dbscan(H.to_dev(z))
+    lab = lab.cpu().numpy()
+    cnt = cnt.cpu().numpy()
+    olab, ocore, ocnt, oM = oracle.dbscan(z.astype(np.float64), spec.dbscan_eps, spec.dbscan_min_pts)
+    assert np.array_equal(cnt, ocnt), name
+    assert int(M.cpu().item()) == oM, name
+    assert np.array_equal(lab, olab), name
+
+
+def test_stage_dbscan_empty_and_single():
+    spec = W.PlannerSpec(num_samples=64, dbscan_eps=0.3, dbscan_min_pts=1).rounded()
+    pl = _planner(spec)
+    lab, cnt, M = pl.stage_dbscan(H.to_dev(np.zeros((0, 2), np.float32)))
+    assert int(M.cpu().item()) == 0 and lab.numel() == 0
+    lab, cnt, M = pl.stage_dbscan(H.to_dev(np.ones((1, 2), np.float32)))
+    assert int(M.cpu().item()) == 1 and lab.cpu().tolist() == [0]
+
+
+# ------------------------------------------------------------------ end to end
+E2E = [
+    ("config1_probe", lambda: W.config1_probe(1)),
+    ("config1_probe_s5", lambda: W.config1_probe(5)),
+    ("config2_probe", lambda: W.config2_probe(1, num_samples=4096)),
+    ("random_uni", lambda: W.random_scene(11, num_samples=2000, horizon=40, n_obs=10)),
+    ("random_arm", lambda: W.random_scene(12, dynamics=W.ARM6, num_samples=1000, horizon=24, n_obs=12)),
+    ("no_obstacles", lambda: W.random_scene(13, num_samples=700, horizon=20, n_obs=0)),
+]
+
+
+@pytest.mark.parametrize("name,make", E2E, ids=[s[0] for s in E2E])
+def test_end_to_end_replan(name, make):
+    s = make()
+    pl = _planner(s.spec)
+    _set_U(pl, s.U0)
+    r = H.gpu_replan(pl, s.x0, s.obstacles)
+    o = oracle.replan(s.spec, s.x0, s.U0, s.obstacles)
+    bnd = _compare_rollouts(r, o, s.spec)
+    if not np.array_equal(r["col"], o["col"]):
+        pytest.skip(f"{int(bnd.sum())} boundary rollouts changed the feasible set")
+    _check_post(r, o, s.spec)
+    # end-to-end update bound: weights move by ~ dS / lambda
+    dS = np.abs(r["S"].astype(np.float64) - o["S"]).max()
+    emax = np.abs(o["eps_eff"]).max()
+    bound = 2.0 * (dS / s.spec.lam) * emax + 1e-4 * np.maximum(np.abs(o["U_new"]), 1.0)
+    assert np.all(np.abs(r["U_new"] - o["U_new"]) <= bound + 1e-4 * emax)
+    assert np.array_equal(r["u_out"], r["U_new"][0])
+    assert np.array_equal(r["U_next"][:-1], r["U_new"][1:])
+    assert np.array_equal(r["U_next"][-1], r["U_new"][-1])
+
+
+def test_determinism_and_checkpoint():
+    s = W.config1_probe(2)
+    pl = _planner(s.spec)
+    _set_U(pl, s.U0)
+    state = pl.get_state()
+    a = H.gpu_replan(pl, s.x0, s.obstacles)
+    b2 = H.gpu_replan(pl, s.x0, s.obstacles)  # next step: different noise
+    pl.set_state(state)
+    c = H.gpu_replan(pl, s.x0, s.obstacles)
+    for k in ("S", "col", "label", "u_out", "U_new", "U_next", "z"):
+        assert np.array_equal(a[k], c[k]), k
+    assert a["info"]["step"] == 0 and b2["info"]["step"] == 1 and c["info"]["step"] == 0
+    assert not np.array_equal(a["S"], b2["S"])
+
+
+def test_lockstep_dynamic_loop():
+    """Config-2 shaped dynamic scene, a few closed-loop steps in lockstep: at
+    every step both sides start from the same state, nominal and history."""
+    s = W.config2_probe(3, num_samples=2048)
+    spec = s.spec
+    pl = _planner(spec)
+    fld = s.field.copy()
+    x = s.x0.astype(np.float64)
+    U = s.U0.astype(np.float64)
+    hist = []
+    compared = 0
+    for t in range(8):
+        obs = fld.observation()
+        hist.insert(0, obs[:, : spec.p].astype(np.float64))
+        hist = hist[: spec.history_len]
+        _set_U(pl, np.float32(U))
+        r = H.gpu_replan(pl, np.float32(x), obs)
+        o = oracle.replan(spec, np.float32(x), np.float32(U), obs, np.array(hist), step=t)
+        assert r["info"]["step"] == t
+        _compare_rollouts(r, o, spec)
+        if np.array_equal(r["col"], o["col"]):
+            _check_post(r, o, spec)
+            compared += 1
+        U = o["U_next"]
+        x = oracle.unicycle_step(x, o["u_out"], spec.dt)
+        fld.step(spec.dt)
+    assert compared >= 6
+
+
+def test_degenerate_branches():
+    # every rollout collides
+    s = W.config1_probe(1)
+    s.field.c[0] = s.x0[:2]
+    s.field.r[0] = 5.0
+    pl = _planner(s.spec)
+    _set_U(pl, s.U0)
+    r = H.gpu_replan(pl, s.x0, s.obstacles)
+    o = oracle.replan(s.spec, s.x0, s.U0, s.obstacles)
+    assert r["info"]["branch"] == 2 == o["branch"] and r["info"]["status"] == o["status"]
+    assert np.abs(r["U_new"] - o["U_new"]).max() <= 1e-3
+    # no cluster (minPts larger than |V|)
+    s = W.config1_probe(1)
+    s.spec = s.spec.replace(dbscan_min_pts=100000)
+    pl = _planner(s.spec)
+    _set_U(pl, s.U0)
+    r = H.gpu_replan(pl, s.x0, s.obstacles)
+    o = oracle.replan(s.spec, s.x0, s.U0, s.obstacles)
+    assert r["info"]["status"] == o["status"] and r["info"]["n_clusters"] == 0
+    assert np.abs(r["U_new"] - o["U_new"]).max() <= 1e-3
+    # non-finite input: no-op
+    x = s.x0.copy()
+    x[0] = np.nan
+    before = pl.get_nominal().cpu().numpy()
+    r = H.gpu_replan(pl, x, s.obstacles)
+    assert r["info"]["status"] & 16
+    assert np.array_equal(r["U_next"], before)
+    assert np.array_equal(r["u_out"], before[0])
+
+
+def test_tiny_problem():
+    s = W.random_scene(21, num_samples=1, horizon=1, n_obs=1)
+    pl = _planner(s.spec)
+    _set_U(pl, s.U0)
+    r = H.gpu_replan(pl, s.x0, s.obstacles)
+    o = oracle.replan(s.spec, s.x0, s.U0, s.obstacles)
+    assert r["info"]["branch"] == o["branch"]
+    assert H.rel_err(r["S"], o["S"]).max() <= H.TRAJ_RTOL
+    assert np.abs(r["U_new"] - o["U_new"]).max() <= 1e-5
