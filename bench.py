@@ -1,0 +1,295 @@
+#!/usr/bin/env python3
+"""CE-MPPI replan benchmark on one MI355X.
+
+Workload (default): the dynamic 2-D scene -- unicycle, K=8192 rollouts,
+horizon N=50, dt=0.05 s, 24 moving circular obstacles in a 20x20 m box,
+dynamic selection rule, DBSCAN eps=0.25 / minPts=20 -- driven through a
+closed loop.  A step is one replan (the whole hot path).  The loop's states
+and observations are recorded first (untimed), uploaded to the GPU, and the
+planner (reset to its initial state) then replans over them back to back:
+inputs are resident in HBM when the timed region starts, and the timed
+replans reproduce the recorded loop bit for bit.
+
+Prints one JSON line: replans/s (value), rollout-steps/s, p50/p99 latency,
+the branch mix, the roofline of the rollout kernel and the CPU oracle
+baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "CE-MPPI replans/s + rollout-steps/s at K=8192; p50/p99 replan latency"
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (datasheet)
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--workload", default="config2", choices=["config2", "config2_probe", "config1",
+                                                              "config3"])
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="budget of the CPU-oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the clustering-branch companion measurement")
+    return ap.parse_args()
+
+
+def scene_for(name, seed):
+    from paper_2607_06499_amd import workloads as W
+
+    return {"config2": W.config2, "config2_probe": W.config2_probe, "config1": W.config1,
+            "config3": W.config3}[name](seed)
+
+
+def record_loop(pl, scene, T, torch):
+    """Run the closed loop for T replans (host plant), returning the inputs
+    each replan saw, the applied controls and the per-replan info."""
+    from paper_2607_06499_amd import plant
+
+    spec = scene.spec
+    fld = scene.field.copy()
+    x = scene.x0.astype(np.float64)
+    X, OBS, UO, INFO = [], [], [], []
+    xd = torch.zeros(spec.n, dtype=torch.float32, device="cuda")
+    od = torch.zeros(max(fld.n, 1), spec.p + 1, dtype=torch.float32, device="cuda")
+    for _ in range(T):
+        xf = np.asarray(x, np.float32)
+        obs = fld.observation()
+        X.append(xf)
+        OBS.append(obs)
+        xd.copy_(torch.from_numpy(xf))
+        od[: fld.n].copy_(torch.from_numpy(obs))
+        u, _, _ = pl.replan(xd, od[: fld.n])
+        torch.cuda.synchronize()
+        info = pl.info()
+        un = u.cpu().numpy().copy()
+        UO.append(un)
+        INFO.append(info)
+        x = plant.step(spec.dynamics, x, un, spec.dt)
+        fld.step(spec.dt)
+    return np.stack(X), np.stack(OBS), np.stack(UO), INFO
+
+
+def timed_replays(pl, lib, Xd, Od, n_obs, W, K, torch):
+    """Back-to-back replans over the recorded inputs: W warm-up, K timed."""
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    h = pl.handle
+    u_ptr = pl.u_out.data_ptr()
+    xs = [Xd[t].data_ptr() for t in range(W + K)]
+    os_ = [Od[t].data_ptr() for t in range(W + K)]
+    f = lib.ce_mppi_replan
+    for t in range(W):
+        f(h, xs[t], os_[t], n_obs, u_ptr, None, None, sh)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for t in range(W, W + K):
+        f(h, xs[t], os_[t], n_obs, u_ptr, None, None, sh)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / 1e3
+
+
+def latency_replays(pl, lib, Xd, Od, n_obs, W, K, torch, Uo):
+    """One replan at a time, host wall clock from the call to u_out ready."""
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    h = pl.handle
+    f = lib.ce_mppi_replan
+    lat = []
+    outs = torch.zeros(W + K, pl.m, dtype=torch.float32, device="cuda")
+    for t in range(W + K):
+        t0 = time.perf_counter()
+        f(h, Xd[t].data_ptr(), Od[t].data_ptr(), n_obs, outs[t].data_ptr(), None, None, sh)
+        stream.synchronize()
+        if t >= W:
+            lat.append(time.perf_counter() - t0)
+    same = bool(np.array_equal(outs.cpu().numpy(), Uo[: W + K]))
+    return np.array(lat), same
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel_sources):
+    """HBM traffic per launch from the committed counter summary, if it was
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "rollout_unicycle_config2_traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    rec = json.load(open(path))
+    if rec.get("source_digest") != source_digest(kernel_sources):
+        return None, rec
+    return rec.get("hbm_bytes_per_launch"), rec
+
+
+def cpu_baseline(scene, X, OBS, W, budget_s, hist_len):
+    import oracle
+
+    spec = scene.spec
+    U = scene.U0.astype(np.float64)
+    hist = []
+    n = 0
+    t0 = time.perf_counter()
+    # the oracle replays the same loop from its start (its own nominal
+    # sequence), one replan after another, until the budget is spent
+    for t in range(len(X)):
+        hist.insert(0, OBS[t][:, : spec.p].astype(np.float64))
+        hist = hist[:hist_len]
+        r = oracle.replan(spec, X[t], U, OBS[t], np.array(hist), step=t)
+        U = r["U_next"]
+        n += 1
+        if time.perf_counter() - t0 >= budget_s and n >= 2:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="replans/s", cores=1, kind="oracle",
+                sample=f"first {n} replans of the same closed loop (K={spec.num_samples}, "
+                       f"N={spec.horizon}), single-threaded FP64 C oracle, "
+                       f"{spec.num_samples * spec.horizon * n / dt:.3g} rollout-steps/s")
+
+
+def run_workload(name, seed, W, K, torch, B, want_timing=True):
+    scene = scene_for(name, seed)
+    spec = scene.spec
+    lib = B.load()
+    pl = B.Planner(spec)
+    pl.set_nominal(torch.as_tensor(scene.U0).cuda())
+    state0 = pl.get_state()
+    X, OBS, Uo, INFO = record_loop(pl, scene, W + K, torch)
+    Xd = torch.as_tensor(X).cuda()
+    Od = torch.as_tensor(OBS).cuda()
+    n_obs = OBS.shape[1]
+    # throughput
+    pl.set_state(state0)
+    wall, gpu = timed_replays(pl, lib, Xd, Od, n_obs, W, K, torch)
+    # latency (and a bit-for-bit replay check)
+    pl.set_state(state0)
+    lat, same = latency_replays(pl, lib, Xd, Od, n_obs, W, K, torch, Uo)
+    timing = None
+    if want_timing:
+        pl.set_state(state0)
+        pl.timing_enable(W + K)
+        for t in range(W + K):
+            lib.ce_mppi_replan(pl.handle, Xd[t].data_ptr(), Od[t].data_ptr(), n_obs,
+                               pl.u_out.data_ptr(), None, None, int(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        timing = pl.timing_read()
+        timing["count"] = max(timing["count"], 1)
+        pl.timing_enable(0)
+    branches = [i["branch"] for i in INFO[W:]]
+    mix = {"cluster": branches.count(0), "fallback": branches.count(1),
+           "all_collide": branches.count(2)}
+    ncl = [i["n_feasible"] for i in INFO[W:] if i["branch"] == 0]
+    pl.close()
+    return dict(scene=scene, X=X, OBS=OBS, wall=wall, gpu=gpu, lat=lat, same=same, timing=timing,
+                mix=mix, mean_V=float(np.mean(ncl)) if ncl else 0.0)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the CE-MPPI planners are "
+                                   "independent, so more GPUs would each run their own share of "
+                                   "planners (see the design notes); run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2607_06499_amd import binding as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    W, K = args.warmup, args.steps
+    res = run_workload(args.workload, args.seed, W, K, torch, B)
+    spec = res["scene"].spec
+    replans_per_s = K / res["wall"]
+    rollout_steps = spec.num_samples * spec.horizon
+    lat = res["lat"]
+    # roofline of the rollout kernel: algorithmic FP32 flops per rollout-step
+    # 25 + 5 n_obs (noise transform, clamp, dynamics, cost, 5 per obstacle)
+    n_obs = res["OBS"].shape[1]
+    flops = rollout_steps * (25 + 5 * n_obs) if spec.dynamics == 0 else \
+        rollout_steps * (480 + 48 + 8 * n_obs * spec.n_link_spheres + 40)
+    t_roll = res["timing"]["rollout_ms"] / res["timing"]["count"] * 1e-3
+    achieved = flops / t_roll / 1e12
+    ksrc = [os.path.join(ROOT, "paper_2607_06499_amd", "csrc", f)
+            for f in ("rollout.hip", "device.hpp")]
+    traffic, _ = traffic_record(ksrc)
+    out = {
+        "metric": METRIC,
+        "value": round(replans_per_s, 2),
+        "unit": "replans/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(1e3 * res["wall"] / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: unicycle K={spec.num_samples} N={spec.horizon} "
+                        f"dt={spec.dt:g} {n_obs} obstacles, "
+                        f"{'dynamic' if spec.scene_mode else 'static'} rule, "
+                        f"closed loop of {W + K} replans (seed {args.seed})"
+            if spec.dynamics == 0 else
+            f"{args.workload}: 6-joint arm K={spec.num_samples} N={spec.horizon} {n_obs} spheres",
+            "K": spec.num_samples, "N": spec.horizon, "n_obs": n_obs,
+            "branch_mix": res["mix"], "mean_feasible_when_clustering": round(res["mean_V"], 1),
+            "launch": "hipGraph replay per replan",
+        },
+        "rollout_steps_per_s": round(replans_per_s * rollout_steps, 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 4)},
+        "gpu_ms_per_step": round(1e3 * res["gpu"] / K, 4),
+        "replay_bit_exact": res["same"],
+        "roofline": {
+            "bound": "alu", "kernel": "rollout",
+            "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 6),
+            "traffic": traffic,
+            "kernel_ms": round(t_roll * 1e3, 5),
+            "algorithmic_flop_per_launch": flops,
+        },
+    }
+    if not args.no_probe and args.workload == "config2":
+        pr = run_workload("config2_probe", args.seed, W, K, torch, B, want_timing=False)
+        out["clustering_branch"] = {
+            "workload": "config2_probe: same planner, obstacle ahead in the robot's path",
+            "replans_per_s": round(K / pr["wall"], 2),
+            "latency_ms": {"p50": round(float(np.percentile(pr["lat"], 50)) * 1e3, 4),
+                           "p99": round(float(np.percentile(pr["lat"], 99)) * 1e3, 4)},
+            "branch_mix": pr["mix"], "mean_feasible": round(pr["mean_V"], 1),
+        }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(res["scene"], res["X"], res["OBS"], W, args.cpu_seconds,
+                                           spec.history_len)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

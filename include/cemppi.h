@@ -232,6 +232,23 @@ ce_status ce_mppi_replan_from_rollouts(ce_mppi_planner* planner, const float* x_
 ce_status ce_mppi_stage_dbscan(ce_mppi_planner* planner, const float* z, int32_t V, int32_t* ncount,
                                int32_t* label, int32_t* n_clusters, void* stream);
 
+/* ---- launch mode and timing ---- */
+enum { CE_LAUNCH_GRAPH = 0, CE_LAUNCH_DIRECT = 1 };
+/* CE_LAUNCH_GRAPH (default): the first replan records the planner's kernel
+ * chain into a hipGraph and every replan replays it (the first and last
+ * kernels are re-pointed when the caller's buffers change).
+ * CE_LAUNCH_DIRECT: every kernel is launched individually.  Both run the same
+ * kernels with the same arguments. */
+ce_status ce_mppi_set_launch_mode(ce_mppi_planner* planner, int32_t mode);
+/* capacity > 0: the next `capacity` replans are launched directly with HIP
+ * events recorded on the replan stream before the rollout kernel, after it
+ * and after the last kernel; 0 disables.  Allocates the events. */
+ce_status ce_mppi_timing_enable(ce_mppi_planner* planner, int32_t capacity);
+/* Sums (ms) over the timed replans of the rollout kernel, of everything after
+ * it and of the whole replan, and their count; waits for the events. */
+ce_status ce_mppi_timing_read(ce_mppi_planner* planner, double* rollout_ms, double* post_ms,
+                              double* total_ms, int32_t* count);
+
 /* ---- errors ---- */
 const char* ce_mppi_status_string(ce_status status);
 /* Message of the last failed call on this thread ("" if none). */

@@ -23,6 +23,7 @@ REF_TERMINAL, REF_FIRST_CONTACT = 0, 1
 BRANCH_CLUSTER, BRANCH_FALLBACK, BRANCH_ALL_COLLIDE = 0, 1, 2
 STATUS_FALLBACK, STATUS_ALL_COLLIDE, STATUS_NO_CLUSTER, STATUS_DYN_STATIC, STATUS_NONFINITE = (
     1, 2, 4, 8, 16)
+LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
 (DBG_COST, DBG_COLLIDE, DBG_FIRST_OBS, DBG_P_TERM, DBG_P_FIRST, DBG_EPS, DBG_V_IDX, DBG_Z, DBG_G,
  DBG_NCOUNT, DBG_LABEL, DBG_CLUSTER_COST, DBG_CLUSTER_DIR, DBG_CLUSTER_SIZE) = range(14)
 
@@ -128,6 +129,10 @@ def load():
         "ce_mppi_replan_from_rollouts": [_vp, _vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp,
                                          _vp, _vp, _vp, _vp],
         "ce_mppi_stage_dbscan": [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp],
+        "ce_mppi_set_launch_mode": [_vp, C.c_int32],
+        "ce_mppi_timing_enable": [_vp, C.c_int32],
+        "ce_mppi_timing_read": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.POINTER(C.c_double), C.POINTER(C.c_int32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -321,6 +326,19 @@ class Planner:
             p_first.data_ptr(), eps.data_ptr(), self.u_out.data_ptr(), self.U_out.data_ptr(),
             self.info_buf.data_ptr(), _stream_handle(stream)))
         return self.u_out, self.U_out, self.info_buf
+
+    # -- launch mode and timing
+    def set_launch_mode(self, mode: int):
+        _check("ce_mppi_set_launch_mode", load().ce_mppi_set_launch_mode(self.handle, int(mode)))
+
+    def timing_enable(self, capacity: int):
+        _check("ce_mppi_timing_enable", load().ce_mppi_timing_enable(self.handle, int(capacity)))
+
+    def timing_read(self) -> dict:
+        r, q, a, n = C.c_double(), C.c_double(), C.c_double(), C.c_int32()
+        _check("ce_mppi_timing_read", load().ce_mppi_timing_read(
+            self.handle, C.byref(r), C.byref(q), C.byref(a), C.byref(n)))
+        return dict(rollout_ms=r.value, post_ms=q.value, total_ms=a.value, count=n.value)
 
     # -- stages and diagnostics
     def stage_noise(self, step: int, stream=None):

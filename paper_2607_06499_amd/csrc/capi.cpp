@@ -12,23 +12,45 @@
 
 #include "cemppi.h"
 #include "device.hpp"
+#include "launch.hpp"
 
 namespace cemppi {
-hipError_t launch_rollout(const Cfg& c, const Bufs& b, const float* x_t, const float* obs, int n_obs,
-                          hipStream_t s);
-hipError_t launch_reduce_records(const Cfg& c, const Bufs& b, const float* x_t, const float* obs,
-                                 int n_obs, hipStream_t s);
-hipError_t launch_stage_noise(const Cfg& c, uint32_t step, uint32_t* words, float* gauss,
-                              hipStream_t s);
-hipError_t launch_post_rollout(const Cfg& c, const Bufs& b, float* u_out, float* U_out, void* info,
-                               hipStream_t s);
-hipError_t launch_stage_dbscan(const Cfg& c, const Bufs& b, const float* z, int V, int* ncount,
-                               int* label, int* mout, hipStream_t s);
+void launch_rollout(Launcher& L, const Cfg& c, const Bufs& b, const float* x_t, const float* obs,
+                    int n_obs);
+void launch_reduce_records(Launcher& L, const Cfg& c, const Bufs& b, const float* x_t,
+                           const float* obs, int n_obs);
+void launch_stage_noise(Launcher& L, const Cfg& c, uint32_t step, uint32_t* words, float* gauss);
+void launch_post_rollout(Launcher& L, const Cfg& c, const Bufs& b);
+void launch_finish(Launcher& L, const Cfg& c, const Bufs& b, float* u_out, float* U_out, void* info);
+void launch_stage_dbscan(Launcher& L, const Cfg& c, const Bufs& b, const float* z, int V,
+                         int* ncount, int* label, int* mout);
 }  // namespace cemppi
 
 using namespace cemppi;
 
 static_assert(sizeof(ce_mppi_info) == 4 * (12 + 2 + 10), "ce_mppi_info layout");
+
+// Replan as a hipGraph: the whole kernel chain recorded once, the first
+// (rollout) and last (finish) nodes re-pointed when the caller's buffers
+// change.
+struct ReplanGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  Launcher::Node first{}, last{};
+  const float* x = nullptr;
+  const float* obs = nullptr;
+  int n_obs = -1;
+  float* u_out = nullptr;
+  float* U_out = nullptr;
+  void* info = nullptr;
+};
+
+// HIP-event timing of each replan: events before the rollout kernel, after
+// it and after the final kernel.
+struct Timing {
+  int cap = 0, n = 0;
+  std::vector<hipEvent_t> ev;
+};
 
 struct ce_mppi_planner {
   ce_mppi_config cfg;
@@ -37,6 +59,9 @@ struct ce_mppi_planner {
   void* arena = nullptr;
   size_t arena_bytes = 0;
   size_t cap_K = 0;
+  int launch_mode = CE_LAUNCH_GRAPH;
+  ReplanGraph g;
+  Timing t;
 };
 
 namespace {
@@ -134,7 +159,7 @@ void build_cfg(const ce_mppi_config* u, Cfg& c) {
   c.NM = c.N * c.m;
   c.B = (c.NM + 3) / 4;
   c.seg = (c.dyn == CE_DYN_UNICYCLE && c.N + 1 <= 32) ? 32 : 64;
-  c.rpb = 4 * (64 / c.seg);
+  c.rpb = kRollWaves * (64 / c.seg);
   c.nblk_roll = (c.K + c.rpb - 1) / c.rpb;
   c.dt = u->dt;
   c.lambda = u->lambda;
@@ -343,10 +368,86 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   return CE_OK;
 }
 
+namespace {
+void drop_graph(ReplanGraph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = ReplanGraph();
+}
+
+void drop_timing(Timing& t) {
+  for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+  t = Timing();
+}
+
+hipError_t build_graph(ce_mppi_planner* P, const float* x_t, const float* obs, int n_obs, float* u_out,
+                       float* U_out, void* info) {
+  ReplanGraph& g = P->g;
+  hipError_t e = hipGraphCreate(&g.graph, 0);
+  if (e != hipSuccess) return e;
+  Launcher L(nullptr, g.graph);
+  launch_rollout(L, P->c, P->b, x_t, obs, n_obs);
+  launch_post_rollout(L, P->c, P->b);
+  launch_finish(L, P->c, P->b, u_out, U_out, info);
+  if (L.err != hipSuccess) return L.err;
+  g.first = L.nodes.front();
+  g.last = L.nodes.back();
+  e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return e;
+  g.x = x_t;
+  g.obs = obs;
+  g.n_obs = n_obs;
+  g.u_out = u_out;
+  g.U_out = U_out;
+  g.info = info;
+  return hipSuccess;
+}
+
+hipError_t replan_graph(ce_mppi_planner* P, const float* x_t, const float* obs, int n_obs,
+                        float* u_out, float* U_out, void* info, hipStream_t s) {
+  ReplanGraph& g = P->g;
+  hipError_t e = hipSuccess;
+  if (!g.exec) {
+    e = build_graph(P, x_t, obs, n_obs, u_out, U_out, info);
+    if (e != hipSuccess) {
+      drop_graph(g);
+      return e;
+    }
+  }
+  if (x_t != g.x || obs != g.obs || n_obs != g.n_obs) {
+    Cfg c = P->c;
+    Bufs b = P->b;
+    const float* xx = x_t;
+    const float* oo = obs;
+    int nn = n_obs;
+    e = set_node_args(g.exec, g.first, c, b, xx, oo, nn);
+    if (e != hipSuccess) return e;
+    g.x = x_t;
+    g.obs = obs;
+    g.n_obs = n_obs;
+  }
+  if (u_out != g.u_out || U_out != g.U_out || info != g.info) {
+    Cfg c = P->c;
+    Bufs b = P->b;
+    float* uo = u_out;
+    float* Uo = U_out;
+    void* in = info;
+    e = set_node_args(g.exec, g.last, c, b, uo, Uo, in);
+    if (e != hipSuccess) return e;
+    g.u_out = u_out;
+    g.U_out = U_out;
+    g.info = info;
+  }
+  return hipGraphLaunch(g.exec, s);
+}
+}  // namespace
+
 void ce_mppi_destroy(ce_mppi_planner* P) {
   if (!P) return;
   {
     DeviceGuard guard(P->cfg.device);
+    drop_graph(P->g);
+    drop_timing(P->t);
     if (P->arena) (void)hipFree(P->arena);
   }
   delete P;
@@ -359,9 +460,80 @@ ce_status ce_mppi_replan(ce_mppi_planner* P, const float* x_t, const float* obst
   if (n_obs < 0 || n_obs > P->c.max_obs) return fail(CE_EINVAL, "n_obs outside 0..max_obstacles");
   if (n_obs > 0 && !obstacles) return fail(CE_EINVAL, "obstacles is NULL with n_obs > 0");
   DeviceGuard guard(P->cfg.device);
-  hipError_t e = launch_rollout(P->c, P->b, x_t, obstacles, n_obs, S(stream));
-  if (e == hipSuccess) e = launch_post_rollout(P->c, P->b, u_out, U_out, info, S(stream));
+  hipStream_t s = S(stream);
+  Timing& t = P->t;
+  hipError_t e = hipSuccess;
+  if (t.cap > 0 && t.n < t.cap) {
+    // timed replan: direct launches between events
+    const int i = t.n++;
+    Launcher L(s);
+    e = hipEventRecord(t.ev[3 * i], s);
+    launch_rollout(L, P->c, P->b, x_t, obstacles, n_obs);
+    if (e == hipSuccess && L.err == hipSuccess) e = hipEventRecord(t.ev[3 * i + 1], s);
+    launch_post_rollout(L, P->c, P->b);
+    launch_finish(L, P->c, P->b, u_out, U_out, info);
+    if (e == hipSuccess && L.err == hipSuccess) e = hipEventRecord(t.ev[3 * i + 2], s);
+    if (e == hipSuccess) e = L.err;
+  } else if (P->launch_mode == CE_LAUNCH_GRAPH) {
+    e = replan_graph(P, x_t, obstacles, n_obs, u_out, U_out, info, s);
+  } else {
+    Launcher L(s);
+    launch_rollout(L, P->c, P->b, x_t, obstacles, n_obs);
+    launch_post_rollout(L, P->c, P->b);
+    launch_finish(L, P->c, P->b, u_out, U_out, info);
+    e = L.err;
+  }
   if (e != hipSuccess) return hip_fail(e, "replan launch");
+  return CE_OK;
+}
+
+ce_status ce_mppi_set_launch_mode(ce_mppi_planner* P, int32_t mode) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  if (mode != CE_LAUNCH_GRAPH && mode != CE_LAUNCH_DIRECT) return fail(CE_EINVAL, "unknown launch mode");
+  P->launch_mode = mode;
+  return CE_OK;
+}
+
+ce_status ce_mppi_timing_enable(ce_mppi_planner* P, int32_t capacity) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  if (capacity < 0 || capacity > (1 << 20)) return fail(CE_EINVAL, "capacity out of range");
+  DeviceGuard guard(P->cfg.device);
+  drop_timing(P->t);
+  if (capacity == 0) return CE_OK;
+  P->t.ev.resize((size_t)capacity * 3, nullptr);
+  for (auto& ev : P->t.ev) {
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) {
+      drop_timing(P->t);
+      return hip_fail(e, "hipEventCreate");
+    }
+  }
+  P->t.cap = capacity;
+  P->t.n = 0;
+  return CE_OK;
+}
+
+ce_status ce_mppi_timing_read(ce_mppi_planner* P, double* rollout_ms, double* post_ms,
+                              double* total_ms, int32_t* count) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  DeviceGuard guard(P->cfg.device);
+  const Timing& t = P->t;
+  double r = 0.0, q = 0.0, a = 0.0;
+  for (int i = 0; i < t.n; ++i) {
+    hipError_t e = hipEventSynchronize(t.ev[3 * i + 2]);
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&x, t.ev[3 * i], t.ev[3 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&y, t.ev[3 * i + 1], t.ev[3 * i + 2]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&z, t.ev[3 * i], t.ev[3 * i + 2]);
+    if (e != hipSuccess) return hip_fail(e, "timing_read");
+    r += x;
+    q += y;
+    a += z;
+  }
+  if (rollout_ms) *rollout_ms = r;
+  if (post_ms) *post_ms = q;
+  if (total_ms) *total_ms = a;
+  if (count) *count = t.n;
   return CE_OK;
 }
 
@@ -386,9 +558,12 @@ ce_status ce_mppi_replan_from_rollouts(ce_mppi_planner* P, const float* x_t, con
   if (e == hipSuccess) e = hipMemcpyAsync(b.pT, p_term, K * c.p * 4, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(b.pF, p_first, K * c.p * 4, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(b.eps, eps, K * c.NM * 4, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) e = launch_reduce_records(c, b, x_t, obstacles, n_obs, s);
-  if (e == hipSuccess) e = launch_post_rollout(c, b, u_out, U_out, info, s);
-  if (e != hipSuccess) return hip_fail(e, "replan_from_rollouts");
+  if (e != hipSuccess) return hip_fail(e, "replan_from_rollouts copy");
+  Launcher L(s);
+  launch_reduce_records(L, c, b, x_t, obstacles, n_obs);
+  launch_post_rollout(L, c, b);
+  launch_finish(L, c, b, u_out, U_out, info);
+  if (L.err != hipSuccess) return hip_fail(L.err, "replan_from_rollouts");
   return CE_OK;
 }
 
@@ -408,8 +583,10 @@ ce_status ce_mppi_stage_dbscan(ce_mppi_planner* P, const float* z, int32_t V, in
     e = hipMemcpy2DAsync(b.gv, 16, z, 12, 12, V, hipMemcpyDeviceToDevice, s);
     zin = b.gv;
   }
-  if (e == hipSuccess) e = launch_stage_dbscan(c, b, zin, V, ncount, label, n_clusters, s);
-  if (e != hipSuccess) return hip_fail(e, "stage_dbscan");
+  if (e != hipSuccess) return hip_fail(e, "stage_dbscan copy");
+  Launcher L(s);
+  launch_stage_dbscan(L, c, b, zin, V, ncount, label, n_clusters);
+  if (L.err != hipSuccess) return hip_fail(L.err, "stage_dbscan");
   return CE_OK;
 }
 
@@ -417,8 +594,9 @@ ce_status ce_mppi_stage_noise(ce_mppi_planner* P, uint32_t step, uint32_t* words
                               void* stream) {
   if (!P) return fail(CE_EINVAL, "planner is NULL");
   DeviceGuard guard(P->cfg.device);
-  hipError_t e = launch_stage_noise(P->c, step, words, gauss, S(stream));
-  if (e != hipSuccess) return hip_fail(e, "stage_noise");
+  Launcher L(S(stream));
+  launch_stage_noise(L, P->c, step, words, gauss);
+  if (L.err != hipSuccess) return hip_fail(L.err, "stage_noise");
   return CE_OK;
 }
 

@@ -24,6 +24,7 @@
 // With more than 64 trees, steps 4-5 are replaced by an exact
 // single-workgroup union-find over the core graph.
 #include "device.hpp"
+#include "launch.hpp"
 
 namespace cemppi {
 
@@ -386,27 +387,24 @@ __device__ void uf_fallback(const Cfg& c, const Bufs& b, const float* zin, int V
 
 template <int P>
 __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const float* __restrict__ zin,
-                                                         int Vin, int ntile, int* mout) {
+                                                         int Vin, int ntile, int* mout, int* lab_out,
+                                                         int* cnt_out) {
   __shared__ int s_woff[kMaxWords];
   __shared__ unsigned long long s_adj[kMaxTrees];
   __shared__ unsigned long long s_part[kFinThreads / kWave][kMaxTrees];
+  __shared__ int s_tc[kMaxTrees];
+  __shared__ int s_M;
   const int V = dbscan_V(b, zin, Vin);
   const int R = V > 0 ? tree_prefix<kFinThreads>(b, V, s_woff) : 0;
-  const int nwords = (V + 63) >> 6;
-  for (int i = threadIdx.x; i < nwords; i += kFinThreads) b.woff[i] = s_woff[i];
+  const bool overflow = R > kMaxTrees;
   if (threadIdx.x == 0) {
     b.ctrl->n_trees = R;
-    b.ctrl->tree_overflow = R > kMaxTrees ? 1 : 0;
+    b.ctrl->tree_overflow = overflow ? 1 : 0;
+    s_M = R <= 1 ? R : 0;
   }
-  if (R <= 1) {
-    if (threadIdx.x == 0) {
-      if (R == 1) b.tree_cluster[0] = 0;
-      b.ctrl->M = R;
-      if (mout) *mout = R;
-    }
-    return;
-  }
-  if (R <= kMaxTrees) {
+  if (threadIdx.x < kMaxTrees) s_tc[threadIdx.x] = 0;
+  __syncthreads();
+  if (R >= 2 && !overflow) {
     // OR the tile slots: wave w takes tiles w, w+16, ...; lane = tree row
     const int nt = (V + kTile - 1) / kTile;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -425,78 +423,75 @@ __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const fl
       s_adj[threadIdx.x] = a;
     }
     __syncthreads();
-    if (threadIdx.x >= kWave) return;
-    const int r = threadIdx.x;
-    // make the relation symmetric, then close it transitively
-    unsigned long long reach = r < R ? (s_adj[r] | (1ull << r)) : 0ull;
-    for (int t = 0; t < R; ++t)
-      if ((s_adj[t] >> r) & 1ull) reach |= 1ull << t;
-    if (r >= R) reach = 0ull;
-    for (int it = 0; it < 64; ++it) {
-      unsigned long long nr = reach;
-      for (int t = 0; t < R; ++t) {
-        const unsigned long long rt = __shfl(reach, t, kWave);
-        if ((reach >> t) & 1ull) nr |= rt;
+    if (threadIdx.x < kWave) {
+      const int r = threadIdx.x;
+      // make the relation symmetric, then close it transitively
+      unsigned long long reach = r < R ? (s_adj[r] | (1ull << r)) : 0ull;
+      for (int t = 0; t < R; ++t)
+        if ((s_adj[t] >> r) & 1ull) reach |= 1ull << t;
+      if (r >= R) reach = 0ull;
+      for (int it = 0; it < 64; ++it) {
+        unsigned long long nr = reach;
+        for (int t = 0; t < R; ++t) {
+          const unsigned long long rt = __shfl(reach, t, kWave);
+          if ((reach >> t) & 1ull) nr |= rt;
+        }
+        const bool changed = __ballot(nr != reach) != 0ull;
+        reach = nr;
+        if (!changed) break;
       }
-      const bool changed = __ballot(nr != reach) != 0ull;
-      reach = nr;
-      if (!changed) break;
+      const int cmin = r < R ? __ffsll((long long)reach) - 1 : kInt32Max;
+      const unsigned long long heads = __ballot(r < R && cmin == r);
+      if (r < R) {
+        const unsigned long long below = cmin ? (heads & ((1ull << cmin) - 1ull)) : 0ull;
+        s_tc[r] = __popcll(below);
+      }
+      if (r == 0) s_M = __popcll(heads);
     }
-    const int cmin = r < R ? __ffsll((long long)reach) - 1 : kInt32Max;
-    const unsigned long long heads = __ballot(r < R && cmin == r);
-    if (r < R) {
-      const unsigned long long below = cmin ? (heads & ((1ull << cmin) - 1ull)) : 0ull;
-      b.tree_cluster[r] = __popcll(below);
+    __syncthreads();
+  } else if (overflow) {
+    // exact fallback; clusters = components ranked by their root (lowest core
+    // index), the number of each root parked in label[root]
+    uf_fallback<P>(c, b, zin, V);
+    int base = 0;
+    for (int a0 = 0; a0 < V; a0 += kFinThreads) {
+      const int a = a0 + threadIdx.x;
+      const int isr = (a < V && b.ncount[a] >= c.min_pts && b.root[a] == a) ? 1 : 0;
+      int tot;
+      const int ex = block_excl_scan<kFinThreads>(isr, &tot);
+      if (isr) b.label[a] = base + ex;
+      base += tot;
+      __syncthreads();
     }
-    if (r == 0) {
-      b.ctrl->M = __popcll(heads);
-      if (mout) *mout = __popcll(heads);
-    }
-    return;
-  }
-  // exact fallback
-  uf_fallback<P>(c, b, zin, V);
-  // clusters = components ranked by their root (lowest core index); the
-  // cluster number of each root is parked in label[root] for k_label
-  int base = 0;
-  for (int a0 = 0; a0 < V; a0 += kFinThreads) {
-    const int a = a0 + threadIdx.x;
-    const int isr = (a < V && b.ncount[a] >= c.min_pts && b.root[a] == a) ? 1 : 0;
-    int tot;
-    const int ex = block_excl_scan<kFinThreads>(isr, &tot);
-    if (isr) b.label[a] = base + ex;
-    base += tot;
+    if (threadIdx.x == 0) s_M = base;
     __syncthreads();
   }
+  const int M = s_M;
   if (threadIdx.x == 0) {
-    b.ctrl->M = base;
-    if (mout) *mout = base;
+    b.ctrl->M = M;
+    if (mout) *mout = M;
   }
-}
-
-// final labels: core -> cluster of its tree / component; border -> cluster of
-// its lowest-index core neighbour; noise -> -1.  In the fallback, label[] of
-// a root holds its cluster number (written by k_tree_cc); a root's own thread
-// rewrites the same value, so every read of it is stable.
-__global__ __launch_bounds__(256) void k_label(Cfg c, Bufs b, const float* zin, int Vin,
-                                               int* lab_out, int* cnt_out) {
-  const int V = dbscan_V(b, zin, Vin);
-  const int a = blockIdx.x * 256 + threadIdx.x;
-  if (a >= V) return;
-  const bool overflow = b.ctrl->tree_overflow != 0;
-  const int R = b.ctrl->n_trees;
-  int x = -1;
-  if (b.ncount[a] >= c.min_pts) x = a;
-  else if (b.mcn[a] != kInt32Max) x = b.mcn[a];
-  int lab = -1;
-  if (x >= 0) {
-    const int r = b.root[x];
-    if (overflow) lab = b.label[r];
-    else lab = R == 1 ? 0 : b.tree_cluster[tree_id(b.rootmask, b.woff, r)];
+  // labels: core -> cluster of its tree (or component), border -> cluster of
+  // its lowest-index core neighbour, noise -> -1.  In the fallback the
+  // cluster number of a root sits in label[root] and is never overwritten
+  // (a root's own label is that same number).
+  for (int a0 = 0; a0 < V; a0 += kFinThreads) {
+    const int a = a0 + threadIdx.x;
+    if (a >= V) continue;
+    int lab = -1;
+    int x = -1;
+    const bool core = b.ncount[a] >= c.min_pts;
+    if (core) x = a;
+    else if (b.mcn[a] != kInt32Max) x = b.mcn[a];
+    if (x >= 0) {
+      const int r = b.root[x];
+      if (overflow) lab = b.label[r];
+      else lab = R == 1 ? 0 : s_tc[tree_id(b.rootmask, s_woff, r)];
+    }
+    if (!(overflow && core && b.root[a] == a)) b.label[a] = lab;
+    if (lab_out) lab_out[a] = lab;
+    if (cnt_out) cnt_out[a] = b.ncount[a];
   }
-  b.label[a] = lab;
-  if (lab_out) lab_out[a] = lab;
-  if (cnt_out) cnt_out[a] = b.ncount[a];
 }
 
 // ---------------------------------------------------------------------------
@@ -820,55 +815,56 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Cfg c, Bufs b, float* __
 // ---------------------------------------------------------------------------
 // launchers
 template <int P>
-static hipError_t launch_dbscan_p(const Cfg& c, const Bufs& b, const float* zin, int Vin, int ntile,
-                                  int* lab_out, int* cnt_out, int* mout, hipStream_t s) {
+static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const float* zin, int Vin,
+                            int ntile, int* lab_out, int* cnt_out, int* mout) {
   dim3 tiles(ntile, ntile), tb(kTile);
   const int nr = (ntile * kTile + 255) / 256;
-  hipLaunchKernelGGL(k_count<P>, tiles, tb, 0, s, c, b, zin, Vin);
-  hipLaunchKernelGGL(k_mcn<P>, tiles, tb, 0, s, c, b, zin, Vin);
-  hipLaunchKernelGGL(k_roots, dim3(nr), dim3(256), 0, s, c, b, zin, Vin);
-  hipLaunchKernelGGL(k_tree_adj<P>, tiles, tb, 0, s, c, b, zin, Vin, ntile);
-  hipLaunchKernelGGL(k_tree_cc<P>, dim3(1), dim3(kFinThreads), 0, s, c, b, zin, Vin, ntile, mout);
-  hipLaunchKernelGGL(k_label, dim3(nr), dim3(256), 0, s, c, b, zin, Vin, lab_out, cnt_out);
-  return hipGetLastError();
+  L(k_count<P>, tiles, tb, c, b, zin, Vin);
+  L(k_mcn<P>, tiles, tb, c, b, zin, Vin);
+  L(k_roots, dim3(nr), dim3(256), c, b, zin, Vin);
+  L(k_tree_adj<P>, tiles, tb, c, b, zin, Vin, ntile);
+  L(k_tree_cc<P>, dim3(1), dim3(kFinThreads), c, b, zin, Vin, ntile, mout, lab_out, cnt_out);
 }
 
-hipError_t launch_post_rollout(const Cfg& c, const Bufs& b, float* u_out, float* U_out, void* info,
-                               hipStream_t s) {
+// Everything between the rollouts and the final combination.
+void launch_post_rollout(Launcher& L, const Cfg& c, const Bufs& b) {
   const int nk = (c.K + 255) / 256;
-  hipError_t e;
+  int* none = nullptr;
   if (c.p == 2) {
-    hipLaunchKernelGGL(k_compact<2>, dim3(nk), dim3(256), 0, s, c, b);
-    e = launch_dbscan_p<2>(c, b, nullptr, 0, c.ntile, nullptr, nullptr, nullptr, s);
-    hipLaunchKernelGGL(k_stats<2>, dim3(64), dim3(256), 0, s, c, b);
+    L(k_compact<2>, dim3(nk), dim3(256), c, b);
+    launch_dbscan_p<2>(L, c, b, nullptr, 0, c.ntile, none, none, none);
+    L(k_stats<2>, dim3(64), dim3(256), c, b);
   } else {
-    hipLaunchKernelGGL(k_compact<3>, dim3(nk), dim3(256), 0, s, c, b);
-    e = launch_dbscan_p<3>(c, b, nullptr, 0, c.ntile, nullptr, nullptr, nullptr, s);
-    hipLaunchKernelGGL(k_stats<3>, dim3(64), dim3(256), 0, s, c, b);
+    L(k_compact<3>, dim3(nk), dim3(256), c, b);
+    launch_dbscan_p<3>(L, c, b, nullptr, 0, c.ntile, none, none, none);
+    L(k_stats<3>, dim3(64), dim3(256), c, b);
   }
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_update, dim3(c.nblk_upd), dim3(kUpdThreads), 0, s, c, b);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinThreads), 0, s, c, b, u_out, U_out, info);
-  return hipGetLastError();
+  L(k_update, dim3(c.nblk_upd), dim3(kUpdThreads), c, b);
 }
 
-hipError_t launch_stage_dbscan(const Cfg& c, const Bufs& b, const float* z, int V, int* ncount,
-                               int* label, int* mout, hipStream_t s) {
+void launch_finish(Launcher& L, const Cfg& c, const Bufs& b, float* u_out, float* U_out, void* info) {
+  L(k_finish, dim3(1), dim3(kFinThreads), c, b, u_out, U_out, info);
+}
+
+void launch_stage_dbscan(Launcher& L, const Cfg& c, const Bufs& b, const float* z, int V,
+                         int* ncount, int* label, int* mout) {
   // the stage runs on caller features: initialise the per-point arrays.  A
   // non-null feature pointer marks stage mode in the kernels.
   if (z == nullptr) z = b.z;
   if (V == 0) {
     // no points: only the cluster count (0) is produced
     if (c.p == 2)
-      hipLaunchKernelGGL(k_tree_cc<2>, dim3(1), dim3(kFinThreads), 0, s, c, b, z, 0, 1, mout);
+      L(k_tree_cc<2>, dim3(1), dim3(kFinThreads), c, b, z, 0, 1, mout, (int*)nullptr, (int*)nullptr);
     else
-      hipLaunchKernelGGL(k_tree_cc<3>, dim3(1), dim3(kFinThreads), 0, s, c, b, z, 0, 1, mout);
-    return hipGetLastError();
+      L(k_tree_cc<3>, dim3(1), dim3(kFinThreads), c, b, z, 0, 1, mout, (int*)nullptr, (int*)nullptr);
+    return;
   }
   const int ntile = (V + kTile - 1) / kTile;
-  hipLaunchKernelGGL(k_init_points, dim3((V + 255) / 256), dim3(256), 0, s, b, V);
-  if (c.p == 2) return launch_dbscan_p<2>(c, b, z, V, ntile, label, ncount, mout, s);
-  return launch_dbscan_p<3>(c, b, z, V, ntile, label, ncount, mout, s);
+  L(k_init_points, dim3((V + 255) / 256), dim3(256), b, V);
+  if (c.p == 2)
+    launch_dbscan_p<2>(L, c, b, z, V, ntile, label, ncount, mout);
+  else
+    launch_dbscan_p<3>(L, c, b, z, V, ntile, label, ncount, mout);
 }
 
 }  // namespace cemppi

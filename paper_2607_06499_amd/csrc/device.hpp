@@ -15,9 +15,11 @@ constexpr int kMaxSpheres = 16;
 constexpr int kMaxNM = kMaxHorizon * kMaxCtrl;
 constexpr int kWave = 64;
 
-// rollout kernel: 256 threads = 4 waves; a wave holds one rollout (64-lane
+// rollout kernel: 512 threads = 8 waves; a wave holds one rollout (64-lane
 // segment) or two (32-lane segments) when N + 1 <= 32.
-constexpr int kRollThreads = 256;
+constexpr int kRollThreads = 512;
+constexpr int kRollWaves = kRollThreads / 64;
+constexpr int kMaxRpb = 2 * kRollWaves;
 // per-block partial record of the rollout reduction (floats)
 constexpr int kPart = 12;
 enum PartField {
@@ -136,8 +138,11 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    // one 32x32 -> 64-bit product each (v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
     c1 = lo1;
@@ -164,32 +169,63 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& ga, 
   gb = r * s;
 }
 
-// Standard normals g[0..m) of step j of rollout k (elements j*m .. j*m+m-1 of
-// the flattened sequence; pair q uses words (0,1) or (2,3) of block q/2).
-__device__ __forceinline__ void step_gaussians(const Cfg& c, uint32_t step, int k, int j, float* g) {
-  const int q0 = (j * c.m) >> 1;
-  const int nq = c.m >> 1;
-  int cached = -1;
-  uint32_t w[4] = {0u, 0u, 0u, 0u};
-  for (int q = 0; q < nq; ++q) {
-    const int b = (q0 + q) >> 1;
-    if (b != cached) {
-      philox((uint32_t)b, (uint32_t)k, step, c.stream_id, c.seed_lo, c.seed_hi, w);
-      cached = b;
-    }
-    const int h = (q0 + q) & 1;
-    box_muller(w[2 * h], w[2 * h + 1], g[2 * q], g[2 * q + 1]);
-  }
+// Standard normals g[0..M) of step j of rollout k: elements j*M .. j*M+M-1 of
+// the flattened sequence; element pair q (elements 2q, 2q+1) is the
+// Box-Muller pair of words (0,1) of counter block q/2 when q is even and of
+// words (2,3) when q is odd.  Straight-line code for the two control sizes.
+template <int M>
+__device__ __forceinline__ void step_gaussians(const Cfg& c, uint32_t step, int k, int j, float* g);
+
+template <>
+__device__ __forceinline__ void step_gaussians<2>(const Cfg& c, uint32_t step, int k, int j, float* g) {
+  // pair q = j: block j/2, half j&1
+  uint32_t w[4];
+  philox((uint32_t)(j >> 1), (uint32_t)k, step, c.stream_id, c.seed_lo, c.seed_hi, w);
+  const bool odd = (j & 1) != 0;
+  box_muller(odd ? w[2] : w[0], odd ? w[3] : w[1], g[0], g[1]);
+}
+
+template <>
+__device__ __forceinline__ void step_gaussians<6>(const Cfg& c, uint32_t step, int k, int j, float* g) {
+  // pairs 3j, 3j+1, 3j+2 span blocks b0 = 3j/2 and b0 + 1
+  const int q0 = 3 * j;
+  const int b0 = q0 >> 1;
+  uint32_t w[4], v[4];
+  philox((uint32_t)b0, (uint32_t)k, step, c.stream_id, c.seed_lo, c.seed_hi, w);
+  philox((uint32_t)(b0 + 1), (uint32_t)k, step, c.stream_id, c.seed_lo, c.seed_hi, v);
+  // even q0: (b0,h0) (b0,h1) (b0+1,h0); odd q0: (b0,h1) (b0+1,h0) (b0+1,h1)
+  const bool ev = (q0 & 1) == 0;
+  box_muller(ev ? w[0] : w[2], ev ? w[1] : w[3], g[0], g[1]);
+  box_muller(ev ? w[2] : v[0], ev ? w[3] : v[1], g[2], g[3]);
+  box_muller(ev ? v[0] : v[2], ev ? v[1] : v[3], g[4], g[5]);
 }
 
 // ---------------------------------------------------------------------------
-// Segmented wave primitives (segments of SEG lanes; every lane participates).
+// Segmented wave primitives on DPP lane moves (segments of SEG = 32 or 64
+// lanes; every lane participates).  GFX9 DPP: row_shr:n shifts within a row
+// of 16 lanes, row_bcast:15 / row_bcast:31 feed a row's last lane into the
+// next row(s), wave_shr:1 shifts the whole wave by one lane.
+__device__ __forceinline__ float dpp_shr_row(float v, int n) {
+  // bound_ctrl: lanes whose source is outside the row read 0
+  switch (n) {
+    case 1: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
+    case 2: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));
+    case 4: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));
+    default: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));
+  }
+}
+
 template <int SEG>
-__device__ __forceinline__ float seg_incl_scan(float v, int j) {
-#pragma unroll
-  for (int d = 1; d < SEG; d <<= 1) {
-    const float t = __shfl_up(v, (unsigned)d, SEG);
-    if (j >= d) v += t;
+__device__ __forceinline__ float seg_incl_scan(float v, int /*j*/) {
+  v += dpp_shr_row(v, 1);
+  v += dpp_shr_row(v, 2);
+  v += dpp_shr_row(v, 4);
+  v += dpp_shr_row(v, 8);
+  // rows 1 and 3 add the total of rows 0 and 2
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));
+  if (SEG == 64) {
+    // rows 2 and 3 add the total of rows 0-1
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));
   }
   return v;
 }
@@ -197,16 +233,49 @@ __device__ __forceinline__ float seg_incl_scan(float v, int j) {
 template <int SEG>
 __device__ __forceinline__ float seg_excl_scan(float v, int j) {
   const float inc = seg_incl_scan<SEG>(v, j);
-  const float t = __shfl_up(inc, 1u, SEG);
+  const float t = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(inc), 0x138, 0xf, 0xf, true));
   return j == 0 ? 0.0f : t;
 }
 
-// butterfly sum: every lane of the segment ends with the bitwise same value
+// value of lane `src` of this lane's segment (src < SEG, uniform across the
+// wave); for SEG == 32 the two segments read their own lane
+template <int SEG>
+__device__ __forceinline__ float seg_bcast(float v, int src) {
+  // readlane takes a wave-uniform lane index
+  if (SEG == 64) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src + 32));
+  return (__lane_id() < 32) ? a : b;
+}
+template <int SEG>
+__device__ __forceinline__ int seg_bcast_i(int v, int src) {
+  if (SEG == 64) return __builtin_amdgcn_readlane(v, src);
+  const int a = __builtin_amdgcn_readlane(v, src);
+  const int b = __builtin_amdgcn_readlane(v, src + 32);
+  return (__lane_id() < 32) ? a : b;
+}
+
+// value of lane src0 (segment 0) / src1 (segment 1), both wave-uniform
+template <int SEG>
+__device__ __forceinline__ float seg_pick(float v, int src0, int src1) {
+  if (SEG == 64) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src0));
+  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src0));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + src1));
+  return (__lane_id() < 32) ? a : b;
+}
+template <int SEG>
+__device__ __forceinline__ int seg_pick_i(int v, int src0, int src1) {
+  if (SEG == 64) return __builtin_amdgcn_readlane(v, src0);
+  const int a = __builtin_amdgcn_readlane(v, src0);
+  const int b = __builtin_amdgcn_readlane(v, 32 + src1);
+  return (__lane_id() < 32) ? a : b;
+}
+
+// segment sum = last lane of the inclusive scan (fixed order: every lane of
+// the segment receives the bitwise same value)
 template <int SEG>
 __device__ __forceinline__ float seg_sum(float v) {
-#pragma unroll
-  for (int d = SEG >> 1; d > 0; d >>= 1) v += __shfl_xor(v, d, SEG);
-  return v;
+  return seg_bcast<SEG>(seg_incl_scan<SEG>(v, 0), SEG - 1);
 }
 
 __device__ __forceinline__ float sq(float x) { return x * x; }

@@ -11,13 +11,15 @@
 // test and (arm) forward kinematics.  The serial N-step recursion of Eq. (4)
 // thus becomes log2(N) shuffle steps and all work of a step runs in parallel.
 #include "device.hpp"
+#include "launch.hpp"
 
 namespace cemppi {
 
 // ---------------------------------------------------------------------------
 // shared prologue: obstacles into LDS, finiteness, closest obstacle o*.
 struct ObsLds {
-  float x[kMaxObs], y[kMaxObs], z[kMaxObs], r[kMaxObs], R2[kMaxObs];
+  float4 o[kMaxObs];  // (x, y, z, R^2) with R = robot/sphere radius + obstacle radius
+  float r[kMaxObs];   // obstacle radius
 };
 
 // Arm forward kinematics: origins P0..P6 of the standard DH chain
@@ -58,15 +60,26 @@ __device__ __forceinline__ void arm_origins(const Cfg& c, const float* q, float 
 
 __device__ __forceinline__ void sphere_centre(const Cfg& c, const float P[7][3], int s, float& x,
                                               float& y, float& zz) {
-  // seg and t are compile-time-unknown: select the segment end points
+  // the segment of sphere s is a kernel argument, so this switch is a
+  // wave-uniform (scalar) branch
   const int sg = c.sph_seg[s];
-  float ax = 0.f, ay = 0.f, az = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    if (i == sg) {
-      ax = P[i][0]; ay = P[i][1]; az = P[i][2];
-      bx = P[i + 1][0]; by = P[i + 1][1]; bz = P[i + 1][2];
-    }
+  float ax, ay, az, bx, by, bz;
+  switch (sg) {
+#define CEMPPI_SEG(i)                                     \
+  case i:                                                 \
+    ax = P[i][0]; ay = P[i][1]; az = P[i][2];             \
+    bx = P[i + 1][0]; by = P[i + 1][1]; bz = P[i + 1][2]; \
+    break;
+    CEMPPI_SEG(0)
+    CEMPPI_SEG(1)
+    CEMPPI_SEG(2)
+    CEMPPI_SEG(3)
+    CEMPPI_SEG(4)
+    default:
+      ax = P[5][0]; ay = P[5][1]; az = P[5][2];
+      bx = P[6][0]; by = P[6][1]; bz = P[6][2];
+      break;
+#undef CEMPPI_SEG
   }
   const float t = c.sph_t[s];
   x = ax + t * (bx - ax);
@@ -99,12 +112,9 @@ __device__ void prologue(const Cfg& c, const float* __restrict__ x_t, const floa
     float ok = 1.f;
     for (int i = 0; i <= P; ++i) ok = isfinite(o[i]) ? ok : 0.f;
     if (ok == 0.f) atomicOr(&s_bad, 1);
-    L.x[tid] = o[0];
-    L.y[tid] = o[1];
-    L.z[tid] = DYN == 0 ? 0.f : o[2];
-    L.r[tid] = o[P];
     const float R = (DYN == 0 ? c.robot_r : c.rs) + o[P];
-    L.R2[tid] = R * R;
+    L.o[tid] = make_float4(o[0], o[1], DYN == 0 ? 0.f : o[2], R * R);
+    L.r[tid] = o[P];
   }
   if (tid < c.n && !isfinite(x_t[tid])) atomicOr(&s_bad, 1);
   __syncthreads();
@@ -119,7 +129,7 @@ __device__ void prologue(const Cfg& c, const float* __restrict__ x_t, const floa
         s_p0[2] = 0.f;
       }
       if (tid < n_obs) {
-        cl = sqrtf(dist2_2(x0, y0, L.x[tid], L.y[tid])) - L.r[tid];
+        cl = sqrtf(dist2_2(x0, y0, L.o[tid].x, L.o[tid].y)) - L.r[tid];
         idx = tid;
       }
     } else {
@@ -135,7 +145,7 @@ __device__ void prologue(const Cfg& c, const float* __restrict__ x_t, const floa
         for (int s = 0; s < c.ns; ++s) {
           float sx, sy, sz;
           sphere_centre(c, Pm, s, sx, sy, sz);
-          const float v = sqrtf(dist2_3(sx, sy, sz, L.x[tid], L.y[tid], L.z[tid])) - L.r[tid];
+          const float v = sqrtf(dist2_3(sx, sy, sz, L.o[tid].x, L.o[tid].y, L.o[tid].z)) - L.r[tid];
           cl = v < cl ? v : cl;
         }
         idx = tid;
@@ -237,7 +247,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
-  __shared__ float s_rec[8][kPart];
+  __shared__ float s_rec[kMaxRpb][kPart];
   prologue<0>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
@@ -247,7 +257,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int j = lane & (SEG - 1), sgi = lane / SEG;
   const int kloc = wave * SPW + sgi;
-  const int k = blockIdx.x * (4 * SPW) + kloc;
+  const int k = blockIdx.x * (kRollWaves * SPW) + kloc;
   const int N = c.N;
   const bool act = (k < c.K) && !bad;
   const float dt = c.dt;
@@ -257,7 +267,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b
   float uv = 0.f, uw = 0.f;
   if (act && j < N) {
     float g[2];
-    step_gaussians(c, step, k, j, g);
+    step_gaussians<2>(c, step, k, j, g);
     const float e0 = c.L[0] * g[0];
     const float e1 = c.L[2] * g[0] + c.L[3] * g[1];
     const float n0 = b.U[j * 2], n1 = b.U[j * 2 + 1];
@@ -272,7 +282,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b
   // forward simulation, Eq. (4)/(21): heading and position are prefix sums
   const float th = th0 + seg_excl_scan<SEG>(uw * dt, j);
   float sn, cs;
-  sincosf(th, &sn, &cs);
+  __sincosf(th, &sn, &cs);
   const float px = x0 + seg_excl_scan<SEG>(uv * cs * dt, j);
   const float py = y0 + seg_excl_scan<SEG>(uv * sn * dt, j);
 
@@ -287,21 +297,34 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b
   const float S = seg_sum<SEG>(l);
 
   // collision of states 1..N against the frozen obstacles: lowest index hit
-  int hit = kInt32Max;
-  if (act && j >= 1 && j <= N) {
+  // pass 1: does this state touch any obstacle?  pass 2 (only in waves with
+  // a contact): the lowest obstacle index touched
+  const bool chk = act && j >= 1 && j <= N;
+  bool any = false;
+  if (chk) {
     for (int i = 0; i < n_obs; ++i) {
-      const bool h = dist2_2(px, py, L.x[i], L.y[i]) <= L.R2[i];
-      hit = (h && hit == kInt32Max) ? i : hit;
+      const float4 o = L.o[i];
+      any |= dist2_2(px, py, o.x, o.y) <= o.w;
     }
   }
-  const unsigned long long segmask = SEG == 64 ? ~0ull : (0xffffffffull << (sgi * 32));
-  const unsigned long long hm = __ballot(hit != kInt32Max) & segmask;
-  const int col = hm != 0ull;
-  const int fl = col ? __ffsll((long long)hm) - 1 : lane;
-  const int f = __shfl(hit, fl, kWave);
-  const float pfx = __shfl(px, fl, kWave), pfy = __shfl(py, fl, kWave);
-  const int ln = sgi * SEG + (N < SEG ? N : SEG - 1);
-  const float ptx = __shfl(px, ln, kWave), pty = __shfl(py, ln, kWave);
+  int hit = kInt32Max;
+  if (__ballot(any) != 0ull && any) {
+    for (int i = n_obs - 1; i >= 0; --i) {
+      const float4 o = L.o[i];
+      hit = dist2_2(px, py, o.x, o.y) <= o.w ? i : hit;
+    }
+  }
+  // first colliding state of each segment (lowest lane with a hit)
+  const unsigned long long hm = __ballot(hit != kInt32Max);
+  const unsigned long long m0 = SEG == 64 ? hm : (hm & 0xffffffffull);
+  const unsigned long long m1 = SEG == 64 ? 0ull : (hm >> 32);
+  const int f0 = m0 ? __ffsll((long long)m0) - 1 : 0;
+  const int f1 = m1 ? __ffsll((long long)m1) - 1 : 0;
+  const int col = (sgi == 0 ? m0 : m1) != 0ull;
+  const int f = seg_pick_i<SEG>(hit, f0, f1);
+  const float pfx = seg_pick<SEG>(px, f0, f1), pfy = seg_pick<SEG>(py, f0, f1);
+  const int ln = N < SEG ? N : SEG - 1;
+  const float ptx = seg_bcast<SEG>(px, ln), pty = seg_bcast<SEG>(py, ln);
 
   float src[2];
   src[0] = c.ref_mode == 1 ? pfx : ptx;
@@ -323,7 +346,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b
     }
     rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 2);
   }
-  write_block_partial(b, s_rec, 4 * SPW);
+  write_block_partial(b, s_rec, kRollWaves * SPW);
 }
 
 // ---------------------------------------------------------------------------
@@ -338,7 +361,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b,
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
-  __shared__ float s_rec[8][kPart];
+  __shared__ float s_rec[kMaxRpb][kPart];
   prologue<1>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
@@ -347,7 +370,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b,
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int j = lane;
   const int kloc = wave;
-  const int k = blockIdx.x * 4 + kloc;
+  const int k = blockIdx.x * kRollWaves + kloc;
   const int N = c.N;
   const bool act = (k < c.K) && !bad;
   const float dt = c.dt;
@@ -357,7 +380,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b,
   for (int i = 0; i < 6; ++i) u[i] = 0.f;
   if (act && j < N) {
     float g[6];
-    step_gaussians(c, step, k, j, g);
+    step_gaussians<6>(c, step, k, j, g);
     float a[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -393,24 +416,40 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b,
   }
   const float S = seg_sum<SEG>(l);
 
-  int hit = kInt32Max;
-  if (act && j >= 1 && j <= N) {
+  // pass 1: any contact of any link sphere; pass 2 (waves with a contact):
+  // the lowest obstacle index touched
+  const bool chk = act && j >= 1 && j <= N;
+  bool any = false;
+  if (chk) {
     for (int s = 0; s < c.ns; ++s) {
       float sx, sy, sz;
       sphere_centre(c, P, s, sx, sy, sz);
       for (int i = 0; i < n_obs; ++i) {
-        const bool h = dist2_3(sx, sy, sz, L.x[i], L.y[i], L.z[i]) <= L.R2[i];
-        hit = (h && i < hit) ? i : hit;
+        const float4 o = L.o[i];
+        any |= dist2_3(sx, sy, sz, o.x, o.y, o.z) <= o.w;
       }
+    }
+  }
+  int hit = kInt32Max;
+  if (__ballot(any) != 0ull && any) {
+    for (int s = 0; s < c.ns; ++s) {
+      float sx, sy, sz;
+      sphere_centre(c, P, s, sx, sy, sz);
+      int hs = kInt32Max;
+      for (int i = n_obs - 1; i >= 0; --i) {
+        const float4 o = L.o[i];
+        hs = dist2_3(sx, sy, sz, o.x, o.y, o.z) <= o.w ? i : hs;
+      }
+      hit = hs < hit ? hs : hit;
     }
   }
   const unsigned long long hm = __ballot(hit != kInt32Max);
   const int col = hm != 0ull;
-  const int fl = col ? __ffsll((long long)hm) - 1 : lane;
-  const int f = __shfl(hit, fl, kWave);
-  const float pfx = __shfl(ex, fl, kWave), pfy = __shfl(ey, fl, kWave), pfz = __shfl(ez, fl, kWave);
+  const int fl = col ? __ffsll((long long)hm) - 1 : 0;
+  const int f = __builtin_amdgcn_readlane(hit, fl);
+  const float pfx = seg_bcast<64>(ex, fl), pfy = seg_bcast<64>(ey, fl), pfz = seg_bcast<64>(ez, fl);
   const int ln = N;
-  const float ptx = __shfl(ex, ln, kWave), pty = __shfl(ey, ln, kWave), ptz = __shfl(ez, ln, kWave);
+  const float ptx = seg_bcast<64>(ex, ln), pty = seg_bcast<64>(ey, ln), ptz = seg_bcast<64>(ez, ln);
 
   float src[3];
   src[0] = c.ref_mode == 1 ? pfx : ptx;
@@ -435,7 +474,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b,
     }
     rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 3);
   }
-  write_block_partial(b, s_rec, 4);
+  write_block_partial(b, s_rec, kRollWaves);
 }
 
 // ---------------------------------------------------------------------------
@@ -449,7 +488,7 @@ __global__ __launch_bounds__(kRollThreads) void k_reduce_records(Cfg c, Bufs b,
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
-  __shared__ float s_rec[8][kPart];
+  __shared__ float s_rec[kMaxRpb][kPart];
   prologue<DYN>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
@@ -505,36 +544,31 @@ __global__ void k_stage_noise(Cfg c, uint32_t step, uint32_t* __restrict__ words
 
 // ---------------------------------------------------------------------------
 // host-side launchers
-hipError_t launch_rollout(const Cfg& c, const Bufs& b, const float* x_t, const float* obs, int n_obs,
-                          hipStream_t s) {
+void launch_rollout(Launcher& L, const Cfg& c, const Bufs& b, const float* x_t, const float* obs,
+                    int n_obs) {
   dim3 grid(c.nblk_roll), block(kRollThreads);
   if (c.dyn == 0) {
     if (c.seg == 32)
-      hipLaunchKernelGGL(k_rollout_unicycle<32>, grid, block, 0, s, c, b, x_t, obs, n_obs);
+      L(k_rollout_unicycle<32>, grid, block, c, b, x_t, obs, n_obs);
     else
-      hipLaunchKernelGGL(k_rollout_unicycle<64>, grid, block, 0, s, c, b, x_t, obs, n_obs);
+      L(k_rollout_unicycle<64>, grid, block, c, b, x_t, obs, n_obs);
   } else {
-    hipLaunchKernelGGL(k_rollout_arm, grid, block, 0, s, c, b, x_t, obs, n_obs);
+    L(k_rollout_arm, grid, block, c, b, x_t, obs, n_obs);
   }
-  return hipGetLastError();
 }
 
-hipError_t launch_reduce_records(const Cfg& c, const Bufs& b, const float* x_t, const float* obs,
-                                 int n_obs, hipStream_t s) {
+void launch_reduce_records(Launcher& L, const Cfg& c, const Bufs& b, const float* x_t,
+                           const float* obs, int n_obs) {
   dim3 grid(c.nblk_roll), block(kRollThreads);
   if (c.dyn == 0)
-    hipLaunchKernelGGL(k_reduce_records<0>, grid, block, 0, s, c, b, x_t, obs, n_obs);
+    L(k_reduce_records<0>, grid, block, c, b, x_t, obs, n_obs);
   else
-    hipLaunchKernelGGL(k_reduce_records<1>, grid, block, 0, s, c, b, x_t, obs, n_obs);
-  return hipGetLastError();
+    L(k_reduce_records<1>, grid, block, c, b, x_t, obs, n_obs);
 }
 
-hipError_t launch_stage_noise(const Cfg& c, uint32_t step, uint32_t* words, float* gauss,
-                              hipStream_t s) {
+void launch_stage_noise(Launcher& L, const Cfg& c, uint32_t step, uint32_t* words, float* gauss) {
   const int total = c.K * c.B;
-  dim3 grid((total + 255) / 256), block(256);
-  hipLaunchKernelGGL(k_stage_noise, grid, block, 0, s, c, step, words, gauss);
-  return hipGetLastError();
+  L(k_stage_noise, dim3((total + 255) / 256), dim3(256), c, step, words, gauss);
 }
 
 }  // namespace cemppi
