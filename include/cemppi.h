@@ -198,7 +198,9 @@ enum {
   CE_DBG_CLUSTER_COST = 11, /* float [M]         mean cost per cluster             */
   CE_DBG_CLUSTER_DIR = 12,  /* float [M][p]      normalised mean direction Eq.(16) */
   CE_DBG_CLUSTER_SIZE = 13, /* int32 [M]                                           */
-  CE_DBG_COUNT_ = 14
+  CE_DBG_TREES = 14,        /* int32 [2]  hook-forest trees, 1 if the exact         */
+                            /*            union-find fallback ran (> 64 trees)      */
+  CE_DBG_COUNT_ = 15
 };
 /* Copy the named buffer into device memory dst of `bytes` bytes (at most the
  * buffer's full capacity is copied; rows beyond |V| or M are unspecified). */

@@ -25,7 +25,7 @@ STATUS_FALLBACK, STATUS_ALL_COLLIDE, STATUS_NO_CLUSTER, STATUS_DYN_STATIC, STATU
     1, 2, 4, 8, 16)
 LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
 (DBG_COST, DBG_COLLIDE, DBG_FIRST_OBS, DBG_P_TERM, DBG_P_FIRST, DBG_EPS, DBG_V_IDX, DBG_Z, DBG_G,
- DBG_NCOUNT, DBG_LABEL, DBG_CLUSTER_COST, DBG_CLUSTER_DIR, DBG_CLUSTER_SIZE) = range(14)
+ DBG_NCOUNT, DBG_LABEL, DBG_CLUSTER_COST, DBG_CLUSTER_DIR, DBG_CLUSTER_SIZE, DBG_TREES) = range(15)
 
 
 class CeMppiConfig(C.Structure):
@@ -371,7 +371,7 @@ class Planner:
 
         if dtype is None:
             dtype = torch.int32 if which in (DBG_COLLIDE, DBG_FIRST_OBS, DBG_V_IDX, DBG_NCOUNT,
-                                             DBG_LABEL, DBG_CLUSTER_SIZE) else torch.float32
+                                             DBG_LABEL, DBG_CLUSTER_SIZE, DBG_TREES) else torch.float32
         shape = (count,) if cols is None else (count, cols)
         out = torch.zeros(shape if count else (1,), dtype=dtype, device=self.device)
         nbytes = out.numel() * out.element_size() if count else 0

@@ -304,7 +304,7 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_nc = cv.take<int>(K), o_mcn = cv.take<int>(K), o_root = cv.take<int>(K);
   const size_t o_rid = cv.take<int>(K), o_lab = cv.take<int>(K);
   const size_t o_rm = cv.take<unsigned long long>(nw), o_woff = cv.take<int>(nw);
-  const size_t o_tslot = cv.take<unsigned long long>((size_t)c.ntile * c.ntile * kMaxTrees);
+  const size_t o_tslot = cv.take<unsigned long long>((size_t)c.ntile * ((c.ntile + kColGroup - 1) / kColGroup) * kMaxTrees);
   const size_t o_tcl = cv.take<int>(kMaxTrees), o_troot = cv.take<int>(kMaxTrees);
   const size_t o_ccost = cv.take<float>((size_t)c.mcap), o_cdir = cv.take<float>((size_t)c.mcap * 4);
   const size_t o_csize = cv.take<int>((size_t)c.mcap), o_csmin = cv.take<float>((size_t)c.mcap);
@@ -751,6 +751,7 @@ ce_status ce_mppi_debug_get(const ce_mppi_planner* P, int32_t which, void* dst, 
     case CE_DBG_CLUSTER_COST: src = b.c_cost; cap = (size_t)c.mcap * 4; break;
     case CE_DBG_CLUSTER_DIR: src = b.c_dir; cap = (size_t)c.mcap * p * 4; rows = c.mcap; src_pitch = 16; break;
     case CE_DBG_CLUSTER_SIZE: src = b.c_size; cap = (size_t)c.mcap * 4; break;
+    case CE_DBG_TREES: src = &b.ctrl->n_trees; cap = 8; break;
     default: return fail(CE_EINVAL, "unknown debug buffer");
   }
   const size_t n = bytes < cap ? bytes : cap;

@@ -189,55 +189,90 @@ __device__ __forceinline__ int dbscan_V(const Bufs& b, const float* zin, int Vin
   return zin ? Vin : (b.ctrl->branch == 0 ? b.ctrl->n_feas : 0);
 }
 
-// ---------------------------------------------------------------------------
-// 1. neighbour counts: block (I, J) counts, for each row point of tile I, its
-// neighbours among the column points of tile J (closed ball, itself included).
+// Tiled passes: block (g, I) takes row tile I against the column tiles
+// g*kColGroup .. g*kColGroup + kColGroup - 1 (clipped to the tiles in use),
+// the row point in registers and each column tile staged through LDS.
+__device__ __forceinline__ int ntiles_of(int V) { return (V + kTile - 1) / kTile; }
+
+// 1. neighbour counts: for each row point, its neighbours among the block's
+// column points (closed ball, itself included).
 template <int P>
 __global__ __launch_bounds__(kTile) void k_count(Cfg c, Bufs b, const float* __restrict__ zin,
                                                  int Vin) {
   using ZT = typename ZVec<P>::T;
   __shared__ ZT s_z[kTile];
   const int V = dbscan_V(b, zin, Vin);
-  const int I = blockIdx.y, J = blockIdx.x;
-  if (I * kTile >= V || J * kTile >= V) return;
+  const int nt = ntiles_of(V);
+  const int I = blockIdx.y, J0 = blockIdx.x * kColGroup;
+  if (I >= nt || J0 >= nt) return;
+  const int J1 = min(J0 + kColGroup, nt);
   const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
-  const int l = J * kTile + threadIdx.x;
-  s_z[threadIdx.x] = l < V ? z[l] : ZVec<P>::far();
   const int k = I * kTile + threadIdx.x;
   const ZT zk = k < V ? z[k] : ZVec<P>::far();
-  __syncthreads();
+  ZT zl[kColGroup];
+#pragma unroll
+  for (int u = 0; u < kColGroup; ++u) {
+    const int l = (J0 + u) * kTile + threadIdx.x;
+    zl[u] = (J0 + u < J1 && l < V) ? z[l] : ZVec<P>::far();
+  }
   const float r2 = c.eps2;
-  const int ncol = min(kTile, V - J * kTile);
   int cnt = 0;
-  for (int t = 0; t < ncol; ++t) cnt += ZVec<P>::d2(zk, s_z[t]) <= r2 ? 1 : 0;
+#pragma unroll
+  for (int u = 0; u < kColGroup; ++u) {
+    const int J = J0 + u;
+    if (J >= J1) break;
+    __syncthreads();
+    s_z[threadIdx.x] = zl[u];
+    __syncthreads();
+    const int ncol = min(kTile, V - J * kTile);
+    for (int t = 0; t < ncol; ++t) cnt += ZVec<P>::d2(zk, s_z[t]) <= r2 ? 1 : 0;
+  }
   if (k < V && cnt) atomicAdd(&b.ncount[k], cnt);
 }
 
 // 2. lowest-index core neighbour of every point (core points include
-// themselves).
+// themselves).  Column tiles are visited in increasing order, so the first
+// hit of a row is its minimum within the block.
 template <int P>
 __global__ __launch_bounds__(kTile) void k_mcn(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
   __shared__ ZT s_z[kTile];
   const int V = dbscan_V(b, zin, Vin);
-  const int I = blockIdx.y, J = blockIdx.x;
-  if (I * kTile >= V || J * kTile >= V) return;
+  const int nt = ntiles_of(V);
+  const int I = blockIdx.y, J0 = blockIdx.x * kColGroup;
+  if (I >= nt || J0 >= nt) return;
+  const int J1 = min(J0 + kColGroup, nt);
   const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
-  const int l = J * kTile + threadIdx.x;
-  // non-core columns are parked far away: they can never be a neighbour here
-  s_z[threadIdx.x] = (l < V && b.ncount[l] >= c.min_pts) ? z[l] : ZVec<P>::far();
   const int k = I * kTile + threadIdx.x;
   const ZT zk = k < V ? z[k] : ZVec<P>::far();
-  __syncthreads();
-  if (k >= V) return;
-  const float r2 = c.eps2;
-  const int ncol = min(kTile, V - J * kTile);
-  int m = kInt32Max;
-  for (int t = 0; t < ncol; ++t) {
-    const bool h = ZVec<P>::d2(zk, s_z[t]) <= r2;
-    m = (h && m == kInt32Max) ? J * kTile + t : m;
+  ZT zl[kColGroup];
+  int ncl[kColGroup];
+#pragma unroll
+  for (int u = 0; u < kColGroup; ++u) {
+    const int l = (J0 + u) * kTile + threadIdx.x;
+    const bool ok = J0 + u < J1 && l < V;
+    zl[u] = ok ? z[l] : ZVec<P>::far();
+    ncl[u] = ok ? b.ncount[l] : 0;
   }
-  if (m != kInt32Max) atomicMin(&b.mcn[k], m);
+  const float r2 = c.eps2;
+  int m = kInt32Max;
+#pragma unroll
+  for (int u = 0; u < kColGroup; ++u) {
+    const int J = J0 + u;
+    if (J >= J1) break;
+    __syncthreads();
+    // non-core columns are parked far away: they can never be a neighbour here
+    s_z[threadIdx.x] = ncl[u] >= c.min_pts ? zl[u] : ZVec<P>::far();
+    __syncthreads();
+    if (m == kInt32Max) {
+      const int ncol = min(kTile, V - J * kTile);
+      for (int t = 0; t < ncol; ++t) {
+        const bool h = ZVec<P>::d2(zk, s_z[t]) <= r2;
+        m = (h && m == kInt32Max) ? J * kTile + t : m;
+      }
+    }
+  }
+  if (k < V && m != kInt32Max) atomicMin(&b.mcn[k], m);
 }
 
 // 3. roots: follow the hook chain of each core point (indices decrease, so the
@@ -266,73 +301,112 @@ __global__ __launch_bounds__(256) void k_roots(Cfg c, Bufs b, const float* zin, 
 }
 
 // Tree numbering: exclusive prefix of root counts over the root-flag words,
-// computed by each block that needs it into LDS; returns the number of trees.
+// computed by each block that needs it into LDS (the flag words are kept in
+// LDS too); returns the number of trees.
 template <int NT>
-__device__ int tree_prefix(const Bufs& b, int V, int* s_woff) {
+__device__ int tree_prefix(const Bufs& b, int V, int* s_woff, unsigned long long* s_rm) {
   const int nwords = (V + 63) >> 6;
   const int per = (nwords + NT - 1) / NT;
   const int lo = min((int)threadIdx.x * per, nwords), hi = min(lo + per, nwords);
   int mine = 0;
-  for (int i = lo; i < hi; ++i) mine += __popcll(b.rootmask[i]);
+  for (int i = lo; i < hi; ++i) {
+    const unsigned long long m = b.rootmask[i];
+    s_rm[i] = m;
+    mine += __popcll(m);
+  }
   int tot;
   int off = block_excl_scan<NT>(mine, &tot);
   for (int i = lo; i < hi; ++i) {
     s_woff[i] = off;
-    off += __popcll(b.rootmask[i]);
+    off += __popcll(s_rm[i]);
   }
   __syncthreads();
   return tot;
 }
 
-__device__ __forceinline__ int tree_id(const unsigned long long* rootmask, const int* woff, int r) {
+__device__ __forceinline__ int tree_id(const unsigned long long* s_rm, const int* s_woff, int r) {
   const int w = r >> 6, bit = r & 63;
-  const unsigned long long below = bit ? (rootmask[w] & ((1ull << bit) - 1ull)) : 0ull;
-  return woff[w] + __popcll(below);
+  const unsigned long long below = bit ? (s_rm[w] & ((1ull << bit) - 1ull)) : 0ull;
+  return s_woff[w] + __popcll(below);
 }
 
 constexpr int kMaxWords = (65536 + 63) / 64;
 
-// 4. tree adjacency: for every core-core neighbour pair (row k, column l) of
-// different trees set bit tree(l) in the row of tree(k); the tile's rows go
-// to its own slot (no cross-block atomics).
+// 4. tree adjacency over the upper triangle of tiles (J >= I; the closure
+// makes the relation symmetric): for every core-core neighbour pair (row k,
+// column l) of different trees set bit tree(l) in the row of tree(k).  Block
+// (g, I) writes the rows it saw to its own slot (no cross-block atomics).
+__device__ __forceinline__ bool adj_block_live(int I, int g, int nt) {
+  const int J0 = g * kColGroup;
+  return I < nt && J0 < nt && J0 + kColGroup > I;
+}
+
 template <int P>
 __global__ __launch_bounds__(kTile) void k_tree_adj(Cfg c, Bufs b, const float* __restrict__ zin,
-                                                    int Vin, int ntile) {
+                                                    int Vin, int ngrp) {
   using ZT = typename ZVec<P>::T;
   __shared__ ZT s_z[kTile];
-  __shared__ int s_t[kTile];
+  __shared__ uint2 s_bit[kTile];  // tree bit of the column point as two words, 0 if not core
   __shared__ int s_woff[kMaxWords];
+  __shared__ unsigned long long s_rm[kMaxWords];
   __shared__ unsigned long long s_adj[kMaxTrees];
   const int V = dbscan_V(b, zin, Vin);
-  const int I = blockIdx.y, J = blockIdx.x;
-  if (I * kTile >= V || J * kTile >= V) return;
-  const int R = tree_prefix<kTile>(b, V, s_woff);
+  const int nt = ntiles_of(V);
+  const int I = blockIdx.y, g = blockIdx.x;
+  if (!adj_block_live(I, g, nt)) return;
+  const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
+  const int J0 = max(g * kColGroup, I), J1 = min(g * kColGroup + kColGroup, nt);
+  // every operand of the block is requested before the first wait
+  const int k = I * kTile + threadIdx.x;
+  const int nck = k < V ? b.ncount[k] : 0;
+  const int rk = k < V ? b.root[k] : -1;
+  const ZT zk0 = k < V ? z[k] : ZVec<P>::far();
+  int ncl[kColGroup], rl[kColGroup];
+  ZT zl[kColGroup];
+#pragma unroll
+  for (int u = 0; u < kColGroup; ++u) {
+    const int l = (J0 + u) * kTile + threadIdx.x;
+    const bool ok = J0 + u < J1 && l < V;
+    ncl[u] = ok ? b.ncount[l] : 0;
+    rl[u] = ok ? b.root[l] : -1;
+    zl[u] = ok ? z[l] : ZVec<P>::far();
+  }
+  const int R = tree_prefix<kTile>(b, V, s_woff, s_rm);
   if (R < 2 || R > kMaxTrees) return;
   if (threadIdx.x < kMaxTrees) s_adj[threadIdx.x] = 0ull;
-  const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
-  const int l = J * kTile + threadIdx.x;
-  int tl = -1;
-  if (l < V && b.ncount[l] >= c.min_pts) tl = tree_id(b.rootmask, s_woff, b.root[l]);
-  s_z[threadIdx.x] = tl >= 0 ? z[l] : ZVec<P>::far();
-  s_t[threadIdx.x] = tl >= 0 ? tl : 0;
-  const int k = I * kTile + threadIdx.x;
-  int tk = -1;
-  if (k < V && b.ncount[k] >= c.min_pts) tk = tree_id(b.rootmask, s_woff, b.root[k]);
-  const ZT zk = tk >= 0 ? z[k] : ZVec<P>::far();
-  __syncthreads();
-  if (tk >= 0) {
-    const float r2 = c.eps2;
-    const int ncol = min(kTile, V - J * kTile);
-    unsigned long long mask = 0ull;
-    for (int t = 0; t < ncol; ++t) {
-      const bool h = ZVec<P>::d2(zk, s_z[t]) <= r2;
-      mask |= h ? (1ull << s_t[t]) : 0ull;
+  const int tk = nck >= c.min_pts ? tree_id(s_rm, s_woff, rk) : -1;
+  const ZT zk = tk >= 0 ? zk0 : ZVec<P>::far();
+  const float r2 = c.eps2;
+  uint32_t mlo = 0u, mhi = 0u;
+#pragma unroll
+  for (int u = 0; u < kColGroup; ++u) {
+    const int J = J0 + u;
+    if (J >= J1) break;
+    const int tl = ncl[u] >= c.min_pts ? tree_id(s_rm, s_woff, rl[u]) : -1;
+    __syncthreads();
+    s_z[threadIdx.x] = tl >= 0 ? zl[u] : ZVec<P>::far();
+    s_bit[threadIdx.x] = tl < 0 ? make_uint2(0u, 0u)
+                                : (tl < 32 ? make_uint2(1u << tl, 0u) : make_uint2(0u, 1u << (tl - 32)));
+    __syncthreads();
+    if (tk >= 0) {
+      // branch-free: both LDS words are read for every column
+      const int ncol = min(kTile, V - J * kTile);
+#pragma unroll 8
+      for (int t = 0; t < ncol; ++t) {
+        const uint2 bt = s_bit[t];
+        const uint32_t h = ZVec<P>::d2(zk, s_z[t]) <= r2 ? 0xffffffffu : 0u;
+        mlo |= bt.x & h;
+        mhi |= bt.y & h;
+      }
     }
+  }
+  if (tk >= 0) {
+    unsigned long long mask = ((unsigned long long)mhi << 32) | mlo;
     mask &= ~(1ull << tk);
     if (mask) atomicOr(&s_adj[tk], mask);
   }
   __syncthreads();
-  if (threadIdx.x < R) b.tslot[((size_t)I * ntile + J) * kMaxTrees + threadIdx.x] = s_adj[threadIdx.x];
+  if (threadIdx.x < R) b.tslot[((size_t)I * ngrp + g) * kMaxTrees + threadIdx.x] = s_adj[threadIdx.x];
 }
 
 // 5. connected components of the tree graph and canonical cluster numbers
@@ -387,15 +461,16 @@ __device__ void uf_fallback(const Cfg& c, const Bufs& b, const float* zin, int V
 
 template <int P>
 __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const float* __restrict__ zin,
-                                                         int Vin, int ntile, int* mout, int* lab_out,
+                                                         int Vin, int ngrp, int* mout, int* lab_out,
                                                          int* cnt_out) {
   __shared__ int s_woff[kMaxWords];
+  __shared__ unsigned long long s_rm[kMaxWords];
   __shared__ unsigned long long s_adj[kMaxTrees];
   __shared__ unsigned long long s_part[kFinThreads / kWave][kMaxTrees];
   __shared__ int s_tc[kMaxTrees];
   __shared__ int s_M;
   const int V = dbscan_V(b, zin, Vin);
-  const int R = V > 0 ? tree_prefix<kFinThreads>(b, V, s_woff) : 0;
+  const int R = V > 0 ? tree_prefix<kFinThreads>(b, V, s_woff, s_rm) : 0;
   const bool overflow = R > kMaxTrees;
   if (threadIdx.x == 0) {
     b.ctrl->n_trees = R;
@@ -405,19 +480,34 @@ __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const fl
   if (threadIdx.x < kMaxTrees) s_tc[threadIdx.x] = 0;
   __syncthreads();
   if (R >= 2 && !overflow) {
-    // OR the tile slots: wave w takes tiles w, w+16, ...; lane = tree row
-    const int nt = (V + kTile - 1) / kTile;
+    // OR the live slots.  Rows are padded to Rp = 2^ceil(log2 R) lanes: thread
+    // t owns row t % Rp of slots t / Rp, t / Rp + 1024 / Rp, ... (kOrBatch
+    // loads in flight), then the lanes of one row are OR-ed across the wave
+    // and the 16 waves' rows across LDS.
+    const int nt = ntiles_of(V);
+    const int nslot = nt * ngrp;
+    int Rp = 2;
+    while (Rp < R) Rp <<= 1;
+    const int row = threadIdx.x & (Rp - 1), grp = threadIdx.x / Rp, ngr = kFinThreads / Rp;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     unsigned long long acc = 0ull;
-    if (lane < R) {
-      for (int t = w; t < nt * nt; t += kFinThreads / kWave) {
-        const int I = t / nt, J = t % nt;
-        acc |= b.tslot[((size_t)I * ntile + J) * kMaxTrees + lane];
+    if (row < R) {
+      for (int t0 = grp; t0 < nslot; t0 += ngr * kOrBatch) {
+        unsigned long long v[kOrBatch];
+#pragma unroll
+        for (int u = 0; u < kOrBatch; ++u) {
+          const int t = t0 + u * ngr;
+          const int I = t / ngrp, g = t - I * ngrp;
+          v[u] = (t < nslot && adj_block_live(I, g, nt)) ? b.tslot[(size_t)t * kMaxTrees + row] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kOrBatch; ++u) acc |= v[u];
       }
     }
-    s_part[w][lane] = acc;
+    for (int off = Rp; off < kWave; off <<= 1) acc |= __shfl_xor(acc, off, kWave);
+    if (lane < Rp) s_part[w][lane] = acc;
     __syncthreads();
-    if (threadIdx.x < kMaxTrees) {
+    if (threadIdx.x < R) {
       unsigned long long a = 0ull;
       for (int i = 0; i < kFinThreads / kWave; ++i) a |= s_part[i][threadIdx.x];
       s_adj[threadIdx.x] = a;
@@ -474,23 +564,34 @@ __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const fl
   // labels: core -> cluster of its tree (or component), border -> cluster of
   // its lowest-index core neighbour, noise -> -1.  In the fallback the
   // cluster number of a root sits in label[root] and is never overwritten
-  // (a root's own label is that same number).
-  for (int a0 = 0; a0 < V; a0 += kFinThreads) {
-    const int a = a0 + threadIdx.x;
-    if (a >= V) continue;
-    int lab = -1;
-    int x = -1;
-    const bool core = b.ncount[a] >= c.min_pts;
-    if (core) x = a;
-    else if (b.mcn[a] != kInt32Max) x = b.mcn[a];
-    if (x >= 0) {
-      const int r = b.root[x];
-      if (overflow) lab = b.label[r];
-      else lab = R == 1 ? 0 : s_tc[tree_id(b.rootmask, s_woff, r)];
+  // (a root's own label is that same number).  Each thread takes kLabBatch
+  // points at a time and issues all their loads before any store.
+  for (int a0 = 0; a0 < V; a0 += kFinThreads * kLabBatch) {
+    int nc[kLabBatch], x[kLabBatch], r[kLabBatch], lab[kLabBatch];
+#pragma unroll
+    for (int u = 0; u < kLabBatch; ++u) {
+      const int a = a0 + u * kFinThreads + threadIdx.x;
+      nc[u] = a < V ? b.ncount[a] : 0;
+      const int mc = a < V ? b.mcn[a] : kInt32Max;
+      x[u] = a >= V ? -1 : (nc[u] >= c.min_pts ? a : (mc != kInt32Max ? mc : -1));
     }
-    if (!(overflow && core && b.root[a] == a)) b.label[a] = lab;
-    if (lab_out) lab_out[a] = lab;
-    if (cnt_out) cnt_out[a] = b.ncount[a];
+#pragma unroll
+    for (int u = 0; u < kLabBatch; ++u) r[u] = x[u] >= 0 ? b.root[x[u]] : -1;
+#pragma unroll
+    for (int u = 0; u < kLabBatch; ++u) {
+      if (r[u] < 0) lab[u] = -1;
+      else if (overflow) lab[u] = b.label[r[u]];
+      else lab[u] = R == 1 ? 0 : s_tc[tree_id(s_rm, s_woff, r[u])];
+    }
+#pragma unroll
+    for (int u = 0; u < kLabBatch; ++u) {
+      const int a = a0 + u * kFinThreads + threadIdx.x;
+      if (a >= V) continue;
+      const bool core = nc[u] >= c.min_pts;
+      if (!(overflow && core && r[u] == a)) b.label[a] = lab[u];
+      if (lab_out) lab_out[a] = lab[u];
+      if (cnt_out) cnt_out[a] = nc[u];
+    }
   }
 }
 
@@ -509,16 +610,29 @@ __global__ __launch_bounds__(256) void k_stats(Cfg c, Bufs b) {
   const ZT* gv = reinterpret_cast<const ZT*>(b.gv);
   for (int cl = blockIdx.x; cl < M; cl += gridDim.x) {
     float n = 0.f, sS = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, mn = INFINITY;
-    for (int a = threadIdx.x; a < V; a += 256) {
-      if (b.label[a] != cl) continue;
-      const float S = b.Sv[a];
-      const ZT g = gv[a];
-      n += 1.f;
-      sS += S;
-      g0 += g.x;
-      g1 += g.y;
-      if constexpr (P == 3) g2 += g.z;
-      mn = fminf(mn, S);
+    // thread t visits points t, t + 256, ... in increasing order, kStatBatch
+    // of them per pass with all their loads issued first
+    for (int a0 = threadIdx.x; a0 < V; a0 += 256 * kStatBatch) {
+      int lb[kStatBatch];
+      float Sa[kStatBatch];
+      ZT ga[kStatBatch];
+#pragma unroll
+      for (int u = 0; u < kStatBatch; ++u) {
+        const int a = a0 + u * 256;
+        lb[u] = a < V ? b.label[a] : -1;
+        Sa[u] = a < V ? b.Sv[a] : 0.f;
+        ga[u] = a < V ? gv[a] : ZT{};
+      }
+#pragma unroll
+      for (int u = 0; u < kStatBatch; ++u) {
+        if (lb[u] != cl) continue;
+        n += 1.f;
+        sS += Sa[u];
+        g0 += ga[u].x;
+        g1 += ga[u].y;
+        if constexpr (P == 3) g2 += ga[u].z;
+        mn = fminf(mn, Sa[u]);
+      }
     }
     s_r[0][threadIdx.x] = n;
     s_r[1][threadIdx.x] = sS;
@@ -557,11 +671,11 @@ __global__ __launch_bounds__(256) void k_stats(Cfg c, Bufs b) {
 struct Sel {
   int sel, rule, h_used;
   uint32_t status_add;
-  float margin, v[3], vh[3];
+  float margin, smin, v[3], vh[3];
 };
 
 __device__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
-  __shared__ float s_k1[kUpdThreads], s_k2[kUpdThreads];
+  __shared__ float s_k1[kUpdThreads], s_k2[kUpdThreads], s_m1[kUpdThreads];
   __shared__ int s_i1[kUpdThreads];
   __shared__ Sel s_sel;
   const Ctrl* ct = b.ctrl;
@@ -572,6 +686,7 @@ __device__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
     s.h_used = 0;
     s.status_add = 0u;
     s.margin = INFINITY;
+    s.smin = INFINITY;
     for (int i = 0; i < 3; ++i) s.v[i] = s.vh[i] = 0.f;
     if (M == 0) {
       s.status_add = 4u;  // no cluster: update over all of V
@@ -602,16 +717,17 @@ __device__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
   __syncthreads();
   Sel s = s_sel;
   if (M == 0) return s;
-  float k1 = INFINITY, k2 = INFINITY;
+  float k1 = INFINITY, k2 = INFINITY, m1 = INFINITY;
   int i1 = kInt32Max;
   for (int cl = threadIdx.x; cl < M; cl += kUpdThreads) {
-    float key;
-    if (s.rule == 0) key = b.c_cost[cl];
-    else key = b.c_dir[4 * cl] * s.vh[0] + b.c_dir[4 * cl + 1] * s.vh[1] + b.c_dir[4 * cl + 2] * s.vh[2];
+    const float cost = b.c_cost[cl], mn = b.c_smin[cl];
+    const float4 dir = reinterpret_cast<const float4*>(b.c_dir)[cl];
+    const float key = s.rule == 0 ? cost : dir.x * s.vh[0] + dir.y * s.vh[1] + dir.z * s.vh[2];
     if (key < k1) {  // clusters are visited in increasing order: strict < keeps the lowest
       k2 = k1;
       k1 = key;
       i1 = cl;
+      m1 = mn;
     } else if (key < k2) {
       k2 = key;
     }
@@ -619,6 +735,7 @@ __device__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
   s_k1[threadIdx.x] = k1;
   s_k2[threadIdx.x] = k2;
   s_i1[threadIdx.x] = i1;
+  s_m1[threadIdx.x] = m1;
   __syncthreads();
   for (int w = kUpdThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
@@ -628,11 +745,13 @@ __device__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
       const bool takeb = b1 < a1 || (b1 == a1 && bi < ai);
       s_k1[threadIdx.x] = takeb ? b1 : a1;
       s_i1[threadIdx.x] = takeb ? bi : ai;
+      s_m1[threadIdx.x] = takeb ? s_m1[threadIdx.x + w] : s_m1[threadIdx.x];
       s_k2[threadIdx.x] = fminf(fminf(a2, b2), takeb ? a1 : b1);
     }
     __syncthreads();
   }
   s.sel = s_i1[0];
+  s.smin = s_m1[0];
   s.margin = M > 1 ? s_k2[0] - s_k1[0] : INFINITY;
   __syncthreads();
   return s;
@@ -652,6 +771,23 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
   const int NM = c.NM;
   const bool over_all = branch != 0;
   const int M = branch == 0 ? ct->M : 0;
+  const int ncand = over_all ? c.K : ct->n_feas;
+  // the candidate record is requested before the selection needs the block
+  const int a0 = blockIdx.x * kUpdChunk;
+  const int a = a0 + (int)threadIdx.x;
+  const bool mine = threadIdx.x < kUpdChunk && !bad && a < ncand;
+  int lab = -1, kk = 0;
+  float Sa = 0.f;
+  if (mine) {
+    if (over_all) {
+      kk = a;
+      Sa = b.S[a];
+    } else {
+      lab = b.label[a];
+      kk = b.vidx[a];
+      Sa = b.Sv[a];
+    }
+  }
   Sel s;
   if (branch == 0) {
     s = select_cluster(c, b, M);
@@ -661,6 +797,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
     s.h_used = 0;
     s.status_add = 0u;
     s.margin = INFINITY;
+    s.smin = INFINITY;
     for (int i = 0; i < 3; ++i) s.v[i] = s.vh[i] = 0.f;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && branch == 0) {
@@ -676,26 +813,14 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
     }
     cw->sel_size = s.sel >= 0 ? b.c_size[s.sel] : 0;
   }
-  const int ncand = over_all ? c.K : ct->n_feas;
   const int sel = s.sel;
-  const float smin = over_all ? ct->smin_all : (sel >= 0 ? b.c_smin[sel] : ct->smin_feas);
+  const float smin = over_all ? ct->smin_all : (sel >= 0 ? s.smin : ct->smin_feas);
   const float inv_l = 1.0f / c.lambda;
-  const int a0 = blockIdx.x * kUpdChunk;
   if (threadIdx.x < kUpdChunk) {
-    const int a = a0 + threadIdx.x;
     float w = 0.f;
-    int k = 0;
-    if (!bad && a < ncand) {
-      if (over_all) {
-        k = a;
-        w = expf(-(b.S[a] - smin) * inv_l);
-      } else if (sel < 0 || b.label[a] == sel) {
-        k = b.vidx[a];
-        w = expf(-(b.Sv[a] - smin) * inv_l);
-      }
-    }
+    if (mine && (over_all || sel < 0 || lab == sel)) w = expf(-(Sa - smin) * inv_l);
     s_w[threadIdx.x] = w;
-    s_k[threadIdx.x] = k;
+    s_k[threadIdx.x] = kk;  // a valid row whenever the weight is nonzero
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
@@ -817,13 +942,14 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Cfg c, Bufs b, float* __
 template <int P>
 static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const float* zin, int Vin,
                             int ntile, int* lab_out, int* cnt_out, int* mout) {
-  dim3 tiles(ntile, ntile), tb(kTile);
+  const int ngrp = (ntile + kColGroup - 1) / kColGroup;
+  dim3 tiles(ngrp, ntile), tb(kTile);
   const int nr = (ntile * kTile + 255) / 256;
   L(k_count<P>, tiles, tb, c, b, zin, Vin);
   L(k_mcn<P>, tiles, tb, c, b, zin, Vin);
   L(k_roots, dim3(nr), dim3(256), c, b, zin, Vin);
-  L(k_tree_adj<P>, tiles, tb, c, b, zin, Vin, ntile);
-  L(k_tree_cc<P>, dim3(1), dim3(kFinThreads), c, b, zin, Vin, ntile, mout, lab_out, cnt_out);
+  L(k_tree_adj<P>, tiles, tb, c, b, zin, Vin, ngrp);
+  L(k_tree_cc<P>, dim3(1), dim3(kFinThreads), c, b, zin, Vin, ngrp, mout, lab_out, cnt_out);
 }
 
 // Everything between the rollouts and the final combination.

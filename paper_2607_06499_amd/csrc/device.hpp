@@ -37,6 +37,10 @@ constexpr int kUpdThreads = 256;
 constexpr int kFinThreads = 1024;
 // tree graph handled by the fast path
 constexpr int kMaxTrees = 64;
+constexpr int kColGroup = 2;   // column tiles per tiled DBSCAN block
+constexpr int kOrBatch = 8;    // tree-slot loads in flight per lane
+constexpr int kLabBatch = 8;   // points per thread per labelling pass
+constexpr int kStatBatch = 4;  // points per thread per cluster-statistics pass
 
 constexpr int kInt32Max = 0x7fffffff;
 
@@ -111,7 +115,7 @@ struct Bufs {
   int* mcn;        // [K] lowest-index core neighbour (kInt32Max if none)
   int* root;       // [K] tree root (core points), -1 otherwise
   int* rid;        // [K] compacted tree id of each root point
-  unsigned long long* tslot;    // [ntile*ntile][kMaxTrees] tree adjacency per DBSCAN tile
+  unsigned long long* tslot;    // [ntile][ceil(ntile/kColGroup)][kMaxTrees] tree adjacency per block
   int* tree_cluster;            // [kMaxTrees] cluster of each tree
   int* tree_root;               // [kMaxTrees] root point of each tree
   int* label;      // [K]

@@ -210,10 +210,17 @@ def test_stage_dbscan_bit_exact(case):
     lab, cnt, M = pl.stage_dbscan(H.to_dev(z))
     lab = lab.cpu().numpy()
     cnt = cnt.cpu().numpy()
+    from paper_2607_06499_amd import binding as B
+
+    n_trees, overflow = pl.debug(B.DBG_TREES, 2).cpu().tolist()
+    print(f"{name}: V={len(z)} trees={n_trees} overflow={overflow}")
     olab, ocore, ocnt, oM = oracle.dbscan(z.astype(np.float64), spec.dbscan_eps, spec.dbscan_min_pts)
     assert np.array_equal(cnt, ocnt), name
     assert int(M.cpu().item()) == oM, name
     assert np.array_equal(lab, olab), name
+    assert overflow == (1 if n_trees > 64 else 0)
+    if name == "90_groups":
+        assert overflow == 1
 
 
 def test_stage_dbscan_empty_and_single():
