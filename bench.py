@@ -40,27 +40,35 @@ def parse():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--workload", default="config2", choices=["config2", "config2_probe", "config1",
-                                                              "config3"])
+    ap.add_argument("--workload", default="unicycle_dynamic",
+                    choices=["unicycle_dynamic", "unicycle_dynamic_ahead", "unicycle_static",
+                             "arm6_dynamic"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the clustering-branch companion measurement")
+    ap.add_argument("--rollout-reps", type=int, default=2000,
+                    help="back-to-back rollout launches timed for the roofline")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (profiler calibration)")
     return ap.parse_args()
 
 
 def scene_for(name, seed):
     from paper_2607_06499_amd import workloads as W
 
-    return {"config2": W.config2, "config2_probe": W.config2_probe, "config1": W.config1,
-            "config3": W.config3}[name](seed)
+    return {"unicycle_dynamic": W.unicycle_dynamic,
+            "unicycle_dynamic_ahead": W.unicycle_dynamic_ahead,
+            "unicycle_static": W.unicycle_static,
+            "arm6_dynamic": W.arm6_dynamic}[name](seed)
 
 
 def record_loop(pl, scene, T, torch):
     """Run the closed loop for T replans (host plant), returning the inputs
     each replan saw, the applied controls and the per-replan info."""
     from paper_2607_06499_amd import plant
+    from paper_2607_06499_amd.binding import DBG_TREES
 
     spec = scene.spec
     fld = scene.field.copy()
@@ -78,6 +86,8 @@ def record_loop(pl, scene, T, torch):
         u, _, _ = pl.replan(xd, od[: fld.n])
         torch.cuda.synchronize()
         info = pl.info()
+        if info["branch"] == 0:
+            info["trees"], info["tree_fallback"] = pl.debug(DBG_TREES, 2).cpu().tolist()
         un = u.cpu().numpy().copy()
         UO.append(un)
         INFO.append(info)
@@ -128,6 +138,16 @@ def latency_replays(pl, lib, Xd, Od, n_obs, W, K, torch, Uo):
     return np.array(lat), same
 
 
+def copy_calibration(torch, mib: int, reps: int = 5):
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters of a profiler run: reads and writes exactly mib MiB each."""
+    src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def source_digest(paths):
     h = hashlib.sha256()
     for p in paths:
@@ -139,7 +159,7 @@ def source_digest(paths):
 def traffic_record(kernel_sources):
     """HBM traffic per launch from the committed counter summary, if it was
     taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "rollout_unicycle_config2_traffic.json")
+    path = os.path.join(ROOT, "profiles", "rollout_unicycle_k8192_n50_traffic.json")
     if not os.path.exists(path):
         return None, None
     rec = json.load(open(path))
@@ -173,7 +193,7 @@ def cpu_baseline(scene, X, OBS, W, budget_s, hist_len):
                        f"{spec.num_samples * spec.horizon * n / dt:.3g} rollout-steps/s")
 
 
-def run_workload(name, seed, W, K, torch, B, want_timing=True):
+def run_workload(name, seed, W, K, torch, B, want_timing=True, rollout_reps=2000):
     scene = scene_for(name, seed)
     spec = scene.spec
     lib = B.load()
@@ -191,7 +211,12 @@ def run_workload(name, seed, W, K, torch, B, want_timing=True):
     pl.set_state(state0)
     lat, same = latency_replays(pl, lib, Xd, Od, n_obs, W, K, torch, Uo)
     timing = None
+    kernel_ms = None
     if want_timing:
+        # the rollout kernel alone, back to back on the replan stream, on the
+        # first timed replan's inputs (the planner state is restored after)
+        pl.set_state(state0)
+        kernel_ms = pl.time_rollout(Xd[W], Od[W], reps=rollout_reps)
         pl.set_state(state0)
         pl.timing_enable(W + K)
         for t in range(W + K):
@@ -205,9 +230,13 @@ def run_workload(name, seed, W, K, torch, B, want_timing=True):
     mix = {"cluster": branches.count(0), "fallback": branches.count(1),
            "all_collide": branches.count(2)}
     ncl = [i["n_feasible"] for i in INFO[W:] if i["branch"] == 0]
+    trees = [i["trees"] for i in INFO[W:] if i["branch"] == 0]
+    tstat = {"mean": round(float(np.mean(trees)), 1) if trees else 0.0,
+             "max": int(max(trees)) if trees else 0,
+             "union_find_fallback": int(sum(i["tree_fallback"] for i in INFO[W:] if i["branch"] == 0))}
     pl.close()
     return dict(scene=scene, X=X, OBS=OBS, wall=wall, gpu=gpu, lat=lat, same=same, timing=timing,
-                mix=mix, mean_V=float(np.mean(ncl)) if ncl else 0.0)
+                kernel_ms=kernel_ms, mix=mix, mean_V=float(np.mean(ncl)) if ncl else 0.0, trees=tstat)
 
 
 def main():
@@ -223,7 +252,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     W, K = args.warmup, args.steps
-    res = run_workload(args.workload, args.seed, W, K, torch, B)
+    res = run_workload(args.workload, args.seed, W, K, torch, B, rollout_reps=args.rollout_reps)
+    if args.calibrate_copy_mib:
+        copy_calibration(torch, args.calibrate_copy_mib)
     spec = res["scene"].spec
     replans_per_s = K / res["wall"]
     rollout_steps = spec.num_samples * spec.horizon
@@ -233,7 +264,8 @@ def main():
     n_obs = res["OBS"].shape[1]
     flops = rollout_steps * (25 + 5 * n_obs) if spec.dynamics == 0 else \
         rollout_steps * (480 + 48 + 8 * n_obs * spec.n_link_spheres + 40)
-    t_roll = res["timing"]["rollout_ms"] / res["timing"]["count"] * 1e-3
+    t_roll = res["kernel_ms"] * 1e-3
+    t_roll_launch = res["timing"]["rollout_ms"] / res["timing"]["count"] * 1e-3
     achieved = flops / t_roll / 1e12
     ksrc = [os.path.join(ROOT, "paper_2607_06499_amd", "csrc", f)
             for f in ("rollout.hip", "device.hpp")]
@@ -260,6 +292,7 @@ def main():
             f"{args.workload}: 6-joint arm K={spec.num_samples} N={spec.horizon} {n_obs} spheres",
             "K": spec.num_samples, "N": spec.horizon, "n_obs": n_obs,
             "branch_mix": res["mix"], "mean_feasible_when_clustering": round(res["mean_V"], 1),
+            "dbscan_trees": res["trees"],
             "launch": "hipGraph replay per replan",
         },
         "rollout_steps_per_s": round(replans_per_s * rollout_steps, 1),
@@ -273,17 +306,19 @@ def main():
             "frac": round(achieved / PEAK_FP32_TFLOPS, 6),
             "traffic": traffic,
             "kernel_ms": round(t_roll * 1e3, 5),
+            "kernel_ms_in_replan_with_launch": round(t_roll_launch * 1e3, 5),
             "algorithmic_flop_per_launch": flops,
         },
     }
-    if not args.no_probe and args.workload == "config2":
-        pr = run_workload("config2_probe", args.seed, W, K, torch, B, want_timing=False)
+    if not args.no_probe and args.workload == "unicycle_dynamic":
+        pr = run_workload("unicycle_dynamic_ahead", args.seed, W, K, torch, B, want_timing=False)
         out["clustering_branch"] = {
-            "workload": "config2_probe: same planner, obstacle ahead in the robot's path",
+            "workload": "unicycle_dynamic_ahead: same planner, obstacle ahead in the robot's path",
             "replans_per_s": round(K / pr["wall"], 2),
             "latency_ms": {"p50": round(float(np.percentile(pr["lat"], 50)) * 1e3, 4),
                            "p99": round(float(np.percentile(pr["lat"], 99)) * 1e3, 4)},
             "branch_mix": pr["mix"], "mean_feasible": round(pr["mean_V"], 1),
+            "dbscan_trees": pr["trees"],
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(res["scene"], res["X"], res["OBS"], W, args.cpu_seconds,

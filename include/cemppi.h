@@ -251,6 +251,17 @@ ce_status ce_mppi_timing_enable(ce_mppi_planner* planner, int32_t capacity);
 ce_status ce_mppi_timing_read(ce_mppi_planner* planner, double* rollout_ms, double* post_ms,
                               double* total_ms, int32_t* count);
 
+/* Time the rollout phase alone: `reps` back-to-back launches of the rollout
+ * kernel of a replan on (x_t, obstacles) between two HIP events on `stream`;
+ * *ms_per_launch receives the mean time per launch.  Device pointers as in
+ * ce_mppi_replan.  The planner's persistent state (nominal sequence,
+ * observation history, step counter) is saved before and restored after, so
+ * the next replan is unaffected; the per-rollout diagnostic buffers hold the
+ * last launch's values.  Synchronises the stream.  Errors: CE_EINVAL for
+ * NULL pointers or reps outside [1, 100000]; CE_EDEVICE for HIP failures. */
+ce_status ce_mppi_time_rollout(ce_mppi_planner* planner, const float* x_t, const float* obstacles,
+                               int32_t n_obs, int32_t reps, void* stream, double* ms_per_launch);
+
 /* ---- errors ---- */
 const char* ce_mppi_status_string(ce_status status);
 /* Message of the last failed call on this thread ("" if none). */

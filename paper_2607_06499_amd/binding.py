@@ -133,6 +133,7 @@ def load():
         "ce_mppi_timing_enable": [_vp, C.c_int32],
         "ce_mppi_timing_read": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_double), C.POINTER(C.c_int32)],
+        "ce_mppi_time_rollout": [_vp, _vp, _vp, C.c_int32, C.c_int32, _vp, C.POINTER(C.c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -339,6 +340,15 @@ class Planner:
         _check("ce_mppi_timing_read", load().ce_mppi_timing_read(
             self.handle, C.byref(r), C.byref(q), C.byref(a), C.byref(n)))
         return dict(rollout_ms=r.value, post_ms=q.value, total_ms=a.value, count=n.value)
+
+    def time_rollout(self, x_t, obstacles=None, reps: int = 100, stream=None) -> float:
+        """Mean ms per launch of the rollout kernel alone (state restored)."""
+        n_obs = 0 if obstacles is None else int(obstacles.shape[0])
+        ms = C.c_double()
+        _check("ce_mppi_time_rollout", load().ce_mppi_time_rollout(
+            self.handle, x_t.data_ptr(), obstacles.data_ptr() if n_obs else None, n_obs, int(reps),
+            _stream_handle(stream), C.byref(ms)))
+        return ms.value
 
     # -- stages and diagnostics
     def stage_noise(self, step: int, stream=None):

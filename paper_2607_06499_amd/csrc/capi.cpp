@@ -298,14 +298,12 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_pT = cv.take<float>(K * p), o_pF = cv.take<float>(K * p), o_g = cv.take<float>(K * p);
   const size_t o_eps = cv.take<float>(K * NM);
   const size_t o_part = cv.take<float>((size_t)c.nblk_roll * kPart);
-  const size_t o_foff = cv.take<int>((size_t)c.nblk_roll);
   const size_t o_vidx = cv.take<int>(K), o_z = cv.take<float>(K * zs), o_gv = cv.take<float>(K * zs);
   const size_t o_Sv = cv.take<float>(K);
   const size_t o_nc = cv.take<int>(K), o_mcn = cv.take<int>(K), o_root = cv.take<int>(K);
-  const size_t o_rid = cv.take<int>(K), o_lab = cv.take<int>(K);
-  const size_t o_rm = cv.take<unsigned long long>(nw), o_woff = cv.take<int>(nw);
+  const size_t o_lab = cv.take<int>(K);
+  const size_t o_rm = cv.take<unsigned long long>(nw);
   const size_t o_tslot = cv.take<unsigned long long>((size_t)c.ntile * ((c.ntile + kColGroup - 1) / kColGroup) * kMaxTrees);
-  const size_t o_tcl = cv.take<int>(kMaxTrees), o_troot = cv.take<int>(kMaxTrees);
   const size_t o_ccost = cv.take<float>((size_t)c.mcap), o_cdir = cv.take<float>((size_t)c.mcap * 4);
   const size_t o_csize = cv.take<int>((size_t)c.mcap), o_csmin = cv.take<float>((size_t)c.mcap);
   const size_t o_upart = cv.take<float>((size_t)c.nblk_upd * (NM + 1));
@@ -329,7 +327,6 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   b.g = reinterpret_cast<float*>(base + o_g);
   b.eps = reinterpret_cast<float*>(base + o_eps);
   b.part = reinterpret_cast<float*>(base + o_part);
-  b.feas_off = reinterpret_cast<int*>(base + o_foff);
   b.vidx = reinterpret_cast<int*>(base + o_vidx);
   b.z = reinterpret_cast<float*>(base + o_z);
   b.gv = reinterpret_cast<float*>(base + o_gv);
@@ -337,13 +334,9 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   b.ncount = reinterpret_cast<int*>(base + o_nc);
   b.mcn = reinterpret_cast<int*>(base + o_mcn);
   b.root = reinterpret_cast<int*>(base + o_root);
-  b.rid = reinterpret_cast<int*>(base + o_rid);
   b.label = reinterpret_cast<int*>(base + o_lab);
   b.rootmask = reinterpret_cast<unsigned long long*>(base + o_rm);
-  b.woff = reinterpret_cast<int*>(base + o_woff);
   b.tslot = reinterpret_cast<unsigned long long*>(base + o_tslot);
-  b.tree_cluster = reinterpret_cast<int*>(base + o_tcl);
-  b.tree_root = reinterpret_cast<int*>(base + o_troot);
   b.c_cost = reinterpret_cast<float*>(base + o_ccost);
   b.c_dir = reinterpret_cast<float*>(base + o_cdir);
   b.c_size = reinterpret_cast<int*>(base + o_csize);
@@ -535,6 +528,41 @@ ce_status ce_mppi_timing_read(ce_mppi_planner* P, double* rollout_ms, double* po
   if (total_ms) *total_ms = a;
   if (count) *count = t.n;
   return CE_OK;
+}
+
+ce_status ce_mppi_time_rollout(ce_mppi_planner* P, const float* x_t, const float* obstacles,
+                               int32_t n_obs, int32_t reps, void* stream, double* ms_per_launch) {
+  if (!P || !x_t || !ms_per_launch) return fail(CE_EINVAL, "NULL argument");
+  if (reps < 1 || reps > 100000) return fail(CE_EINVAL, "reps out of range");
+  if (n_obs < 0 || n_obs > P->c.max_obs) return fail(CE_EINVAL, "n_obs out of range");
+  if (n_obs > 0 && !obstacles) return fail(CE_EINVAL, "obstacles is NULL");
+  size_t need = 0;
+  ce_status st = ce_mppi_state_size(P, &need);
+  if (st != CE_OK) return st;
+  std::vector<char> saved(need);
+  st = ce_mppi_get_state(P, saved.data(), need, stream);
+  if (st != CE_OK) return st;
+  DeviceGuard guard(P->cfg.device);
+  hipStream_t s = S(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  Launcher L(s);
+  for (int i = 0; i < reps && e == hipSuccess && L.err == hipSuccess; ++i)
+    launch_rollout(L, P->c, P->b, x_t, obstacles, n_obs);
+  if (e == hipSuccess) e = L.err;
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "time_rollout");
+  *ms_per_launch = (double)ms / reps;
+  // the rollout phase pushes the observation into the history ring: put the
+  // saved state back
+  return ce_mppi_set_state(P, saved.data(), need, stream);
 }
 
 ce_status ce_mppi_replan_from_rollouts(ce_mppi_planner* P, const float* x_t, const float* obstacles,

@@ -104,7 +104,6 @@ struct Bufs {
   float* g;        // [K][p]
   float* eps;      // [K][N][m]
   float* part;     // [nblk_roll][kPart]
-  int* feas_off;   // [nblk_roll] exclusive prefix of feasible counts
   // compacted feasible set
   int* vidx;       // [K]
   float* z;        // [K][zs] zs = 2 (p = 2) or 4 (p = 3)
@@ -114,13 +113,9 @@ struct Bufs {
   int* ncount;     // [K]
   int* mcn;        // [K] lowest-index core neighbour (kInt32Max if none)
   int* root;       // [K] tree root (core points), -1 otherwise
-  int* rid;        // [K] compacted tree id of each root point
   unsigned long long* tslot;    // [ntile][ceil(ntile/kColGroup)][kMaxTrees] tree adjacency per block
-  int* tree_cluster;            // [kMaxTrees] cluster of each tree
-  int* tree_root;               // [kMaxTrees] root point of each tree
   int* label;      // [K]
   unsigned long long* rootmask;  // [ceil(K/64)] root flags
-  int* woff;                     // [ceil(K/64)] roots before each word
   // cluster statistics
   float* c_cost;   // [mcap] mean cost
   float* c_dir;    // [mcap][4] normalised mean direction

@@ -199,7 +199,7 @@ def _unicycle_spec(**kw) -> PlannerSpec:
     return PlannerSpec(**base).rounded()
 
 
-def config1(seed: int = 1, num_samples: int = 1024) -> Scene:
+def unicycle_static(seed: int = 1, num_samples: int = 1024) -> Scene:
     """Static 2-D scene: 10x10 m box, 8 circles r~U[0.3,0.8], start (0.5,0.5),
     goal (9.5,9.5); N=30, dt=0.1, lambda=1, eps=0.3, minPts=10, static rule."""
     rng = np.random.default_rng(seed)
@@ -210,22 +210,22 @@ def config1(seed: int = 1, num_samples: int = 1024) -> Scene:
                           seed=seed, stream_id=0)
     x0 = f32a([0.5, 0.5, math.pi / 4])
     return Scene(spec, x0, np.zeros((30, 2), np.float32), ObstacleField(c, r, v, [0, 0], [10, 10]),
-                 "config1")
+                 "unicycle_static")
 
 
-def config1_probe(seed: int = 1, num_samples: int = 1024) -> Scene:
-    """Config-1 scene with obstacle 0 moved onto the start-goal segment 1.2 m
+def unicycle_static_ahead(seed: int = 1, num_samples: int = 1024) -> Scene:
+    """unicycle_static scene with obstacle 0 moved onto the start-goal segment 1.2 m
     ahead and a constant nominal (0.5, 0): the obstacle-directly-ahead case
     that makes Alg. 1 take the clustering branch."""
-    s = config1(seed, num_samples)
+    s = unicycle_static(seed, num_samples)
     d = np.array([1.0, 1.0]) / math.sqrt(2.0)
     s.field.c[0] = np.array([0.5, 0.5]) + 1.2 * d
     U0 = np.zeros((s.spec.horizon, 2), np.float32)
     U0[:, 0] = 0.5
-    return Scene(s.spec, s.x0, U0, s.field, "config1_probe")
+    return Scene(s.spec, s.x0, U0, s.field, "unicycle_static_ahead")
 
 
-def config2(seed: int = 1, num_samples: int = 8192) -> Scene:
+def unicycle_dynamic(seed: int = 1, num_samples: int = 8192) -> Scene:
     """Dynamic 2-D scene: 20x20 m box, 24 circles r~U[0.2,0.6] moving at
     U[0.2,1.0] m/s with wall reflection; N=50, dt=0.05, lambda=1, H=5,
     eps=0.25, minPts=20, dynamic rule; start (1,1), goal (19,19)."""
@@ -238,21 +238,21 @@ def config2(seed: int = 1, num_samples: int = 8192) -> Scene:
                           goal=[19.0, 19.0, 0, 0, 0, 0], seed=seed, stream_id=0)
     x0 = f32a([1.0, 1.0, math.pi / 4])
     return Scene(spec, x0, np.zeros((50, 2), np.float32),
-                 ObstacleField(c, r, v, [0, 0], [20, 20]), "config2")
+                 ObstacleField(c, r, v, [0, 0], [20, 20]), "unicycle_dynamic")
 
 
-def config2_probe(seed: int = 1, num_samples: int = 8192) -> Scene:
-    """Config-2 scene with obstacle 0 placed 1.0 m ahead of the start, moving
+def unicycle_dynamic_ahead(seed: int = 1, num_samples: int = 8192) -> Scene:
+    """unicycle_dynamic scene with obstacle 0 placed 1.0 m ahead of the start, moving
     along the robot's heading, and a constant nominal (0.6, 0): every replan
     of the probe takes the clustering branch with the dynamic rule."""
-    s = config2(seed, num_samples)
+    s = unicycle_dynamic(seed, num_samples)
     d = np.array([1.0, 1.0]) / math.sqrt(2.0)
     s.field.c[0] = np.array([1.0, 1.0]) + 1.0 * d
     s.field.r[0] = 0.45
     s.field.v[0] = 0.4 * d
     U0 = np.zeros((s.spec.horizon, 2), np.float32)
     U0[:, 0] = 0.6
-    return Scene(s.spec, s.x0, U0, s.field, "config2_probe")
+    return Scene(s.spec, s.x0, U0, s.field, "unicycle_dynamic_ahead")
 
 
 # Six-joint arm with the joint-axis pattern of a UR-type manipulator:
@@ -271,7 +271,7 @@ def arm_dh(lengths) -> List[float]:
     return [v for row in rows for v in row]
 
 
-def config3(seed: int = 1, num_samples: int = 4096) -> Scene:
+def arm6_dynamic(seed: int = 1, num_samples: int = 4096) -> Scene:
     """Arm scene: seeded DH lengths U[0.08,0.45] m, joint-velocity noise
     sigma=0.3 rad/s, N=32, dt=0.05, 8 link spheres (r=0.05), 16 moving spheres
     r~U[0.04,0.12] at U[0.05,0.3] m/s in the cube [-0.6,0.6]^2 x [0,1.2],
@@ -299,7 +299,67 @@ def config3(seed: int = 1, num_samples: int = 4096) -> Scene:
         seed=seed, stream_id=0,
     ).rounded()
     x0 = np.zeros(12, np.float32)
-    return Scene(spec, x0, np.zeros((32, 6), np.float32), ObstacleField(c, r, v, lo, hi), "config3")
+    return Scene(spec, x0, np.zeros((32, 6), np.float32), ObstacleField(c, r, v, lo, hi), "arm6_dynamic")
+
+
+# ---------------------------------------------------------------- paper presets
+def paper_unicycle_preset(scenario: int = 1, seed: int = 1) -> Scene:
+    """Unicycle planner with the simulation parameters of Sec. III-A: K=300,
+    N=30, dt=0.03, the Table I bounds, lambda 0.7 (scenario 1) or 0.01
+    (scenario 2), stage weight Q=diag(10,10,0) and terminal weight
+    diag(50,50,50) with no control term.  The layouts are synthetic:
+    scenario 1 has one static obstacle on the start-goal line; scenario 2 a
+    0.43 m/s obstacle moving along +x plus two static ones."""
+    if scenario == 1:
+        c = np.array([[0.55, 0.0]])
+        r = np.array([0.2])
+        v = np.zeros((1, 2))
+        goal = [2.0, 0.0]
+        lam, mode = 0.7, STATIC
+    else:
+        c = np.array([[0.45, 0.25], [2.0, 1.3], [3.0, 0.4]])
+        r = np.array([0.2, 0.3, 0.3])
+        v = np.array([[0.43, 0.0], [0.0, 0.0], [0.0, 0.0]])
+        goal = [4.0, 2.0]
+        lam, mode = 0.01, DYNAMIC
+    spec = _unicycle_spec(horizon=30, num_samples=300, dt=0.03, lam=lam, dbscan_eps=0.3,
+                          dbscan_min_pts=10, scene_mode=mode, history_len=5,
+                          Q=[10.0, 10.0, 0.0, 0.0, 0.0, 0.0], R=[0.0] * 6,
+                          Qf=[50.0, 50.0, 50.0, 0.0, 0.0, 0.0], goal=goal + [0.0] * 4,
+                          seed=seed, stream_id=scenario)
+    U0 = np.zeros((30, 2), np.float32)
+    U0[:, 0] = 0.5
+    return Scene(spec, f32a([0.0, 0.0, 0.0]), U0,
+                 ObstacleField(c, r, v, [-1.0, -2.0], [5.0, 3.0]), f"paper_unicycle_{scenario}")
+
+
+# published UR5e kinematic lengths (d1, a2, a3, d4, d5, d6) in metres
+UR5E_LENGTHS = [0.1625, 0.425, 0.3922, 0.1333, 0.0997, 0.0996]
+
+
+def paper_arm_preset(seed: int = 1) -> Scene:
+    """Six-joint arm planner with the real-world parameters of Sec. III-C:
+    K=50, N=12, dt=0.1, joint velocity bound 0.1 rad/s, joint position bound
+    2 pi, lambda=0.05, DBSCAN eps=0.3 m on the end-effector feature, position
+    weight w_p=10.  UR5e kinematic lengths; a synthetic target with
+    an obstacle sphere between the start pose and the target and one
+    elsewhere."""
+    rng = np.random.default_rng(70_000 + seed)
+    bound = 0.1
+    spec = PlannerSpec(
+        dynamics=ARM6, horizon=12, num_samples=50, dt=0.1, lam=0.05,
+        noise_chol=diag_chol([0.05] * 6, 6), u_min=[-bound] * 6, u_max=[bound] * 6,
+        dbscan_eps=0.3, dbscan_min_pts=5, scene_mode=STATIC, history_len=5,
+        goal=[-0.6, -0.45, 0.4, 0.0, 0.0, 0.0], Q=[10.0] + [0.0] * 5, R=[0.0] * 6,
+        Qf=[10.0] + [0.0] * 5, dh=arm_dh(UR5E_LENGTHS), n_link_spheres=8, link_sphere_radius=0.05,
+        q_limit=[2.0 * math.pi] * 6, w_limit=100.0, seed=seed, stream_id=7,
+    ).rounded()
+    q0 = np.array([0.0, -1.2, 1.4, -1.8, -1.57, 0.0]) + rng.normal(0.0, 0.02, 6)
+    x0 = np.concatenate([q0, np.zeros(6)]).astype(np.float32)
+    c = np.array([[-0.64, -0.22, 0.40], [-0.3, 0.2, 0.3]])
+    r = np.array([0.05, 0.05])
+    fld = ObstacleField(c, r, np.zeros((2, 3)), [-0.8, -0.8, 0.0], [0.8, 0.8, 1.2])
+    return Scene(spec, x0, np.zeros((12, 6), np.float32), fld, "paper_arm")
 
 
 def random_scene(seed: int, dynamics: int = UNICYCLE, num_samples: int = 512, horizon: int = 24,
@@ -367,10 +427,10 @@ class BatchMember:
     kind: str
 
 
-def config4(seed: int = 1, n_planners: int = 256) -> List[BatchMember]:
+def batch_uneven(seed: int = 1, n_planners: int = 256) -> List[BatchMember]:
     """256 independent 2-D planners: K log-uniform in [256,16384], N uniform
     in [20,60], obstacle count uniform in [4,64]; even members static
-    (config-1 style), odd members dynamic (config-2 style)."""
+    (unicycle_static style), odd members dynamic (unicycle_dynamic style)."""
     rng = np.random.default_rng(40_000 + seed)
     out = []
     for i in range(n_planners):
@@ -401,7 +461,7 @@ def config4(seed: int = 1, n_planners: int = 256) -> List[BatchMember]:
         fld.c[0] = ahead
         U0 = np.zeros((N, 2), np.float32)
         U0[:, 0] = 0.5
-        out.append(BatchMember(Scene(spec, x0, U0, fld, f"config4[{i}]"),
+        out.append(BatchMember(Scene(spec, x0, U0, fld, f"batch_uneven[{i}]"),
                                "static" if i % 2 == 0 else "dynamic"))
     return out
 
@@ -413,9 +473,9 @@ class SessionSpec:
     kind: str
 
 
-def config5_sessions(seed: int = 1, n_sessions: int = 512) -> List[SessionSpec]:
-    """512 persistent sessions: 70 % 2-D planners (config-1 scene, K
-    log-uniform in [1024,8192]) and 30 % arm planners (config-3 scene, K
+def served_sessions(seed: int = 1, n_sessions: int = 512) -> List[SessionSpec]:
+    """512 persistent sessions: 70 % 2-D planners (unicycle_static_ahead scene, K
+    log-uniform in [1024,8192]) and 30 % arm planners (arm6_dynamic scene, K
     log-uniform in [1024,4096])."""
     rng = np.random.default_rng(50_000 + seed)
     out = []
@@ -423,12 +483,12 @@ def config5_sessions(seed: int = 1, n_sessions: int = 512) -> List[SessionSpec]:
         sub = int(rng.integers(1, 2**31 - 1))
         if rng.uniform() < 0.7:
             K = int(round(math.exp(rng.uniform(math.log(1024), math.log(8192)))))
-            s = config1_probe(sub, K)
+            s = unicycle_static_ahead(sub, K)
             s.spec = s.spec.replace(stream_id=i)
             out.append(SessionSpec(s, "unicycle"))
         else:
             K = int(round(math.exp(rng.uniform(math.log(1024), math.log(4096)))))
-            s = config3(sub, K)
+            s = arm6_dynamic(sub, K)
             s.spec = s.spec.replace(stream_id=i)
             out.append(SessionSpec(s, "arm"))
     return out

@@ -79,8 +79,8 @@ SCENES = [
     ("random_uni", lambda: W.random_scene(1, num_samples=1000, horizon=30, n_obs=7)),
     ("random_uni_noclamp", lambda: W.random_scene(2, num_samples=777, horizon=50, n_obs=12, clamp=False)),
     ("random_uni_short", lambda: W.random_scene(3, num_samples=513, horizon=9, n_obs=3)),
-    ("config1_probe", lambda: W.config1_probe(1)),
-    ("config2_probe", lambda: W.config2_probe(2, num_samples=2048)),
+    ("unicycle_static_ahead", lambda: W.unicycle_static_ahead(1)),
+    ("unicycle_dynamic_ahead", lambda: W.unicycle_dynamic_ahead(2, num_samples=2048)),
     ("random_arm", lambda: W.random_scene(4, dynamics=W.ARM6, num_samples=600, horizon=20, n_obs=10)),
     ("random_arm_noclamp", lambda: W.random_scene(5, dynamics=W.ARM6, num_samples=301, horizon=32,
                                                   n_obs=16, clamp=False)),
@@ -137,9 +137,9 @@ def _check_post(r, o, spec, exact_labels=True):
 
 
 POST = [
-    ("config1_probe", lambda: W.config1_probe(1)),
-    ("config1_probe_s3", lambda: W.config1_probe(3)),
-    ("config2_probe", lambda: W.config2_probe(2, num_samples=3000)),
+    ("unicycle_static_ahead", lambda: W.unicycle_static_ahead(1)),
+    ("unicycle_static_ahead_s3", lambda: W.unicycle_static_ahead(3)),
+    ("unicycle_dynamic_ahead", lambda: W.unicycle_dynamic_ahead(2, num_samples=3000)),
     ("random_uni", lambda: W.random_scene(7, num_samples=1500, horizon=40, n_obs=8)),
     ("random_uni_first_contact", lambda: W.random_scene(8, num_samples=900, horizon=30, n_obs=8,
                                                         ref_mode=W.REF_FIRST_CONTACT)),
@@ -234,12 +234,15 @@ def test_stage_dbscan_empty_and_single():
 
 # ------------------------------------------------------------------ end to end
 E2E = [
-    ("config1_probe", lambda: W.config1_probe(1)),
-    ("config1_probe_s5", lambda: W.config1_probe(5)),
-    ("config2_probe", lambda: W.config2_probe(1, num_samples=4096)),
+    ("unicycle_static_ahead", lambda: W.unicycle_static_ahead(1)),
+    ("unicycle_static_ahead_s5", lambda: W.unicycle_static_ahead(5)),
+    ("unicycle_dynamic_ahead", lambda: W.unicycle_dynamic_ahead(1, num_samples=4096)),
     ("random_uni", lambda: W.random_scene(11, num_samples=2000, horizon=40, n_obs=10)),
     ("random_arm", lambda: W.random_scene(12, dynamics=W.ARM6, num_samples=1000, horizon=24, n_obs=12)),
     ("no_obstacles", lambda: W.random_scene(13, num_samples=700, horizon=20, n_obs=0)),
+    ("paper_unicycle_1", lambda: W.paper_unicycle_preset(1)),
+    ("paper_unicycle_2", lambda: W.paper_unicycle_preset(2)),
+    ("paper_arm", lambda: W.paper_arm_preset(1)),
 ]
 
 
@@ -265,7 +268,7 @@ def test_end_to_end_replan(name, make):
 
 
 def test_determinism_and_checkpoint():
-    s = W.config1_probe(2)
+    s = W.unicycle_static_ahead(2)
     pl = _planner(s.spec)
     _set_U(pl, s.U0)
     state = pl.get_state()
@@ -279,10 +282,27 @@ def test_determinism_and_checkpoint():
     assert not np.array_equal(a["S"], b2["S"])
 
 
+def test_time_rollout_restores_state():
+    """The rollout-only timing call leaves the planner exactly as it was."""
+    s = W.unicycle_dynamic_ahead(4, num_samples=1024)
+    pl = _planner(s.spec)
+    _set_U(pl, s.U0)
+    a0 = H.gpu_replan(pl, s.x0, s.obstacles)
+    state = pl.get_state()
+    a1 = H.gpu_replan(pl, s.x0, s.obstacles)
+    pl.set_state(state)
+    ms = pl.time_rollout(H.to_dev(s.x0), H.to_dev(s.obstacles), reps=5)
+    assert ms > 0.0
+    b1 = H.gpu_replan(pl, s.x0, s.obstacles)
+    for k in ("S", "col", "u_out", "U_new", "U_next"):
+        assert np.array_equal(a1[k], b1[k]), k
+    assert a1["info"]["step"] == b1["info"]["step"] == a0["info"]["step"] + 1
+
+
 def test_lockstep_dynamic_loop():
-    """Config-2 shaped dynamic scene, a few closed-loop steps in lockstep: at
+    """unicycle_dynamic shaped scene, a few closed-loop steps in lockstep: at
     every step both sides start from the same state, nominal and history."""
-    s = W.config2_probe(3, num_samples=2048)
+    s = W.unicycle_dynamic_ahead(3, num_samples=2048)
     spec = s.spec
     pl = _planner(spec)
     fld = s.field.copy()
@@ -310,7 +330,7 @@ def test_lockstep_dynamic_loop():
 
 def test_degenerate_branches():
     # every rollout collides
-    s = W.config1_probe(1)
+    s = W.unicycle_static_ahead(1)
     s.field.c[0] = s.x0[:2]
     s.field.r[0] = 5.0
     pl = _planner(s.spec)
@@ -320,7 +340,7 @@ def test_degenerate_branches():
     assert r["info"]["branch"] == 2 == o["branch"] and r["info"]["status"] == o["status"]
     assert np.abs(r["U_new"] - o["U_new"]).max() <= 1e-3
     # no cluster (minPts larger than |V|)
-    s = W.config1_probe(1)
+    s = W.unicycle_static_ahead(1)
     s.spec = s.spec.replace(dbscan_min_pts=100000)
     pl = _planner(s.spec)
     _set_U(pl, s.U0)

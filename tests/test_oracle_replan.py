@@ -55,9 +55,9 @@ def test_clamp_and_applied_perturbation(orc):
 
 
 def _ahead_scene(seed=1, D=1.5, rad=0.3, v=0.7):
-    """Config-1 robot with a single obstacle D m straight ahead and a constant
+    """unicycle_static robot with a single obstacle D m straight ahead and a constant
     nominal speed: the feasible rollouts split into a left and a right group."""
-    s = W.config1_probe(seed)
+    s = W.unicycle_static_ahead(seed)
     h = math.pi / 4
     s.field.c = (s.x0[:2] + D * np.array([math.cos(h), math.sin(h)]))[None]
     s.field.r = np.array([rad])
@@ -76,7 +76,7 @@ def _cluster_scene(orc, seed=1):
 
 def test_reference_point_and_features(orc):
     for mode in (W.REF_TERMINAL, W.REF_FIRST_CONTACT):
-        s = W.config1_probe(1)
+        s = W.unicycle_static_ahead(1)
         s.spec = s.spec.replace(ref_mode=mode)
         r = _replan(orc, s)
         assert r["branch"] == 0
@@ -126,7 +126,7 @@ def test_reference_point_uses_closest_obstacle_hits(orc):
 def test_reference_point_falls_back_to_all_colliding(orc):
     # the closest obstacle is off to the side and never hit: A is empty and the
     # reference point is the mean over every colliding rollout (Eq. (11))
-    s = W.config1_probe(1)
+    s = W.unicycle_static_ahead(1)
     fld = s.field
     fld.c = np.concatenate([[s.x0[:2] + np.array([0.45, -0.45])], fld.c])
     fld.r = np.concatenate([[0.05], fld.r])
@@ -213,7 +213,7 @@ def test_obstacle_velocity_estimate(orc):
 
 
 def test_dynamic_rule_needs_history_and_motion(orc):
-    s = W.config1_probe(1)
+    s = W.unicycle_static_ahead(1)
     s.spec = s.spec.replace(scene_mode=W.DYNAMIC)
     r = _replan(orc, s)  # one observation only
     assert r["rule"] == 0 and r["status"] & orc.ST_DYN_STATIC
@@ -223,13 +223,13 @@ def test_dynamic_rule_needs_history_and_motion(orc):
 
 
 def test_all_collide_and_no_cluster(orc):
-    s = W.config1_probe(1)
+    s = W.unicycle_static_ahead(1)
     s.field.c[0] = s.x0[:2]
     s.field.r[0] = 5.0
     r = _replan(orc, s)
     assert r["branch"] == 2 and r["status"] & orc.ST_ALL_COLLIDE and r["n_feas"] == 0
     assert np.count_nonzero(r["weight"]) == s.spec.num_samples
-    s = W.config1_probe(1)
+    s = W.unicycle_static_ahead(1)
     s.spec = s.spec.replace(dbscan_min_pts=100000)
     r = _replan(orc, s)
     assert r["branch"] == 0 and r["n_clusters"] == 0 and r["status"] & orc.ST_NO_CLUSTER
@@ -245,7 +245,7 @@ def test_shift_and_output(orc):
 
 
 def test_nonfinite_input_is_a_noop(orc):
-    s = W.config1_probe(1)
+    s = W.unicycle_static_ahead(1)
     x = s.x0.copy()
     x[1] = np.nan
     r = orc.replan(s.spec, x, s.U0, s.obstacles)
