@@ -40,6 +40,7 @@ extern "C" {
 #define CE_MPPI_MAX_HORIZON 63    /* N: the N+1 states of a rollout share a wave */
 #define CE_MPPI_MAX_HISTORY 16    /* H                                          */
 #define CE_MPPI_MAX_SAMPLES 65536 /* K                                          */
+#define CE_MPPI_MAX_BATCH 1024    /* planners per batch                         */
 #define CE_MPPI_MAX_SPHERES 16    /* arm link spheres                           */
 
 typedef int32_t ce_status;
@@ -261,6 +262,69 @@ ce_status ce_mppi_timing_read(ce_mppi_planner* planner, double* rollout_ms, doub
  * NULL pointers or reps outside [1, 100000]; CE_EDEVICE for HIP failures. */
 ce_status ce_mppi_time_rollout(ce_mppi_planner* planner, const float* x_t, const float* obstacles,
                                int32_t n_obs, int32_t reps, void* stream, double* ms_per_launch);
+
+/* ---- batched form: many planners per launch ----
+ *
+ * A batch runs one replan of each of its planners (Alg. 1 for every member,
+ * each exactly as ce_mppi_replan would run it) as one graph launch.  Every
+ * phase of the replan is one persistent kernel per planner kind (rollout
+ * kind: unicycle on 32 or 64 lanes, arm; feature dimension p = 2 or 3) whose
+ * fixed grid loops over the work items of all members; the DBSCAN work
+ * tables are sized on the device from each member's feasible count.  The
+ * results of a member are bitwise those of ce_mppi_replan on the same inputs
+ * and state.
+ *
+ * Ownership: the batch holds references to its planners, which must outlive
+ * it, stay on the batch's device, and must not run a replan concurrently with
+ * a batch replan.  The batch owns a small device table (about 1 KB per
+ * member) and a pinned staging buffer for the per-call pointers. */
+typedef struct ce_mppi_batch ce_mppi_batch;
+
+/* Per-member inputs and outputs of one batch replan; the pointers are device
+ * pointers with the layouts of ce_mppi_replan. */
+typedef struct ce_mppi_batch_io {
+  const float* x_t;        /* [n] current state                                */
+  const float* obstacles;  /* [n_obs][p+1] (centre, radius), or NULL if n_obs=0 */
+  int32_t n_obs;           /* 0 .. the member's max_obstacles                   */
+  int32_t reserved;        /* must be 0                                         */
+  float* u_out;            /* [m] applied control (required)                    */
+  float* U_out;            /* [N][m] updated sequence before the shift, or NULL */
+  void* info;              /* ce_mppi_info, or NULL                             */
+} ce_mppi_batch_io;
+
+/* Launch shapes of a batch (chosen by ce_mppi_batch_autotune or set). */
+typedef struct ce_mppi_batch_tuning {
+  int32_t colg;               /* column tiles per DBSCAN count item: 1, 2 or 4  */
+  int32_t tile_blocks_per_cu; /* persistent blocks per CU, tiled DBSCAN: 1..16  */
+  int32_t roll_blocks_per_cu; /* persistent blocks per CU, rollouts: 1..8       */
+  int32_t reserved;           /* must be 0                                      */
+} ce_mppi_batch_tuning;
+
+/* Create a batch of n distinct planners (1 <= n <= CE_MPPI_MAX_BATCH) on the
+ * same device, with the default tuning (colg 2, 8 tile blocks and 4 rollout
+ * blocks per CU).  Errors: CE_EINVAL (NULL, duplicates, mixed devices, n out
+ * of range), CE_ENOMEM, CE_EDEVICE. */
+ce_status ce_mppi_batch_create(ce_mppi_planner* const* planners, int32_t n, ce_mppi_batch** out);
+void ce_mppi_batch_destroy(ce_mppi_batch* batch);
+
+/* One replan of every member on `stream` (asynchronous).  io: host array of
+ * n entries, read during the call; the per-call pointers are uploaded only
+ * when they differ from the previous call's.  Errors: CE_EINVAL for a NULL
+ * u_out or x_t, n_obs out of range, or a nonzero reserved field;
+ * CE_EDEVICE for HIP failures. */
+ce_status ce_mppi_batch_replan(ce_mppi_batch* batch, const ce_mppi_batch_io* io, void* stream);
+
+ce_status ce_mppi_batch_set_tuning(ce_mppi_batch* batch, const ce_mppi_batch_tuning* tuning);
+ce_status ce_mppi_batch_get_tuning(const ce_mppi_batch* batch, ce_mppi_batch_tuning* tuning);
+
+/* Project-written autotuner: times `reps` batch replans on io for every
+ * candidate shape (colg in {1,2,4} x tile blocks per CU in {2,4,8,16} x
+ * rollout blocks per CU in {2,4}), keeps the fastest and returns it with its
+ * mean time per batch replan.  The members' states are saved before and
+ * restored after every candidate, so the batch continues from where it was.
+ * Synchronises the stream. */
+ce_status ce_mppi_batch_autotune(ce_mppi_batch* batch, const ce_mppi_batch_io* io, int32_t reps,
+                                 void* stream, ce_mppi_batch_tuning* best, double* best_ms);
 
 /* ---- errors ---- */
 const char* ce_mppi_status_string(ce_status status);

@@ -93,6 +93,30 @@ class CeMppiInfo(C.Structure):
         return d
 
 
+class CeMppiBatchIO(C.Structure):
+    _fields_ = [
+        ("x_t", C.c_void_p),
+        ("obstacles", C.c_void_p),
+        ("n_obs", C.c_int32),
+        ("reserved", C.c_int32),
+        ("u_out", C.c_void_p),
+        ("U_out", C.c_void_p),
+        ("info", C.c_void_p),
+    ]
+
+
+class CeMppiBatchTuning(C.Structure):
+    _fields_ = [
+        ("colg", C.c_int32),
+        ("tile_blocks_per_cu", C.c_int32),
+        ("roll_blocks_per_cu", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
 INFO_BYTES = C.sizeof(CeMppiInfo)
 _vp = C.c_void_p
 
@@ -134,6 +158,12 @@ def load():
         "ce_mppi_timing_read": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_double), C.POINTER(C.c_int32)],
         "ce_mppi_time_rollout": [_vp, _vp, _vp, C.c_int32, C.c_int32, _vp, C.POINTER(C.c_double)],
+        "ce_mppi_batch_create": [C.POINTER(_vp), C.c_int32, C.POINTER(_vp)],
+        "ce_mppi_batch_replan": [_vp, C.POINTER(CeMppiBatchIO), _vp],
+        "ce_mppi_batch_set_tuning": [_vp, C.POINTER(CeMppiBatchTuning)],
+        "ce_mppi_batch_get_tuning": [_vp, C.POINTER(CeMppiBatchTuning)],
+        "ce_mppi_batch_autotune": [_vp, C.POINTER(CeMppiBatchIO), C.c_int32, _vp,
+                                   C.POINTER(CeMppiBatchTuning), C.POINTER(C.c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -141,6 +171,8 @@ def load():
         f.restype = C.c_int32
     lib.ce_mppi_destroy.argtypes = [_vp]
     lib.ce_mppi_destroy.restype = None
+    lib.ce_mppi_batch_destroy.argtypes = [_vp]
+    lib.ce_mppi_batch_destroy.restype = None
     lib.ce_mppi_status_string.argtypes = [C.c_int32]
     lib.ce_mppi_status_string.restype = C.c_char_p
     lib.ce_mppi_last_error.argtypes = []
@@ -388,3 +420,68 @@ class Planner:
         _check("ce_mppi_debug_get", load().ce_mppi_debug_get(self.handle, int(which), out.data_ptr(),
                                                               nbytes, _stream_handle(None)))
         return out[:count] if count else out[:0]
+
+
+class Batch:
+    """Many planners replanned by one graph launch (``ce_mppi_batch_*``).
+    Every member keeps its own buffers; per-call inputs and outputs are torch
+    tensors on the members' GPU."""
+
+    def __init__(self, planners):
+        self.planners = list(planners)
+        arr = (_vp * len(self.planners))(*[p.handle for p in self.planners])
+        h = _vp()
+        _check("ce_mppi_batch_create",
+               load().ce_mppi_batch_create(arr, len(self.planners), C.byref(h)))
+        self.handle = h.value
+        self._io = (CeMppiBatchIO * len(self.planners))()
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().ce_mppi_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_io(self, xs, obstacles, want_U: bool = True, want_info: bool = True):
+        """Point the per-call inputs at device tensors (one per member) and the
+        outputs at each member planner's own output tensors."""
+        keep = []
+        for i, (pl, x, o) in enumerate(zip(self.planners, xs, obstacles)):
+            e = self._io[i]
+            n_obs = 0 if o is None else int(o.shape[0])
+            e.x_t = x.data_ptr()
+            e.obstacles = o.data_ptr() if n_obs else None
+            e.n_obs = n_obs
+            e.reserved = 0
+            e.u_out = pl.u_out.data_ptr()
+            e.U_out = pl.U_out.data_ptr() if want_U else None
+            e.info = pl.info_buf.data_ptr() if want_info else None
+            keep.append((x, o))
+        self._keep = keep
+
+    def replan(self, stream=None):
+        _check("ce_mppi_batch_replan",
+               load().ce_mppi_batch_replan(self.handle, self._io, _stream_handle(stream)))
+
+    def set_tuning(self, colg: int, tile_blocks_per_cu: int, roll_blocks_per_cu: int):
+        t = CeMppiBatchTuning(int(colg), int(tile_blocks_per_cu), int(roll_blocks_per_cu), 0)
+        _check("ce_mppi_batch_set_tuning", load().ce_mppi_batch_set_tuning(self.handle, C.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = CeMppiBatchTuning()
+        _check("ce_mppi_batch_get_tuning", load().ce_mppi_batch_get_tuning(self.handle, C.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, reps: int = 3, stream=None):
+        t = CeMppiBatchTuning()
+        ms = C.c_double()
+        _check("ce_mppi_batch_autotune",
+               load().ce_mppi_batch_autotune(self.handle, self._io, int(reps), _stream_handle(stream),
+                                             C.byref(t), C.byref(ms)))
+        return t.as_dict(), ms.value

@@ -13,6 +13,7 @@
 #include "cemppi.h"
 #include "device.hpp"
 #include "launch.hpp"
+#include "planner.hpp"
 
 namespace cemppi {
 void launch_rollout(Launcher& L, const Cfg& c, const Bufs& b, const float* x_t, const float* obs,
@@ -29,40 +30,6 @@ void launch_stage_dbscan(Launcher& L, const Cfg& c, const Bufs& b, const float* 
 using namespace cemppi;
 
 static_assert(sizeof(ce_mppi_info) == 4 * (12 + 2 + 10), "ce_mppi_info layout");
-
-// Replan as a hipGraph: the whole kernel chain recorded once, the first
-// (rollout) and last (finish) nodes re-pointed when the caller's buffers
-// change.
-struct ReplanGraph {
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  Launcher::Node first{}, last{};
-  const float* x = nullptr;
-  const float* obs = nullptr;
-  int n_obs = -1;
-  float* u_out = nullptr;
-  float* U_out = nullptr;
-  void* info = nullptr;
-};
-
-// HIP-event timing of each replan: events before the rollout kernel, after
-// it and after the final kernel.
-struct Timing {
-  int cap = 0, n = 0;
-  std::vector<hipEvent_t> ev;
-};
-
-struct ce_mppi_planner {
-  ce_mppi_config cfg;
-  Cfg c;
-  Bufs b;
-  void* arena = nullptr;
-  size_t arena_bytes = 0;
-  size_t cap_K = 0;
-  int launch_mode = CE_LAUNCH_GRAPH;
-  ReplanGraph g;
-  Timing t;
-};
 
 namespace {
 
@@ -235,6 +202,11 @@ struct DeviceGuard {
 };
 
 }  // namespace
+
+namespace cemppi {
+ce_status set_error(ce_status s, const std::string& msg) { return fail(s, msg); }
+ce_status set_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+}  // namespace cemppi
 
 extern "C" {
 

@@ -121,15 +121,15 @@ __device__ __forceinline__ Totals decide(const Cfg& c, const float* tot, int bad
 // in ascending rollout order, features z (Eq. (13)) and the DBSCAN arrays.
 // Block 0 publishes the totals.
 template <int P>
-__global__ __launch_bounds__(256) void k_compact(Cfg c, Bufs b) {
+__device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx) {
   using ZT = typename ZVec<P>::T;
   __shared__ float s_tot[kPart + 1];
   __shared__ int s_before;
-  const int blk0 = (blockIdx.x * 256) / c.rpb;
+  const int blk0 = (bx * 256) / c.rpb;
   reduce_partials(c, b, blk0, s_tot, &s_before);
   const int bad = b.ctrl->nonfinite;
   const Totals T = decide(c, s_tot, bad);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bx == 0 && threadIdx.x == 0) {
     Ctrl* ct = b.ctrl;
     ct->n_col = T.ncol;
     ct->n_feas = T.nfeas;
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_compact(Cfg c, Bufs b) {
     for (int i = 0; i < 3; ++i) ct->ref[i] = T.ref[i];
   }
   if (T.branch != 0) return;
-  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int k = bx * 256 + threadIdx.x;
   const int feas = (k < c.K) ? !b.col[k] : 0;
   int tot;
   const int local = block_excl_scan<256>(feas, &tot);
@@ -174,6 +174,11 @@ __global__ __launch_bounds__(256) void k_compact(Cfg c, Bufs b) {
   b.label[rank] = -1;
 }
 
+template <int P>
+__global__ __launch_bounds__(256) void k_compact(Cfg c, Bufs b) {
+  compact_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+}
+
 // per-point DBSCAN state for a stage call on caller features
 __global__ void k_init_points(Bufs b, int V) {
   const int a = blockIdx.x * 256 + threadIdx.x;
@@ -196,29 +201,28 @@ __device__ __forceinline__ int ntiles_of(int V) { return (V + kTile - 1) / kTile
 
 // 1. neighbour counts: for each row point, its neighbours among the block's
 // column points (closed ball, itself included).
-template <int P>
-__global__ __launch_bounds__(kTile) void k_count(Cfg c, Bufs b, const float* __restrict__ zin,
-                                                 int Vin) {
+template <int P, int COLG = kColGroup>
+__device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
   __shared__ ZT s_z[kTile];
   const int V = dbscan_V(b, zin, Vin);
   const int nt = ntiles_of(V);
-  const int I = blockIdx.y, J0 = blockIdx.x * kColGroup;
+  const int I = by, J0 = bx * COLG;
   if (I >= nt || J0 >= nt) return;
-  const int J1 = min(J0 + kColGroup, nt);
+  const int J1 = min(J0 + COLG, nt);
   const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
   const int k = I * kTile + threadIdx.x;
   const ZT zk = k < V ? z[k] : ZVec<P>::far();
-  ZT zl[kColGroup];
+  ZT zl[COLG];
 #pragma unroll
-  for (int u = 0; u < kColGroup; ++u) {
+  for (int u = 0; u < COLG; ++u) {
     const int l = (J0 + u) * kTile + threadIdx.x;
     zl[u] = (J0 + u < J1 && l < V) ? z[l] : ZVec<P>::far();
   }
   const float r2 = c.eps2;
   int cnt = 0;
 #pragma unroll
-  for (int u = 0; u < kColGroup; ++u) {
+  for (int u = 0; u < COLG; ++u) {
     const int J = J0 + u;
     if (J >= J1) break;
     __syncthreads();
@@ -230,25 +234,30 @@ __global__ __launch_bounds__(kTile) void k_count(Cfg c, Bufs b, const float* __r
   if (k < V && cnt) atomicAdd(&b.ncount[k], cnt);
 }
 
+template <int P>
+__global__ __launch_bounds__(kTile) void k_count(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  count_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
+}
+
 // 2. lowest-index core neighbour of every point (core points include
 // themselves).  Column tiles are visited in increasing order, so the first
 // hit of a row is its minimum within the block.
-template <int P>
-__global__ __launch_bounds__(kTile) void k_mcn(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+template <int P, int COLG = kColGroup>
+__device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
   __shared__ ZT s_z[kTile];
   const int V = dbscan_V(b, zin, Vin);
   const int nt = ntiles_of(V);
-  const int I = blockIdx.y, J0 = blockIdx.x * kColGroup;
+  const int I = by, J0 = bx * COLG;
   if (I >= nt || J0 >= nt) return;
-  const int J1 = min(J0 + kColGroup, nt);
+  const int J1 = min(J0 + COLG, nt);
   const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
   const int k = I * kTile + threadIdx.x;
   const ZT zk = k < V ? z[k] : ZVec<P>::far();
-  ZT zl[kColGroup];
-  int ncl[kColGroup];
+  ZT zl[COLG];
+  int ncl[COLG];
 #pragma unroll
-  for (int u = 0; u < kColGroup; ++u) {
+  for (int u = 0; u < COLG; ++u) {
     const int l = (J0 + u) * kTile + threadIdx.x;
     const bool ok = J0 + u < J1 && l < V;
     zl[u] = ok ? z[l] : ZVec<P>::far();
@@ -257,7 +266,7 @@ __global__ __launch_bounds__(kTile) void k_mcn(Cfg c, Bufs b, const float* __res
   const float r2 = c.eps2;
   int m = kInt32Max;
 #pragma unroll
-  for (int u = 0; u < kColGroup; ++u) {
+  for (int u = 0; u < COLG; ++u) {
     const int J = J0 + u;
     if (J >= J1) break;
     __syncthreads();
@@ -275,12 +284,17 @@ __global__ __launch_bounds__(kTile) void k_mcn(Cfg c, Bufs b, const float* __res
   if (k < V && m != kInt32Max) atomicMin(&b.mcn[k], m);
 }
 
+template <int P>
+__global__ __launch_bounds__(kTile) void k_mcn(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  mcn_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
+}
+
 // 3. roots: follow the hook chain of each core point (indices decrease, so the
 // walk ends at a point that hooks to itself); root flags go into 64-bit words.
-__global__ __launch_bounds__(256) void k_roots(Cfg c, Bufs b, const float* zin, int Vin) {
+__device__ __forceinline__ void roots_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* zin, int Vin) {
   const int V = dbscan_V(b, zin, Vin);
-  const int a = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x * 256 >= V) return;
+  const int a = bx * 256 + threadIdx.x;
+  if (bx * 256 >= V) return;
   bool isroot = false;
   if (a < V) {
     if (b.ncount[a] >= c.min_pts) {
@@ -298,6 +312,10 @@ __global__ __launch_bounds__(256) void k_roots(Cfg c, Bufs b, const float* zin, 
   }
   const unsigned long long m = __ballot(isroot);
   if ((threadIdx.x & 63) == 0 && a < V) b.rootmask[a >> 6] = m;
+}
+
+__global__ __launch_bounds__(256) void k_roots(Cfg c, Bufs b, const float* zin, int Vin) {
+  roots_body(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
 }
 
 // Tree numbering: exclusive prefix of root counts over the root-flag words,
@@ -342,8 +360,7 @@ __device__ __forceinline__ bool adj_block_live(int I, int g, int nt) {
 }
 
 template <int P>
-__global__ __launch_bounds__(kTile) void k_tree_adj(Cfg c, Bufs b, const float* __restrict__ zin,
-                                                    int Vin, int ngrp) {
+__device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin, int ngrp) {
   using ZT = typename ZVec<P>::T;
   __shared__ ZT s_z[kTile];
   __shared__ uint2 s_bit[kTile];  // tree bit of the column point as two words, 0 if not core
@@ -352,7 +369,7 @@ __global__ __launch_bounds__(kTile) void k_tree_adj(Cfg c, Bufs b, const float* 
   __shared__ unsigned long long s_adj[kMaxTrees];
   const int V = dbscan_V(b, zin, Vin);
   const int nt = ntiles_of(V);
-  const int I = blockIdx.y, g = blockIdx.x;
+  const int I = by, g = bx;
   if (!adj_block_live(I, g, nt)) return;
   const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
   const int J0 = max(g * kColGroup, I), J1 = min(g * kColGroup + kColGroup, nt);
@@ -409,6 +426,11 @@ __global__ __launch_bounds__(kTile) void k_tree_adj(Cfg c, Bufs b, const float* 
   if (threadIdx.x < R) b.tslot[((size_t)I * ngrp + g) * kMaxTrees + threadIdx.x] = s_adj[threadIdx.x];
 }
 
+template <int P>
+__global__ __launch_bounds__(kTile) void k_tree_adj(Cfg c, Bufs b, const float* __restrict__ zin, int Vin, int ngrp) {
+  tree_adj_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin, ngrp);
+}
+
 // 5. connected components of the tree graph and canonical cluster numbers
 // (one 1024-thread block), or the exact fallback for more than 64 trees.
 template <int P>
@@ -460,9 +482,7 @@ __device__ void uf_fallback(const Cfg& c, const Bufs& b, const float* zin, int V
 }
 
 template <int P>
-__global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const float* __restrict__ zin,
-                                                         int Vin, int ngrp, int* mout, int* lab_out,
-                                                         int* cnt_out) {
+__device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin, int ngrp, int* mout, int* lab_out, int* cnt_out) {
   __shared__ int s_woff[kMaxWords];
   __shared__ unsigned long long s_rm[kMaxWords];
   __shared__ unsigned long long s_adj[kMaxTrees];
@@ -595,12 +615,17 @@ __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const fl
   }
 }
 
+template <int P>
+__global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const float* __restrict__ zin, int Vin, int ngrp, int* mout, int* lab_out, int* cnt_out) {
+  tree_cc_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin, ngrp, mout, lab_out, cnt_out);
+}
+
 // ---------------------------------------------------------------------------
 // Cluster statistics with fixed-order block reductions: count, mean cost
 // (Alg. 1 [Cluster stats]), normalised mean direction (Eq. (16)), minimum
 // cost.  Block b handles clusters b, b + gridDim.x, ...
 template <int P>
-__global__ __launch_bounds__(256) void k_stats(Cfg c, Bufs b) {
+__device__ __forceinline__ void stats_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx) {
   using ZT = typename ZVec<P>::T;
   __shared__ float s_r[6][256];
   const Ctrl* ct = b.ctrl;
@@ -608,7 +633,7 @@ __global__ __launch_bounds__(256) void k_stats(Cfg c, Bufs b) {
   const int V = branch == 0 ? ct->n_feas : 0;
   const int M = branch == 0 ? ct->M : 0;
   const ZT* gv = reinterpret_cast<const ZT*>(b.gv);
-  for (int cl = blockIdx.x; cl < M; cl += gridDim.x) {
+  for (int cl = bx; cl < M; cl += nbx) {
     float n = 0.f, sS = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, mn = INFINITY;
     // thread t visits points t, t + 256, ... in increasing order, kStatBatch
     // of them per pass with all their loads issued first
@@ -661,6 +686,11 @@ __global__ __launch_bounds__(256) void k_stats(Cfg c, Bufs b) {
     }
     __syncthreads();
   }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_stats(Cfg c, Bufs b) {
+  stats_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -761,7 +791,7 @@ __device__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
 // Update partials, Eq. (19)-(20) (Eq. (6)-(7) on the fallback branches):
 // block b takes kUpdChunk candidates (16 per wave); lane = element of the
 // [N][m] sequence; the four waves' sums are combined in a fixed order.
-__global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
+__device__ __forceinline__ void update_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx) {
   __shared__ float s_w[kUpdChunk];
   __shared__ int s_k[kUpdChunk];
   __shared__ float s_acc[kUpdThreads / kWave][kWave];
@@ -773,7 +803,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
   const int M = branch == 0 ? ct->M : 0;
   const int ncand = over_all ? c.K : ct->n_feas;
   // the candidate record is requested before the selection needs the block
-  const int a0 = blockIdx.x * kUpdChunk;
+  const int a0 = bx * kUpdChunk;
   const int a = a0 + (int)threadIdx.x;
   const bool mine = threadIdx.x < kUpdChunk && !bad && a < ncand;
   int lab = -1, kk = 0;
@@ -800,7 +830,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
     s.smin = INFINITY;
     for (int i = 0; i < 3; ++i) s.v[i] = s.vh[i] = 0.f;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && branch == 0) {
+  if (bx == 0 && threadIdx.x == 0 && branch == 0) {
     Ctrl* cw = b.ctrl;
     cw->sel = s.sel;
     cw->rule = s.rule;
@@ -825,7 +855,7 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   constexpr int PER = kUpdChunk / (kUpdThreads / kWave);
-  float* part = b.upart + (size_t)blockIdx.x * (NM + 1);
+  float* part = b.upart + (size_t)bx * (NM + 1);
   for (int e0 = 0; e0 < NM + 1; e0 += kWave) {
     const int e = e0 + lane;
     float acc = 0.f;
@@ -846,11 +876,14 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
   }
 }
 
+__global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
+  update_body(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+}
+
 // Final combination (one block): sum of the update partials in a fixed order,
 // U_new = U + sum / sum(w), outputs, shift (last control repeated), step
 // counter and the info record.
-__global__ __launch_bounds__(kFinThreads) void k_finish(Cfg c, Bufs b, float* __restrict__ u_out,
-                                                        float* __restrict__ U_out, void* info_out) {
+__device__ __forceinline__ void finish_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, float* __restrict__ u_out, float* __restrict__ U_out, void* info_out) {
   __shared__ float s_sum[kFinThreads];
   __shared__ float s_tot[kMaxNM + 1];
   const Ctrl* ct = b.ctrl;
@@ -937,6 +970,141 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Cfg c, Bufs b, float* __
   }
 }
 
+__global__ __launch_bounds__(kFinThreads) void k_finish(Cfg c, Bufs b, float* __restrict__ u_out, float* __restrict__ U_out, void* info_out) {
+  finish_body(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, u_out, U_out, info_out);
+}
+
+// ---------------------------------------------------------------------------
+// Batched phases: persistent kernels over the work tables of a batch.  The
+// DBSCAN tables depend on each planner's feasible count, so kb_plan fills
+// them on the device after the compaction.
+
+__global__ __launch_bounds__(kFinThreads) void kb_plan(CSlotStatic st, PlanOut o) {
+  for (int kd = 0; kd < 2; ++kd) {
+    const int n = o.n[kd];
+    if (n == 0) continue;
+    const int q = threadIdx.x;
+    int ncnt = 0, nadj = 0, nroot = 0;
+    if (q < n) {
+      const SlotStatic& S = *(const SlotStatic*)(st + o.slot[kd][q]);
+      const Ctrl* ct = S.b.ctrl;
+      const int V = ct->branch == 0 ? ct->n_feas : 0;
+      const int nt = ntiles_of(V);
+      ncnt = nt * ((nt + o.colg - 1) / o.colg);
+      nadj = nt * ((nt + kColGroup - 1) / kColGroup);
+      nroot = (V + 255) / 256;
+    }
+    int t1, t2, t3;
+    const int e1 = block_excl_scan<kFinThreads>(ncnt, &t1);
+    const int e2 = block_excl_scan<kFinThreads>(nadj, &t2);
+    const int e3 = block_excl_scan<kFinThreads>(nroot, &t3);
+    if (q < n) {
+      o.pref_cnt[kd][q] = e1;
+      o.pref_adj[kd][q] = e2;
+      o.pref_roots[kd][q] = e3;
+    }
+    if (q == 0) {
+      o.pref_cnt[kd][n] = t1;
+      o.pref_adj[kd][n] = t2;
+      o.pref_roots[kd][n] = t3;
+    }
+  }
+}
+
+#define CEMPPI_SLOT(slot)                                     \
+  const SlotStatic& S = *(const SlotStatic*)(st + (slot));    \
+  const Cfg& c = S.c;                                         \
+  const Bufs& b = S.b
+
+template <int P>
+__global__ __launch_bounds__(256) void kb_compact(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int local) {
+    CEMPPI_SLOT(slot);
+    compact_body<P>(c, b, local, 0, 0);
+  });
+}
+
+// count / mcn items: local = I * ceil(nt / COLG) + g
+template <int P, int COLG>
+__global__ __launch_bounds__(kTile) void kb_count(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int local) {
+    CEMPPI_SLOT(slot);
+    const int nt = ntiles_of(dbscan_V(b, nullptr, 0));
+    const int ng = (nt + COLG - 1) / COLG;
+    count_body<P, COLG>(c, b, local % ng, local / ng, 0, nullptr, 0);
+  });
+}
+
+template <int P, int COLG>
+__global__ __launch_bounds__(kTile) void kb_mcn(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int local) {
+    CEMPPI_SLOT(slot);
+    const int nt = ntiles_of(dbscan_V(b, nullptr, 0));
+    const int ng = (nt + COLG - 1) / COLG;
+    mcn_body<P, COLG>(c, b, local % ng, local / ng, 0, nullptr, 0);
+  });
+}
+
+__global__ __launch_bounds__(256) void kb_roots(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int local) {
+    CEMPPI_SLOT(slot);
+    roots_body(c, b, local, 0, 0, nullptr, 0);
+  });
+}
+
+template <int P>
+__global__ __launch_bounds__(kTile) void kb_tree_adj(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int local) {
+    CEMPPI_SLOT(slot);
+    const int nt = ntiles_of(dbscan_V(b, nullptr, 0));
+    const int ng = (nt + kColGroup - 1) / kColGroup;
+    tree_adj_body<P>(c, b, local % ng, local / ng, 0, nullptr, 0,
+                     (c.ntile + kColGroup - 1) / kColGroup);
+  });
+}
+
+template <int P>
+__global__ __launch_bounds__(kFinThreads) void kb_tree_cc(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int) {
+    CEMPPI_SLOT(slot);
+    tree_cc_body<P>(c, b, 0, 0, 0, nullptr, 0, (c.ntile + kColGroup - 1) / kColGroup, nullptr,
+                    nullptr, nullptr);
+  });
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void kb_stats(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int local) {
+    CEMPPI_SLOT(slot);
+    stats_body<P>(c, b, local, 0, kStatItems);
+  });
+}
+
+__global__ __launch_bounds__(kUpdThreads) void kb_update(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int local) {
+    CEMPPI_SLOT(slot);
+    update_body(c, b, local, 0, 0);
+  });
+}
+
+__global__ __launch_bounds__(kFinThreads) void kb_finish(CSlotStatic st, CSlotIO io, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int) {
+    CEMPPI_SLOT(slot);
+    const SlotIO& I = *(const SlotIO*)(io + slot);
+    finish_body(c, b, 0, 0, 0, I.u_out, I.U_out, I.info);
+  });
+}
+#undef CEMPPI_SLOT
+
 // ---------------------------------------------------------------------------
 // launchers
 template <int P>
@@ -991,6 +1159,61 @@ void launch_stage_dbscan(Launcher& L, const Cfg& c, const Bufs& b, const float* 
     launch_dbscan_p<2>(L, c, b, z, V, ntile, label, ncount, mout);
   else
     launch_dbscan_p<3>(L, c, b, z, V, ntile, label, ncount, mout);
+}
+
+
+template <int P>
+static void launch_batch_dbscan(Launcher& L, const CSlotStatic cst, const BatchTabs& T, int kd) {
+  const dim3 tb(kTile);
+  switch (T.colg) {
+    case 1:
+      L(kb_count<P, 1>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);
+      L(kb_mcn<P, 1>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);
+      break;
+    case 4:
+      L(kb_count<P, 4>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);
+      L(kb_mcn<P, 4>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);
+      break;
+    default:
+      L(kb_count<P, 2>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);
+      L(kb_mcn<P, 2>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);
+      break;
+  }
+}
+
+void launch_batch_post(Launcher& L, const SlotStatic* st, const SlotIO* io, const BatchTabs& T) {
+  const CSlotStatic cst = (CSlotStatic)st;
+  const CSlotIO cio = (CSlotIO)io;
+  for (int kd = 0; kd < 2; ++kd) {
+    if (!T.compact[kd].n) continue;
+    if (kd == 0) L(kb_compact<2>, dim3(T.grid_compact[0]), dim3(256), cst, T.compact[0]);
+    else L(kb_compact<3>, dim3(T.grid_compact[1]), dim3(256), cst, T.compact[1]);
+  }
+  L(kb_plan, dim3(1), dim3(kFinThreads), cst, T.plan);
+  for (int kd = 0; kd < 2; ++kd) {
+    if (!T.compact[kd].n) continue;
+    if (kd == 0) launch_batch_dbscan<2>(L, cst, T, 0);
+    else launch_batch_dbscan<3>(L, cst, T, 1);
+  }
+  for (int kd = 0; kd < 2; ++kd)
+    if (T.compact[kd].n) L(kb_roots, dim3(T.grid_roots), dim3(256), cst, T.roots[kd]);
+  for (int kd = 0; kd < 2; ++kd) {
+    if (!T.compact[kd].n) continue;
+    if (kd == 0) L(kb_tree_adj<2>, dim3(T.grid_tile), dim3(kTile), cst, T.adj[0]);
+    else L(kb_tree_adj<3>, dim3(T.grid_tile), dim3(kTile), cst, T.adj[1]);
+  }
+  for (int kd = 0; kd < 2; ++kd) {
+    if (!T.compact[kd].n) continue;
+    if (kd == 0) L(kb_tree_cc<2>, dim3(T.grid_cc[0]), dim3(kFinThreads), cst, T.cc[0]);
+    else L(kb_tree_cc<3>, dim3(T.grid_cc[1]), dim3(kFinThreads), cst, T.cc[1]);
+  }
+  for (int kd = 0; kd < 2; ++kd) {
+    if (!T.compact[kd].n) continue;
+    if (kd == 0) L(kb_stats<2>, dim3(T.grid_stats[0]), dim3(256), cst, T.stats[0]);
+    else L(kb_stats<3>, dim3(T.grid_stats[1]), dim3(256), cst, T.stats[1]);
+  }
+  L(kb_update, dim3(T.grid_update), dim3(kUpdThreads), cst, T.update);
+  L(kb_finish, dim3(T.grid_finish), dim3(kFinThreads), cst, cio, T.finish);
 }
 
 }  // namespace cemppi

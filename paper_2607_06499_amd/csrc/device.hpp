@@ -127,6 +127,83 @@ struct Bufs {
 };
 
 // ---------------------------------------------------------------------------
+// Batched execution: many planners per launch.  Each planner of a batch has a
+// slot: its configuration and buffers (written at batch creation) and its
+// per-call inputs and outputs.  Kernels read slots through constant-address
+// pointers, so every field is a scalar load as with a kernel argument.
+constexpr int kMaxBatch = 1024;   // planners per batch
+constexpr int kStatItems = 16;    // cluster-statistics blocks per planner
+
+struct SlotStatic {
+  Cfg c;
+  Bufs b;
+};
+struct SlotIO {
+  const float* x_t;
+  const float* obs;
+  float* u_out;
+  float* U_out;
+  void* info;
+  int n_obs;
+  int pad;
+};
+typedef const __attribute__((address_space(4))) SlotStatic* CSlotStatic;
+typedef const __attribute__((address_space(4))) SlotIO* CSlotIO;
+
+// Work table of one phase over one group of planners: slot[q] is the slot of
+// the q-th planner, pref[0..n] the exclusive prefix of its work items.
+struct Tab {
+  const int* slot;
+  const int* pref;
+  int n;
+};
+
+// Persistent loop over the items of a table: block i takes items i, i +
+// gridDim.x, ...; f(slot, local item) runs with every thread of the block.
+template <typename F>
+__device__ __forceinline__ void for_each_item(const Tab& t, int* s_pref, F&& f) {
+  for (int i = threadIdx.x; i <= t.n; i += blockDim.x) s_pref[i] = t.pref[i];
+  __syncthreads();
+  const int total = s_pref[t.n];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    // the planner of item it: the last q with pref[q] <= it
+    int lo = 0, hi = t.n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_pref[mid] <= it) lo = mid;
+      else hi = mid - 1;
+    }
+    const int q = __builtin_amdgcn_readfirstlane(lo);
+    const int slot = __builtin_amdgcn_readfirstlane(t.slot[q]);
+    f(slot, it - s_pref[q]);
+    __syncthreads();
+  }
+}
+
+// Tables of the batched post-rollout phases.  Index kd is the group of
+// planners with p = 2 (0) or p = 3 (1): static tables for compaction, tree
+// closure and statistics; the DBSCAN tables are filled on the device from
+// each planner's feasible count (PlanOut).  Update and finish run over every
+// planner of the batch.
+struct PlanOut {
+  const int* slot[2];   // planners with p = 2 and p = 3
+  int n[2];
+  int* pref_cnt[2];     // count and lowest-core-neighbour tiles
+  int* pref_adj[2];     // tree-adjacency tiles
+  int* pref_roots[2];   // root-following blocks of 256 points
+  int colg;             // column tiles per count/mcn item
+};
+
+struct BatchTabs {
+  Tab compact[2], cnt[2], adj[2], roots[2], cc[2], stats[2];
+  Tab update, finish;
+  PlanOut plan;
+  int grid_compact[2], grid_cc[2], grid_stats[2], grid_update, grid_finish;
+  int grid_tile, grid_roots;
+  int colg;
+};
+
+// ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, key bumped by
 // the Weyl constants between rounds.
 __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,

@@ -224,7 +224,7 @@ __device__ __forceinline__ void rollout_contrib(float* rec, bool active, int col
 }
 
 // Sum the per-rollout records of this block (fixed order) into part[block].
-__device__ __forceinline__ void write_block_partial(const Bufs& b, float (*recs)[kPart], int rpb) {
+__device__ __forceinline__ void write_block_partial(const Bufs& b, float (*recs)[kPart], int rpb, int bx) {
   __syncthreads();
   if (threadIdx.x < kPart) {
     const int f = threadIdx.x;
@@ -233,17 +233,14 @@ __device__ __forceinline__ void write_block_partial(const Bufs& b, float (*recs)
       const float v = recs[r][f];
       acc = (f == P_SMIN_ALL || f == P_SMIN_FEAS) ? fminf(acc, v) : acc + v;
     }
-    b.part[(size_t)blockIdx.x * kPart + f] = acc;
+    b.part[(size_t)bx * kPart + f] = acc;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Unicycle rollouts (Sec. III-A): state (x, y, theta), control (v, omega).
 template <int SEG>
-__global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b,
-                                                                   const float* __restrict__ x_t,
-                                                                   const float* __restrict__ obs,
-                                                                   int n_obs) {
+__device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ x_t, const float* __restrict__ obs, int n_obs) {
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
@@ -251,13 +248,13 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b
   prologue<0>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
-  if (blockIdx.x == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
+  if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
 
   constexpr int SPW = kWave / SEG;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int j = lane & (SEG - 1), sgi = lane / SEG;
   const int kloc = wave * SPW + sgi;
-  const int k = blockIdx.x * (kRollWaves * SPW) + kloc;
+  const int k = bx * (kRollWaves * SPW) + kloc;
   const int N = c.N;
   const bool act = (k < c.K) && !bad;
   const float dt = c.dt;
@@ -346,17 +343,19 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b
     }
     rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 2);
   }
-  write_block_partial(b, s_rec, kRollWaves * SPW);
+  write_block_partial(b, s_rec, kRollWaves * SPW, bx);
+}
+
+template <int SEG>
+__global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b, const float* __restrict__ x_t, const float* __restrict__ obs, int n_obs) {
+  rollout_unicycle_body<SEG>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, x_t, obs, n_obs);
 }
 
 // ---------------------------------------------------------------------------
 // Six-joint arm rollouts (Sec. III-C): joint-velocity control, q_{j+1} =
 // q_j + u_j dt; end-effector cost, joint-limit penalty, link spheres against
 // obstacle spheres.
-__global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b,
-                                                              const float* __restrict__ x_t,
-                                                              const float* __restrict__ obs,
-                                                              int n_obs) {
+__device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ x_t, const float* __restrict__ obs, int n_obs) {
   constexpr int SEG = 64;
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
@@ -365,12 +364,12 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b,
   prologue<1>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
-  if (blockIdx.x == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
+  if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int j = lane;
   const int kloc = wave;
-  const int k = blockIdx.x * kRollWaves + kloc;
+  const int k = bx * kRollWaves + kloc;
   const int N = c.N;
   const bool act = (k < c.K) && !bad;
   const float dt = c.dt;
@@ -474,7 +473,33 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b,
     }
     rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 3);
   }
-  write_block_partial(b, s_rec, kRollWaves);
+  write_block_partial(b, s_rec, kRollWaves, bx);
+}
+
+__global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b, const float* __restrict__ x_t, const float* __restrict__ obs, int n_obs) {
+  rollout_arm_body(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, x_t, obs, n_obs);
+}
+
+// ---------------------------------------------------------------------------
+// Batched rollouts: one persistent launch per rollout kind covers the rollout
+// blocks of every planner of that kind in the batch.
+template <int SEG>
+__global__ __launch_bounds__(kRollThreads) void kb_rollout_unicycle(CSlotStatic st, CSlotIO io, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int local) {
+    const SlotStatic& S = *(const SlotStatic*)(st + slot);
+    const SlotIO& I = *(const SlotIO*)(io + slot);
+    rollout_unicycle_body<SEG>(S.c, S.b, local, 0, 0, I.x_t, I.obs, I.n_obs);
+  });
+}
+
+__global__ __launch_bounds__(kRollThreads) void kb_rollout_arm(CSlotStatic st, CSlotIO io, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int local) {
+    const SlotStatic& S = *(const SlotStatic*)(st + slot);
+    const SlotIO& I = *(const SlotIO*)(io + slot);
+    rollout_arm_body(S.c, S.b, local, 0, 0, I.x_t, I.obs, I.n_obs);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -514,7 +539,7 @@ __global__ __launch_bounds__(kRollThreads) void k_reduce_records(Cfg c, Bufs b,
     }
     rollout_contrib(s_rec[threadIdx.x], act, col, f, closest, S, src, P);
   }
-  write_block_partial(b, s_rec, c.rpb);
+  write_block_partial(b, s_rec, c.rpb, (int)blockIdx.x);
 }
 
 // Philox words and standard normals of every rollout (stage entry point):
@@ -544,6 +569,17 @@ __global__ void k_stage_noise(Cfg c, uint32_t step, uint32_t* __restrict__ words
 
 // ---------------------------------------------------------------------------
 // host-side launchers
+// kind 0: unicycle on 32-lane segments, 1: unicycle on 64 lanes, 2: arm
+void launch_batch_rollout(Launcher& L, int kind, const SlotStatic* st, const SlotIO* io, Tab t,
+                          int grid) {
+  if (grid <= 0) return;
+  const CSlotStatic cst = (CSlotStatic)st;
+  const CSlotIO cio = (CSlotIO)io;
+  if (kind == 0) L(kb_rollout_unicycle<32>, dim3(grid), dim3(kRollThreads), cst, cio, t);
+  else if (kind == 1) L(kb_rollout_unicycle<64>, dim3(grid), dim3(kRollThreads), cst, cio, t);
+  else L(kb_rollout_arm, dim3(grid), dim3(kRollThreads), cst, cio, t);
+}
+
 void launch_rollout(Launcher& L, const Cfg& c, const Bufs& b, const float* x_t, const float* obs,
                     int n_obs) {
   dim3 grid(c.nblk_roll), block(kRollThreads);

@@ -44,9 +44,11 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "cemppi.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(ce_mppi_config), sizeof(ce_mppi_info),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ce_mppi_config), sizeof(ce_mppi_info),
          offsetof(ce_mppi_config, seed), offsetof(ce_mppi_config, dh),
-         offsetof(ce_mppi_info, margin), offsetof(ce_mppi_info, weight_sum));
+         offsetof(ce_mppi_info, margin), offsetof(ce_mppi_info, weight_sum),
+         sizeof(ce_mppi_batch_io), offsetof(ce_mppi_batch_io, n_obs), offsetof(ce_mppi_batch_io, u_out),
+         offsetof(ce_mppi_batch_io, info), sizeof(ce_mppi_batch_tuning));
   return 0;
 }
 '''
@@ -65,6 +67,11 @@ int main(void) {
     assert vals[3] == B.CeMppiConfig.dh.offset
     assert vals[4] == B.CeMppiInfo.margin.offset
     assert vals[5] == B.CeMppiInfo.weight_sum.offset
+    assert vals[6] == C.sizeof(B.CeMppiBatchIO)
+    assert vals[7] == B.CeMppiBatchIO.n_obs.offset
+    assert vals[8] == B.CeMppiBatchIO.u_out.offset
+    assert vals[9] == B.CeMppiBatchIO.info.offset
+    assert vals[10] == C.sizeof(B.CeMppiBatchTuning)
 
 
 def test_config_init_defaults(lib):
@@ -111,6 +118,15 @@ def test_null_arguments(lib):
     assert lib.ce_mppi_replan(None, None, None, 0, None, None, None, None) == B.CE_EINVAL
     lib.ce_mppi_destroy(None)  # NULL-safe
     assert B.ce_mppi_status_string(B.CE_EINVAL) == "invalid argument"
+    h = C.c_void_p()
+    assert lib.ce_mppi_batch_create(None, 1, C.byref(h)) == B.CE_EINVAL
+    arr = (C.c_void_p * 1)(None)
+    assert lib.ce_mppi_batch_create(arr, 0, C.byref(h)) == B.CE_EINVAL
+    assert lib.ce_mppi_batch_create(arr, 1, C.byref(h)) == B.CE_EINVAL  # NULL member
+    assert lib.ce_mppi_batch_replan(None, None, None) == B.CE_EINVAL
+    t = B.CeMppiBatchTuning(3, 4, 4, 0)
+    assert lib.ce_mppi_batch_set_tuning(None, C.byref(t)) == B.CE_EINVAL
+    lib.ce_mppi_batch_destroy(None)  # NULL-safe
 
 
 def test_no_device_reports_edevice(lib):

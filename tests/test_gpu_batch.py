@@ -1,0 +1,113 @@
+"""Batched form: every member of a batch gets bitwise the result of its own
+single-planner replan (same configuration, nominal, history and step), for
+members of uneven size and of every kind, over consecutive steps and under
+every tuning the autotuner may pick."""
+import numpy as np
+import pytest
+
+from paper_2607_06499_amd import workloads as W
+from tests import harness as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not H.gpu_ok():
+        pytest.skip("no GPU")
+
+
+MEMBERS = [
+    lambda: W.random_scene(21, num_samples=300, horizon=20, n_obs=5),
+    lambda: W.random_scene(22, num_samples=1111, horizon=45, n_obs=12),
+    lambda: W.unicycle_static_ahead(3, num_samples=700),
+    lambda: W.unicycle_dynamic_ahead(2, num_samples=2048),
+    lambda: W.random_scene(23, dynamics=W.ARM6, num_samples=400, horizon=16, n_obs=6),
+    lambda: W.arm6_dynamic(4, num_samples=512),
+    lambda: W.random_scene(24, num_samples=64, horizon=1, n_obs=0),
+    lambda: W.paper_arm_preset(2),
+]
+
+TUNINGS = [None, (1, 2, 2), (4, 16, 4)]
+
+
+def _setup():
+    from paper_2607_06499_amd import binding as B
+
+    scenes = [m() for m in MEMBERS]
+    batched = [B.Planner(s.spec) for s in scenes]
+    single = [B.Planner(s.spec) for s in scenes]
+    for s, a, b in zip(scenes, batched, single):
+        a.set_nominal(H.to_dev(s.U0))
+        b.set_nominal(H.to_dev(s.U0))
+    xs = [H.to_dev(np.asarray(s.x0, np.float32)) for s in scenes]
+    obs = [H.to_dev(np.asarray(s.obstacles, np.float32)) if len(s.obstacles) else None for s in scenes]
+    batch = B.Batch(batched)
+    batch.set_io(xs, obs)
+    return B, scenes, batched, single, xs, obs, batch
+
+
+def _compare(B, batched, single, tag):
+    torch = H.torch_mod()
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(batched, single)):
+        ia, ib = a.info(), b.info()
+        for k in ia:
+            assert np.array_equal(np.asarray(ia[k]), np.asarray(ib[k])), (tag, i, k)
+        assert torch.equal(a.u_out, b.u_out), (tag, i)
+        assert torch.equal(a.U_out, b.U_out), (tag, i)
+        assert torch.equal(a.get_nominal(), b.get_nominal()), (tag, i)
+        assert torch.equal(a.debug(B.DBG_COST, a.K), b.debug(B.DBG_COST, b.K)), (tag, i)
+        if ia["branch"] == 0 and ia["n_feasible"] > 0:
+            V = ia["n_feasible"]
+            assert torch.equal(a.debug(B.DBG_LABEL, V), b.debug(B.DBG_LABEL, V)), (tag, i)
+
+
+def test_batch_matches_single_replans():
+    B, scenes, batched, single, xs, obs, batch = _setup()
+    kinds = set()
+    for step, tune in enumerate(TUNINGS):
+        if tune is not None:
+            batch.set_tuning(*tune)
+        batch.replan()
+        for b, x, o in zip(single, xs, obs):
+            b.replan(x, o)
+        _compare(B, batched, single, f"step {step} tuning {tune}")
+        kinds |= {a.info()["branch"] for a in batched}
+    # the members exercised the clustering branch and a fallback branch
+    assert 0 in kinds and len(kinds) >= 2
+    batch.close()
+
+
+def test_autotune_restores_state_and_keeps_results():
+    B, scenes, batched, single, xs, obs, batch = _setup()
+    best, ms = batch.autotune(reps=2)
+    assert best["colg"] in (1, 2, 4) and ms > 0.0
+    assert batch.get_tuning() == best
+    # the tuner left every member where it was: the next batch replan is the
+    # first step of each member
+    batch.replan()
+    for b, x, o in zip(single, xs, obs):
+        b.replan(x, o)
+    _compare(B, batched, single, f"after autotune {best}")
+    assert all(a.info()["step"] == 0 for a in batched)
+    batch.close()
+
+
+def test_batch_rejects_bad_io():
+    from paper_2607_06499_amd import binding as B
+
+    s = W.random_scene(25, num_samples=128, horizon=10, n_obs=3)
+    pl = B.Planner(s.spec)
+    batch = B.Batch([pl])
+    batch.set_io([H.to_dev(np.asarray(s.x0, np.float32))], [H.to_dev(np.asarray(s.obstacles, np.float32))])
+    batch._io[0].n_obs = 65
+    with pytest.raises(B.CeMppiError):
+        batch.replan()
+    batch._io[0].n_obs = 3
+    batch._io[0].u_out = None
+    with pytest.raises(B.CeMppiError):
+        batch.replan()
+    with pytest.raises(B.CeMppiError):
+        B.Batch([pl, pl])
+    batch.close()

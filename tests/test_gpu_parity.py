@@ -282,6 +282,25 @@ def test_determinism_and_checkpoint():
     assert not np.array_equal(a["S"], b2["S"])
 
 
+def test_graph_and_direct_launch_agree():
+    """The graph replay and direct launches run the same kernels: bitwise
+    equal results over a few consecutive replans."""
+    from paper_2607_06499_amd import binding as B
+
+    s = W.unicycle_dynamic_ahead(5, num_samples=1500)
+    a, b = _planner(s.spec), _planner(s.spec)
+    b.set_launch_mode(B.LAUNCH_DIRECT)
+    for pl in (a, b):
+        _set_U(pl, s.U0)
+    for _ in range(3):
+        ra = H.gpu_replan(a, s.x0, s.obstacles)
+        rb = H.gpu_replan(b, s.x0, s.obstacles)
+        for k in ("S", "col", "label", "u_out", "U_new", "U_next"):
+            assert np.array_equal(ra[k], rb[k]), k
+        for k in ra["info"]:
+            assert np.array_equal(np.asarray(ra["info"][k]), np.asarray(rb["info"][k])), k
+
+
 def test_time_rollout_restores_state():
     """The rollout-only timing call leaves the planner exactly as it was."""
     s = W.unicycle_dynamic_ahead(4, num_samples=1024)
