@@ -42,12 +42,18 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--workload", default="unicycle_dynamic",
                     choices=["unicycle_dynamic", "unicycle_dynamic_ahead", "unicycle_static",
-                             "arm6_dynamic"])
+                             "arm6_dynamic", "batch_uneven", "served_sessions"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the clustering-branch companion measurement")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-form companion measurement")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served-form measurement")
+    ap.add_argument("--batch-steps", type=int, default=30,
+                    help="timed batch steps of the batched-form measurement")
     ap.add_argument("--rollout-reps", type=int, default=2000,
                     help="back-to-back rollout launches timed for the roofline")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -239,6 +245,172 @@ def run_workload(name, seed, W, K, torch, B, want_timing=True, rollout_reps=2000
                 kernel_ms=kernel_ms, mix=mix, mean_V=float(np.mean(ncl)) if ncl else 0.0, trees=tstat)
 
 
+def run_batch(seed, W, K, torch, B, autotune=True, n_planners=256):
+    """Batched form on the uneven 256-planner workload: a closed loop is
+    recorded with the batch (host plant between steps), then replayed from
+    the same initial states twice, as one batch graph launch per step and as
+    one plain replan per planner per step (graph replay each), on the same
+    device-resident inputs.  Returns throughput, step latency and whether the
+    two replays agree bitwise."""
+    from paper_2607_06499_amd import plant
+    from paper_2607_06499_amd import workloads as WL
+
+    members = WL.batch_uneven(seed, n_planners)
+    scenes = [m.scene for m in members]
+    n = len(scenes)
+    pls = [B.Planner(s.spec) for s in scenes]
+    for sc, pl in zip(scenes, pls):
+        pl.set_nominal(torch.as_tensor(sc.U0).cuda())
+    states0 = [pl.get_state() for pl in pls]
+    batch = B.Batch(pls)
+    T = W + K
+    dev = "cuda"
+    xdev = torch.zeros(T, n, 3, dtype=torch.float32, device=dev)
+    odev = [torch.zeros(T, max(sc.field.n, 1), 3, dtype=torch.float32, device=dev) for sc in scenes]
+    nobs = [sc.field.n for sc in scenes]
+    U = torch.zeros(T, n, 2, dtype=torch.float32, device=dev)
+    rows = lambda t: [U[t, i] for i in range(n)]
+    fields = [sc.field.copy() for sc in scenes]
+    xs = [sc.x0.astype(np.float64) for sc in scenes]
+    tune = None
+    # record
+    for t in range(T):
+        xdev[t].copy_(torch.from_numpy(np.asarray(xs, np.float32)))
+        for i, f in enumerate(fields):
+            if nobs[i]:
+                odev[i][t, : nobs[i]].copy_(torch.from_numpy(f.observation()))
+        batch.set_io([xdev[t, i] for i in range(n)],
+                     [odev[i][t, : nobs[i]] if nobs[i] else None for i in range(n)],
+                     want_U=False, want_info=False, u_outs=rows(t))
+        if t == 0 and autotune:
+            tune, _ = batch.autotune(reps=3)
+        batch.replan()
+        u = U[t].cpu().numpy().astype(np.float64)
+        for i in range(n):
+            xs[i] = plant.step(0, xs[i], u[i], scenes[i].spec.dt)
+            fields[i].step(scenes[i].spec.dt)
+    U_rec = U.cpu().numpy().copy()
+    io = []
+    for t in range(T):
+        batch.set_io([xdev[t, i] for i in range(n)],
+                     [odev[i][t, : nobs[i]] if nobs[i] else None for i in range(n)],
+                     want_U=False, want_info=False, u_outs=rows(t))
+        io.append((B.CeMppiBatchIO * n).from_buffer_copy(batch._io))
+    lib = B.load()
+    stream = int(torch.cuda.current_stream().cuda_stream)
+
+    def batch_pass(sync_each):
+        for pl, st in zip(pls, states0):
+            pl.set_state(st)
+        U.zero_()
+        lat = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(T):
+            if t == W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            t1 = time.perf_counter()
+            B._check("ce_mppi_batch_replan", lib.ce_mppi_batch_replan(batch.handle, io[t], stream))
+            if sync_each:
+                torch.cuda.synchronize()
+                if t >= W:
+                    lat.append(time.perf_counter() - t1)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, np.array(lat)
+
+    wall_b, _ = batch_pass(False)
+    same_b = bool(np.array_equal(U.cpu().numpy(), U_rec))
+    _, lat_b = batch_pass(True)
+    # the same steps as plain replans, one planner after another
+    for pl, st in zip(pls, states0):
+        pl.set_state(st)
+    U.zero_()
+    handles = [pl.handle for pl in pls]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(T):
+        if t == W:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        for i in range(n):
+            e = io[t][i]
+            lib.ce_mppi_replan(handles[i], e.x_t, e.obstacles, e.n_obs, e.u_out, None, None, stream)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    same_s = bool(np.array_equal(U.cpu().numpy(), U_rec))
+    Ks = np.array([sc.spec.num_samples for sc in scenes])
+    Ns = np.array([sc.spec.horizon for sc in scenes])
+    batch.close()
+    for pl in pls:
+        pl.close()
+    return {
+        "workload": f"batch_uneven: {n} unicycle planners, K log-uniform [256,16384] "
+                    f"(sum {int(Ks.sum())}), N uniform [20,60], 4..64 obstacles, half static "
+                    f"half dynamic, closed loop of {T} steps (seed {seed})",
+        "replans_per_s": round(n * K / wall_b, 1),
+        "ms_per_batch_step": round(1e3 * wall_b / K, 4),
+        "rollout_steps_per_s": round(float((Ks * Ns).sum()) * K / wall_b, 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat_b, 50)) * 1e3, 4),
+                       "p99": round(float(np.percentile(lat_b, 99)) * 1e3, 4)},
+        "sequential_plain": {"replans_per_s": round(n * K / wall_s, 1),
+                             "ms_per_round": round(1e3 * wall_s / K, 4)},
+        "speedup_vs_sequential": round(wall_s / wall_b, 3),
+        "tuning": tune,
+        "bitwise_equal_to_recorded_loop": {"batched": same_b, "sequential": same_s},
+    }
+
+
+def run_serve(seed, torch, B, rates=(2000.0, 5000.0, 10000.0, 20000.0), seconds=0.75):
+    """Served form: 512 resident sessions, Poisson-arrival replan requests at
+    each rate through the continuous-batching server and through the plain
+    form (one request per launch, one launch at a time), on the same trace.
+    Latency is request arrival to completion."""
+    from paper_2607_06499_amd import workloads as WL
+
+    sess = WL.served_sessions(seed)
+    scenes = [s.scene for s in sess]
+
+    def make(max_batch, max_inflight):
+        srv = B.Server(max_batch=max_batch, max_inflight=max_inflight)
+        for sc in scenes:
+            srv.open_session(sc.spec, sc.U0)
+        srv.start()
+        return srv
+
+    out = {"workload": f"served_sessions: {len(scenes)} sessions "
+                       f"({sum(s.kind == 'unicycle' for s in sess)} unicycle K log-uniform "
+                       f"[1024,8192], {sum(s.kind == 'arm' for s in sess)} arm K log-uniform "
+                       f"[1024,4096]), Poisson arrivals, sessions drawn uniformly (seed {seed})",
+           "rates": []}
+    for rate in rates:
+        n = int(rate * seconds)
+        t, sid = WL.poisson_arrivals(rate, n, len(scenes), seed)
+        x = np.zeros((n, 12), np.float32)
+        ob = np.zeros((n, 256), np.float32)
+        no = np.zeros(n, np.int32)
+        for i, k in enumerate(sid):
+            sc = scenes[k]
+            x[i, : len(sc.x0)] = sc.x0
+            o = np.asarray(sc.obstacles, np.float32)
+            no[i] = len(o)
+            ob[i, : o.size] = o.ravel()
+        row = {"offered_req_per_s": rate, "requests": n}
+        for name, mb, fl in (("continuous_batching", 256, 3), ("plain_one_per_launch", 1, 1)):
+            srv = make(mb, fl)
+            t0 = time.perf_counter()
+            lat, _ = srv.run_trace(t, sid, x, ob, no)
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+            srv.close()
+            row[name] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+                         "replans_per_s": round(n / wall, 1),
+                         "mean_batch": round(st["mean_batch"], 2), "launches": st["launches"]}
+        out["rates"].append(row)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -252,6 +424,27 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     W, K = args.warmup, args.steps
+    if args.workload == "served_sessions":
+        rs = run_serve(args.seed, torch, B)
+        top = rs["rates"][-1]["continuous_batching"]
+        print(json.dumps({"metric": "CE-MPPI served replans/s and p50/p99 latency (continuous batching, "
+                                    "512 sessions, Poisson arrivals)", "value": top["replans_per_s"],
+                          "unit": "replans/s", "n_gpus": 1, "steps": rs["rates"][-1]["requests"],
+                          "warmup": 0, "ms_per_step": round(1e3 / top["replans_per_s"], 5),
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f32", "data": "synthetic", "config": {"workload": rs["workload"]},
+                          "rates": rs["rates"]}))
+        return
+    if args.workload == "batch_uneven":
+        rb = run_batch(args.seed, min(W, 5), args.batch_steps, torch, B)
+        print(json.dumps({"metric": "CE-MPPI replans/s, batched form (256 uneven planners per "
+                                    "graph launch)", "value": rb["replans_per_s"], "unit": "replans/s",
+                          "n_gpus": 1, "steps": args.batch_steps, "warmup": min(W, 5),
+                          "ms_per_step": rb["ms_per_batch_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": rb["workload"]}, **{k: v for k, v in rb.items()
+                                                                     if k != "workload"}}))
+        return
     res = run_workload(args.workload, args.seed, W, K, torch, B, rollout_reps=args.rollout_reps)
     if args.calibrate_copy_mib:
         copy_calibration(torch, args.calibrate_copy_mib)
@@ -320,6 +513,10 @@ def main():
             "branch_mix": pr["mix"], "mean_feasible": round(pr["mean_V"], 1),
             "dbscan_trees": pr["trees"],
         }
+    if not args.no_batch and args.workload == "unicycle_dynamic":
+        out["batched_form"] = run_batch(args.seed, 5, args.batch_steps, torch, B)
+    if not args.no_serve and args.workload == "unicycle_dynamic":
+        out["served_form"] = run_serve(args.seed, torch, B)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(res["scene"], res["X"], res["OBS"], W, args.cpu_seconds,
                                            spec.history_len)

@@ -297,12 +297,12 @@ typedef struct ce_mppi_batch_tuning {
   int32_t colg;               /* column tiles per DBSCAN count item: 1, 2 or 4  */
   int32_t tile_blocks_per_cu; /* persistent blocks per CU, tiled DBSCAN: 1..16  */
   int32_t roll_blocks_per_cu; /* persistent blocks per CU, rollouts: 1..8       */
-  int32_t reserved;           /* must be 0                                      */
+  int32_t roll_per_wave;      /* rollouts per wave per work item: 1, 2, 4 or 8  */
 } ce_mppi_batch_tuning;
 
 /* Create a batch of n distinct planners (1 <= n <= CE_MPPI_MAX_BATCH) on the
  * same device, with the default tuning (colg 2, 8 tile blocks and 4 rollout
- * blocks per CU).  Errors: CE_EINVAL (NULL, duplicates, mixed devices, n out
+ * blocks per CU, 4 rollouts per wave).  Errors: CE_EINVAL (NULL, duplicates, mixed devices, n out
  * of range), CE_ENOMEM, CE_EDEVICE. */
 ce_status ce_mppi_batch_create(ce_mppi_planner* const* planners, int32_t n, ce_mppi_batch** out);
 void ce_mppi_batch_destroy(ce_mppi_batch* batch);
@@ -314,17 +314,104 @@ void ce_mppi_batch_destroy(ce_mppi_batch* batch);
  * CE_EDEVICE for HIP failures. */
 ce_status ce_mppi_batch_replan(ce_mppi_batch* batch, const ce_mppi_batch_io* io, void* stream);
 
+/* One replan of the listed members only (continuous batching): members[q]
+ * indexes the planner list given at creation (distinct), io[q] is its
+ * inputs/outputs.  The work tables of the subset are built on the host and
+ * uploaded with the pointers; launches rotate over three table areas, and a
+ * call waits (host side) until the area it reuses has finished its previous
+ * launch, so up to three subset launches can be in flight on different
+ * streams.  Members of launches in flight must not be listed again until
+ * those launches have finished (each member's replans are sequential).
+ * Errors: CE_EINVAL for NULL, out-of-range or repeated members and the io
+ * errors of ce_mppi_batch_replan; CE_EDEVICE for HIP failures. */
+ce_status ce_mppi_batch_replan_subset(ce_mppi_batch* batch, const int32_t* members, int32_t count,
+                                      const ce_mppi_batch_io* io, void* stream);
+
 ce_status ce_mppi_batch_set_tuning(ce_mppi_batch* batch, const ce_mppi_batch_tuning* tuning);
 ce_status ce_mppi_batch_get_tuning(const ce_mppi_batch* batch, ce_mppi_batch_tuning* tuning);
 
-/* Project-written autotuner: times `reps` batch replans on io for every
- * candidate shape (colg in {1,2,4} x tile blocks per CU in {2,4,8,16} x
- * rollout blocks per CU in {2,4}), keeps the fastest and returns it with its
- * mean time per batch replan.  The members' states are saved before and
+/* Project-written autotuner: times `reps` batch replans on io per candidate
+ * shape, first the rollout shape (rollouts per wave in {1,2,4,8} x rollout
+ * blocks per CU in {2,4}), then the DBSCAN shape (colg in {1,2,4} x tile
+ * blocks per CU in {4,8,16}); keeps the fastest and returns it with its mean
+ * time per batch replan.  Results do not depend on the shape: every member's
+ * output is bitwise the same under every tuning.  The members' states are saved before and
  * restored after every candidate, so the batch continues from where it was.
  * Synchronises the stream. */
 ce_status ce_mppi_batch_autotune(ce_mppi_batch* batch, const ce_mppi_batch_io* io, int32_t reps,
                                  void* stream, ce_mppi_batch_tuning* best, double* best_ms);
+
+/* ---- served form: continuous batching over resident sessions ----
+ *
+ * A server owns planner sessions (each a planner whose nominal sequence and
+ * observation history stay on the device between requests) and a scheduler
+ * thread.  Replan requests carry host inputs; the scheduler launches the
+ * pending requests of idle sessions together (one batched replan over those
+ * members, ce_mppi_batch_replan_subset), in arrival order, at most one request
+ * per session per launch and max_batch per launch, with up to max_inflight
+ * launches running at once on their own streams.  Every request's result is
+ * bitwise the one a plain ce_mppi_replan of its session would give for the
+ * same sequence of requests.  Sessions are admitted while their device memory
+ * (the planner arena) fits memory_budget. */
+typedef struct ce_mppi_server ce_mppi_server;
+
+typedef struct ce_mppi_server_config {
+  int32_t device;
+  int32_t max_batch;       /* requests per launch, 1..CE_MPPI_MAX_BATCH (1: one per launch) */
+  int32_t max_inflight;    /* launches in flight, 1..3                                      */
+  int32_t reserved;        /* must be 0                                                     */
+  uint64_t memory_budget;  /* device bytes the sessions may hold; 0: 90 % of free memory    */
+} ce_mppi_server_config;
+
+typedef struct ce_mppi_server_stats {
+  uint64_t launches, served;
+  double mean_batch;        /* requests per launch */
+  int32_t max_batch, max_inflight, sessions, reserved;
+  uint64_t session_bytes, budget_bytes;
+} ce_mppi_server_stats;
+
+ce_status ce_mppi_server_create(const ce_mppi_server_config* cfg, ce_mppi_server** out);
+
+/* Open a session (before start) with the planner configuration cfg on the
+ * server's device and, if U0 is not NULL, the host nominal sequence [N][m].
+ * Returns its id (0, 1, ...).  CE_EBUSY when its memory would exceed the
+ * budget (or 1024 sessions are open); CE_EINVAL after start. */
+ce_status ce_mppi_server_open_session(ce_mppi_server* server, const ce_mppi_config* cfg,
+                                      const float* U0, int32_t* session);
+
+/* Freeze the session set and start the scheduler thread. */
+ce_status ce_mppi_server_start(ce_mppi_server* server);
+
+/* Queue one replan of `session` with host inputs x_t [n] and obstacles
+ * [n_obs][p+1] (copied before return); *ticket identifies the request.
+ * Thread-safe. */
+ce_status ce_mppi_server_submit(ce_mppi_server* server, int32_t session, const float* x_t,
+                                const float* obstacles, int32_t n_obs, uint64_t* ticket);
+
+/* Block until the request is served: u_out [m] and info (host, may be NULL)
+ * receive its outputs, latency_s (may be NULL) the time from submission to
+ * completion.  A ticket is waited for once.  Thread-safe. */
+ce_status ce_mppi_server_wait(ce_mppi_server* server, uint64_t ticket, float* u_out,
+                              ce_mppi_info* info, double* latency_s);
+
+/* Load generator: submit request i at t_arrival[i] seconds after the call
+ * (ascending), for session[i], with state x_t[i*12 .. ] and obstacles rows
+ * packed from obstacles[i*256 .. ] (n_obs[i] rows of p+1 floats; NULL if no
+ * request has obstacles), then wait for all; latency_s[i] and u_out[i*6 ..]
+ * (host, may be NULL) receive the results. */
+ce_status ce_mppi_server_run_trace(ce_mppi_server* server, int32_t n, const double* t_arrival,
+                                   const int32_t* session, const float* x_t, const float* obstacles,
+                                   const int32_t* n_obs, double* latency_s, float* u_out);
+
+ce_status ce_mppi_server_get_stats(ce_mppi_server* server, ce_mppi_server_stats* out);
+
+/* The planner of a session (owned by the server), e.g. for its diagnostics or
+ * state; NULL for an unknown session.  Not to be replanned while the server
+ * runs. */
+ce_mppi_planner* ce_mppi_server_session_planner(ce_mppi_server* server, int32_t session);
+
+/* Stop the scheduler after serving the pending requests, free everything. */
+void ce_mppi_server_destroy(ce_mppi_server* server);
 
 /* ---- errors ---- */
 const char* ce_mppi_status_string(ce_status status);

@@ -110,7 +110,34 @@ class CeMppiBatchTuning(C.Structure):
         ("colg", C.c_int32),
         ("tile_blocks_per_cu", C.c_int32),
         ("roll_blocks_per_cu", C.c_int32),
+        ("roll_per_wave", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class CeMppiServerConfig(C.Structure):
+    _fields_ = [
+        ("device", C.c_int32),
+        ("max_batch", C.c_int32),
+        ("max_inflight", C.c_int32),
         ("reserved", C.c_int32),
+        ("memory_budget", C.c_uint64),
+    ]
+
+
+class CeMppiServerStats(C.Structure):
+    _fields_ = [
+        ("launches", C.c_uint64),
+        ("served", C.c_uint64),
+        ("mean_batch", C.c_double),
+        ("max_batch", C.c_int32),
+        ("max_inflight", C.c_int32),
+        ("sessions", C.c_int32),
+        ("reserved", C.c_int32),
+        ("session_bytes", C.c_uint64),
+        ("budget_bytes", C.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -160,7 +187,16 @@ def load():
         "ce_mppi_time_rollout": [_vp, _vp, _vp, C.c_int32, C.c_int32, _vp, C.POINTER(C.c_double)],
         "ce_mppi_batch_create": [C.POINTER(_vp), C.c_int32, C.POINTER(_vp)],
         "ce_mppi_batch_replan": [_vp, C.POINTER(CeMppiBatchIO), _vp],
+        "ce_mppi_batch_replan_subset": [_vp, C.POINTER(C.c_int32), C.c_int32, C.POINTER(CeMppiBatchIO),
+                                        _vp],
         "ce_mppi_batch_set_tuning": [_vp, C.POINTER(CeMppiBatchTuning)],
+        "ce_mppi_server_create": [C.POINTER(CeMppiServerConfig), C.POINTER(_vp)],
+        "ce_mppi_server_open_session": [_vp, C.POINTER(CeMppiConfig), _vp, C.POINTER(C.c_int32)],
+        "ce_mppi_server_start": [_vp],
+        "ce_mppi_server_submit": [_vp, C.c_int32, _vp, _vp, C.c_int32, C.POINTER(C.c_uint64)],
+        "ce_mppi_server_wait": [_vp, C.c_uint64, _vp, _vp, C.POINTER(C.c_double)],
+        "ce_mppi_server_run_trace": [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+        "ce_mppi_server_get_stats": [_vp, C.POINTER(CeMppiServerStats)],
         "ce_mppi_batch_get_tuning": [_vp, C.POINTER(CeMppiBatchTuning)],
         "ce_mppi_batch_autotune": [_vp, C.POINTER(CeMppiBatchIO), C.c_int32, _vp,
                                    C.POINTER(CeMppiBatchTuning), C.POINTER(C.c_double)],
@@ -173,6 +209,10 @@ def load():
     lib.ce_mppi_destroy.restype = None
     lib.ce_mppi_batch_destroy.argtypes = [_vp]
     lib.ce_mppi_batch_destroy.restype = None
+    lib.ce_mppi_server_destroy.argtypes = [_vp]
+    lib.ce_mppi_server_destroy.restype = None
+    lib.ce_mppi_server_session_planner.argtypes = [_vp, C.c_int32]
+    lib.ce_mppi_server_session_planner.restype = _vp
     lib.ce_mppi_status_string.argtypes = [C.c_int32]
     lib.ce_mppi_status_string.restype = C.c_char_p
     lib.ce_mppi_last_error.argtypes = []
@@ -448,9 +488,10 @@ class Batch:
         except Exception:
             pass
 
-    def set_io(self, xs, obstacles, want_U: bool = True, want_info: bool = True):
+    def set_io(self, xs, obstacles, want_U: bool = True, want_info: bool = True, u_outs=None):
         """Point the per-call inputs at device tensors (one per member) and the
-        outputs at each member planner's own output tensors."""
+        outputs at each member planner's own output tensors (or at the given
+        u_out tensors)."""
         keep = []
         for i, (pl, x, o) in enumerate(zip(self.planners, xs, obstacles)):
             e = self._io[i]
@@ -459,18 +500,32 @@ class Batch:
             e.obstacles = o.data_ptr() if n_obs else None
             e.n_obs = n_obs
             e.reserved = 0
-            e.u_out = pl.u_out.data_ptr()
+            e.u_out = (u_outs[i] if u_outs is not None else pl.u_out).data_ptr()
             e.U_out = pl.U_out.data_ptr() if want_U else None
             e.info = pl.info_buf.data_ptr() if want_info else None
             keep.append((x, o))
-        self._keep = keep
+        self._keep = (keep, u_outs)
 
     def replan(self, stream=None):
         _check("ce_mppi_batch_replan",
                load().ce_mppi_batch_replan(self.handle, self._io, _stream_handle(stream)))
 
-    def set_tuning(self, colg: int, tile_blocks_per_cu: int, roll_blocks_per_cu: int):
-        t = CeMppiBatchTuning(int(colg), int(tile_blocks_per_cu), int(roll_blocks_per_cu), 0)
+    def replan_subset(self, members, stream=None):
+        """Replan only the listed members (indices into the planner list) with
+        the inputs and outputs last given to ``set_io``."""
+        members = [int(m) for m in members]
+        idx = (C.c_int32 * len(members))(*members)
+        # out-of-range members are passed through for the library to reject
+        io = (CeMppiBatchIO * len(members))(
+            *[self._io[m] if 0 <= m < len(self._io) else CeMppiBatchIO() for m in members])
+        _check("ce_mppi_batch_replan_subset",
+               load().ce_mppi_batch_replan_subset(self.handle, idx, len(members), io,
+                                                  _stream_handle(stream)))
+
+    def set_tuning(self, colg: int, tile_blocks_per_cu: int, roll_blocks_per_cu: int,
+                   roll_per_wave: int = 4):
+        t = CeMppiBatchTuning(int(colg), int(tile_blocks_per_cu), int(roll_blocks_per_cu),
+                              int(roll_per_wave))
         _check("ce_mppi_batch_set_tuning", load().ce_mppi_batch_set_tuning(self.handle, C.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -485,3 +540,84 @@ class Batch:
                load().ce_mppi_batch_autotune(self.handle, self._io, int(reps), _stream_handle(stream),
                                              C.byref(t), C.byref(ms)))
         return t.as_dict(), ms.value
+
+
+class Server:
+    """Continuous-batching replan server over resident sessions
+    (``ce_mppi_server_*``).  Inputs and outputs are host numpy arrays."""
+
+    def __init__(self, device: int = 0, max_batch: int = 256, max_inflight: int = 3,
+                 memory_budget: int = 0):
+        cfg = CeMppiServerConfig(int(device), int(max_batch), int(max_inflight), 0, int(memory_budget))
+        h = _vp()
+        _check("ce_mppi_server_create", load().ce_mppi_server_create(C.byref(cfg), C.byref(h)))
+        self.handle = h.value
+        self.device = int(device)
+        self.dims = []
+
+    def open_session(self, spec, U0=None) -> int:
+        cfg = config_from_spec(spec, self.device)
+        sid = C.c_int32()
+        U = None if U0 is None else np.ascontiguousarray(U0, dtype=np.float32)
+        _check("ce_mppi_server_open_session",
+               load().ce_mppi_server_open_session(self.handle, C.byref(cfg),
+                                                  U.ctypes.data if U is not None else None,
+                                                  C.byref(sid)))
+        self.dims.append(_dims(int(spec.dynamics)))
+        return sid.value
+
+    def start(self):
+        _check("ce_mppi_server_start", load().ce_mppi_server_start(self.handle))
+
+    def submit(self, session: int, x_t, obstacles) -> int:
+        x = np.ascontiguousarray(x_t, dtype=np.float32)
+        o = np.ascontiguousarray(obstacles, dtype=np.float32)
+        t = C.c_uint64()
+        _check("ce_mppi_server_submit",
+               load().ce_mppi_server_submit(self.handle, int(session), x.ctypes.data,
+                                            o.ctypes.data if len(o) else None, len(o), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, session: int):
+        n, m, p = self.dims[session]
+        u = np.zeros(m, np.float32)
+        info = CeMppiInfo()
+        lat = C.c_double()
+        _check("ce_mppi_server_wait",
+               load().ce_mppi_server_wait(self.handle, int(ticket), u.ctypes.data, C.byref(info),
+                                          C.byref(lat)))
+        return u, info.as_dict(), lat.value
+
+    def run_trace(self, t_arrival, sessions, x, obstacles, n_obs):
+        """Replay a request trace: arrays t_arrival [n] (s), sessions [n],
+        x [n][12], obstacles [n][256] (rows of p+1 floats packed), n_obs [n].
+        Returns (latency_s [n], u_out [n][6])."""
+        n = len(t_arrival)
+        t = np.ascontiguousarray(t_arrival, dtype=np.float64)
+        sess = np.ascontiguousarray(sessions, dtype=np.int32)
+        xs = np.ascontiguousarray(x, dtype=np.float32)
+        ob = np.ascontiguousarray(obstacles, dtype=np.float32)
+        no = np.ascontiguousarray(n_obs, dtype=np.int32)
+        lat = np.zeros(n, np.float64)
+        u = np.zeros((n, 6), np.float32)
+        _check("ce_mppi_server_run_trace",
+               load().ce_mppi_server_run_trace(self.handle, n, t.ctypes.data, sess.ctypes.data,
+                                               xs.ctypes.data, ob.ctypes.data, no.ctypes.data,
+                                               lat.ctypes.data, u.ctypes.data))
+        return lat, u
+
+    def stats(self) -> dict:
+        st = CeMppiServerStats()
+        _check("ce_mppi_server_get_stats", load().ce_mppi_server_get_stats(self.handle, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().ce_mppi_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

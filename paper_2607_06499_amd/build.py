@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcemppi.so")
-SOURCES = ["rollout.hip", "cluster.hip", "capi.cpp", "batch.cpp"]
+SOURCES = ["rollout.hip", "cluster.hip", "capi.cpp", "batch.cpp", "server.cpp"]
 ARCH = os.environ.get("CEMPPI_OFFLOAD_ARCH", "gfx950")
 
 
@@ -25,7 +25,7 @@ def command(out: str = LIB, extra=()) -> list:
         hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
         # packed FP32 instructions are kept out of every kernel
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-Wall", "-Wno-unused-function",
+        "-Wall", "-Wno-unused-function", "-pthread",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
         *[os.path.join(CSRC, s) for s in SOURCES],
         *extra,

@@ -3,6 +3,7 @@
 // replan.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -128,6 +129,15 @@ void build_cfg(const ce_mppi_config* u, Cfg& c) {
   c.seg = (c.dyn == CE_DYN_UNICYCLE && c.N + 1 <= 32) ? 32 : 64;
   c.rpb = kRollWaves * (64 / c.seg);
   c.nblk_roll = (c.K + c.rpb - 1) / c.rpb;
+  // every rollout state lies within max|v| N dt of the start position (the
+  // clamped speed bounds each step's displacement)
+  {
+    const double vmax = std::max(std::fabs((double)u->u_min[0]), std::fabs((double)u->u_max[0]));
+    c.reach = (u->dynamics == CE_DYN_UNICYCLE && std::isfinite(vmax))
+                  ? (float)(vmax * u->horizon * (double)u->dt)
+                  : INFINITY;
+  }
+  c.npart = (c.K + kGroup - 1) / kGroup;
   c.dt = u->dt;
   c.lambda = u->lambda;
   c.norm_eps = u->norm_eps;
@@ -269,7 +279,8 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_S = cv.take<float>(K), o_col = cv.take<int>(K), o_first = cv.take<int>(K);
   const size_t o_pT = cv.take<float>(K * p), o_pF = cv.take<float>(K * p), o_g = cv.take<float>(K * p);
   const size_t o_eps = cv.take<float>(K * NM);
-  const size_t o_part = cv.take<float>((size_t)c.nblk_roll * kPart);
+  // room for the groups of the widest block (kMaxR rounds of 2 rollouts per wave)
+  const size_t o_part = cv.take<float>((size_t)(c.npart + kMaxRpb * kMaxR / kGroup) * kPart);
   const size_t o_vidx = cv.take<int>(K), o_z = cv.take<float>(K * zs), o_gv = cv.take<float>(K * zs);
   const size_t o_Sv = cv.take<float>(K);
   const size_t o_nc = cv.take<int>(K), o_mcn = cv.take<int>(K), o_root = cv.take<int>(K);

@@ -46,7 +46,7 @@ struct ZVec<3> {
 __device__ __forceinline__ bool is_min_field(int f) { return f == P_SMIN_ALL || f == P_SMIN_FEAS; }
 
 // ---------------------------------------------------------------------------
-// Reduction of the rollout blocks' partial records (256-thread blocks):
+// Reduction of the rollout-group partial records (256-thread blocks):
 // thread t owns records t, t+256, ... (coalesced), then a fixed tree.  Also
 // returns the number of feasible rollouts in records [0, upto).
 __device__ void reduce_partials(const Cfg& c, const Bufs& b, int upto, float* s_tot, int* s_before) {
@@ -57,7 +57,7 @@ __device__ void reduce_partials(const Cfg& c, const Bufs& b, int upto, float* s_
   for (int f = 0; f < kPart; ++f) acc[f] = is_min_field(f) ? INFINITY : 0.f;
   acc[kPart] = 0.f;
   const float4* rows = reinterpret_cast<const float4*>(b.part);
-  for (int i = tid; i < c.nblk_roll; i += 256) {
+  for (int i = tid; i < c.npart; i += 256) {
     const float4 x = rows[3 * i], y = rows[3 * i + 1], z = rows[3 * i + 2];
     const float v[kPart] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w, z.x, z.y, z.z, z.w};
 #pragma unroll
@@ -125,7 +125,7 @@ __device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx
   using ZT = typename ZVec<P>::T;
   __shared__ float s_tot[kPart + 1];
   __shared__ int s_before;
-  const int blk0 = (bx * 256) / c.rpb;
+  const int blk0 = (bx * 256) / kGroup;
   reduce_partials(c, b, blk0, s_tot, &s_before);
   const int bad = b.ctrl->nonfinite;
   const Totals T = decide(c, s_tot, bad);
@@ -981,7 +981,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Cfg c, Bufs b, float* __
 
 __global__ __launch_bounds__(kFinThreads) void kb_plan(CSlotStatic st, PlanOut o) {
   for (int kd = 0; kd < 2; ++kd) {
-    const int n = o.n[kd];
+    const int n = *o.n[kd];
     if (n == 0) continue;
     const int q = threadIdx.x;
     int ncnt = 0, nadj = 0, nroot = 0;
@@ -1185,30 +1185,30 @@ void launch_batch_post(Launcher& L, const SlotStatic* st, const SlotIO* io, cons
   const CSlotStatic cst = (CSlotStatic)st;
   const CSlotIO cio = (CSlotIO)io;
   for (int kd = 0; kd < 2; ++kd) {
-    if (!T.compact[kd].n) continue;
+    if (!T.has[kd]) continue;
     if (kd == 0) L(kb_compact<2>, dim3(T.grid_compact[0]), dim3(256), cst, T.compact[0]);
     else L(kb_compact<3>, dim3(T.grid_compact[1]), dim3(256), cst, T.compact[1]);
   }
   L(kb_plan, dim3(1), dim3(kFinThreads), cst, T.plan);
   for (int kd = 0; kd < 2; ++kd) {
-    if (!T.compact[kd].n) continue;
+    if (!T.has[kd]) continue;
     if (kd == 0) launch_batch_dbscan<2>(L, cst, T, 0);
     else launch_batch_dbscan<3>(L, cst, T, 1);
   }
   for (int kd = 0; kd < 2; ++kd)
-    if (T.compact[kd].n) L(kb_roots, dim3(T.grid_roots), dim3(256), cst, T.roots[kd]);
+    if (T.has[kd]) L(kb_roots, dim3(T.grid_roots), dim3(256), cst, T.roots[kd]);
   for (int kd = 0; kd < 2; ++kd) {
-    if (!T.compact[kd].n) continue;
+    if (!T.has[kd]) continue;
     if (kd == 0) L(kb_tree_adj<2>, dim3(T.grid_tile), dim3(kTile), cst, T.adj[0]);
     else L(kb_tree_adj<3>, dim3(T.grid_tile), dim3(kTile), cst, T.adj[1]);
   }
   for (int kd = 0; kd < 2; ++kd) {
-    if (!T.compact[kd].n) continue;
+    if (!T.has[kd]) continue;
     if (kd == 0) L(kb_tree_cc<2>, dim3(T.grid_cc[0]), dim3(kFinThreads), cst, T.cc[0]);
     else L(kb_tree_cc<3>, dim3(T.grid_cc[1]), dim3(kFinThreads), cst, T.cc[1]);
   }
   for (int kd = 0; kd < 2; ++kd) {
-    if (!T.compact[kd].n) continue;
+    if (!T.has[kd]) continue;
     if (kd == 0) L(kb_stats<2>, dim3(T.grid_stats[0]), dim3(256), cst, T.stats[0]);
     else L(kb_stats<3>, dim3(T.grid_stats[1]), dim3(256), cst, T.stats[1]);
   }

@@ -19,7 +19,9 @@ constexpr int kWave = 64;
 // segment) or two (32-lane segments) when N + 1 <= 32.
 constexpr int kRollThreads = 512;
 constexpr int kRollWaves = kRollThreads / 64;
-constexpr int kMaxRpb = 2 * kRollWaves;
+constexpr int kMaxRpb = 2 * kRollWaves;  // rollouts per block at one round per wave
+constexpr int kMaxR = 8;                 // rollout rounds per wave (batched form)
+constexpr int kGroup = 8;                // rollouts per partial record
 // per-block partial record of the rollout reduction (floats)
 constexpr int kPart = 12;
 enum PartField {
@@ -68,6 +70,7 @@ struct Ctrl {
 struct Cfg {
   int dyn, N, K, m, n, p, NM, B;
   int seg, rpb, nblk_roll;
+  int npart;        // ceil(K / kGroup) partial records
   float dt, lambda, norm_eps;
   float L[36];
   float umin[6], umax[6];
@@ -77,6 +80,7 @@ struct Cfg {
   float v_obs_min;
   int ref_mode, max_obs;
   float robot_r;
+  float reach;      // unicycle: bound on |p(x_j) - p(x_t)|, max|v| N dt (infinite: no bound)
   float goal[6], Q[6], R[6], Qf[6];
   float dh_a[6], dh_d[6], dh_ca[6], dh_sa[6], dh_off[6];
   int ns;
@@ -103,7 +107,7 @@ struct Bufs {
   float* pF;       // [K][p]
   float* g;        // [K][p]
   float* eps;      // [K][N][m]
-  float* part;     // [nblk_roll][kPart]
+  float* part;     // [npart (+ slack)][kPart] rollout-group partial records
   // compacted feasible set
   int* vidx;       // [K]
   float* z;        // [K][zs] zs = 2 (p = 2) or 4 (p = 3)
@@ -151,23 +155,25 @@ typedef const __attribute__((address_space(4))) SlotStatic* CSlotStatic;
 typedef const __attribute__((address_space(4))) SlotIO* CSlotIO;
 
 // Work table of one phase over one group of planners: slot[q] is the slot of
-// the q-th planner, pref[0..n] the exclusive prefix of its work items.
+// the q-th planner, pref[0..n] the exclusive prefix of its work items; the
+// count n is read from device memory, so one graph serves any member subset.
 struct Tab {
   const int* slot;
   const int* pref;
-  int n;
+  const int* n;
 };
 
 // Persistent loop over the items of a table: block i takes items i, i +
 // gridDim.x, ...; f(slot, local item) runs with every thread of the block.
 template <typename F>
 __device__ __forceinline__ void for_each_item(const Tab& t, int* s_pref, F&& f) {
-  for (int i = threadIdx.x; i <= t.n; i += blockDim.x) s_pref[i] = t.pref[i];
+  const int n = __builtin_amdgcn_readfirstlane(*t.n);
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) s_pref[i] = t.pref[i];
   __syncthreads();
-  const int total = s_pref[t.n];
+  const int total = s_pref[n];
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     // the planner of item it: the last q with pref[q] <= it
-    int lo = 0, hi = t.n - 1;
+    int lo = 0, hi = n - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (s_pref[mid] <= it) lo = mid;
@@ -187,7 +193,7 @@ __device__ __forceinline__ void for_each_item(const Tab& t, int* s_pref, F&& f) 
 // planner of the batch.
 struct PlanOut {
   const int* slot[2];   // planners with p = 2 and p = 3
-  int n[2];
+  const int* n[2];      // their counts (device memory)
   int* pref_cnt[2];     // count and lowest-core-neighbour tiles
   int* pref_adj[2];     // tree-adjacency tiles
   int* pref_roots[2];   // root-following blocks of 256 points
@@ -201,6 +207,7 @@ struct BatchTabs {
   int grid_compact[2], grid_cc[2], grid_stats[2], grid_update, grid_finish;
   int grid_tile, grid_roots;
   int colg;
+  int has[2];  // the batch has planners with p = 2 / p = 3 (their phases are launched)
 };
 
 // ---------------------------------------------------------------------------

@@ -18,8 +18,11 @@ namespace cemppi {
 // ---------------------------------------------------------------------------
 // shared prologue: obstacles into LDS, finiteness, closest obstacle o*.
 struct ObsLds {
-  float4 o[kMaxObs];  // (x, y, z, R^2) with R = robot/sphere radius + obstacle radius
-  float r[kMaxObs];   // obstacle radius
+  float4 o[kMaxObs];     // (x, y, z, R^2) with R = robot/sphere radius + obstacle radius
+  float r[kMaxObs];      // obstacle radius
+  float4 live[kMaxObs];  // the obstacles a rollout can reach, in index order
+  int idx[kMaxObs];      // their obstacle indices
+  int n_live;
 };
 
 // Arm forward kinematics: origins P0..P6 of the standard DH chain
@@ -161,6 +164,24 @@ __device__ void prologue(const Cfg& c, const float* __restrict__ x_t, const floa
       }
     }
     if (tid == 0) s_closest = n_obs > 0 ? idx : -1;
+    // Broad phase (unicycle): every state of a rollout lies within
+    // reach = max|v| N dt of p(x_t), so an obstacle whose surface is farther
+    // than that (with a margin far above the FP32 rounding of the positions)
+    // is never in contact; it is left out of the collision loops.  The kept
+    // obstacles stay in index order, so the lowest-index rule is unchanged.
+    bool keep = tid < n_obs;
+    if (DYN == 0 && keep && c.reach < INFINITY) {
+      const float R = c.robot_r + L.r[tid];
+      const float d = sqrtf(dist2_2(x_t[0], x_t[1], L.o[tid].x, L.o[tid].y));
+      keep = !(d > c.reach + R + (1e-3f * (c.reach + R) + 1e-3f));
+    }
+    const unsigned long long m = __ballot(keep);
+    if (keep) {
+      const int pos = __popcll(m & ((1ull << tid) - 1ull));
+      L.live[pos] = L.o[tid];
+      L.idx[pos] = tid;
+    }
+    if (tid == 0) L.n_live = __popcll(m);
   }
   __syncthreads();
 }
@@ -223,42 +244,54 @@ __device__ __forceinline__ void rollout_contrib(float* rec, bool active, int col
   }
 }
 
-// Sum the per-rollout records of this block (fixed order) into part[block].
-__device__ __forceinline__ void write_block_partial(const Bufs& b, float (*recs)[kPart], int rpb, int bx) {
+// Partial records of groups of kGroup consecutive rollouts, each summed in
+// rollout order: the grouping (and so every rounding) is the same however
+// the rollouts were spread over waves, blocks or loop rounds.  recs holds the
+// rpb records of the block's rollouts bx*rpb .. bx*rpb+rpb-1.
+__device__ __forceinline__ void write_group_partials(const Bufs& b, float (*recs)[kPart], int rpb, int bx) {
   __syncthreads();
-  if (threadIdx.x < kPart) {
-    const int f = threadIdx.x;
-    float acc = (f == P_SMIN_ALL || f == P_SMIN_FEAS) ? INFINITY : 0.f;
-    for (int r = 0; r < rpb; ++r) {
-      const float v = recs[r][f];
-      acc = (f == P_SMIN_ALL || f == P_SMIN_FEAS) ? fminf(acc, v) : acc + v;
+  const int ng = rpb / kGroup;
+  for (int t = threadIdx.x; t < ng * kPart; t += blockDim.x) {
+    const int g = t / kPart, f = t - g * kPart;
+    const bool mn = f == P_SMIN_ALL || f == P_SMIN_FEAS;
+    float acc = mn ? INFINITY : 0.f;
+    for (int r = 0; r < kGroup; ++r) {
+      const float v = recs[g * kGroup + r][f];
+      acc = mn ? fminf(acc, v) : acc + v;
     }
-    b.part[(size_t)bx * kPart + f] = acc;
+    b.part[((size_t)bx * ng + g) * kPart + f] = acc;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Unicycle rollouts (Sec. III-A): state (x, y, theta), control (v, omega).
-template <int SEG>
-__device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ x_t, const float* __restrict__ obs, int n_obs) {
+// R rounds per wave: each wave runs R rollouts per block item, the nominal
+// sequence staying in registers between rounds.
+template <int SEG, int R = 1>
+__device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& b, int bx, int by,
+                                                      int nbx, const float* __restrict__ x_t,
+                                                      const float* __restrict__ obs, int n_obs) {
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
-  __shared__ float s_rec[kMaxRpb][kPart];
+  __shared__ float s_rec[kRollWaves * (kWave / SEG) * R][kPart];
   prologue<0>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
   if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
 
   constexpr int SPW = kWave / SEG;
+  constexpr int RPB = kRollWaves * SPW * R;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int j = lane & (SEG - 1), sgi = lane / SEG;
-  const int kloc = wave * SPW + sgi;
-  const int k = bx * (kRollWaves * SPW) + kloc;
   const int N = c.N;
-  const bool act = (k < c.K) && !bad;
   const float dt = c.dt;
   const float x0 = x_t[0], y0 = x_t[1], th0 = x_t[2];
+  const float n0 = j < N ? b.U[j * 2] : 0.f, n1 = j < N ? b.U[j * 2 + 1] : 0.f;
+  for (int rr = 0; rr < R; ++rr) {
+  const int kloc = (rr * kRollWaves + wave) * SPW + sgi;
+  const int k = bx * RPB + kloc;
+  const bool act = (k < c.K) && !bad;
 
   // noise, perturbation and clamp (Eq. (3)); applied perturbation kept
   float uv = 0.f, uw = 0.f;
@@ -267,7 +300,6 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
     step_gaussians<2>(c, step, k, j, g);
     const float e0 = c.L[0] * g[0];
     const float e1 = c.L[2] * g[0] + c.L[3] * g[1];
-    const float n0 = b.U[j * 2], n1 = b.U[j * 2 + 1];
     const float t0 = n0 + e0, t1 = n1 + e1;
     uv = fminf(fmaxf(t0, c.umin[0]), c.umax[0]);
     uw = fminf(fmaxf(t1, c.umin[1]), c.umax[1]);
@@ -297,18 +329,19 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   // pass 1: does this state touch any obstacle?  pass 2 (only in waves with
   // a contact): the lowest obstacle index touched
   const bool chk = act && j >= 1 && j <= N;
+  const int n_live = L.n_live;
   bool any = false;
   if (chk) {
-    for (int i = 0; i < n_obs; ++i) {
-      const float4 o = L.o[i];
+    for (int i = 0; i < n_live; ++i) {
+      const float4 o = L.live[i];
       any |= dist2_2(px, py, o.x, o.y) <= o.w;
     }
   }
   int hit = kInt32Max;
   if (__ballot(any) != 0ull && any) {
-    for (int i = n_obs - 1; i >= 0; --i) {
-      const float4 o = L.o[i];
-      hit = dist2_2(px, py, o.x, o.y) <= o.w ? i : hit;
+    for (int i = n_live - 1; i >= 0; --i) {
+      const float4 o = L.live[i];
+      hit = dist2_2(px, py, o.x, o.y) <= o.w ? L.idx[i] : hit;
     }
   }
   // first colliding state of each segment (lowest lane with a hit)
@@ -343,7 +376,8 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
     }
     rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 2);
   }
-  write_block_partial(b, s_rec, kRollWaves * SPW, bx);
+  }
+  write_group_partials(b, s_rec, RPB, bx);
 }
 
 template <int SEG>
@@ -355,24 +389,32 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b
 // Six-joint arm rollouts (Sec. III-C): joint-velocity control, q_{j+1} =
 // q_j + u_j dt; end-effector cost, joint-limit penalty, link spheres against
 // obstacle spheres.
-__device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ x_t, const float* __restrict__ obs, int n_obs) {
+template <int R = 1>
+__device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
+                                                 const float* __restrict__ x_t,
+                                                 const float* __restrict__ obs, int n_obs) {
   constexpr int SEG = 64;
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
-  __shared__ float s_rec[kMaxRpb][kPart];
+  __shared__ float s_rec[kRollWaves * R][kPart];
   prologue<1>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
   if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
 
+  constexpr int RPB = kRollWaves * R;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int j = lane;
-  const int kloc = wave;
-  const int k = bx * kRollWaves + kloc;
   const int N = c.N;
-  const bool act = (k < c.K) && !bad;
   const float dt = c.dt;
+  float un[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) un[i] = j < N ? b.U[j * 6 + i] : 0.f;
+  for (int rr = 0; rr < R; ++rr) {
+  const int kloc = rr * kRollWaves + wave;
+  const int k = bx * RPB + kloc;
+  const bool act = (k < c.K) && !bad;
 
   float u[6];
 #pragma unroll
@@ -387,7 +429,7 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
 #pragma unroll
       for (int cc = 0; cc < 6; ++cc)
         if (cc <= i) e += c.L[i * 6 + cc] * g[cc];
-      const float n0 = b.U[j * 6 + i];
+      const float n0 = un[i];
       const float t = n0 + e;
       u[i] = fminf(fmaxf(t, c.umin[i]), c.umax[i]);
       a[i] = u[i] == t ? e : u[i] - n0;
@@ -473,7 +515,8 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
     }
     rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 3);
   }
-  write_block_partial(b, s_rec, kRollWaves, bx);
+  }
+  write_group_partials(b, s_rec, RPB, bx);
 }
 
 __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b, const float* __restrict__ x_t, const float* __restrict__ obs, int n_obs) {
@@ -482,23 +525,24 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b, con
 
 // ---------------------------------------------------------------------------
 // Batched rollouts: one persistent launch per rollout kind covers the rollout
-// blocks of every planner of that kind in the batch.
-template <int SEG>
+// blocks of every planner of that kind in the batch; R rounds per wave.
+template <int SEG, int R>
 __global__ __launch_bounds__(kRollThreads) void kb_rollout_unicycle(CSlotStatic st, CSlotIO io, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
   for_each_item(t, s_pref, [&](int slot, int local) {
     const SlotStatic& S = *(const SlotStatic*)(st + slot);
     const SlotIO& I = *(const SlotIO*)(io + slot);
-    rollout_unicycle_body<SEG>(S.c, S.b, local, 0, 0, I.x_t, I.obs, I.n_obs);
+    rollout_unicycle_body<SEG, R>(S.c, S.b, local, 0, 0, I.x_t, I.obs, I.n_obs);
   });
 }
 
+template <int R>
 __global__ __launch_bounds__(kRollThreads) void kb_rollout_arm(CSlotStatic st, CSlotIO io, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
   for_each_item(t, s_pref, [&](int slot, int local) {
     const SlotStatic& S = *(const SlotStatic*)(st + slot);
     const SlotIO& I = *(const SlotIO*)(io + slot);
-    rollout_arm_body(S.c, S.b, local, 0, 0, I.x_t, I.obs, I.n_obs);
+    rollout_arm_body<R>(S.c, S.b, local, 0, 0, I.x_t, I.obs, I.n_obs);
   });
 }
 
@@ -539,7 +583,7 @@ __global__ __launch_bounds__(kRollThreads) void k_reduce_records(Cfg c, Bufs b,
     }
     rollout_contrib(s_rec[threadIdx.x], act, col, f, closest, S, src, P);
   }
-  write_block_partial(b, s_rec, c.rpb, (int)blockIdx.x);
+  write_group_partials(b, s_rec, c.rpb, (int)blockIdx.x);
 }
 
 // Philox words and standard normals of every rollout (stage entry point):
@@ -569,15 +613,26 @@ __global__ void k_stage_noise(Cfg c, uint32_t step, uint32_t* __restrict__ words
 
 // ---------------------------------------------------------------------------
 // host-side launchers
-// kind 0: unicycle on 32-lane segments, 1: unicycle on 64 lanes, 2: arm
-void launch_batch_rollout(Launcher& L, int kind, const SlotStatic* st, const SlotIO* io, Tab t,
+// kind 0: unicycle on 32-lane segments, 1: unicycle on 64 lanes, 2: arm;
+// r: rounds per wave (1, 2, 4 or 8)
+template <int R>
+static void launch_batch_rollout_r(Launcher& L, int kind, CSlotStatic st, CSlotIO io, Tab t, int grid) {
+  if (kind == 0) L(kb_rollout_unicycle<32, R>, dim3(grid), dim3(kRollThreads), st, io, t);
+  else if (kind == 1) L(kb_rollout_unicycle<64, R>, dim3(grid), dim3(kRollThreads), st, io, t);
+  else L(kb_rollout_arm<R>, dim3(grid), dim3(kRollThreads), st, io, t);
+}
+
+void launch_batch_rollout(Launcher& L, int kind, int r, const SlotStatic* st, const SlotIO* io, Tab t,
                           int grid) {
   if (grid <= 0) return;
   const CSlotStatic cst = (CSlotStatic)st;
   const CSlotIO cio = (CSlotIO)io;
-  if (kind == 0) L(kb_rollout_unicycle<32>, dim3(grid), dim3(kRollThreads), cst, cio, t);
-  else if (kind == 1) L(kb_rollout_unicycle<64>, dim3(grid), dim3(kRollThreads), cst, cio, t);
-  else L(kb_rollout_arm, dim3(grid), dim3(kRollThreads), cst, cio, t);
+  switch (r) {
+    case 2: launch_batch_rollout_r<2>(L, kind, cst, cio, t, grid); break;
+    case 4: launch_batch_rollout_r<4>(L, kind, cst, cio, t, grid); break;
+    case 8: launch_batch_rollout_r<8>(L, kind, cst, cio, t, grid); break;
+    default: launch_batch_rollout_r<1>(L, kind, cst, cio, t, grid); break;
+  }
 }
 
 void launch_rollout(Launcher& L, const Cfg& c, const Bufs& b, const float* x_t, const float* obs,

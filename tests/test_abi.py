@@ -49,6 +49,8 @@ int main(void) {
          offsetof(ce_mppi_info, margin), offsetof(ce_mppi_info, weight_sum),
          sizeof(ce_mppi_batch_io), offsetof(ce_mppi_batch_io, n_obs), offsetof(ce_mppi_batch_io, u_out),
          offsetof(ce_mppi_batch_io, info), sizeof(ce_mppi_batch_tuning));
+  printf("%zu %zu %zu %zu\n", sizeof(ce_mppi_server_config), offsetof(ce_mppi_server_config, memory_budget),
+         sizeof(ce_mppi_server_stats), offsetof(ce_mppi_server_stats, session_bytes));
   return 0;
 }
 '''
@@ -72,6 +74,10 @@ int main(void) {
     assert vals[8] == B.CeMppiBatchIO.u_out.offset
     assert vals[9] == B.CeMppiBatchIO.info.offset
     assert vals[10] == C.sizeof(B.CeMppiBatchTuning)
+    assert vals[11] == C.sizeof(B.CeMppiServerConfig)
+    assert vals[12] == B.CeMppiServerConfig.memory_budget.offset
+    assert vals[13] == C.sizeof(B.CeMppiServerStats)
+    assert vals[14] == B.CeMppiServerStats.session_bytes.offset
 
 
 def test_config_init_defaults(lib):
@@ -124,9 +130,17 @@ def test_null_arguments(lib):
     assert lib.ce_mppi_batch_create(arr, 0, C.byref(h)) == B.CE_EINVAL
     assert lib.ce_mppi_batch_create(arr, 1, C.byref(h)) == B.CE_EINVAL  # NULL member
     assert lib.ce_mppi_batch_replan(None, None, None) == B.CE_EINVAL
-    t = B.CeMppiBatchTuning(3, 4, 4, 0)
+    t = B.CeMppiBatchTuning(3, 4, 4, 1)
     assert lib.ce_mppi_batch_set_tuning(None, C.byref(t)) == B.CE_EINVAL
     lib.ce_mppi_batch_destroy(None)  # NULL-safe
+    assert lib.ce_mppi_server_create(None, None) == B.CE_EINVAL
+    cfg = B.CeMppiServerConfig(0, 0, 1, 0, 0)
+    assert lib.ce_mppi_server_create(C.byref(cfg), C.byref(h)) == B.CE_EINVAL  # max_batch 0
+    cfg = B.CeMppiServerConfig(0, 4, 4, 0, 0)
+    assert lib.ce_mppi_server_create(C.byref(cfg), C.byref(h)) == B.CE_EINVAL  # max_inflight 4
+    assert lib.ce_mppi_server_start(None) == B.CE_EINVAL
+    assert lib.ce_mppi_server_session_planner(None, 0) is None
+    lib.ce_mppi_server_destroy(None)  # NULL-safe
 
 
 def test_no_device_reports_edevice(lib):

@@ -28,7 +28,7 @@ MEMBERS = [
     lambda: W.paper_arm_preset(2),
 ]
 
-TUNINGS = [None, (1, 2, 2), (4, 16, 4)]
+TUNINGS = [None, (1, 2, 2, 1), (4, 16, 4, 8), (2, 4, 2, 2)]
 
 
 def _setup():
@@ -91,6 +91,33 @@ def test_autotune_restores_state_and_keeps_results():
         b.replan(x, o)
     _compare(B, batched, single, f"after autotune {best}")
     assert all(a.info()["step"] == 0 for a in batched)
+    batch.close()
+
+
+def test_subset_launches_match_single_replans():
+    """Launches over member subsets (the continuous-batching primitive), on
+    two streams, give each listed member exactly its single-planner step."""
+    B, scenes, batched, single, xs, obs, batch = _setup()
+    torch = H.torch_mod()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    rounds = [[0, 2, 4, 6], [1, 3, 5, 7], [7, 0], [2, 3, 4], [5], [6, 1, 0]]
+    for i, members in enumerate(rounds):
+        with torch.cuda.stream(streams[i % 2]):
+            batch.replan_subset(members, stream=streams[i % 2])
+        streams[i % 2].synchronize()
+        for m in members:
+            single[m].replan(xs[m], obs[m])
+        torch.cuda.synchronize()
+        for m in members:
+            assert torch.equal(batched[m].u_out, single[m].u_out), (i, m)
+            assert torch.equal(batched[m].get_nominal(), single[m].get_nominal()), (i, m)
+            ia, ib = batched[m].info(), single[m].info()
+            for k in ia:
+                assert np.array_equal(np.asarray(ia[k]), np.asarray(ib[k])), (i, m, k)
+    with pytest.raises(B.CeMppiError):
+        batch.replan_subset([0, 0])
+    with pytest.raises(B.CeMppiError):
+        batch.replan_subset([len(batched)])
     batch.close()
 
 

@@ -301,6 +301,38 @@ def test_graph_and_direct_launch_agree():
             assert np.array_equal(np.asarray(ra["info"][k]), np.asarray(rb["info"][k])), k
 
 
+def test_broad_phase_keeps_every_reachable_obstacle():
+    """Rollouts at the speed bound reach max|v| N dt: an obstacle whose
+    surface lies just inside that reach is hit, one just beyond the margin is
+    left out, and every collision flag and first contact equals the oracle's
+    (which tests every obstacle)."""
+    import math
+
+    N, dt, v = 40, 0.05, 0.8
+    reach = v * N * dt
+    spec = W.PlannerSpec(num_samples=1024, horizon=N, dt=dt, noise_chol=W.diag_chol([0.5, 1e-3], 2),
+                         u_min=W.TABLE1_UMIN, u_max=W.TABLE1_UMAX, dbscan_eps=0.3,
+                         dbscan_min_pts=10, goal=[5.0, 0.0, 0, 0, 0, 0], seed=9).rounded()
+    R = 0.3
+    # surfaces at reach - 0.01 (hit), reach + 0.0025 (inside the margin, no
+    # contact) and reach + 0.02 (left out), on three headings fanned around +x
+    obs = []
+    for d, ang in ((reach - 0.01, 0.0), (reach + 0.0025, 0.6), (reach + 0.02, -0.6)):
+        c = d + R
+        obs.append([c * math.cos(ang), c * math.sin(ang), R])
+    obs = np.asarray(obs, np.float32)
+    U0 = np.zeros((N, 2), np.float32)
+    U0[:, 0] = 5.0  # every step clamps at the bound
+    x0 = np.zeros(3, np.float32)
+    pl = _planner(spec)
+    _set_U(pl, U0)
+    r = H.gpu_replan(pl, x0, obs)
+    o = oracle.replan(spec, x0, U0, obs)
+    _compare_rollouts(r, o, spec)
+    assert int(o["col"].sum()) > 0 and set(np.unique(o["first_obs"][o["col"] == 1])) == {0}
+    assert np.array_equal(r["col"], o["col"])
+
+
 def test_time_rollout_restores_state():
     """The rollout-only timing call leaves the planner exactly as it was."""
     s = W.unicycle_dynamic_ahead(4, num_samples=1024)
