@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--workload", default="unicycle_dynamic",
                     choices=["unicycle_dynamic", "unicycle_dynamic_ahead", "unicycle_static",
-                             "arm6_dynamic", "batch_uneven", "served_sessions"])
+                             "unicycle_static_ahead", "arm6_dynamic", "batch_uneven",
+                             "served_sessions"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -50,6 +51,8 @@ def parse():
                     help="skip the clustering-branch companion measurement")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-form companion measurement")
+    ap.add_argument("--no-companions", action="store_true",
+                    help="skip the static 2-D and arm workloads")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served-form measurement")
     ap.add_argument("--batch-steps", type=int, default=30,
@@ -67,6 +70,7 @@ def scene_for(name, seed):
     return {"unicycle_dynamic": W.unicycle_dynamic,
             "unicycle_dynamic_ahead": W.unicycle_dynamic_ahead,
             "unicycle_static": W.unicycle_static,
+            "unicycle_static_ahead": W.unicycle_static_ahead,
             "arm6_dynamic": W.arm6_dynamic}[name](seed)
 
 
@@ -243,6 +247,35 @@ def run_workload(name, seed, W, K, torch, B, want_timing=True, rollout_reps=2000
     pl.close()
     return dict(scene=scene, X=X, OBS=OBS, wall=wall, gpu=gpu, lat=lat, same=same, timing=timing,
                 kernel_ms=kernel_ms, mix=mix, mean_V=float(np.mean(ncl)) if ncl else 0.0, trees=tstat)
+
+
+def rollout_flops(spec, n_obs):
+    """Algorithmic FP32 flops of one rollout launch: 25 + 5 n_obs per
+    unicycle rollout-step (noise transform, clamp, dynamics, cost, 5 per
+    obstacle test); forward kinematics 480, link spheres 48, 8 per
+    sphere-obstacle test and 40 for noise and cost per arm rollout-step."""
+    steps = spec.num_samples * spec.horizon
+    if spec.dynamics == 0:
+        return steps * (25 + 5 * n_obs)
+    return steps * (480 + 48 + 8 * n_obs * spec.n_link_spheres + 40)
+
+
+def companion(name, seed, W, K, torch, B, label):
+    """Throughput, latency and rollout roofline of another single-planner
+    workload (same protocol as the headline)."""
+    r = run_workload(name, seed, W, K, torch, B, rollout_reps=500)
+    spec = r["scene"].spec
+    n_obs = r["OBS"].shape[1]
+    flops = rollout_flops(spec, n_obs)
+    return {
+        "workload": label, "replans_per_s": round(K / r["wall"], 1),
+        "rollout_steps_per_s": round(K / r["wall"] * spec.num_samples * spec.horizon, 1),
+        "latency_ms": {"p50": round(float(np.percentile(r["lat"], 50)) * 1e3, 4),
+                       "p99": round(float(np.percentile(r["lat"], 99)) * 1e3, 4)},
+        "branch_mix": r["mix"], "replay_bit_exact": r["same"],
+        "rollout_kernel_ms": round(r["kernel_ms"], 5),
+        "rollout_tflops": round(flops / (r["kernel_ms"] * 1e-3) / 1e12, 4),
+    }
 
 
 def run_batch(seed, W, K, torch, B, autotune=True, n_planners=256):
@@ -455,8 +488,7 @@ def main():
     # roofline of the rollout kernel: algorithmic FP32 flops per rollout-step
     # 25 + 5 n_obs (noise transform, clamp, dynamics, cost, 5 per obstacle)
     n_obs = res["OBS"].shape[1]
-    flops = rollout_steps * (25 + 5 * n_obs) if spec.dynamics == 0 else \
-        rollout_steps * (480 + 48 + 8 * n_obs * spec.n_link_spheres + 40)
+    flops = rollout_flops(spec, n_obs)
     t_roll = res["kernel_ms"] * 1e-3
     t_roll_launch = res["timing"]["rollout_ms"] / res["timing"]["count"] * 1e-3
     achieved = flops / t_roll / 1e12
@@ -513,6 +545,16 @@ def main():
             "branch_mix": pr["mix"], "mean_feasible": round(pr["mean_V"], 1),
             "dbscan_trees": pr["trees"],
         }
+    if not args.no_companions and args.workload == "unicycle_dynamic":
+        out["static_2d"] = companion("unicycle_static", args.seed, W, 200, torch, B,
+                                     "unicycle_static: K=1024 N=30 dt=0.1, 8 static obstacles, "
+                                     "closed loop of 200 timed replans")
+        out["static_2d_ahead"] = companion("unicycle_static_ahead", args.seed, W, 200, torch, B,
+                                           "unicycle_static_ahead: obstacle 1.2 m ahead, clustering "
+                                           "branch")
+        out["arm_6dof"] = companion("arm6_dynamic", args.seed, W, K, torch, B,
+                                    "arm6_dynamic: K=4096 N=32 dt=0.05, 16 moving spheres, "
+                                    "8 link spheres, closed loop")
     if not args.no_batch and args.workload == "unicycle_dynamic":
         out["batched_form"] = run_batch(args.seed, 5, args.batch_steps, torch, B)
     if not args.no_serve and args.workload == "unicycle_dynamic":

@@ -194,7 +194,8 @@ enum {
   CE_DBG_V_IDX = 6,      /* int32 [|V|]          feasible rollouts, ascending      */
   CE_DBG_Z = 7,          /* float [|V|][p]       feature of Eq. (13)               */
   CE_DBG_G = 8,          /* float [|V|][p]       direction of Eq. (15)             */
-  CE_DBG_NCOUNT = 9,     /* int32 [|V|]          eps-neighbour counts              */
+  CE_DBG_NCOUNT = 9,     /* int32 [|V|]  eps-neighbour count; exact below minPts, */
+                         /*              between minPts and the count above it */
   CE_DBG_LABEL = 10,     /* int32 [|V|]          cluster label, -1 noise           */
   CE_DBG_CLUSTER_COST = 11, /* float [M]         mean cost per cluster             */
   CE_DBG_CLUSTER_DIR = 12,  /* float [M][p]      normalised mean direction Eq.(16) */
@@ -294,14 +295,14 @@ typedef struct ce_mppi_batch_io {
 
 /* Launch shapes of a batch (chosen by ce_mppi_batch_autotune or set). */
 typedef struct ce_mppi_batch_tuning {
-  int32_t colg;               /* column tiles per DBSCAN count item: 1, 2 or 4  */
+  int32_t colg;               /* column tiles per DBSCAN count item: 1,2,4 or 8 */
   int32_t tile_blocks_per_cu; /* persistent blocks per CU, tiled DBSCAN: 1..16  */
   int32_t roll_blocks_per_cu; /* persistent blocks per CU, rollouts: 1..8       */
   int32_t roll_per_wave;      /* rollouts per wave per work item: 1, 2, 4 or 8  */
 } ce_mppi_batch_tuning;
 
 /* Create a batch of n distinct planners (1 <= n <= CE_MPPI_MAX_BATCH) on the
- * same device, with the default tuning (colg 2, 8 tile blocks and 4 rollout
+ * same device, with the default tuning (colg 8, 8 tile blocks and 4 rollout
  * blocks per CU, 4 rollouts per wave).  Errors: CE_EINVAL (NULL, duplicates, mixed devices, n out
  * of range), CE_ENOMEM, CE_EDEVICE. */
 ce_status ce_mppi_batch_create(ce_mppi_planner* const* planners, int32_t n, ce_mppi_batch** out);
@@ -332,7 +333,7 @@ ce_status ce_mppi_batch_get_tuning(const ce_mppi_batch* batch, ce_mppi_batch_tun
 
 /* Project-written autotuner: times `reps` batch replans on io per candidate
  * shape, first the rollout shape (rollouts per wave in {1,2,4,8} x rollout
- * blocks per CU in {2,4}), then the DBSCAN shape (colg in {1,2,4} x tile
+ * blocks per CU in {2,4}), then the DBSCAN shape (colg in {2,4,8} x tile
  * blocks per CU in {4,8,16}); keeps the fastest and returns it with its mean
  * time per batch replan.  Results do not depend on the shape: every member's
  * output is bitwise the same under every tuning.  The members' states are saved before and

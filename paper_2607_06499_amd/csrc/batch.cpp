@@ -105,7 +105,7 @@ struct ce_mppi_batch {
   // totals of the full member set (upper bounds of any subset): grid sizes
   int roll_total[3][4] = {};
   int compact_total[2] = {0, 0}, stats_total[2] = {0, 0}, update_total = 0, n_p[2] = {0, 0};
-  ce_mppi_batch_tuning tune{2, 8, 4, 4};
+  ce_mppi_batch_tuning tune{8, 8, 4, 4};
 };
 
 namespace {
@@ -243,8 +243,8 @@ hipError_t build_graph(ce_mppi_batch* B, Area& a) {
 
 ce_status check_tuning(const ce_mppi_batch_tuning* t) {
   if (!t) return set_error(CE_EINVAL, "tuning is NULL");
-  if (t->colg != 1 && t->colg != 2 && t->colg != 4)
-    return set_error(CE_EINVAL, "colg must be 1, 2 or 4");
+  if (t->colg != 1 && t->colg != 2 && t->colg != 4 && t->colg != 8)
+    return set_error(CE_EINVAL, "colg must be 1, 2, 4 or 8");
   if (t->tile_blocks_per_cu < 1 || t->tile_blocks_per_cu > 16)
     return set_error(CE_EINVAL, "tile_blocks_per_cu out of range 1..16");
   if (t->roll_blocks_per_cu < 1 || t->roll_blocks_per_cu > 8)
@@ -425,8 +425,13 @@ ce_status ce_mppi_batch_replan_subset(ce_mppi_batch* B, const int32_t* members, 
   Area& a = B->area[B->next_area];
   B->next_area = B->next_area + 1 < kAreas ? B->next_area + 1 : 1;
   hipError_t e = hipSuccess;
-  // the area's tables are in use until its previous launch has finished
-  if (a.used) e = hipEventSynchronize(a.done);
+  // the area's tables are in use until its previous launch has finished; the
+  // wait polls the event (a blocking wait may give up the thread's time
+  // slice, which shows up as millisecond latency spikes in a serving loop)
+  if (a.used) {
+    while ((e = hipEventQuery(a.done)) == hipErrorNotReady) {
+    }
+  }
   if (e != hipSuccess) return set_hip_error(e, "batch area wait");
   SlotIO* hio = reinterpret_cast<SlotIO*>(a.h_mem);
   for (int q = 0; q < count; ++q) hio[members[q]] = s[q];
@@ -500,7 +505,7 @@ ce_status ce_mppi_batch_autotune(ce_mppi_batch* B, const ce_mppi_batch_io* io, i
   for (int stage = 0; stage < 2 && result == CE_OK; ++stage) {
     if (stage == 1) {
       cand.clear();
-      for (int cg : {1, 2, 4})
+      for (int cg : {2, 4, 8})
         for (int tb : {4, 8, 16}) cand.push_back({cg, tb, win.roll_blocks_per_cu, win.roll_per_wave});
     }
     for (const ce_mppi_batch_tuning& tc : cand) {

@@ -225,7 +225,9 @@ __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, 
   for (int u = 0; u < COLG; ++u) {
     const int J = J0 + u;
     if (J >= J1) break;
-    __syncthreads();
+    // only the core test needs the count: once every row of the block has
+    // minPts neighbours in this chunk, the rest of the chunk cannot change it
+    if (__syncthreads_and(k >= V || cnt >= c.min_pts)) break;
     s_z[threadIdx.x] = zl[u];
     __syncthreads();
     const int ncol = min(kTile, V - J * kTile);
@@ -236,7 +238,7 @@ __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, 
 
 template <int P>
 __global__ __launch_bounds__(kTile) void k_count(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
-  count_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
+  count_body<P, kCntGroup>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
 }
 
 // 2. lowest-index core neighbour of every point (core points include
@@ -269,7 +271,9 @@ __device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, in
   for (int u = 0; u < COLG; ++u) {
     const int J = J0 + u;
     if (J >= J1) break;
-    __syncthreads();
+    // columns ascend: once every row of the block has a core neighbour, the
+    // later tiles hold only higher indices
+    if (__syncthreads_and(k >= V || m != kInt32Max)) break;
     // non-core columns are parked far away: they can never be a neighbour here
     s_z[threadIdx.x] = ncl[u] >= c.min_pts ? zl[u] : ZVec<P>::far();
     __syncthreads();
@@ -286,7 +290,7 @@ __device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, in
 
 template <int P>
 __global__ __launch_bounds__(kTile) void k_mcn(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
-  mcn_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
+  mcn_body<P, kCntGroup>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
 }
 
 // 3. roots: follow the hook chain of each core point (indices decrease, so the
@@ -1111,10 +1115,11 @@ template <int P>
 static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const float* zin, int Vin,
                             int ntile, int* lab_out, int* cnt_out, int* mout) {
   const int ngrp = (ntile + kColGroup - 1) / kColGroup;
-  dim3 tiles(ngrp, ntile), tb(kTile);
+  const int ncnt = (ntile + kCntGroup - 1) / kCntGroup;
+  dim3 tiles(ngrp, ntile), ctiles(ncnt, ntile), tb(kTile);
   const int nr = (ntile * kTile + 255) / 256;
-  L(k_count<P>, tiles, tb, c, b, zin, Vin);
-  L(k_mcn<P>, tiles, tb, c, b, zin, Vin);
+  L(k_count<P>, ctiles, tb, c, b, zin, Vin);
+  L(k_mcn<P>, ctiles, tb, c, b, zin, Vin);
   L(k_roots, dim3(nr), dim3(256), c, b, zin, Vin);
   L(k_tree_adj<P>, tiles, tb, c, b, zin, Vin, ngrp);
   L(k_tree_cc<P>, dim3(1), dim3(kFinThreads), c, b, zin, Vin, ngrp, mout, lab_out, cnt_out);
@@ -1169,6 +1174,10 @@ static void launch_batch_dbscan(Launcher& L, const CSlotStatic cst, const BatchT
     case 1:
       L(kb_count<P, 1>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);
       L(kb_mcn<P, 1>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);
+      break;
+    case 8:
+      L(kb_count<P, 8>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);
+      L(kb_mcn<P, 8>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);
       break;
     case 4:
       L(kb_count<P, 4>, dim3(T.grid_tile), tb, cst, T.cnt[kd]);

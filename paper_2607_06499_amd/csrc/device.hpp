@@ -39,7 +39,8 @@ constexpr int kUpdThreads = 256;
 constexpr int kFinThreads = 1024;
 // tree graph handled by the fast path
 constexpr int kMaxTrees = 64;
-constexpr int kColGroup = 2;   // column tiles per tiled DBSCAN block
+constexpr int kColGroup = 2;   // column tiles per tree-adjacency block
+constexpr int kCntGroup = 2;   // column tiles per count / core-neighbour block (early exit)
 constexpr int kOrBatch = 8;    // tree-slot loads in flight per lane
 constexpr int kLabBatch = 8;   // points per thread per labelling pass
 constexpr int kStatBatch = 4;  // points per thread per cluster-statistics pass

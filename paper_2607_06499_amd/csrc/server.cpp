@@ -342,6 +342,34 @@ ce_status ce_mppi_server_start(ce_mppi_server* S) {
     S->batch = nullptr;
     return set_hip_error(e, "server_start");
   }
+  // warm-up: one launch through every subset area, so that graph builds and
+  // first kernel loads happen before the first request (session 0 replans a
+  // zero state without obstacles; its state is saved before and restored)
+  {
+    size_t bytes = 0;
+    st = ce_mppi_state_size(S->sessions[0], &bytes);
+    std::vector<char> saved(bytes);
+    if (st == CE_OK) st = ce_mppi_get_state(S->sessions[0], saved.data(), bytes, S->launch[0].stream);
+    Launch& L = S->launch[0];
+    if (st == CE_OK) e = hipMemsetAsync(L.d_in, 0, sizeof(float) * kInStride, L.stream);
+    for (int k = 0; k < 3 && st == CE_OK && e == hipSuccess; ++k) {
+      const int32_t m = 0;
+      ce_mppi_batch_io io{};
+      io.x_t = L.d_in;
+      io.u_out = L.d_out;
+      io.info = L.d_info;
+      st = ce_mppi_batch_replan_subset(S->batch, &m, 1, &io, L.stream);
+    }
+    if (st == CE_OK && e == hipSuccess) e = hipStreamSynchronize(L.stream);
+    if (st == CE_OK && e == hipSuccess)
+      st = ce_mppi_set_state(S->sessions[0], saved.data(), bytes, L.stream);
+    if (st != CE_OK || e != hipSuccess) {
+      free_launches(S);
+      ce_mppi_batch_destroy(S->batch);
+      S->batch = nullptr;
+      return st != CE_OK ? st : set_hip_error(e, "server warm-up");
+    }
+  }
   S->session_busy.assign(S->sessions.size(), 0);
   S->started = true;
   S->t0 = Clock::now();

@@ -100,3 +100,14 @@ def canonical_partition(labels):
         if l >= 0:
             groups.setdefault(int(l), []).append(i)
     return sorted(tuple(g) for g in groups.values())
+
+
+def counts_agree(gpu, exact, min_pts: int) -> bool:
+    """Neighbour counts as the kernels report them: a count scan stops once
+    a point is known to be core, so the count is exact below minPts and lies
+    between minPts and the exact count for core points."""
+    gpu = np.asarray(gpu)
+    exact = np.asarray(exact)
+    low = exact < min_pts
+    return bool(np.array_equal(gpu[low], exact[low])
+                and np.all(gpu[~low] >= min_pts) and np.all(gpu[~low] <= exact[~low]))
