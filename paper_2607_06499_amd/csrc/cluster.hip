@@ -1126,6 +1126,10 @@ static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const floa
 }
 
 // Everything between the rollouts and the final combination.
+// Everything between the rollouts and the final combination, as one chain
+// (a graph fork into a clustering and a fallback branch was measured slower:
+// the cross-stream synchronisation of the branches costs more than the
+// overlap saves).
 void launch_post_rollout(Launcher& L, const Cfg& c, const Bufs& b) {
   const int nk = (c.K + 255) / 256;
   int* none = nullptr;
