@@ -283,6 +283,8 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_part = cv.take<float>((size_t)(c.npart + kMaxRpb * kMaxR / kGroup) * kPart);
   const size_t o_vidx = cv.take<int>(K), o_z = cv.take<float>(K * zs), o_gv = cv.take<float>(K * zs);
   const size_t o_Sv = cv.take<float>(K);
+  const size_t o_zs = cv.take<float>(K * zs), o_sid = cv.take<int>(K);
+  const size_t o_tlo = cv.take<float4>((size_t)c.ntile), o_thi = cv.take<float4>((size_t)c.ntile);
   const size_t o_nc = cv.take<int>(K), o_mcn = cv.take<int>(K), o_root = cv.take<int>(K);
   const size_t o_lab = cv.take<int>(K);
   const size_t o_rm = cv.take<unsigned long long>(nw);
@@ -314,6 +316,10 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   b.z = reinterpret_cast<float*>(base + o_z);
   b.gv = reinterpret_cast<float*>(base + o_gv);
   b.Sv = reinterpret_cast<float*>(base + o_Sv);
+  b.zs = reinterpret_cast<float*>(base + o_zs);
+  b.sid = reinterpret_cast<int*>(base + o_sid);
+  b.tlo = reinterpret_cast<float4*>(base + o_tlo);
+  b.thi = reinterpret_cast<float4*>(base + o_thi);
   b.ncount = reinterpret_cast<int*>(base + o_nc);
   b.mcn = reinterpret_cast<int*>(base + o_mcn);
   b.root = reinterpret_cast<int*>(base + o_root);

@@ -30,18 +30,57 @@ namespace cemppi {
 
 template <int P>
 struct ZVec;
+// Morton cell of a feature (points of the unit disc / ball; values outside
+// [-1, 1] are clamped): 64 x 64 cells in 2-D, 16 x 16 x 16 in 3-D, 12 bits.
+__device__ __forceinline__ int morton_q(float v, int g) {
+  const int q = (int)floorf((v + 1.f) * (0.5f * (float)g));
+  return q < 0 ? 0 : (q >= g ? g - 1 : q);
+}
+__device__ __forceinline__ unsigned spread2(unsigned v) {  // 6 bits -> every 2nd bit
+  v = (v | (v << 4)) & 0x0F0Fu;
+  v = (v | (v << 2)) & 0x3333u;
+  v = (v | (v << 1)) & 0x5555u;
+  return v;
+}
+__device__ __forceinline__ unsigned spread3(unsigned v) {  // 4 bits -> every 3rd bit
+  v = (v | (v << 4)) & 0x0C3u;
+  v = (v | (v << 2)) & 0x249u;
+  return v;
+}
 template <>
 struct ZVec<2> {
   using T = float2;
   static __device__ __forceinline__ T far() { return make_float2(1e30f, 1e30f); }
   static __device__ __forceinline__ float d2(T a, T b) { return dist2_2(a.x, a.y, b.x, b.y); }
+  static __device__ __forceinline__ int key(T a) {
+    return (int)(spread2((unsigned)morton_q(a.x, 64)) | (spread2((unsigned)morton_q(a.y, 64)) << 1));
+  }
+  static __device__ __forceinline__ float4 lift(T a) { return make_float4(a.x, a.y, 0.f, 0.f); }
 };
 template <>
 struct ZVec<3> {
   using T = float4;
   static __device__ __forceinline__ T far() { return make_float4(1e30f, 1e30f, 1e30f, 0.f); }
   static __device__ __forceinline__ float d2(T a, T b) { return dist2_3(a.x, a.y, a.z, b.x, b.y, b.z); }
+  static __device__ __forceinline__ int key(T a) {
+    return (int)(spread3((unsigned)morton_q(a.x, 16)) | (spread3((unsigned)morton_q(a.y, 16)) << 1) |
+                 (spread3((unsigned)morton_q(a.z, 16)) << 2));
+  }
+  static __device__ __forceinline__ float4 lift(T a) { return make_float4(a.x, a.y, a.z, 0.f); }
 };
+
+// Lower bound of the squared distance between two points of two boxes.
+__device__ __forceinline__ float box_gap2(float4 alo, float4 ahi, float4 blo, float4 bhi) {
+  const float gx = fmaxf(0.f, fmaxf(blo.x - ahi.x, alo.x - bhi.x));
+  const float gy = fmaxf(0.f, fmaxf(blo.y - ahi.y, alo.y - bhi.y));
+  const float gz = fmaxf(0.f, fmaxf(blo.z - ahi.z, alo.z - bhi.z));
+  return gx * gx + gy * gy + gz * gz;
+}
+// Tile pairs whose boxes are farther apart than eps hold no neighbour pair;
+// the margin is far above the FP32 rounding of the pair distances.
+__device__ __forceinline__ bool tiles_apart(const Cfg& c, const Bufs& b, int I, int J) {
+  return box_gap2(b.tlo[I], b.thi[I], b.tlo[J], b.thi[J]) > c.eps2 * (1.f + 1e-4f) + 1e-12f;
+}
 
 __device__ __forceinline__ bool is_min_field(int f) { return f == P_SMIN_ALL || f == P_SMIN_FEAS; }
 
@@ -199,10 +238,85 @@ __device__ __forceinline__ int dbscan_V(const Bufs& b, const float* zin, int Vin
 // the row point in registers and each column tile staged through LDS.
 __device__ __forceinline__ int ntiles_of(int V) { return (V + kTile - 1) / kTile; }
 
+// 0. spatial order (batched form): the features sorted by Morton cell
+// (counting sort in one block per planner), with their original indices, and
+// the bounding box of every tile of kTile consecutive sorted points.  The
+// batched count and tree-adjacency passes work on this order and skip tile
+// pairs whose boxes are farther apart than eps; every rule that names a point
+// (lowest-index core neighbour, roots, labels) uses the original index, so
+// no result depends on the order.  The single-planner path keeps the
+// original order: at one planner's sizes the extra launch costs more than
+// the culling saves.
+template <int P>
+__device__ __forceinline__ void sort_body(const Cfg& c, const Bufs& b, const float* zin, int Vin) {
+  using ZT = typename ZVec<P>::T;
+  __shared__ int s_bin[kSortBins];
+  const int V = dbscan_V(b, zin, Vin);
+  if (V == 0) return;
+  const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
+  ZT* zs = reinterpret_cast<ZT*>(b.zs);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kSortBins; i += kFinThreads) s_bin[i] = 0;
+  __syncthreads();
+  for (int a = tid; a < V; a += kFinThreads) atomicAdd(&s_bin[ZVec<P>::key(z[a])], 1);
+  __syncthreads();
+  constexpr int PER = kSortBins / kFinThreads;
+  int loc[PER], sum = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    loc[q] = s_bin[tid * PER + q];
+    sum += loc[q];
+  }
+  int tot;
+  int off = block_excl_scan<kFinThreads>(sum, &tot);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    s_bin[tid * PER + q] = off;
+    off += loc[q];
+  }
+  __syncthreads();
+  for (int a = tid; a < V; a += kFinThreads) {
+    const ZT v = z[a];
+    const int pos = atomicAdd(&s_bin[ZVec<P>::key(v)], 1);
+    zs[pos] = v;
+    b.sid[pos] = a;
+  }
+  __syncthreads();
+  // tile boxes: wave w takes tiles w, w + 16, ...; two points per lane
+  const int lane = tid & (kWave - 1), w = tid / kWave;
+  const int nt = ntiles_of(V);
+  for (int t = w; t < nt; t += kFinThreads / kWave) {
+    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.f), hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = t * kTile + h * kWave + lane;
+      if (k < V) {
+        const float4 v = ZVec<P>::lift(zs[k]);
+        lo = make_float4(fminf(lo.x, v.x), fminf(lo.y, v.y), fminf(lo.z, v.z), 0.f);
+        hi = make_float4(fmaxf(hi.x, v.x), fmaxf(hi.y, v.y), fmaxf(hi.z, v.z), 0.f);
+      }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      lo.x = fminf(lo.x, __shfl_xor(lo.x, d, kWave));
+      lo.y = fminf(lo.y, __shfl_xor(lo.y, d, kWave));
+      lo.z = fminf(lo.z, __shfl_xor(lo.z, d, kWave));
+      hi.x = fmaxf(hi.x, __shfl_xor(hi.x, d, kWave));
+      hi.y = fmaxf(hi.y, __shfl_xor(hi.y, d, kWave));
+      hi.z = fmaxf(hi.z, __shfl_xor(hi.z, d, kWave));
+    }
+    if (lane == 0) {
+      b.tlo[t] = lo;
+      b.thi[t] = hi;
+    }
+  }
+}
+
 // 1. neighbour counts: for each row point, its neighbours among the block's
-// column points (closed ball, itself included).
-template <int P, int COLG = kColGroup>
-__device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin) {
+// column points (closed ball, itself included), in sorted order.
+template <int P, int COLG = kColGroup, bool SORTED = false>
+__device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
+                                           const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
   __shared__ ZT s_z[kTile];
   const int V = dbscan_V(b, zin, Vin);
@@ -210,9 +324,10 @@ __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, 
   const int I = by, J0 = bx * COLG;
   if (I >= nt || J0 >= nt) return;
   const int J1 = min(J0 + COLG, nt);
-  const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
+  const ZT* z = reinterpret_cast<const ZT*>(SORTED ? b.zs : (zin ? zin : b.z));
   const int k = I * kTile + threadIdx.x;
   const ZT zk = k < V ? z[k] : ZVec<P>::far();
+  const int ok_k = SORTED ? (k < V ? b.sid[k] : 0) : k;
   ZT zl[COLG];
 #pragma unroll
   for (int u = 0; u < COLG; ++u) {
@@ -225,6 +340,7 @@ __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, 
   for (int u = 0; u < COLG; ++u) {
     const int J = J0 + u;
     if (J >= J1) break;
+    if (SORTED && tiles_apart(c, b, I, J)) continue;
     // only the core test needs the count: once every row of the block has
     // minPts neighbours in this chunk, the rest of the chunk cannot change it
     if (__syncthreads_and(k >= V || cnt >= c.min_pts)) break;
@@ -233,7 +349,7 @@ __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, 
     const int ncol = min(kTile, V - J * kTile);
     for (int t = 0; t < ncol; ++t) cnt += ZVec<P>::d2(zk, s_z[t]) <= r2 ? 1 : 0;
   }
-  if (k < V && cnt) atomicAdd(&b.ncount[k], cnt);
+  if (k < V && cnt) atomicAdd(&b.ncount[ok_k], cnt);
 }
 
 template <int P>
@@ -242,10 +358,12 @@ __global__ __launch_bounds__(kTile) void k_count(Cfg c, Bufs b, const float* __r
 }
 
 // 2. lowest-index core neighbour of every point (core points include
-// themselves).  Column tiles are visited in increasing order, so the first
-// hit of a row is its minimum within the block.
+// themselves).  This pass runs in the original order: column tiles ascend,
+// so the first hit of a row is its minimum within the block, and a block
+// stops once every row has one (in dense regions after the first tile).
 template <int P, int COLG = kColGroup>
-__device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin) {
+__device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
+                                         const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
   __shared__ ZT s_z[kTile];
   const int V = dbscan_V(b, zin, Vin);
@@ -271,8 +389,6 @@ __device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, in
   for (int u = 0; u < COLG; ++u) {
     const int J = J0 + u;
     if (J >= J1) break;
-    // columns ascend: once every row of the block has a core neighbour, the
-    // later tiles hold only higher indices
     if (__syncthreads_and(k >= V || m != kInt32Max)) break;
     // non-core columns are parked far away: they can never be a neighbour here
     s_z[threadIdx.x] = ncl[u] >= c.min_pts ? zl[u] : ZVec<P>::far();
@@ -363,8 +479,9 @@ __device__ __forceinline__ bool adj_block_live(int I, int g, int nt) {
   return I < nt && J0 < nt && J0 + kColGroup > I;
 }
 
-template <int P>
-__device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin, int ngrp) {
+template <int P, bool SORTED = false>
+__device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
+                                              const float* __restrict__ zin, int Vin, int ngrp) {
   using ZT = typename ZVec<P>::T;
   __shared__ ZT s_z[kTile];
   __shared__ uint2 s_bit[kTile];  // tree bit of the column point as two words, 0 if not core
@@ -375,22 +492,28 @@ __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int b
   const int nt = ntiles_of(V);
   const int I = by, g = bx;
   if (!adj_block_live(I, g, nt)) return;
-  const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
+  const ZT* z = reinterpret_cast<const ZT*>(SORTED ? b.zs : (zin ? zin : b.z));
   const int J0 = max(g * kColGroup, I), J1 = min(g * kColGroup + kColGroup, nt);
-  // every operand of the block is requested before the first wait
+  // every operand of the block is requested before the first wait (sorted
+  // positions first, then the per-point arrays at the original indices)
   const int k = I * kTile + threadIdx.x;
-  const int nck = k < V ? b.ncount[k] : 0;
-  const int rk = k < V ? b.root[k] : -1;
+  const int idk = SORTED ? (k < V ? b.sid[k] : 0) : k;
   const ZT zk0 = k < V ? z[k] : ZVec<P>::far();
-  int ncl[kColGroup], rl[kColGroup];
+  int idl[kColGroup], ncl[kColGroup], rl[kColGroup];
   ZT zl[kColGroup];
 #pragma unroll
   for (int u = 0; u < kColGroup; ++u) {
     const int l = (J0 + u) * kTile + threadIdx.x;
     const bool ok = J0 + u < J1 && l < V;
-    ncl[u] = ok ? b.ncount[l] : 0;
-    rl[u] = ok ? b.root[l] : -1;
+    idl[u] = ok ? (SORTED ? b.sid[l] : l) : -1;
     zl[u] = ok ? z[l] : ZVec<P>::far();
+  }
+  const int nck = k < V ? b.ncount[idk] : 0;
+  const int rk = k < V ? b.root[idk] : -1;
+#pragma unroll
+  for (int u = 0; u < kColGroup; ++u) {
+    ncl[u] = idl[u] >= 0 ? b.ncount[idl[u]] : 0;
+    rl[u] = idl[u] >= 0 ? b.root[idl[u]] : -1;
   }
   const int R = tree_prefix<kTile>(b, V, s_woff, s_rm);
   if (R < 2 || R > kMaxTrees) return;
@@ -403,6 +526,7 @@ __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int b
   for (int u = 0; u < kColGroup; ++u) {
     const int J = J0 + u;
     if (J >= J1) break;
+    if (SORTED && tiles_apart(c, b, I, J)) continue;
     const int tl = ncl[u] >= c.min_pts ? tree_id(s_rm, s_woff, rl[u]) : -1;
     __syncthreads();
     s_z[threadIdx.x] = tl >= 0 ? zl[u] : ZVec<P>::far();
@@ -1030,6 +1154,15 @@ __global__ __launch_bounds__(256) void kb_compact(CSlotStatic st, Tab t) {
 }
 
 // count / mcn items: local = I * ceil(nt / COLG) + g
+template <int P>
+__global__ __launch_bounds__(kFinThreads) void kb_sort(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item(t, s_pref, [&](int slot, int) {
+    CEMPPI_SLOT(slot);
+    sort_body<P>(c, b, nullptr, 0);
+  });
+}
+
 template <int P, int COLG>
 __global__ __launch_bounds__(kTile) void kb_count(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
@@ -1037,7 +1170,7 @@ __global__ __launch_bounds__(kTile) void kb_count(CSlotStatic st, Tab t) {
     CEMPPI_SLOT(slot);
     const int nt = ntiles_of(dbscan_V(b, nullptr, 0));
     const int ng = (nt + COLG - 1) / COLG;
-    count_body<P, COLG>(c, b, local % ng, local / ng, 0, nullptr, 0);
+    count_body<P, COLG, true>(c, b, local % ng, local / ng, 0, nullptr, 0);
   });
 }
 
@@ -1067,8 +1200,8 @@ __global__ __launch_bounds__(kTile) void kb_tree_adj(CSlotStatic st, Tab t) {
     CEMPPI_SLOT(slot);
     const int nt = ntiles_of(dbscan_V(b, nullptr, 0));
     const int ng = (nt + kColGroup - 1) / kColGroup;
-    tree_adj_body<P>(c, b, local % ng, local / ng, 0, nullptr, 0,
-                     (c.ntile + kColGroup - 1) / kColGroup);
+    tree_adj_body<P, true>(c, b, local % ng, local / ng, 0, nullptr, 0,
+                           (c.ntile + kColGroup - 1) / kColGroup);
   });
 }
 
@@ -1203,6 +1336,11 @@ void launch_batch_post(Launcher& L, const SlotStatic* st, const SlotIO* io, cons
     else L(kb_compact<3>, dim3(T.grid_compact[1]), dim3(256), cst, T.compact[1]);
   }
   L(kb_plan, dim3(1), dim3(kFinThreads), cst, T.plan);
+  for (int kd = 0; kd < 2; ++kd) {
+    if (!T.has[kd]) continue;
+    if (kd == 0) L(kb_sort<2>, dim3(T.grid_cc[0]), dim3(kFinThreads), cst, T.cc[0]);
+    else L(kb_sort<3>, dim3(T.grid_cc[1]), dim3(kFinThreads), cst, T.cc[1]);
+  }
   for (int kd = 0; kd < 2; ++kd) {
     if (!T.has[kd]) continue;
     if (kd == 0) launch_batch_dbscan<2>(L, cst, T, 0);

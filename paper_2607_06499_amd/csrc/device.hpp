@@ -41,6 +41,7 @@ constexpr int kFinThreads = 1024;
 constexpr int kMaxTrees = 64;
 constexpr int kColGroup = 2;   // column tiles per tree-adjacency block
 constexpr int kCntGroup = 2;   // column tiles per count / core-neighbour block (early exit)
+constexpr int kSortBins = 4096; // Morton cells of the DBSCAN spatial order
 constexpr int kOrBatch = 8;    // tree-slot loads in flight per lane
 constexpr int kLabBatch = 8;   // points per thread per labelling pass
 constexpr int kStatBatch = 4;  // points per thread per cluster-statistics pass
@@ -115,6 +116,10 @@ struct Bufs {
   float* gv;       // [K][zs]
   float* Sv;       // [K]
   // DBSCAN
+  float* zs;       // [K][zs] features in Morton order
+  int* sid;        // [K] original index of each sorted position
+  float4* tlo;     // [ntile] lower corner of each sorted tile's box
+  float4* thi;     // [ntile] upper corner
   int* ncount;     // [K]
   int* mcn;        // [K] lowest-index core neighbour (kInt32Max if none)
   int* root;       // [K] tree root (core points), -1 otherwise
