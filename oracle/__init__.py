@@ -17,6 +17,9 @@ from .oracle import (  # noqa: F401
     arm_frames,
     arm_spheres,
     simulate,
+    rotvec_quat,
+    rot_quat,
+    quat_angle,
     closest_obstacle,
     obstacle_velocity,
     dbscan,
@@ -25,6 +28,8 @@ from .oracle import (  # noqa: F401
     noise_blocks,
     UNICYCLE,
     ARM6,
+    FLAG_POSE_COST,
+    FLAG_OBS_CONST_VEL,
     ST_FALLBACK,
     ST_ALL_COLLIDE,
     ST_NO_CLUSTER,

@@ -220,6 +220,75 @@ void orc_arm_spheres(const double origins[7][3], int32_t ns, double* centres) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Orientation error of the arm's pose cost (Sec. III-C)              */
+/* ------------------------------------------------------------------ */
+
+/* Unit quaternion (w, x, y, z) of the rotation by angle |r| about r/|r|:
+ * (cos(|r|/2), sin(|r|/2) r/|r|); the identity for r = 0. */
+void orc_rotvec_quat(const double r[3], double q[4]) {
+  double th = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (th == 0.0) {
+    q[0] = 1.0;
+    q[1] = q[2] = q[3] = 0.0;
+    return;
+  }
+  double s = sin(0.5 * th) / th;
+  q[0] = cos(0.5 * th);
+  q[1] = s * r[0];
+  q[2] = s * r[1];
+  q[3] = s * r[2];
+}
+
+/* Unit quaternion of a rotation matrix.  The four quantities
+ * 4w^2 = 1 + R00 + R11 + R22, 4x^2 = 1 + R00 - R11 - R22, and so on, are
+ * compared and the largest component is recovered from its square root; the
+ * others follow from the off-diagonal sums and differences, divided by it.
+ * The sign of q is arbitrary (q and -q are the same rotation). */
+void orc_rot_quat(const double R[3][3], double q[4]) {
+  double d[4] = {1.0 + R[0][0] + R[1][1] + R[2][2], 1.0 + R[0][0] - R[1][1] - R[2][2],
+                 1.0 - R[0][0] + R[1][1] - R[2][2], 1.0 - R[0][0] - R[1][1] + R[2][2]};
+  int b = 0;
+  for (int i = 1; i < 4; ++i)
+    if (d[i] > d[b]) b = i;
+  double f = 0.5 * sqrt(d[b]); /* the largest |component| */
+  double k = 0.25 / f;
+  switch (b) {
+    case 0:
+      q[0] = f;
+      q[1] = (R[2][1] - R[1][2]) * k;
+      q[2] = (R[0][2] - R[2][0]) * k;
+      q[3] = (R[1][0] - R[0][1]) * k;
+      break;
+    case 1:
+      q[1] = f;
+      q[0] = (R[2][1] - R[1][2]) * k;
+      q[2] = (R[0][1] + R[1][0]) * k;
+      q[3] = (R[0][2] + R[2][0]) * k;
+      break;
+    case 2:
+      q[2] = f;
+      q[0] = (R[0][2] - R[2][0]) * k;
+      q[1] = (R[0][1] + R[1][0]) * k;
+      q[3] = (R[1][2] + R[2][1]) * k;
+      break;
+    default:
+      q[3] = f;
+      q[0] = (R[1][0] - R[0][1]) * k;
+      q[1] = (R[0][2] + R[2][0]) * k;
+      q[2] = (R[1][2] + R[2][1]) * k;
+      break;
+  }
+}
+
+/* Angle between two orientations given as unit quaternions: the relative
+ * rotation a^-1 b has scalar part <a, b>, so its angle is 2 acos |<a, b>|. */
+double orc_quat_angle(const double a[4], const double b[4]) {
+  double c = fabs(a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3]);
+  if (c > 1.0) c = 1.0;
+  return 2.0 * acos(c);
+}
+
+/* ------------------------------------------------------------------ */
 /* Single-precision decisions                                         */
 /* ------------------------------------------------------------------ */
 
@@ -271,16 +340,31 @@ static double sqdist(const double* a, const double* b, int32_t p) {
   return s;
 }
 
-/* stage cost l(x, u) */
-static double stage_cost(const orc_problem* P, const double* x, const double* u) {
+/* Pose terms of the real-robot cost (Sec. III-C) at joint angles q, with
+ * weights w = (w_p, w_R, w_c) and the collision indicator icol. */
+static double pose_terms(const orc_problem* P, const double* q, const double* w, int32_t icol) {
+  double org[7][3], rot[3][3], qe[4], qg[4];
+  orc_arm_frames(q, P->dh, org, rot);
+  orc_rot_quat(rot, qe);
+  orc_rotvec_quat(P->goal + 3, qg);
+  return w[0] * sqrt(sqdist(org[6], P->goal, 3)) + w[1] * orc_quat_angle(qe, qg) +
+         w[2] * (double)icol;
+}
+
+/* stage cost l(x, u); icol is I_col(x), used by the pose cost only */
+static double stage_cost(const orc_problem* P, const double* x, const double* u, int32_t icol) {
   double s = 0.0;
   if (P->dynamics == ORC_UNICYCLE) {
     for (int i = 0; i < 3; ++i) s += P->Q[i] * (x[i] - P->goal[i]) * (x[i] - P->goal[i]);
     for (int i = 0; i < 2; ++i) s += P->R[i] * u[i] * u[i];
   } else {
-    double org[7][3];
-    orc_arm_frames(x, P->dh, org, NULL);
-    s += P->Q[0] * sqdist(org[6], P->goal, 3);
+    if (P->flags & ORC_FLAG_POSE_COST) {
+      s += pose_terms(P, x, P->Q, icol);
+    } else {
+      double org[7][3];
+      orc_arm_frames(x, P->dh, org, NULL);
+      s += P->Q[0] * sqdist(org[6], P->goal, 3);
+    }
     s += limit_penalty(P, x);
     for (int i = 0; i < 6; ++i) s += P->R[i] * u[i] * u[i];
   }
@@ -288,14 +372,18 @@ static double stage_cost(const orc_problem* P, const double* x, const double* u)
 }
 
 /* terminal cost phi(x) */
-static double terminal_cost(const orc_problem* P, const double* x) {
+static double terminal_cost(const orc_problem* P, const double* x, int32_t icol) {
   double s = 0.0;
   if (P->dynamics == ORC_UNICYCLE) {
     for (int i = 0; i < 3; ++i) s += P->Qf[i] * (x[i] - P->goal[i]) * (x[i] - P->goal[i]);
   } else {
-    double org[7][3];
-    orc_arm_frames(x, P->dh, org, NULL);
-    s += P->Qf[0] * sqdist(org[6], P->goal, 3);
+    if (P->flags & ORC_FLAG_POSE_COST) {
+      s += pose_terms(P, x, P->Qf, icol);
+    } else {
+      double org[7][3];
+      orc_arm_frames(x, P->dh, org, NULL);
+      s += P->Qf[0] * sqdist(org[6], P->goal, 3);
+    }
     s += limit_penalty(P, x);
   }
   return s;
@@ -315,20 +403,25 @@ static void task_point(const orc_problem* P, const double* x, double* pt) {
   }
 }
 
-/* Collision test of one state against every obstacle (Sec. II-B.1).
- * Returns the lowest obstacle index in contact, or -1; lowers *clear to the
- * smallest relative distance to a contact boundary seen. */
-static int32_t state_contact(const orc_problem* P, const double* x, const double* obs, int32_t n_obs,
-                             double* clear) {
+/* Collision test of one state against every obstacle (Sec. II-B.1), the
+ * obstacles displaced by tj * vel (vel NULL: frozen).  Returns the lowest
+ * obstacle index in contact, or -1; lowers *clear to the smallest relative
+ * distance to a contact boundary seen. */
+static int32_t state_contact(const orc_problem* P, const double* x, const double* obs,
+                             const double* vel, int32_t n_obs, double tj, double* clear) {
   int32_t hit = -1;
   if (P->dynamics == ORC_UNICYCLE) {
     for (int32_t i = 0; i < n_obs; ++i) {
-      const double* o = obs + 3 * i;
-      double R = P->robot_radius + o[2];
+      double o[2] = {obs[3 * i], obs[3 * i + 1]};
+      if (vel) {
+        o[0] += tj * vel[2 * i];
+        o[1] += tj * vel[2 * i + 1];
+      }
+      double R = P->robot_radius + obs[3 * i + 2];
       double d = sqrt(sqdist(x, o, 2));
       double c = fabs(d - R) / (R > 0.0 ? R : 1.0);
       if (c < *clear) *clear = c;
-      if (hit < 0 && dec32_contact(x, o, 2, P->robot_radius, o[2])) hit = i;
+      if (hit < 0 && dec32_contact(x, o, 2, P->robot_radius, obs[3 * i + 2])) hit = i;
     }
   } else {
     double org[7][3];
@@ -336,13 +429,15 @@ static int32_t state_contact(const orc_problem* P, const double* x, const double
     orc_arm_frames(x, P->dh, org, NULL);
     orc_arm_spheres(org, P->n_link_spheres, cen);
     for (int32_t i = 0; i < n_obs; ++i) {
-      const double* o = obs + 4 * i;
+      double o[3] = {obs[4 * i], obs[4 * i + 1], obs[4 * i + 2]};
+      if (vel)
+        for (int c = 0; c < 3; ++c) o[c] += tj * vel[3 * i + c];
       for (int32_t s = 0; s < P->n_link_spheres; ++s) {
-        double R = P->link_sphere_radius + o[3];
+        double R = P->link_sphere_radius + obs[4 * i + 3];
         double d = sqrt(sqdist(cen + 3 * s, o, 3));
         double c = fabs(d - R) / (R > 0.0 ? R : 1.0);
         if (c < *clear) *clear = c;
-        if (hit < 0 && dec32_contact(cen + 3 * s, o, 3, P->link_sphere_radius, o[3])) hit = i;
+        if (hit < 0 && dec32_contact(cen + 3 * s, o, 3, P->link_sphere_radius, obs[4 * i + 3])) hit = i;
       }
     }
   }
@@ -363,37 +458,50 @@ static void step_dynamics(const orc_problem* P, const double* x, const double* u
 }
 
 /* One rollout: Alg. 1 "simulate", cost Eq. (5), collision indicator and the
- * first contact (Sec. II-B.1). */
-void orc_simulate(const orc_problem* P, const double* x0, const double* ut, const double* obs,
-                  int32_t n_obs, double* traj, double* S, int32_t* col, int32_t* first_obs,
-                  double* p_term, double* p_first, double* clearance) {
+ * first contact (Sec. II-B.1), tested on x_1..x_N.  With the pose cost the
+ * stage and terminal terms also count I_col(x_j) for j = 0..N, and x_0
+ * enters the boundary clearance. */
+void orc_simulate_moving(const orc_problem* P, const double* x0, const double* ut,
+                         const double* obs, const double* vel, int32_t n_obs, double* traj,
+                         double* S, int32_t* col, int32_t* first_obs, double* p_term,
+                         double* p_first, double* clearance) {
   int32_t n, m, p;
   orc_dims(P->dynamics, &n, &m, &p);
+  const int pose = P->dynamics == ORC_ARM6 && (P->flags & ORC_FLAG_POSE_COST);
   double x[12], xn[12];
   memcpy(x, x0, sizeof(double) * (size_t)n);
   if (traj) memcpy(traj, x, sizeof(double) * (size_t)n);
   double cost = 0.0, clear = INFINITY;
   int32_t c = 0, f = -1;
   double pf[3] = {0.0, 0.0, 0.0};
+  int32_t icol = pose ? (state_contact(P, x, obs, vel, n_obs, 0.0, &clear) >= 0) : 0;
   for (int32_t j = 0; j < P->N; ++j) {
-    cost += stage_cost(P, x, ut + j * m);
+    cost += stage_cost(P, x, ut + j * m, icol);
     step_dynamics(P, x, ut + j * m, xn);
     memcpy(x, xn, sizeof(double) * (size_t)n);
     if (traj) memcpy(traj + (size_t)(j + 1) * n, x, sizeof(double) * (size_t)n);
-    int32_t hit = state_contact(P, x, obs, n_obs, &clear);
+    int32_t hit = state_contact(P, x, obs, vel, n_obs, (double)(j + 1) * P->dt, &clear);
+    icol = hit >= 0;
     if (hit >= 0 && !c) {
       c = 1;
       f = hit;
       task_point(P, x, pf);
     }
   }
-  cost += terminal_cost(P, x);
+  cost += terminal_cost(P, x, icol);
   *S = cost;
   *col = c;
   *first_obs = f;
   task_point(P, x, p_term);
   for (int32_t i = 0; i < p; ++i) p_first[i] = pf[i];
   if (clearance) *clearance = clear;
+}
+
+void orc_simulate(const orc_problem* P, const double* x0, const double* ut, const double* obs,
+                  int32_t n_obs, double* traj, double* S, int32_t* col, int32_t* first_obs,
+                  double* p_term, double* p_first, double* clearance) {
+  orc_simulate_moving(P, x0, ut, obs, NULL, n_obs, traj, S, col, first_obs, p_term, p_first,
+                      clearance);
 }
 
 /* Closest obstacle o* to the current robot (the reference obstacle of
@@ -778,6 +886,17 @@ int32_t orc_replan(const orc_problem* P, const double* x_t, const double* U, con
   double* eps = (double*)malloc(sizeof(double) * (size_t)NM);
   double* ut = (double*)malloc(sizeof(double) * (size_t)NM);
 
+  /* constant-velocity obstacles: each obstacle's own velocity by Eq. (17) */
+  double* vel = NULL;
+  if ((P->flags & ORC_FLAG_OBS_CONST_VEL) && n_obs > 0) {
+    vel = (double*)malloc(sizeof(double) * (size_t)n_obs * p);
+    for (int32_t i = 0; i < n_obs; ++i) {
+      double v[3];
+      orc_obstacle_velocity(hist, h_avail, n_obs, p, i, P->history_len, P->dt, v);
+      for (int32_t d = 0; d < p; ++d) vel[(size_t)i * p + d] = v[d];
+    }
+  }
+
   /* [Rollouts] Alg. 1: sample, perturb (Eq. (3)), simulate (Eq. (4)),
    * cost (Eq. (5)), collision indicator. */
   for (int32_t k = 0; k < K; ++k) {
@@ -791,8 +910,8 @@ int32_t orc_replan(const orc_problem* P, const double* x_t, const double* U, con
         E[(size_t)k * NM + j * m + i] = u - U[j * m + i];
       }
     double clear;
-    orc_simulate(P, x_t, ut, obs, n_obs, NULL, &S[k], &col[k], &fo[k], pT + (size_t)k * p,
-                 pF + (size_t)k * p, &clear);
+    orc_simulate_moving(P, x_t, ut, obs, vel, n_obs, NULL, &S[k], &col[k], &fo[k],
+                        pT + (size_t)k * p, pF + (size_t)k * p, &clear);
     if (out->clearance) out->clearance[k] = clear;
   }
 
@@ -812,6 +931,7 @@ int32_t orc_replan(const orc_problem* P, const double* x_t, const double* U, con
   free(E);
   free(eps);
   free(ut);
+  free(vel);
   return 0;
 }
 

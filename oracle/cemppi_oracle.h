@@ -38,6 +38,21 @@ enum { ORC_UNICYCLE = 0, ORC_ARM6 = 1 };
 enum { ORC_STATIC = 0, ORC_DYNAMIC = 1 };
 enum { ORC_REF_TERMINAL = 0, ORC_REF_FIRST_CONTACT = 1 };
 
+/* Optional variants (orc_problem.flags).
+ * ORC_FLAG_POSE_COST (arm only): the goal-reaching stage cost of the
+ *   real-robot experiment, Sec. III-C: w_p |p_ee - p_g| + w_R d_R(R_ee, R_g)
+ *   + w_c I_col(q_t), with (w_p, w_R, w_c) = (Q[0], Q[1], Q[2]) on the stage
+ *   states x_0..x_{N-1} and (Qf[0], Qf[1], Qf[2]) on x_N.  R_g is given as a
+ *   rotation vector (axis times angle, radians) in goal[3..5]; d_R is the
+ *   angle of the relative rotation, from unit quaternions.  The control and
+ *   joint-limit terms stay as in the default cost.
+ * ORC_FLAG_OBS_CONST_VEL: inside the rollouts every obstacle moves with its
+ *   own constant velocity, estimated as in Eq. (17) from the observation
+ *   history; state x_j is tested against the obstacles at time j dt.  The
+ *   default keeps the obstacles where they were observed. */
+#define ORC_FLAG_POSE_COST 1u
+#define ORC_FLAG_OBS_CONST_VEL 2u
+
 /* branch taken by Alg. 1 */
 enum { ORC_BRANCH_CLUSTER = 0, ORC_BRANCH_FALLBACK = 1, ORC_BRANCH_ALL_COLLIDE = 2 };
 
@@ -73,6 +88,7 @@ typedef struct orc_problem {
   double w_limit;           /* arm: joint-limit penalty weight                    */
   uint64_t seed;            /* Philox key                                         */
   uint32_t stream_id;       /* Philox counter word 3                              */
+  uint32_t flags;           /* ORC_FLAG_* bits                                    */
 } orc_problem;
 
 /* Outputs of orc_replan.  Every pointer may be NULL (not produced).
@@ -125,12 +141,26 @@ void orc_unicycle_step(const double x[3], const double u[2], double dt, double x
 void orc_arm_frames(const double q[6], const double dh[6][4], double origins[7][3], double rot[3][3]);
 void orc_arm_spheres(const double origins[7][3], int32_t ns, double* centres);
 
+/* Orientation error of the arm's pose cost (Sec. III-C): unit quaternions
+ * (w, x, y, z) of a rotation vector and of a rotation matrix, and the angle
+ * 2 acos |<a, b>| between two orientations, in [0, pi]. */
+void orc_rotvec_quat(const double r[3], double q[4]);
+void orc_rot_quat(const double R[3][3], double q[4]);
+double orc_quat_angle(const double a[4], const double b[4]);
+
 /* One rollout from x0 with applied controls ut[N][m]: fills traj[(N+1)][n]
  * (may be NULL), returns cost, collision flag, first-hit obstacle, terminal
  * and first-contact points and the boundary clearance. */
 void orc_simulate(const orc_problem* P, const double* x0, const double* ut, const double* obs,
                   int32_t n_obs, double* traj, double* S, int32_t* col, int32_t* first_obs,
                   double* p_term, double* p_first, double* clearance);
+
+/* orc_simulate with moving obstacles: obstacle i is at obs_i + j dt vel_i
+ * when state x_j is tested (vel [n_obs][p]; NULL = frozen). */
+void orc_simulate_moving(const orc_problem* P, const double* x0, const double* ut,
+                         const double* obs, const double* vel, int32_t n_obs, double* traj,
+                         double* S, int32_t* col, int32_t* first_obs, double* p_term,
+                         double* p_first, double* clearance);
 
 int32_t orc_closest_obstacle(const orc_problem* P, const double* x0, const double* obs, int32_t n_obs);
 void orc_obstacle_velocity(const double* hist, int32_t h_avail, int32_t n_obs, int32_t p, int32_t idx,

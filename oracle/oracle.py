@@ -4,7 +4,8 @@ The problem description is any object (or mapping) carrying the planner
 parameters by name: dynamics, horizon, num_samples, dt, lam, noise_chol,
 u_min, u_max, dbscan_eps, dbscan_min_pts, norm_eps, scene_mode,
 history_len, v_obs_min, ref_mode, robot_radius, goal, Q, R, Qf, dh,
-n_link_spheres, link_sphere_radius, q_limit, w_limit, seed, stream_id.
+n_link_spheres, link_sphere_radius, q_limit, w_limit, seed, stream_id and
+(optional, default 0) flags.
 """
 from __future__ import annotations
 
@@ -19,6 +20,7 @@ _SRC = os.path.join(_HERE, "cemppi_oracle.c")
 _LIB = os.path.join(_HERE, "libcemppi_oracle.so")
 
 UNICYCLE, ARM6 = 0, 1
+FLAG_POSE_COST, FLAG_OBS_CONST_VEL = 1, 2
 ST_FALLBACK, ST_ALL_COLLIDE, ST_NO_CLUSTER, ST_DYN_STATIC, ST_NONFINITE = 1, 2, 4, 8, 16
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -55,6 +57,7 @@ class OrcProblem(C.Structure):
         ("w_limit", C.c_double),
         ("seed", C.c_uint64),
         ("stream_id", C.c_uint32),
+        ("flags", C.c_uint32),
     ]
 
 
@@ -140,6 +143,14 @@ def load():
         _p(OrcProblem), _f64p, _f64p, _f64p, C.c_int32, C.c_void_p, _p(C.c_double),
         _p(C.c_int32), _p(C.c_int32), _f64p, _f64p, _p(C.c_double),
     ]
+    lib.orc_simulate_moving.argtypes = [
+        _p(OrcProblem), _f64p, _f64p, _f64p, C.c_void_p, C.c_int32, C.c_void_p, _p(C.c_double),
+        _p(C.c_int32), _p(C.c_int32), _f64p, _f64p, _p(C.c_double),
+    ]
+    lib.orc_rotvec_quat.argtypes = [_f64p, _f64p]
+    lib.orc_rot_quat.argtypes = [_f64p, _f64p]
+    lib.orc_quat_angle.argtypes = [_f64p, _f64p]
+    lib.orc_quat_angle.restype = C.c_double
     lib.orc_closest_obstacle.argtypes = [_p(OrcProblem), _f64p, _f64p, C.c_int32]
     lib.orc_closest_obstacle.restype = C.c_int32
     lib.orc_obstacle_velocity.argtypes = [
@@ -207,6 +218,7 @@ def make_problem(spec) -> OrcProblem:
     P.w_limit = float(np.float32(_get(spec, "w_limit")))
     P.seed = int(_get(spec, "seed")) & 0xFFFFFFFFFFFFFFFF
     P.stream_id = int(_get(spec, "stream_id")) & 0xFFFFFFFF
+    P.flags = int(_get(spec, "flags", 0) or 0) & 0xFFFFFFFF
     return P
 
 
@@ -281,8 +293,9 @@ def arm_spheres(origins, ns: int):
     return out
 
 
-def simulate(spec, x0, ut, obs):
-    """One rollout with the applied controls ut [N][m]; returns a dict."""
+def simulate(spec, x0, ut, obs, vel=None):
+    """One rollout with the applied controls ut [N][m]; obstacles move with
+    velocities vel [n_obs][p] (None: frozen).  Returns a dict."""
     lib = load()
     P = make_problem(spec)
     n, m, p = dims(P.dynamics)
@@ -290,12 +303,32 @@ def simulate(spec, x0, ut, obs):
     traj = np.zeros((P.N + 1, n))
     S, col, fo, clr = C.c_double(), C.c_int32(), C.c_int32(), C.c_double()
     pT, pF = np.zeros(p), np.zeros(p)
-    lib.orc_simulate(
-        C.byref(P), _f64(x0), _f64(ut).ravel(), np.ascontiguousarray(obs.ravel()), obs.shape[0],
+    v = None
+    if vel is not None:
+        v = np.ascontiguousarray(_f64(vel).reshape(obs.shape[0], p).ravel())
+    lib.orc_simulate_moving(
+        C.byref(P), _f64(x0), _f64(ut).ravel(), np.ascontiguousarray(obs.ravel()),
+        v.ctypes.data_as(C.c_void_p) if v is not None and v.size else None, obs.shape[0],
         traj.ctypes.data_as(C.c_void_p), C.byref(S), C.byref(col), C.byref(fo), pT, pF, C.byref(clr),
     )
     return dict(traj=traj, S=S.value, col=col.value, first_obs=fo.value, p_term=pT, p_first=pF,
                 clearance=clr.value)
+
+
+def rotvec_quat(r) -> np.ndarray:
+    q = np.zeros(4)
+    load().orc_rotvec_quat(_f64(r), q)
+    return q
+
+
+def rot_quat(R) -> np.ndarray:
+    q = np.zeros(4)
+    load().orc_rot_quat(np.ascontiguousarray(_f64(R).reshape(3, 3)), q)
+    return q
+
+
+def quat_angle(a, b) -> float:
+    return float(load().orc_quat_angle(_f64(a), _f64(b)))
 
 
 def closest_obstacle(spec, x0, obs) -> int:

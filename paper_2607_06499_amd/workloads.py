@@ -23,6 +23,7 @@ import numpy as np
 
 UNICYCLE, ARM6 = 0, 1
 STATIC, DYNAMIC = 0, 1
+FLAG_POSE_COST, FLAG_OBS_CONST_VEL = 1, 2
 REF_TERMINAL, REF_FIRST_CONTACT = 0, 1
 INF = float("inf")
 
@@ -72,6 +73,7 @@ class PlannerSpec:
     max_obstacles: int = 64
     seed: int = 1
     stream_id: int = 0
+    flags: int = 0
 
     @property
     def n(self) -> int:
