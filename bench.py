@@ -42,8 +42,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--workload", default="unicycle_dynamic",
                     choices=["unicycle_dynamic", "unicycle_dynamic_ahead", "unicycle_static",
-                             "unicycle_static_ahead", "arm6_dynamic", "batch_uneven",
-                             "served_sessions"])
+                             "unicycle_static_ahead", "arm6_dynamic", "unicycle_dynamic_cv",
+                             "arm6_pose", "batch_uneven", "served_sessions"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -71,7 +71,9 @@ def scene_for(name, seed):
             "unicycle_dynamic_ahead": W.unicycle_dynamic_ahead,
             "unicycle_static": W.unicycle_static,
             "unicycle_static_ahead": W.unicycle_static_ahead,
-            "arm6_dynamic": W.arm6_dynamic}[name](seed)
+            "arm6_dynamic": W.arm6_dynamic,
+            "unicycle_dynamic_cv": W.unicycle_dynamic_cv,
+            "arm6_pose": W.arm6_pose}[name](seed)
 
 
 def record_loop(pl, scene, T, torch):
@@ -253,11 +255,16 @@ def rollout_flops(spec, n_obs):
     """Algorithmic FP32 flops of one rollout launch: 25 + 5 n_obs per
     unicycle rollout-step (noise transform, clamp, dynamics, cost, 5 per
     obstacle test); forward kinematics 480, link spheres 48, 8 per
-    sphere-obstacle test and 40 for noise and cost per arm rollout-step."""
+    sphere-obstacle test and 40 for noise and cost per arm rollout-step.
+    Constant-velocity obstacles add the displacement of each tested obstacle
+    (4 flops in 2-D, 6 in 3-D); the pose cost adds 62 per arm rollout-step
+    (orientation error 60, distance 2)."""
     steps = spec.num_samples * spec.horizon
+    cv = bool(getattr(spec, "flags", 0) & 2)
+    pose = bool(getattr(spec, "flags", 0) & 1)
     if spec.dynamics == 0:
-        return steps * (25 + 5 * n_obs)
-    return steps * (480 + 48 + 8 * n_obs * spec.n_link_spheres + 40)
+        return steps * (25 + (9 if cv else 5) * n_obs)
+    return steps * (480 + 48 + (14 if cv else 8) * n_obs * spec.n_link_spheres + 40 + (62 if pose else 0))
 
 
 def companion(name, seed, W, K, torch, B, label):
@@ -555,6 +562,14 @@ def main():
         out["arm_6dof"] = companion("arm6_dynamic", args.seed, W, K, torch, B,
                                     "arm6_dynamic: K=4096 N=32 dt=0.05, 16 moving spheres, "
                                     "8 link spheres, closed loop")
+        out["dynamic_2d_const_vel"] = companion(
+            "unicycle_dynamic_cv", args.seed, W, K, torch, B,
+            "unicycle_dynamic_cv: the headline scene with constant-velocity obstacle prediction "
+            "inside the rollouts")
+        out["arm_6dof_pose"] = companion(
+            "arm6_pose", args.seed, W, K, torch, B,
+            "arm6_pose: arm6_dynamic with the real-robot pose cost (10, 3, 1000) and "
+            "constant-velocity obstacles")
     if not args.no_batch and args.workload == "unicycle_dynamic":
         out["batched_form"] = run_batch(args.seed, 5, args.batch_steps, torch, B)
     if not args.no_serve and args.workload == "unicycle_dynamic":

@@ -64,6 +64,27 @@ enum { CE_SCENE_STATIC = 0, CE_SCENE_DYNAMIC = 1 };
 /* point averaged into the collision-derived reference point, Sec. II-B.2:
  * terminal position (the paper's Eq. (11)) or first-contact position */
 enum { CE_REF_TERMINAL = 0, CE_REF_FIRST_CONTACT = 1 };
+
+/* ce_mppi_config.flags: optional variants of the rollout model.
+ *
+ * CE_FLAG_POSE_COST (arm only): the goal-reaching cost of the real-robot
+ *   experiment, Sec. III-C.  Stage state x_j (j = 0..N-1) costs
+ *     Q[0] |p_ee - p_g| + Q[1] d_R(R_ee, R_g) + Q[2] I_col(x_j)
+ *   and the terminal state the same terms with Qf[0..2]; the R control term
+ *   and the joint-limit penalty are kept.  p_g = goal[0..2]; R_g is the
+ *   rotation vector goal[3..5] (axis times angle, radians); d_R is the angle
+ *   of the relative rotation R_g^T R_ee, in [0, pi].  I_col is the contact
+ *   of any link sphere with any obstacle; x_0 counts in the cost but, as in
+ *   the default model, only x_1..x_N decide the pruning of Eq. (9).  The
+ *   paper's weights are (w_p, w_R, w_c) = (10, 3, 1000).
+ * CE_FLAG_OBS_CONST_VEL: inside the rollouts every obstacle moves with its
+ *   own constant velocity, estimated from the planner's observation history
+ *   as in Eq. (17) (zero until two observations with the same obstacle count
+ *   exist); state x_j is tested against the obstacles at time j dt.  Needs
+ *   history_len >= 2.  Without it the obstacles stay where observed.
+ * Unknown bits are rejected with CE_EINVAL. */
+#define CE_FLAG_POSE_COST 1u
+#define CE_FLAG_OBS_CONST_VEL 2u
 /* branch of Alg. 1 taken by a replan */
 enum { CE_BRANCH_CLUSTER = 0, CE_BRANCH_FALLBACK = 1, CE_BRANCH_ALL_COLLIDE = 2 };
 
@@ -94,8 +115,10 @@ typedef struct ce_mppi_config {
   int32_t ref_mode;          /* CE_REF_*                                                */
   int32_t max_obstacles;     /* capacity, 0..CE_MPPI_MAX_OBSTACLES                      */
   float robot_radius;        /* unicycle body radius (0 = point robot)                  */
-  float goal[6];             /* unicycle: goal state x_f; arm: end-effector target p_g  */
-  float Q[6];                /* unicycle: diag state weight; arm: Q[0] = position weight */
+  float goal[6];             /* unicycle: goal state x_f; arm: end-effector target p_g
+                                (pose cost: goal[3..5] = goal orientation, rotation vector) */
+  float Q[6];                /* unicycle: diag state weight; arm: Q[0] = position weight
+                                (pose cost: Q[0..2] = w_p, w_R, w_c)                    */
   float R[6];                /* diag control weight                                     */
   float Qf[6];               /* unicycle: diag terminal weight; arm: Qf[0]              */
   float dh[6][4];            /* arm: per joint (a, d, alpha, theta offset), standard DH */
@@ -106,7 +129,7 @@ typedef struct ce_mppi_config {
   uint64_t seed;             /* Philox key                                              */
   uint32_t stream_id;        /* Philox counter word 3 (e.g. the planner id)             */
   int32_t device;            /* HIP device ordinal                                      */
-  uint32_t flags;            /* reserved, 0                                             */
+  uint32_t flags;            /* CE_FLAG_* bits, 0 = the default model                   */
 } ce_mppi_config;
 
 /* Per-replan diagnostics, written on the device. */

@@ -20,6 +20,7 @@ CE_OK, CE_EINVAL, CE_ENOMEM, CE_EDEVICE, CE_EUNSUPPORTED, CE_EBUSY = range(6)
 DYN_UNICYCLE, DYN_ARM6 = 0, 1
 SCENE_STATIC, SCENE_DYNAMIC = 0, 1
 REF_TERMINAL, REF_FIRST_CONTACT = 0, 1
+FLAG_POSE_COST, FLAG_OBS_CONST_VEL = 1, 2
 BRANCH_CLUSTER, BRANCH_FALLBACK, BRANCH_ALL_COLLIDE = 0, 1, 2
 STATUS_FALLBACK, STATUS_ALL_COLLIDE, STATUS_NO_CLUSTER, STATUS_DYN_STATIC, STATUS_NONFINITE = (
     1, 2, 4, 8, 16)
@@ -293,6 +294,7 @@ def config_from_spec(spec, device: int = 0) -> CeMppiConfig:
     cfg.w_limit = float(spec.w_limit)
     cfg.seed = int(spec.seed) & 0xFFFFFFFFFFFFFFFF
     cfg.stream_id = int(spec.stream_id) & 0xFFFFFFFF
+    cfg.flags = int(getattr(spec, "flags", 0) or 0) & 0xFFFFFFFF
     cfg.device = int(device)
     return cfg
 

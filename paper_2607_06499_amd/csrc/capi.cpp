@@ -103,6 +103,12 @@ ce_status validate(const ce_mppi_config* c) {
     if (!finite(c->goal[i]) || !finite(c->Q[i]) || !finite(c->R[i]) || !finite(c->Qf[i]))
       return fail(CE_EINVAL, "cost parameters must be finite");
   }
+  if (c->flags & ~(CE_FLAG_POSE_COST | CE_FLAG_OBS_CONST_VEL))
+    return fail(CE_EINVAL, "unknown flags");
+  if ((c->flags & CE_FLAG_POSE_COST) && c->dynamics != CE_DYN_ARM6)
+    return fail(CE_EINVAL, "the pose cost needs the arm dynamics");
+  if ((c->flags & CE_FLAG_OBS_CONST_VEL) && c->history_len < 2)
+    return fail(CE_EINVAL, "constant-velocity obstacles need history_len >= 2");
   if (c->dynamics == CE_DYN_ARM6) {
     if (c->n_link_spheres < 1 || c->n_link_spheres > CE_MPPI_MAX_SPHERES)
       return fail(CE_EINVAL, "n_link_spheres out of range 1..16");
@@ -161,6 +167,26 @@ void build_cfg(const ce_mppi_config* u, Cfg& c) {
   c.max_obs = u->max_obstacles;
   c.robot_r = u->robot_radius;
   c.wlim = u->w_limit;
+  c.cv = (u->flags & CE_FLAG_OBS_CONST_VEL) ? 1 : 0;
+  c.pose = (u->flags & CE_FLAG_POSE_COST) ? 1 : 0;
+  {
+    // goal orientation of the pose cost from its rotation vector (Rodrigues)
+    const double r0 = u->goal[3], r1 = u->goal[4], r2 = u->goal[5];
+    const double th = std::sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+    double R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    if (c.pose && th > 0.0) {
+      const double k0 = r0 / th, k1 = r1 / th, k2 = r2 / th;
+      const double s = std::sin(th), v = 1.0 - std::cos(th);
+      const double K[9] = {0, -k2, k1, k2, 0, -k0, -k1, k0, 0};
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double kk = 0.0;
+          for (int l = 0; l < 3; ++l) kk += K[i * 3 + l] * K[l * 3 + j];
+          R[i * 3 + j] = (i == j ? 1.0 : 0.0) + s * K[i * 3 + j] + v * kk;
+        }
+    }
+    for (int i = 0; i < 9; ++i) c.Rg[i] = (float)R[i];
+  }
   if (c.dyn == CE_DYN_ARM6) {
     double seg[6], total = 0.0;
     for (int i = 0; i < 6; ++i) {
@@ -337,6 +363,8 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
     std::memset(&init, 0, sizeof(init));
     init.hist_head = c.H - 1;
     init.hist_nobs = -1;
+    init.hs_head = c.H - 1;
+    init.hs_nobs = -1;
     e = hipMemcpy(b.ctrl, &init, sizeof(init), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -646,8 +674,16 @@ struct StateHeader {
 };
 constexpr uint32_t kStateMagic = 0x43454d50u;  // "CEMP"
 
+// writes the persistent prefix and sets the start-of-replan ring snapshot to
+// the same ring state
 ce_status write_persist(ce_mppi_planner* P, const Persist& ps, hipStream_t s) {
-  hipError_t e = hipMemcpyAsync(P->b.ctrl, &ps, sizeof(ps), hipMemcpyHostToDevice, s);
+  struct {
+    Persist p;
+    int32_t hs_head, hs_count, hs_nobs;
+  } w{ps, ps.hist_head, ps.hist_count, ps.hist_nobs};
+  static_assert(offsetof(Ctrl, hs_head) == sizeof(Persist) && sizeof(w) == offsetof(Ctrl, n_obs),
+                "Ctrl snapshot follows the persistent prefix");
+  hipError_t e = hipMemcpyAsync(P->b.ctrl, &w, sizeof(w), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "control block update");
   return CE_OK;

@@ -1061,6 +1061,10 @@ __device__ __forceinline__ void finish_body(const Cfg& c, const Bufs& b, int bx,
     const bool hasM = cl && cw->M > 0;
     const float smin = !cl ? cw->smin_all : (hasM ? b.c_smin[cw->sel] : cw->smin_feas);
     cw->wsum = wsum;
+    // ring state for the next replan's rollout blocks
+    cw->hs_head = cw->hist_head;
+    cw->hs_count = cw->hist_count;
+    cw->hs_nobs = cw->hist_nobs;
     if (!bad) {
       const uint32_t lo = cw->step_lo + 1u;
       if (lo == 0u) cw->step_hi += 1u;

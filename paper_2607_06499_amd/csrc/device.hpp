@@ -54,6 +54,10 @@ struct Ctrl {
   // persistent
   uint32_t step_lo, step_hi;
   int32_t hist_head, hist_count, hist_nobs;
+  // the ring state at the start of the replan (copied by the last kernel of
+  // each replan): the rollout blocks read it while block 0 pushes the new
+  // observation
+  int32_t hs_head, hs_count, hs_nobs;
   // per replan
   int32_t n_obs, nonfinite, closest;
   int32_t n_col, n_feas, n_ref, branch;
@@ -90,6 +94,9 @@ struct Cfg {
   int sph_seg[kMaxSpheres];
   float sph_t[kMaxSpheres];
   float qlim[6], wlim;
+  int pose;        // arm: pose cost of the real-robot experiment
+  int cv;          // obstacles move with constant velocity inside the rollouts
+  float Rg[9];     // pose cost: goal orientation, row-major
   uint32_t seed_lo, seed_hi, stream_id;
   int ntile;       // ceil(K / kTile)
   int nblk_upd;    // update kernel blocks

@@ -20,14 +20,17 @@ namespace cemppi {
 struct ObsLds {
   float4 o[kMaxObs];     // (x, y, z, R^2) with R = robot/sphere radius + obstacle radius
   float r[kMaxObs];      // obstacle radius
+  float4 v[kMaxObs];     // obstacle velocity (constant-velocity obstacles; else 0)
   float4 live[kMaxObs];  // the obstacles a rollout can reach, in index order
+  float4 vlive[kMaxObs]; // their velocities
   int idx[kMaxObs];      // their obstacle indices
   int n_live;
 };
 
 // Arm forward kinematics: origins P0..P6 of the standard DH chain
 // (A_i = Rz(q_i + off_i) Tz(d_i) Tx(a_i) Rx(alpha_i)); P6 is p_ee(q).
-__device__ __forceinline__ void arm_origins(const Cfg& c, const float* q, float P[7][3]) {
+__device__ __forceinline__ void arm_origins(const Cfg& c, const float* q, float P[7][3],
+                                            float* Re = nullptr) {
   float r00 = 1.f, r01 = 0.f, r02 = 0.f, r10 = 0.f, r11 = 1.f, r12 = 0.f, r20 = 0.f, r21 = 0.f,
         r22 = 1.f;
   float tx = 0.f, ty = 0.f, tz = 0.f;
@@ -59,6 +62,29 @@ __device__ __forceinline__ void arm_origins(const Cfg& c, const float* q, float 
     P[i + 1][1] = ty;
     P[i + 1][2] = tz;
   }
+  if (Re) {
+    Re[0] = r00; Re[1] = r01; Re[2] = r02;
+    Re[3] = r10; Re[4] = r11; Re[5] = r12;
+    Re[6] = r20; Re[7] = r21; Re[8] = r22;
+  }
+}
+
+// Orientation error of the pose cost (Sec. III-C): the angle of the relative
+// rotation R_g^T R_ee, atan2(|v|, tr - 1) with tr its trace and v its
+// antisymmetric part (|v| = 2 sin, tr - 1 = 2 cos); well conditioned at every
+// angle in [0, pi].
+__device__ __forceinline__ float rot_angle(const Cfg& c, const float* Re) {
+  float tr = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float g0 = c.Rg[3 * i], g1 = c.Rg[3 * i + 1], g2 = c.Rg[3 * i + 2];
+    const float e0 = Re[3 * i], e1 = Re[3 * i + 1], e2 = Re[3 * i + 2];
+    tr += g0 * e0 + g1 * e1 + g2 * e2;
+    vx += g2 * e1 - g1 * e2;
+    vy += g0 * e2 - g2 * e0;
+    vz += g1 * e0 - g0 * e1;
+  }
+  return atan2f(sqrtf(vx * vx + vy * vy + vz * vz), tr - 1.f);
 }
 
 __device__ __forceinline__ void sphere_centre(const Cfg& c, const float P[7][3], int s, float& x,
@@ -103,9 +129,11 @@ __device__ __forceinline__ float limit_penalty(const Cfg& c, const float* q) {
 // Prologue run by every block: stages the obstacles, checks the inputs and
 // computes o* (smallest surface clearance, ties to the lowest index) and
 // p(x_t).  Returns through LDS: s_bad, s_closest, s_p0.
-template <int DYN>
-__device__ void prologue(const Cfg& c, const float* __restrict__ x_t, const float* __restrict__ obs,
-                         int n_obs, ObsLds& L, int& s_bad, int& s_closest, float* s_p0) {
+// CVM: constant-velocity obstacles never (0), always (1) or as c.cv says (2).
+template <int DYN, int CVM = 2>
+__device__ void prologue(const Cfg& c, const Bufs& b, const float* __restrict__ x_t,
+                         const float* __restrict__ obs, int n_obs, ObsLds& L, int& s_bad,
+                         int& s_closest, float* s_p0) {
   const int tid = threadIdx.x;
   const int P = DYN == 0 ? 2 : 3;
   if (tid == 0) s_bad = 0;
@@ -118,6 +146,24 @@ __device__ void prologue(const Cfg& c, const float* __restrict__ x_t, const floa
     const float R = (DYN == 0 ? c.robot_r : c.rs) + o[P];
     L.o[tid] = make_float4(o[0], o[1], DYN == 0 ? 0.f : o[2], R * R);
     L.r[tid] = o[P];
+    // constant-velocity obstacles: Eq. (17) for every obstacle over the ring
+    // as it will be after this replan's push (the current observation is the
+    // newest entry), telescoped to (o_t - o_{t-H'+1}) / ((H' - 1) dt)
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (CVM == 2 ? c.cv != 0 : CVM == 1) {
+      const Ctrl* ct = b.ctrl;
+      const int cnt = (ct->hs_nobs == n_obs ? ct->hs_count : 0) + 1;
+      const int Hp = cnt < c.H ? cnt : c.H;
+      if (Hp >= 2) {
+        const int h1 = (ct->hs_head - (Hp - 2) + 2 * c.H) % c.H;
+        const float* old = b.hist + ((size_t)h1 * c.max_obs + tid) * P;
+        const float den = (float)(Hp - 1) * c.dt;
+        v.x = (o[0] - old[0]) / den;
+        v.y = (o[1] - old[1]) / den;
+        if (DYN != 0) v.z = (o[2] - old[2]) / den;
+      }
+    }
+    L.v[tid] = v;
   }
   if (tid < c.n && !isfinite(x_t[tid])) atomicOr(&s_bad, 1);
   __syncthreads();
@@ -169,16 +215,21 @@ __device__ void prologue(const Cfg& c, const float* __restrict__ x_t, const floa
     // than that (with a margin far above the FP32 rounding of the positions)
     // is never in contact; it is left out of the collision loops.  The kept
     // obstacles stay in index order, so the lowest-index rule is unchanged.
+    // A moving obstacle covers at most |v| N dt more.
     bool keep = tid < n_obs;
     if (DYN == 0 && keep && c.reach < INFINITY) {
       const float R = c.robot_r + L.r[tid];
       const float d = sqrtf(dist2_2(x_t[0], x_t[1], L.o[tid].x, L.o[tid].y));
-      keep = !(d > c.reach + R + (1e-3f * (c.reach + R) + 1e-3f));
+      const float4 v = L.v[tid];
+      const float ov = sqrtf(v.x * v.x + v.y * v.y) * ((float)c.N * c.dt);
+      const float ext = c.reach + R + ov;
+      keep = !(d > ext + (1e-3f * ext + 1e-3f));
     }
     const unsigned long long m = __ballot(keep);
     if (keep) {
       const int pos = __popcll(m & ((1ull << tid) - 1ull));
       L.live[pos] = L.o[tid];
+      L.vlive[pos] = L.v[tid];
       L.idx[pos] = tid;
     }
     if (tid == 0) L.n_live = __popcll(m);
@@ -266,8 +317,8 @@ __device__ __forceinline__ void write_group_partials(const Bufs& b, float (*recs
 // ---------------------------------------------------------------------------
 // Unicycle rollouts (Sec. III-A): state (x, y, theta), control (v, omega).
 // R rounds per wave: each wave runs R rollouts per block item, the nominal
-// sequence staying in registers between rounds.
-template <int SEG, int R = 1>
+// sequence staying in registers between rounds.  CVM as for the prologue.
+template <int SEG, int R = 1, int CVM = 2>
 __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& b, int bx, int by,
                                                       int nbx, const float* __restrict__ x_t,
                                                       const float* __restrict__ obs, int n_obs) {
@@ -275,10 +326,11 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
   __shared__ float s_rec[kRollWaves * (kWave / SEG) * R][kPart];
-  prologue<0>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
+  prologue<0, CVM>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
   if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
+  const bool cv = CVM == 2 ? c.cv != 0 : CVM == 1;
 
   constexpr int SPW = kWave / SEG;
   constexpr int RPB = kRollWaves * SPW * R;
@@ -325,23 +377,40 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   }
   const float S = seg_sum<SEG>(l);
 
-  // collision of states 1..N against the frozen obstacles: lowest index hit
+  // collision of states 1..N against the obstacles: lowest index hit
   // pass 1: does this state touch any obstacle?  pass 2 (only in waves with
   // a contact): the lowest obstacle index touched
+  // (constant-velocity obstacles: obstacle i at o_i + j dt v_i for state j)
   const bool chk = act && j >= 1 && j <= N;
   const int n_live = L.n_live;
+  const float tj = (float)j * dt;
   bool any = false;
   if (chk) {
-    for (int i = 0; i < n_live; ++i) {
-      const float4 o = L.live[i];
-      any |= dist2_2(px, py, o.x, o.y) <= o.w;
+    if (cv) {
+      for (int i = 0; i < n_live; ++i) {
+        const float4 o = L.live[i], v = L.vlive[i];
+        any |= dist2_2(px, py, __builtin_fmaf(tj, v.x, o.x), __builtin_fmaf(tj, v.y, o.y)) <= o.w;
+      }
+    } else {
+      for (int i = 0; i < n_live; ++i) {
+        const float4 o = L.live[i];
+        any |= dist2_2(px, py, o.x, o.y) <= o.w;
+      }
     }
   }
   int hit = kInt32Max;
   if (__ballot(any) != 0ull && any) {
-    for (int i = n_live - 1; i >= 0; --i) {
-      const float4 o = L.live[i];
-      hit = dist2_2(px, py, o.x, o.y) <= o.w ? L.idx[i] : hit;
+    if (cv) {
+      for (int i = n_live - 1; i >= 0; --i) {
+        const float4 o = L.live[i], v = L.vlive[i];
+        hit = dist2_2(px, py, __builtin_fmaf(tj, v.x, o.x), __builtin_fmaf(tj, v.y, o.y)) <= o.w
+                  ? L.idx[i] : hit;
+      }
+    } else {
+      for (int i = n_live - 1; i >= 0; --i) {
+        const float4 o = L.live[i];
+        hit = dist2_2(px, py, o.x, o.y) <= o.w ? L.idx[i] : hit;
+      }
     }
   }
   // first colliding state of each segment (lowest lane with a hit)
@@ -380,15 +449,16 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   write_group_partials(b, s_rec, RPB, bx);
 }
 
-template <int SEG>
+template <int SEG, int CV>
 __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b, const float* __restrict__ x_t, const float* __restrict__ obs, int n_obs) {
-  rollout_unicycle_body<SEG>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, x_t, obs, n_obs);
+  rollout_unicycle_body<SEG, 1, CV>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, x_t, obs, n_obs);
 }
 
 // ---------------------------------------------------------------------------
 // Six-joint arm rollouts (Sec. III-C): joint-velocity control, q_{j+1} =
-// q_j + u_j dt; end-effector cost, joint-limit penalty, link spheres against
-// obstacle spheres.
+// q_j + u_j dt; end-effector cost (squared distance, or the pose cost of the
+// real-robot experiment), joint-limit penalty, link spheres against obstacle
+// spheres.
 template <int R = 1>
 __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
                                                  const float* __restrict__ x_t,
@@ -398,7 +468,7 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
   __shared__ float s_rec[kRollWaves * R][kPart];
-  prologue<1>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
+  prologue<1>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
   if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
@@ -442,12 +512,22 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
   float q[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) q[i] = x_t[i] + seg_excl_scan<SEG>(u[i] * dt, j);
-  float P[7][3];
-  arm_origins(c, q, P);
+  float P[7][3], Re[9];
+  arm_origins(c, q, P, Re);
   const float ex = P[6][0], ey = P[6][1], ez = P[6][2];
   float l = 0.f;
   const float d2g = sq(ex - c.goal[0]) + sq(ey - c.goal[1]) + sq(ez - c.goal[2]);
-  if (act && j < N) {
+  if (c.pose) {
+    // Sec. III-C: w_p |p_ee - p_g| + w_R d_R (+ w_c I_col, below)
+    if (act && j <= N) {
+      const bool st = j < N;
+      float r = 0.f;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) r += c.R[i] * u[i] * u[i];
+      l = (st ? c.Q[0] : c.Qf[0]) * sqrtf(d2g) + (st ? c.Q[1] : c.Qf[1]) * rot_angle(c, Re) +
+          limit_penalty(c, q) + (st ? r : 0.f);
+    }
+  } else if (act && j < N) {
     float r = 0.f;
 #pragma unroll
     for (int i = 0; i < 6; ++i) r += c.R[i] * u[i] * u[i];
@@ -455,31 +535,51 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
   } else if (act && j == N) {
     l = c.Qf[0] * d2g + limit_penalty(c, q);
   }
-  const float S = seg_sum<SEG>(l);
 
-  // pass 1: any contact of any link sphere; pass 2 (waves with a contact):
+  // pass 1: any contact of any link sphere (states 1..N; with the pose cost
+  // also x_0, which enters the cost only); pass 2 (waves with a contact):
   // the lowest obstacle index touched
-  const bool chk = act && j >= 1 && j <= N;
+  const bool chk = act && j <= N && (j >= 1 || c.pose);
+  const float tj = (float)j * dt;
   bool any = false;
   if (chk) {
     for (int s = 0; s < c.ns; ++s) {
       float sx, sy, sz;
       sphere_centre(c, P, s, sx, sy, sz);
-      for (int i = 0; i < n_obs; ++i) {
-        const float4 o = L.o[i];
-        any |= dist2_3(sx, sy, sz, o.x, o.y, o.z) <= o.w;
+      if (c.cv) {
+        for (int i = 0; i < n_obs; ++i) {
+          const float4 o = L.o[i], v = L.v[i];
+          any |= dist2_3(sx, sy, sz, __builtin_fmaf(tj, v.x, o.x), __builtin_fmaf(tj, v.y, o.y),
+                         __builtin_fmaf(tj, v.z, o.z)) <= o.w;
+        }
+      } else {
+        for (int i = 0; i < n_obs; ++i) {
+          const float4 o = L.o[i];
+          any |= dist2_3(sx, sy, sz, o.x, o.y, o.z) <= o.w;
+        }
       }
     }
   }
+  if (c.pose && any) l += j < N ? c.Q[2] : c.Qf[2];
+  const float S = seg_sum<SEG>(l);
+  const bool anyc = any && j >= 1;
   int hit = kInt32Max;
-  if (__ballot(any) != 0ull && any) {
+  if (__ballot(anyc) != 0ull && anyc) {
     for (int s = 0; s < c.ns; ++s) {
       float sx, sy, sz;
       sphere_centre(c, P, s, sx, sy, sz);
       int hs = kInt32Max;
-      for (int i = n_obs - 1; i >= 0; --i) {
-        const float4 o = L.o[i];
-        hs = dist2_3(sx, sy, sz, o.x, o.y, o.z) <= o.w ? i : hs;
+      if (c.cv) {
+        for (int i = n_obs - 1; i >= 0; --i) {
+          const float4 o = L.o[i], v = L.v[i];
+          hs = dist2_3(sx, sy, sz, __builtin_fmaf(tj, v.x, o.x), __builtin_fmaf(tj, v.y, o.y),
+                       __builtin_fmaf(tj, v.z, o.z)) <= o.w ? i : hs;
+        }
+      } else {
+        for (int i = n_obs - 1; i >= 0; --i) {
+          const float4 o = L.o[i];
+          hs = dist2_3(sx, sy, sz, o.x, o.y, o.z) <= o.w ? i : hs;
+        }
       }
       hit = hs < hit ? hs : hit;
     }
@@ -558,7 +658,7 @@ __global__ __launch_bounds__(kRollThreads) void k_reduce_records(Cfg c, Bufs b,
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
   __shared__ float s_rec[kMaxRpb][kPart];
-  prologue<DYN>(c, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
+  prologue<DYN>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
   if (blockIdx.x == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
@@ -640,9 +740,9 @@ void launch_rollout(Launcher& L, const Cfg& c, const Bufs& b, const float* x_t, 
   dim3 grid(c.nblk_roll), block(kRollThreads);
   if (c.dyn == 0) {
     if (c.seg == 32)
-      L(k_rollout_unicycle<32>, grid, block, c, b, x_t, obs, n_obs);
+      L(c.cv ? k_rollout_unicycle<32, 1> : k_rollout_unicycle<32, 0>, grid, block, c, b, x_t, obs, n_obs);
     else
-      L(k_rollout_unicycle<64>, grid, block, c, b, x_t, obs, n_obs);
+      L(c.cv ? k_rollout_unicycle<64, 1> : k_rollout_unicycle<64, 0>, grid, block, c, b, x_t, obs, n_obs);
   } else {
     L(k_rollout_arm, grid, block, c, b, x_t, obs, n_obs);
   }

@@ -342,19 +342,22 @@ UR5E_LENGTHS = [0.1625, 0.425, 0.3922, 0.1333, 0.0997, 0.0996]
 def paper_arm_preset(seed: int = 1) -> Scene:
     """Six-joint arm planner with the real-world parameters of Sec. III-C:
     K=50, N=12, dt=0.1, joint velocity bound 0.1 rad/s, joint position bound
-    2 pi, lambda=0.05, DBSCAN eps=0.3 m on the end-effector feature, position
-    weight w_p=10.  UR5e kinematic lengths; a synthetic target with
-    an obstacle sphere between the start pose and the target and one
-    elsewhere."""
+    2 pi, lambda=0.05, DBSCAN eps=0.3 m on the end-effector feature, and the
+    pose cost with (w_p, w_R, w_c) = (10, 3, 1000).  UR5e kinematic lengths;
+    a synthetic target: a position with an obstacle sphere between it and the
+    start pose (one more sphere elsewhere), and a tool-down orientation
+    (half turn about a horizontal axis) turned 0.3 rad in yaw from the start."""
     rng = np.random.default_rng(70_000 + seed)
     bound = 0.1
+    yaw = math.pi / 4 + 0.15
     spec = PlannerSpec(
         dynamics=ARM6, horizon=12, num_samples=50, dt=0.1, lam=0.05,
         noise_chol=diag_chol([0.05] * 6, 6), u_min=[-bound] * 6, u_max=[bound] * 6,
         dbscan_eps=0.3, dbscan_min_pts=5, scene_mode=STATIC, history_len=5,
-        goal=[-0.6, -0.45, 0.4, 0.0, 0.0, 0.0], Q=[10.0] + [0.0] * 5, R=[0.0] * 6,
-        Qf=[10.0] + [0.0] * 5, dh=arm_dh(UR5E_LENGTHS), n_link_spheres=8, link_sphere_radius=0.05,
-        q_limit=[2.0 * math.pi] * 6, w_limit=100.0, seed=seed, stream_id=7,
+        goal=[-0.6, -0.45, 0.4, math.pi * math.cos(yaw), math.pi * math.sin(yaw), 0.0],
+        Q=[10.0, 3.0, 1000.0, 0.0, 0.0, 0.0], R=[0.0] * 6, Qf=[10.0, 3.0, 1000.0, 0.0, 0.0, 0.0],
+        dh=arm_dh(UR5E_LENGTHS), n_link_spheres=8, link_sphere_radius=0.05,
+        q_limit=[2.0 * math.pi] * 6, w_limit=100.0, seed=seed, stream_id=7, flags=FLAG_POSE_COST,
     ).rounded()
     q0 = np.array([0.0, -1.2, 1.4, -1.8, -1.57, 0.0]) + rng.normal(0.0, 0.02, 6)
     x0 = np.concatenate([q0, np.zeros(6)]).astype(np.float32)
@@ -362,6 +365,27 @@ def paper_arm_preset(seed: int = 1) -> Scene:
     r = np.array([0.05, 0.05])
     fld = ObstacleField(c, r, np.zeros((2, 3)), [-0.8, -0.8, 0.0], [0.8, 0.8, 1.2])
     return Scene(spec, x0, np.zeros((12, 6), np.float32), fld, "paper_arm")
+
+
+def arm6_pose(seed: int = 1, num_samples: int = 4096) -> Scene:
+    """arm6_dynamic with the pose cost of Sec. III-C (weights 10, 3, 1000;
+    goal orientation a seeded rotation vector) and constant-velocity
+    prediction of the moving spheres inside the rollouts."""
+    s = arm6_dynamic(seed, num_samples)
+    rng = np.random.default_rng(90_000 + seed)
+    rv = rng.normal(size=3)
+    rv *= rng.uniform(0.5, 2.5) / np.linalg.norm(rv)
+    spec = s.spec.replace(goal=list(s.spec.goal[:3]) + list(rv), Q=[10.0, 3.0, 1000.0, 0.0, 0.0, 0.0],
+                          Qf=[10.0, 3.0, 1000.0, 0.0, 0.0, 0.0],
+                          flags=FLAG_POSE_COST | FLAG_OBS_CONST_VEL)
+    return Scene(spec, s.x0, s.U0, s.field, "arm6_pose")
+
+
+def unicycle_dynamic_cv(seed: int = 1, num_samples: int = 8192) -> Scene:
+    """unicycle_dynamic with every obstacle predicted at constant velocity
+    inside the rollouts (velocities from the observation history)."""
+    s = unicycle_dynamic(seed, num_samples)
+    return Scene(s.spec.replace(flags=FLAG_OBS_CONST_VEL), s.x0, s.U0, s.field, "unicycle_dynamic_cv")
 
 
 def random_scene(seed: int, dynamics: int = UNICYCLE, num_samples: int = 512, horizon: int = 24,

@@ -104,6 +104,19 @@ def test_invalid_config_rejected(lib, field, value):
     assert lib.ce_mppi_last_error().decode() != ""
 
 
+def test_flags_validated(lib):
+    h = C.c_void_p()
+    cfg = B.ce_mppi_config_init(B.DYN_UNICYCLE)
+    cfg.flags = 4
+    assert lib.ce_mppi_create(C.byref(cfg), C.byref(h)) == B.CE_EINVAL
+    cfg.flags = B.FLAG_POSE_COST  # the pose cost is an arm cost
+    assert lib.ce_mppi_create(C.byref(cfg), C.byref(h)) == B.CE_EINVAL
+    cfg.flags = B.FLAG_OBS_CONST_VEL
+    cfg.history_len = 1  # no velocity without two observations
+    assert lib.ce_mppi_create(C.byref(cfg), C.byref(h)) == B.CE_EINVAL
+    assert h.value is None
+
+
 def test_dynamic_scene_needs_history(lib):
     cfg = B.ce_mppi_config_init(B.DYN_UNICYCLE)
     cfg.scene_mode = B.SCENE_DYNAMIC

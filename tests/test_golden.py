@@ -58,7 +58,9 @@ def test_arm_preset_matches_real_world_table():
     assert spec.u_max == [f32(g["joint_velocity_bound"])] * 6
     assert spec.u_min == [-f32(g["joint_velocity_bound"])] * 6
     assert spec.q_limit == [f32(g["joint_position_bound"])] * 6
-    assert spec.Q[0] == f32(g["w_p"])
+    assert spec.Q[:3] == [f32(g["w_p"]), f32(g["w_R"]), f32(g["w_c"])]
+    assert spec.Qf[:3] == spec.Q[:3]
+    assert spec.flags == W.FLAG_POSE_COST
     assert abs(g["joint_position_bound"] - 2 * math.pi) < 1e-15
 
 

@@ -26,6 +26,8 @@ MEMBERS = [
     lambda: W.arm6_dynamic(4, num_samples=512),
     lambda: W.random_scene(24, num_samples=64, horizon=1, n_obs=0),
     lambda: W.paper_arm_preset(2),
+    lambda: W.unicycle_dynamic_cv(5, num_samples=1024),
+    lambda: W.arm6_pose(6, num_samples=640),
 ]
 
 TUNINGS = [None, (1, 2, 2, 1), (4, 16, 4, 8), (8, 4, 2, 2)]
@@ -74,6 +76,13 @@ def test_batch_matches_single_replans():
             b.replan(x, o)
         _compare(B, batched, single, f"step {step} tuning {tune}")
         kinds |= {a.info()["branch"] for a in batched}
+        # the obstacles move between steps (in place: both forms read the same
+        # tensors), so the constant-velocity members predict real motion
+        H.torch_mod().cuda.synchronize()
+        for o in obs:
+            if o is not None:
+                o[:, 0] += 0.02
+                o[:, 1] -= 0.01
     # the members exercised the clustering branch and a fallback branch
     assert 0 in kinds and len(kinds) >= 2
     batch.close()
@@ -100,7 +109,7 @@ def test_subset_launches_match_single_replans():
     B, scenes, batched, single, xs, obs, batch = _setup()
     torch = H.torch_mod()
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-    rounds = [[0, 2, 4, 6], [1, 3, 5, 7], [7, 0], [2, 3, 4], [5], [6, 1, 0]]
+    rounds = [[0, 2, 4, 6, 8], [1, 3, 5, 7, 9], [7, 0], [9, 2, 3, 4], [5, 8], [6, 1, 0], [8, 9]]
     for i, members in enumerate(rounds):
         with torch.cuda.stream(streams[i % 2]):
             batch.replan_subset(members, stream=streams[i % 2])
