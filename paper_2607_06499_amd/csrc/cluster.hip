@@ -86,11 +86,13 @@ __device__ __forceinline__ bool is_min_field(int f) { return f == P_SMIN_ALL || 
 
 // ---------------------------------------------------------------------------
 // Reduction of the rollout-group partial records (256-thread blocks):
-// thread t owns records t, t+256, ... (coalesced), then a fixed tree.  Also
-// returns the number of feasible rollouts in records [0, upto).
+// thread t owns records t, t+256, ... (coalesced), each wave combines its
+// lanes by an xor butterfly (every lane ends with the same value), and the
+// four wave results are added in wave order.  Also returns the number of
+// feasible rollouts in records [0, upto).
 __device__ void reduce_partials(const Cfg& c, const Bufs& b, int upto, float* s_tot, int* s_before) {
-  __shared__ float s_red[kPart + 1][256];
-  const int tid = threadIdx.x;
+  __shared__ float s_w[4][kPart + 1];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   float acc[kPart + 1];
 #pragma unroll
   for (int f = 0; f < kPart; ++f) acc[f] = is_min_field(f) ? INFINITY : 0.f;
@@ -104,19 +106,27 @@ __device__ void reduce_partials(const Cfg& c, const Bufs& b, int upto, float* s_
     if (i < upto) acc[kPart] += v[P_NFEAS];
   }
 #pragma unroll
-  for (int f = 0; f <= kPart; ++f) s_red[f][tid] = acc[f];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) {
+  for (int f = 0; f <= kPart; ++f) {
+    float v = acc[f];
 #pragma unroll
-      for (int f = 0; f <= kPart; ++f)
-        s_red[f][tid] = (f < kPart && is_min_field(f)) ? fminf(s_red[f][tid], s_red[f][tid + w])
-                                                        : s_red[f][tid] + s_red[f][tid + w];
+    for (int off = 32; off > 0; off >>= 1) {
+      const float o = __shfl_xor(v, off, kWave);
+      v = (f < kPart && is_min_field(f)) ? fminf(v, o) : v + o;
     }
-    __syncthreads();
+    acc[f] = v;
   }
-  if (tid <= kPart) s_tot[tid] = s_red[tid][0];
-  if (tid == 0) *s_before = (int)s_red[kPart][0];
+  if (lane == 0) {
+#pragma unroll
+    for (int f = 0; f <= kPart; ++f) s_w[wv][f] = acc[f];
+  }
+  __syncthreads();
+  if (tid <= kPart) {
+    const bool mn = tid < kPart && is_min_field(tid);
+    const float a = s_w[0][tid], b1 = s_w[1][tid], b2 = s_w[2][tid], b3 = s_w[3][tid];
+    const float t = mn ? fminf(fminf(fminf(a, b1), b2), b3) : ((a + b1) + b2) + b3;
+    if (tid < kPart) s_tot[tid] = t;
+    else *s_before = (int)t;
+  }
   __syncthreads();
 }
 
