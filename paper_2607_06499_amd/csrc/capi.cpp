@@ -135,6 +135,7 @@ void build_cfg(const ce_mppi_config* u, Cfg& c) {
   c.seg = (c.dyn == CE_DYN_UNICYCLE && c.N + 1 <= 32) ? 32 : 64;
   c.rpb = kRollWaves * (64 / c.seg);
   c.nblk_roll = (c.K + c.rpb - 1) / c.rpb;
+  c.roll_r = 1;
   // every rollout state lies within max|v| N dt of the start position (the
   // clamped speed bounds each step's displacement)
   {
@@ -294,6 +295,18 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   if (!P) return fail(CE_ENOMEM, "host allocation failed");
   P->cfg = *cfg;
   build_cfg(cfg, P->c);
+  {
+    // Two rollout rounds per wave halve the per-block prologue when the
+    // unicycle launch still has at least two blocks per compute unit; a
+    // smaller grid (or the arm, whose waves are long) runs one round.
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    Cfg& cm = P->c;
+    const int blocks2 = (cm.K + 2 * cm.rpb - 1) / (2 * cm.rpb);
+    cm.roll_r = (cm.dyn == CE_DYN_UNICYCLE && blocks2 >= 2 * cus) ? 2 : 1;
+  }
   const Cfg& c = P->c;
   const size_t K = (size_t)c.K, NM = (size_t)c.NM, p = (size_t)c.p;
   const size_t zs = c.p == 2 ? 2 : 4;

@@ -76,6 +76,7 @@ struct Ctrl {
 struct Cfg {
   int dyn, N, K, m, n, p, NM, B;
   int seg, rpb, nblk_roll;
+  int roll_r;       // rollout rounds per wave of the single-planner launch (1 or 2)
   int npart;        // ceil(K / kGroup) partial records
   float dt, lambda, norm_eps;
   float L[36];

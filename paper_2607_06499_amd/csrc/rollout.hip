@@ -449,9 +449,9 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   write_group_partials(b, s_rec, RPB, bx);
 }
 
-template <int SEG, int CV>
+template <int SEG, int CV, int R>
 __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b, const float* __restrict__ x_t, const float* __restrict__ obs, int n_obs) {
-  rollout_unicycle_body<SEG, 1, CV>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, x_t, obs, n_obs);
+  rollout_unicycle_body<SEG, R, CV>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, x_t, obs, n_obs);
 }
 
 // ---------------------------------------------------------------------------
@@ -739,10 +739,18 @@ void launch_rollout(Launcher& L, const Cfg& c, const Bufs& b, const float* x_t, 
                     int n_obs) {
   dim3 grid(c.nblk_roll), block(kRollThreads);
   if (c.dyn == 0) {
+    // R rounds per wave: the block count shrinks by R; the partial records
+    // (fixed groups of kGroup rollouts) do not depend on it
+    using KFn = void (*)(Cfg, Bufs, const float*, const float*, int);
+    KFn f;
     if (c.seg == 32)
-      L(c.cv ? k_rollout_unicycle<32, 1> : k_rollout_unicycle<32, 0>, grid, block, c, b, x_t, obs, n_obs);
+      f = c.roll_r == 2 ? (c.cv ? k_rollout_unicycle<32, 1, 2> : k_rollout_unicycle<32, 0, 2>)
+                        : (c.cv ? k_rollout_unicycle<32, 1, 1> : k_rollout_unicycle<32, 0, 1>);
     else
-      L(c.cv ? k_rollout_unicycle<64, 1> : k_rollout_unicycle<64, 0>, grid, block, c, b, x_t, obs, n_obs);
+      f = c.roll_r == 2 ? (c.cv ? k_rollout_unicycle<64, 1, 2> : k_rollout_unicycle<64, 0, 2>)
+                        : (c.cv ? k_rollout_unicycle<64, 1, 1> : k_rollout_unicycle<64, 0, 1>);
+    const int rr = c.roll_r == 2 ? 2 : 1;
+    L(f, dim3((c.K + c.rpb * rr - 1) / (c.rpb * rr)), block, c, b, x_t, obs, n_obs);
   } else {
     L(k_rollout_arm, grid, block, c, b, x_t, obs, n_obs);
   }

@@ -28,6 +28,8 @@ MEMBERS = [
     lambda: W.paper_arm_preset(2),
     lambda: W.unicycle_dynamic_cv(5, num_samples=1024),
     lambda: W.arm6_pose(6, num_samples=640),
+    # large enough for two rollout rounds per wave in the single-planner launch
+    lambda: W.unicycle_dynamic_ahead(4, num_samples=8192),
 ]
 
 TUNINGS = [None, (1, 2, 2, 1), (4, 16, 4, 8), (8, 4, 2, 2)]
@@ -109,7 +111,7 @@ def test_subset_launches_match_single_replans():
     B, scenes, batched, single, xs, obs, batch = _setup()
     torch = H.torch_mod()
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-    rounds = [[0, 2, 4, 6, 8], [1, 3, 5, 7, 9], [7, 0], [9, 2, 3, 4], [5, 8], [6, 1, 0], [8, 9]]
+    rounds = [[0, 2, 4, 6, 8, 10], [1, 3, 5, 7, 9], [7, 0], [9, 2, 3, 4], [5, 8, 10], [6, 1, 0], [8, 9]]
     for i, members in enumerate(rounds):
         with torch.cuda.stream(streams[i % 2]):
             batch.replan_subset(members, stream=streams[i % 2])
