@@ -340,16 +340,39 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   const float dt = c.dt;
   const float x0 = x_t[0], y0 = x_t[1], th0 = x_t[2];
   const float n0 = j < N ? b.U[j * 2] : 0.f, n1 = j < N ? b.U[j * 2 + 1] : 0.f;
+  // Paired rounds (64-lane segments, R >= 2): one Philox evaluation per lane
+  // serves two rounds.  Lane l owns counter block l & 31 of the rollout of
+  // round rr + (l >> 5) (a rollout has ceil(2N/4) <= 32 blocks); each lane
+  // then takes the words of its own block (j >> 1) from the owner lane, so
+  // every Gaussian is the one step_gaussians<2> would give.
+  constexpr bool PAIRED = SEG == 64 && R >= 2 && (R % 2) == 0;
+  uint32_t pw[4] = {0u, 0u, 0u, 0u};
   for (int rr = 0; rr < R; ++rr) {
   const int kloc = (rr * kRollWaves + wave) * SPW + sgi;
   const int k = bx * RPB + kloc;
   const bool act = (k < c.K) && !bad;
 
   // noise, perturbation and clamp (Eq. (3)); applied perturbation kept
+  uint32_t qw[4] = {0u, 0u, 0u, 0u};
+  if constexpr (PAIRED) {
+    if ((rr & 1) == 0) {
+      const int orr = rr + (lane >> 5), ob = lane & 31;
+      const int ok = bx * RPB + orr * kRollWaves + wave;
+      if (ok < c.K && ob < c.B && !bad) philox((uint32_t)ob, (uint32_t)ok, step, c.stream_id, c.seed_lo, c.seed_hi, pw);
+    }
+    const int src = ((rr & 1) << 5) + (j >> 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) qw[i] = (uint32_t)__shfl((int)pw[i], src, kWave);
+  }
   float uv = 0.f, uw = 0.f;
   if (act && j < N) {
     float g[2];
-    step_gaussians<2>(c, step, k, j, g);
+    if constexpr (PAIRED) {
+      const bool odd = (j & 1) != 0;
+      box_muller(odd ? qw[2] : qw[0], odd ? qw[3] : qw[1], g[0], g[1]);
+    } else {
+      step_gaussians<2>(c, step, k, j, g);
+    }
     const float e0 = c.L[0] * g[0];
     const float e1 = c.L[2] * g[0] + c.L[3] * g[1];
     const float t0 = n0 + e0, t1 = n1 + e1;
