@@ -525,7 +525,7 @@ def main():
             "K": spec.num_samples, "N": spec.horizon, "n_obs": n_obs,
             "branch_mix": res["mix"], "mean_feasible_when_clustering": round(res["mean_V"], 1),
             "dbscan_trees": res["trees"],
-            "launch": "hipGraph replay per replan",
+            "launch": "direct kernel launches per replan (library default)",
         },
         "rollout_steps_per_s": round(replans_per_s * rollout_steps, 1),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),

@@ -292,6 +292,7 @@ def test_graph_and_direct_launch_agree():
 
     s = W.unicycle_dynamic_ahead(5, num_samples=1500)
     a, b = _planner(s.spec), _planner(s.spec)
+    a.set_launch_mode(B.LAUNCH_GRAPH)
     b.set_launch_mode(B.LAUNCH_DIRECT)
     for pl in (a, b):
         _set_U(pl, s.U0)
