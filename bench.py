@@ -216,9 +216,18 @@ def run_workload(name, seed, W, K, torch, B, want_timing=True, rollout_reps=2000
     Xd = torch.as_tensor(X).cuda()
     Od = torch.as_tensor(OBS).cuda()
     n_obs = OBS.shape[1]
-    # throughput
-    pl.set_state(state0)
-    wall, gpu = timed_replays(pl, lib, Xd, Od, n_obs, W, K, torch)
+    # throughput, in both launch modes (graph replay, direct launches): which
+    # one is faster depends on the host of this box; the faster is reported
+    walls = {}
+    for mode, code in (("graph", B.LAUNCH_GRAPH), ("direct", B.LAUNCH_DIRECT)):
+        pl.set_launch_mode(code)
+        pl.set_state(state0)
+        walls[mode] = timed_replays(pl, lib, Xd, Od, n_obs, W, K, torch)
+    best = min(walls, key=lambda m: walls[m][0])
+    wall, gpu = walls[best]
+    pl.set_launch_mode(B.LAUNCH_GRAPH if best == "graph" else B.LAUNCH_DIRECT)
+    launch = {"mode": best, "us_per_replan_graph": round(1e6 * walls["graph"][0] / K, 2),
+              "us_per_replan_direct": round(1e6 * walls["direct"][0] / K, 2)}
     # latency (and a bit-for-bit replay check)
     pl.set_state(state0)
     lat, same = latency_replays(pl, lib, Xd, Od, n_obs, W, K, torch, Uo)
@@ -247,7 +256,7 @@ def run_workload(name, seed, W, K, torch, B, want_timing=True, rollout_reps=2000
              "max": int(max(trees)) if trees else 0,
              "union_find_fallback": int(sum(i["tree_fallback"] for i in INFO[W:] if i["branch"] == 0))}
     pl.close()
-    return dict(scene=scene, X=X, OBS=OBS, wall=wall, gpu=gpu, lat=lat, same=same, timing=timing,
+    return dict(scene=scene, X=X, OBS=OBS, wall=wall, gpu=gpu, lat=lat, same=same, timing=timing, launch=launch,
                 kernel_ms=kernel_ms, mix=mix, mean_V=float(np.mean(ncl)) if ncl else 0.0, trees=tstat)
 
 
@@ -279,7 +288,7 @@ def companion(name, seed, W, K, torch, B, label):
         "rollout_steps_per_s": round(K / r["wall"] * spec.num_samples * spec.horizon, 1),
         "latency_ms": {"p50": round(float(np.percentile(r["lat"], 50)) * 1e3, 4),
                        "p99": round(float(np.percentile(r["lat"], 99)) * 1e3, 4)},
-        "branch_mix": r["mix"], "replay_bit_exact": r["same"],
+        "branch_mix": r["mix"], "replay_bit_exact": r["same"], "launch": r["launch"],
         "rollout_kernel_ms": round(r["kernel_ms"], 5),
         "rollout_tflops": round(flops / (r["kernel_ms"] * 1e-3) / 1e12, 4),
     }
@@ -362,23 +371,32 @@ def run_batch(seed, W, K, torch, B, autotune=True, n_planners=256):
     wall_b, _ = batch_pass(False)
     same_b = bool(np.array_equal(U.cpu().numpy(), U_rec))
     _, lat_b = batch_pass(True)
-    # the same steps as plain replans, one planner after another
-    for pl, st in zip(pls, states0):
-        pl.set_state(st)
-    U.zero_()
+    # the same steps as plain replans, one planner after another, in each
+    # launch mode (the faster one is the plain form's number on this machine)
     handles = [pl.handle for pl in pls]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t in range(T):
-        if t == W:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-        for i in range(n):
-            e = io[t][i]
-            lib.ce_mppi_replan(handles[i], e.x_t, e.obstacles, e.n_obs, e.u_out, None, None, stream)
-    torch.cuda.synchronize()
-    wall_s = time.perf_counter() - t0
-    same_s = bool(np.array_equal(U.cpu().numpy(), U_rec))
+
+    def sequential_pass(mode):
+        for pl, st in zip(pls, states0):
+            pl.set_state(st)
+            pl.set_launch_mode(mode)
+        U.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(T):
+            if t == W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            for i in range(n):
+                e = io[t][i]
+                lib.ce_mppi_replan(handles[i], e.x_t, e.obstacles, e.n_obs, e.u_out, None, None, stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, bool(np.array_equal(U.cpu().numpy(), U_rec))
+
+    wall_g, same_g = sequential_pass(B.LAUNCH_GRAPH)
+    wall_d, same_d = sequential_pass(B.LAUNCH_DIRECT)
+    seq_mode = "direct" if wall_d < wall_g else "graph"
+    wall_s = min(wall_g, wall_d)
+    same_s = same_g and same_d
     Ks = np.array([sc.spec.num_samples for sc in scenes])
     Ns = np.array([sc.spec.horizon for sc in scenes])
     batch.close()
@@ -394,7 +412,9 @@ def run_batch(seed, W, K, torch, B, autotune=True, n_planners=256):
         "latency_ms": {"p50": round(float(np.percentile(lat_b, 50)) * 1e3, 4),
                        "p99": round(float(np.percentile(lat_b, 99)) * 1e3, 4)},
         "sequential_plain": {"replans_per_s": round(n * K / wall_s, 1),
-                             "ms_per_round": round(1e3 * wall_s / K, 4)},
+                             "ms_per_round": round(1e3 * wall_s / K, 4), "launch": seq_mode,
+                             "ms_per_round_graph": round(1e3 * wall_g / K, 4),
+                             "ms_per_round_direct": round(1e3 * wall_d / K, 4)},
         "speedup_vs_sequential": round(wall_s / wall_b, 3),
         "tuning": tune,
         "bitwise_equal_to_recorded_loop": {"batched": same_b, "sequential": same_s},
@@ -525,7 +545,7 @@ def main():
             "K": spec.num_samples, "N": spec.horizon, "n_obs": n_obs,
             "branch_mix": res["mix"], "mean_feasible_when_clustering": round(res["mean_V"], 1),
             "dbscan_trees": res["trees"],
-            "launch": "direct kernel launches per replan (library default)",
+            "launch": res["launch"],
         },
         "rollout_steps_per_s": round(replans_per_s * rollout_steps, 1),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),

@@ -261,16 +261,28 @@ ce_status ce_mppi_stage_dbscan(ce_mppi_planner* planner, const float* z, int32_t
 
 /* ---- launch mode and timing ---- */
 enum { CE_LAUNCH_GRAPH = 0, CE_LAUNCH_DIRECT = 1 };
-/* CE_LAUNCH_DIRECT (default): every kernel of the replan is launched on the
- * caller's stream.
- * CE_LAUNCH_GRAPH: the first replan records the planner's kernel chain into a
- * hipGraph and every replan replays it (the first and last kernels are
- * re-pointed when the caller's buffers change).  On MI355X a replay of the
- * ten-kernel chain costs the device more than ten direct launches (measured
- * 37.3 vs 33.7 us per back-to-back replan at K=8192), so the graph is the
- * choice only where host launch cost matters more.  Both run the same
- * kernels with the same arguments and give the same bits. */
+/* CE_LAUNCH_GRAPH (default): the first replan records the planner's kernel
+ * chain into a hipGraph and every replan replays it (the first and last
+ * kernels are re-pointed when the caller's buffers change).
+ * CE_LAUNCH_DIRECT: every kernel of the replan is launched on the caller's
+ * stream.  Both run the same kernels with the same arguments and give the
+ * same bits.  Which is faster depends on the host: a replay costs the device
+ * a few microseconds more than ten direct launches, while direct launches
+ * cost the host a few microseconds each (see ce_mppi_tune_launch). */
 ce_status ce_mppi_set_launch_mode(ce_mppi_planner* planner, int32_t mode);
+/* For callers that replan back to back: run `reps` replans on (x_t,
+ * obstacles) in each launch mode, timing host wall clock from the first call
+ * to the stream being idle (so the slower of host submission and device work
+ * counts), and keep the faster mode.  The per-call times in microseconds go
+ * to *us_graph and *us_direct (either may be NULL).  u_out is a device buffer
+ * of m floats that receives scratch outputs.  The persistent state (nominal,
+ * history, step) is saved before and restored after each mode's run; the
+ * per-rollout diagnostic buffers hold the last replan's values.
+ * Synchronises the stream.  Errors: CE_EINVAL for NULL pointers, reps outside
+ * [1, 10000] or bad n_obs; CE_EDEVICE for HIP failures. */
+ce_status ce_mppi_tune_launch(ce_mppi_planner* planner, const float* x_t, const float* obstacles,
+                              int32_t n_obs, float* u_out, int32_t reps, void* stream,
+                              double* us_graph, double* us_direct);
 /* capacity > 0: the next `capacity` replans are launched directly with HIP
  * events recorded on the replan stream before the rollout kernel, after it
  * and after the last kernel; 0 disables.  Allocates the events. */

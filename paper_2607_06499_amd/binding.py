@@ -182,6 +182,8 @@ def load():
                                          _vp, _vp, _vp, _vp],
         "ce_mppi_stage_dbscan": [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp],
         "ce_mppi_set_launch_mode": [_vp, C.c_int32],
+        "ce_mppi_tune_launch": [_vp, _vp, _vp, C.c_int32, _vp, C.c_int32, _vp,
+                                C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "ce_mppi_timing_enable": [_vp, C.c_int32],
         "ce_mppi_timing_read": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_double), C.POINTER(C.c_int32)],
@@ -405,6 +407,16 @@ class Planner:
     # -- launch mode and timing
     def set_launch_mode(self, mode: int):
         _check("ce_mppi_set_launch_mode", load().ce_mppi_set_launch_mode(self.handle, int(mode)))
+
+    def tune_launch(self, x_t, obstacles=None, reps: int = 50, stream=None):
+        """Time both launch modes on these inputs and keep the faster;
+        returns (us_graph, us_direct) per replan."""
+        n_obs = 0 if obstacles is None else int(obstacles.shape[0])
+        g, d = C.c_double(), C.c_double()
+        _check("ce_mppi_tune_launch", load().ce_mppi_tune_launch(
+            self.handle, x_t.data_ptr(), obstacles.data_ptr() if n_obs else None, n_obs,
+            self.u_out.data_ptr(), int(reps), _stream_handle(stream), C.byref(g), C.byref(d)))
+        return g.value, d.value
 
     def timing_enable(self, capacity: int):
         _check("ce_mppi_timing_enable", load().ce_mppi_timing_enable(self.handle, int(capacity)))

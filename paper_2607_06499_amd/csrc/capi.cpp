@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -132,7 +133,9 @@ void build_cfg(const ce_mppi_config* u, Cfg& c) {
   c.K = u->num_samples;
   c.NM = c.N * c.m;
   c.B = (c.NM + 3) / 4;
-  c.seg = (c.dyn == CE_DYN_UNICYCLE && c.N + 1 <= 32) ? 32 : 64;
+  // lanes per rollout: the unicycle keeps x_0..x_N in lanes 0..N, the arm
+  // keeps u_j and x_{j+1} in lane j
+  c.seg = (c.dyn == CE_DYN_UNICYCLE ? c.N + 1 <= 32 : c.N <= 32) ? 32 : 64;
   c.rpb = kRollWaves * (64 / c.seg);
   c.nblk_roll = (c.K + c.rpb - 1) / c.rpb;
   c.roll_r = 1;
@@ -593,6 +596,48 @@ ce_status ce_mppi_time_rollout(ce_mppi_planner* P, const float* x_t, const float
   // the rollout phase pushes the observation into the history ring: put the
   // saved state back
   return ce_mppi_set_state(P, saved.data(), need, stream);
+}
+
+ce_status ce_mppi_tune_launch(ce_mppi_planner* P, const float* x_t, const float* obstacles,
+                              int32_t n_obs, float* u_out, int32_t reps, void* stream,
+                              double* us_graph, double* us_direct) {
+  if (!P || !x_t || !u_out) return fail(CE_EINVAL, "NULL argument");
+  if (reps < 1 || reps > 10000) return fail(CE_EINVAL, "reps out of range");
+  if (n_obs < 0 || n_obs > P->c.max_obs) return fail(CE_EINVAL, "n_obs out of range");
+  if (n_obs > 0 && !obstacles) return fail(CE_EINVAL, "obstacles is NULL");
+  size_t need = 0;
+  ce_status st = ce_mppi_state_size(P, &need);
+  if (st != CE_OK) return st;
+  std::vector<char> saved(need);
+  st = ce_mppi_get_state(P, saved.data(), need, stream);
+  if (st != CE_OK) return st;
+  DeviceGuard guard(P->cfg.device);
+  hipStream_t s = S(stream);
+  const int keep_cap = P->t.cap;
+  P->t.cap = 0;  // the timed mode would bypass the launch mode under test
+  double us[2] = {0.0, 0.0};
+  const int32_t modes[2] = {CE_LAUNCH_GRAPH, CE_LAUNCH_DIRECT};
+  for (int m = 0; m < 2 && st == CE_OK; ++m) {
+    P->launch_mode = modes[m];
+    // one untimed replan (builds the graph), then `reps` back to back: host
+    // wall time from the first call to the stream being idle, which counts
+    // whichever of host submission and device work is the bottleneck
+    st = ce_mppi_replan(P, x_t, obstacles, n_obs, u_out, nullptr, nullptr, stream);
+    if (st == CE_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(CE_EDEVICE, "tune_launch sync");
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < reps && st == CE_OK; ++i)
+      st = ce_mppi_replan(P, x_t, obstacles, n_obs, u_out, nullptr, nullptr, stream);
+    if (st == CE_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(CE_EDEVICE, "tune_launch sync");
+    const auto t1 = std::chrono::steady_clock::now();
+    us[m] = std::chrono::duration<double, std::micro>(t1 - t0).count() / reps;
+    if (st == CE_OK) st = ce_mppi_set_state(P, saved.data(), need, stream);
+  }
+  P->t.cap = keep_cap;
+  if (st != CE_OK) return st;
+  P->launch_mode = us[1] < us[0] ? CE_LAUNCH_DIRECT : CE_LAUNCH_GRAPH;
+  if (us_graph) *us_graph = us[0];
+  if (us_direct) *us_direct = us[1];
+  return CE_OK;
 }
 
 ce_status ce_mppi_replan_from_rollouts(ce_mppi_planner* P, const float* x_t, const float* obstacles,

@@ -44,7 +44,7 @@ struct ce_mppi_planner {
   void* arena = nullptr;
   size_t arena_bytes = 0;
   size_t cap_K = 0;
-  int launch_mode = CE_LAUNCH_DIRECT;
+  int launch_mode = CE_LAUNCH_GRAPH;
   cemppi::ReplanGraph g;
   cemppi::Timing t;
 };

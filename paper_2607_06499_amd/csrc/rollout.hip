@@ -130,10 +130,12 @@ __device__ __forceinline__ float limit_penalty(const Cfg& c, const float* q) {
 // computes o* (smallest surface clearance, ties to the lowest index) and
 // p(x_t).  Returns through LDS: s_bad, s_closest, s_p0.
 // CVM: constant-velocity obstacles never (0), always (1) or as c.cv says (2).
+// Arm (DYN 1): *s_c0 receives the state part of the stage cost of x_t
+// (with the pose cost, including its contact indicator).
 template <int DYN, int CVM = 2>
 __device__ void prologue(const Cfg& c, const Bufs& b, const float* __restrict__ x_t,
                          const float* __restrict__ obs, int n_obs, ObsLds& L, int& s_bad,
-                         int& s_closest, float* s_p0) {
+                         int& s_closest, float* s_p0, float* s_c0 = nullptr) {
   const int tid = threadIdx.x;
   const int P = DYN == 0 ? 2 : 3;
   if (tid == 0) s_bad = 0;
@@ -182,22 +184,32 @@ __device__ void prologue(const Cfg& c, const Bufs& b, const float* __restrict__ 
         idx = tid;
       }
     } else {
-      float q[6], Pm[7][3];
+      float q[6], Pm[7][3], Re[9];
       for (int i = 0; i < 6; ++i) q[i] = x_t[i];
-      arm_origins(c, q, Pm);
+      arm_origins(c, q, Pm, Re);
       if (tid == 0) {
         s_p0[0] = Pm[6][0];
         s_p0[1] = Pm[6][1];
         s_p0[2] = Pm[6][2];
       }
+      bool touch = false;
       if (tid < n_obs) {
         for (int s = 0; s < c.ns; ++s) {
           float sx, sy, sz;
           sphere_centre(c, Pm, s, sx, sy, sz);
-          const float v = sqrtf(dist2_3(sx, sy, sz, L.o[tid].x, L.o[tid].y, L.o[tid].z)) - L.r[tid];
+          const float d2 = dist2_3(sx, sy, sz, L.o[tid].x, L.o[tid].y, L.o[tid].z);
+          const float v = sqrtf(d2) - L.r[tid];
           cl = v < cl ? v : cl;
+          touch |= d2 <= L.o[tid].w;
         }
         idx = tid;
+      }
+      const bool icol0 = __ballot(touch) != 0ull;
+      if (tid == 0 && s_c0) {
+        const float d2g = sq(Pm[6][0] - c.goal[0]) + sq(Pm[6][1] - c.goal[1]) + sq(Pm[6][2] - c.goal[2]);
+        *s_c0 = c.pose ? c.Q[0] * sqrtf(d2g) + c.Q[1] * rot_angle(c, Re) + limit_penalty(c, q) +
+                             (icol0 ? c.Q[2] : 0.f)
+                       : c.Q[0] * d2g + limit_penalty(c, q);
       }
     }
 #pragma unroll
@@ -481,38 +493,44 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_unicycle(Cfg c, Bufs b
 // Six-joint arm rollouts (Sec. III-C): joint-velocity control, q_{j+1} =
 // q_j + u_j dt; end-effector cost (squared distance, or the pose cost of the
 // real-robot experiment), joint-limit penalty, link spheres against obstacle
-// spheres.
-template <int R = 1>
+// spheres.  Lane j of a segment holds control u_j and the state x_{j+1} it
+// leads to (an inclusive scan), so N <= 32 fits a 32-lane segment and a wave
+// runs two rollouts; the state part of the cost of x_t (the same for every
+// rollout) comes from the prologue.
+template <int SEG, int R = 1>
 __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
                                                  const float* __restrict__ x_t,
                                                  const float* __restrict__ obs, int n_obs) {
-  constexpr int SEG = 64;
+  constexpr int SPW = kWave / SEG;
+  constexpr int RPB = kRollWaves * SPW * R;
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
-  __shared__ float s_p0[3];
-  __shared__ float s_rec[kRollWaves * R][kPart];
-  prologue<1>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
+  __shared__ float s_p0[3], s_c0;
+  __shared__ float s_rec[RPB][kPart];
+  prologue<1>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0, &s_c0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
   if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
+  const float c0 = s_c0;
 
-  constexpr int RPB = kRollWaves * R;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const int j = lane;
+  const int j = lane & (SEG - 1), sgi = lane / SEG;
   const int N = c.N;
   const float dt = c.dt;
   float un[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) un[i] = j < N ? b.U[j * 6 + i] : 0.f;
   for (int rr = 0; rr < R; ++rr) {
-  const int kloc = rr * kRollWaves + wave;
+  const int kloc = (rr * kRollWaves + wave) * SPW + sgi;
   const int k = bx * RPB + kloc;
   const bool act = (k < c.K) && !bad;
+  const bool live = act && j < N;  // control u_j, state x_{j+1}
+  const bool last = j == N - 1;    // state x_N: terminal weights
 
   float u[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) u[i] = 0.f;
-  if (act && j < N) {
+  if (live) {
     float g[6];
     step_gaussians<6>(c, step, k, j, g);
     float a[6];
@@ -534,38 +552,29 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
   }
   float q[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) q[i] = x_t[i] + seg_excl_scan<SEG>(u[i] * dt, j);
+  for (int i = 0; i < 6; ++i) q[i] = x_t[i] + seg_incl_scan<SEG>(u[i] * dt, j);
   float P[7][3], Re[9];
   arm_origins(c, q, P, Re);
   const float ex = P[6][0], ey = P[6][1], ez = P[6][2];
   float l = 0.f;
   const float d2g = sq(ex - c.goal[0]) + sq(ey - c.goal[1]) + sq(ez - c.goal[2]);
-  if (c.pose) {
-    // Sec. III-C: w_p |p_ee - p_g| + w_R d_R (+ w_c I_col, below)
-    if (act && j <= N) {
-      const bool st = j < N;
-      float r = 0.f;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) r += c.R[i] * u[i] * u[i];
-      l = (st ? c.Q[0] : c.Qf[0]) * sqrtf(d2g) + (st ? c.Q[1] : c.Qf[1]) * rot_angle(c, Re) +
-          limit_penalty(c, q) + (st ? r : 0.f);
-    }
-  } else if (act && j < N) {
+  if (live) {
     float r = 0.f;
 #pragma unroll
     for (int i = 0; i < 6; ++i) r += c.R[i] * u[i] * u[i];
-    l = c.Q[0] * d2g + limit_penalty(c, q) + r;
-  } else if (act && j == N) {
-    l = c.Qf[0] * d2g + limit_penalty(c, q);
+    if (c.pose)  // Sec. III-C: w_p |p_ee - p_g| + w_R d_R (+ w_c I_col, below)
+      l = (last ? c.Qf[0] : c.Q[0]) * sqrtf(d2g) + (last ? c.Qf[1] : c.Q[1]) * rot_angle(c, Re) +
+          limit_penalty(c, q) + r;
+    else
+      l = (last ? c.Qf[0] : c.Q[0]) * d2g + limit_penalty(c, q) + r;
   }
 
-  // pass 1: any contact of any link sphere (states 1..N; with the pose cost
-  // also x_0, which enters the cost only); pass 2 (waves with a contact):
-  // the lowest obstacle index touched
-  const bool chk = act && j <= N && (j >= 1 || c.pose);
-  const float tj = (float)j * dt;
+  // pass 1: any contact of any link sphere with any obstacle (at time
+  // (j + 1) dt for moving obstacles); pass 2 (waves with a contact): the
+  // lowest obstacle index touched
+  const float tj = (float)(j + 1) * dt;
   bool any = false;
-  if (chk) {
+  if (live) {
     for (int s = 0; s < c.ns; ++s) {
       float sx, sy, sz;
       sphere_centre(c, P, s, sx, sy, sz);
@@ -583,11 +592,10 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
       }
     }
   }
-  if (c.pose && any) l += j < N ? c.Q[2] : c.Qf[2];
-  const float S = seg_sum<SEG>(l);
-  const bool anyc = any && j >= 1;
+  if (c.pose && any) l += last ? c.Qf[2] : c.Q[2];
+  const float S = seg_sum<SEG>(l) + c0;
   int hit = kInt32Max;
-  if (__ballot(anyc) != 0ull && anyc) {
+  if (__ballot(any) != 0ull && any) {
     for (int s = 0; s < c.ns; ++s) {
       float sx, sy, sz;
       sphere_centre(c, P, s, sx, sy, sz);
@@ -607,13 +615,18 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
       hit = hs < hit ? hs : hit;
     }
   }
+  // first colliding state of each segment (lowest lane with a hit)
   const unsigned long long hm = __ballot(hit != kInt32Max);
-  const int col = hm != 0ull;
-  const int fl = col ? __ffsll((long long)hm) - 1 : 0;
-  const int f = __builtin_amdgcn_readlane(hit, fl);
-  const float pfx = seg_bcast<64>(ex, fl), pfy = seg_bcast<64>(ey, fl), pfz = seg_bcast<64>(ez, fl);
-  const int ln = N;
-  const float ptx = seg_bcast<64>(ex, ln), pty = seg_bcast<64>(ey, ln), ptz = seg_bcast<64>(ez, ln);
+  const unsigned long long m0 = SEG == 64 ? hm : (hm & 0xffffffffull);
+  const unsigned long long m1 = SEG == 64 ? 0ull : (hm >> 32);
+  const int f0 = m0 ? __ffsll((long long)m0) - 1 : 0;
+  const int f1 = m1 ? __ffsll((long long)m1) - 1 : 0;
+  const int col = (sgi == 0 ? m0 : m1) != 0ull;
+  const int f = seg_pick_i<SEG>(hit, f0, f1);
+  const float pfx = seg_pick<SEG>(ex, f0, f1), pfy = seg_pick<SEG>(ey, f0, f1),
+              pfz = seg_pick<SEG>(ez, f0, f1);
+  const int ln = N - 1;
+  const float ptx = seg_bcast<SEG>(ex, ln), pty = seg_bcast<SEG>(ey, ln), ptz = seg_bcast<SEG>(ez, ln);
 
   float src[3];
   src[0] = c.ref_mode == 1 ? pfx : ptx;
@@ -642,8 +655,9 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
   write_group_partials(b, s_rec, RPB, bx);
 }
 
+template <int SEG>
 __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b, const float* __restrict__ x_t, const float* __restrict__ obs, int n_obs) {
-  rollout_arm_body(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, x_t, obs, n_obs);
+  rollout_arm_body<SEG>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, x_t, obs, n_obs);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,7 +679,11 @@ __global__ __launch_bounds__(kRollThreads) void kb_rollout_arm(CSlotStatic st, C
   for_each_item(t, s_pref, [&](int slot, int local) {
     const SlotStatic& S = *(const SlotStatic*)(st + slot);
     const SlotIO& I = *(const SlotIO*)(io + slot);
-    rollout_arm_body<R>(S.c, S.b, local, 0, 0, I.x_t, I.obs, I.n_obs);
+    // the segment width is the member's own (a block-uniform branch)
+    if (S.c.seg == 32)
+      rollout_arm_body<32, R>(S.c, S.b, local, 0, 0, I.x_t, I.obs, I.n_obs);
+    else
+      rollout_arm_body<64, R>(S.c, S.b, local, 0, 0, I.x_t, I.obs, I.n_obs);
   });
 }
 
@@ -775,7 +793,7 @@ void launch_rollout(Launcher& L, const Cfg& c, const Bufs& b, const float* x_t, 
     const int rr = c.roll_r == 2 ? 2 : 1;
     L(f, dim3((c.K + c.rpb * rr - 1) / (c.rpb * rr)), block, c, b, x_t, obs, n_obs);
   } else {
-    L(k_rollout_arm, grid, block, c, b, x_t, obs, n_obs);
+    L(c.seg == 32 ? k_rollout_arm<32> : k_rollout_arm<64>, grid, block, c, b, x_t, obs, n_obs);
   }
 }
 

@@ -82,13 +82,29 @@ def rel_err(a, b, floor=1.0):
     return np.abs(a - b) / np.maximum(np.abs(b), floor)
 
 
-def flagged_pairs(z, eps: float, band: float = PAIR_BAND):
-    """Indices of points in a pair whose distance is within band*eps of eps."""
+def feature_slack(p_term, ref, floor: float = 2e-5, rel: float = 1e-6):
+    """Per-point bound on |z_gpu - z_oracle| for z = d / |d|, d = p_term - ref:
+    a perturbation delta of d moves z by at most 2 |delta| / |d|, and the FP32
+    path perturbs d by about rel * (|p_term| + |ref| + 1)."""
+    p_term = np.asarray(p_term, np.float64)
+    ref = np.asarray(ref, np.float64)
+    dn = np.linalg.norm(p_term - ref[None, :], axis=1)
+    mag = np.linalg.norm(p_term, axis=1) + np.linalg.norm(ref) + 1.0
+    return floor + 2.0 * rel * mag / np.maximum(dn, 1e-9)
+
+
+def flagged_pairs(z, eps: float, band: float = PAIR_BAND, slack=None):
+    """Indices of points in a pair whose distance is within band*eps of eps
+    (plus the two points' feature slack, when given)."""
     z = np.asarray(z, np.float64)
     if len(z) < 2:
         return np.zeros(0, int), 0
     d = np.sqrt(((z[:, None, :] - z[None, :, :]) ** 2).sum(-1))
-    near = np.abs(d - eps) <= band * eps
+    lim = band * eps
+    if slack is not None:
+        sl = np.asarray(slack, np.float64)
+        lim = lim + sl[:, None] + sl[None, :]
+    near = np.abs(d - eps) <= lim
     np.fill_diagonal(near, False)
     pts = np.nonzero(near.any(1))[0]
     return pts, int(near.sum() // 2)

@@ -151,6 +151,7 @@ def test_null_arguments(lib):
     assert lib.ce_mppi_server_create(C.byref(cfg), C.byref(h)) == B.CE_EINVAL  # max_batch 0
     cfg = B.CeMppiServerConfig(0, 4, 4, 0, 0)
     assert lib.ce_mppi_server_create(C.byref(cfg), C.byref(h)) == B.CE_EINVAL  # max_inflight 4
+    assert lib.ce_mppi_tune_launch(None, None, None, 0, None, 1, None, None, None) == B.CE_EINVAL
     assert lib.ce_mppi_server_start(None) == B.CE_EINVAL
     assert lib.ce_mppi_server_session_planner(None, 0) is None
     lib.ce_mppi_server_destroy(None)  # NULL-safe

@@ -116,9 +116,11 @@ def _check_post(r, o, spec, exact_labels=True):
     assert inf["closest"] == o["closest"]
     assert np.array_equal(r["v_idx"], o["v_idx"])
     assert H.rel_err(inf["ref_point"][: spec.p], o["ref_point"]).max() <= 1e-5
-    assert np.abs(r["z"] - o["z"]).max() <= 2e-5
+    # z = d / |d| amplifies the FP32 error of d = p_term - ref by 2 / |d|
+    slack = H.feature_slack(o["p_term"][o["v_idx"]], o["ref_point"])
+    assert np.all(np.abs(r["z"] - o["z"]).max(axis=1) <= slack)
     assert np.abs(r["g"] - o["g"]).max() <= 2e-5
-    pts, npairs = H.flagged_pairs(o["z"], float(np.float32(spec.dbscan_eps)))
+    pts, npairs = H.flagged_pairs(o["z"], float(np.float32(spec.dbscan_eps)), slack=slack)
     if npairs == 0 and exact_labels:
         assert H.counts_agree(r["ncount"], o["ncount"], spec.dbscan_min_pts)
         assert np.array_equal(r["label"], o["label"])
@@ -354,6 +356,29 @@ def test_time_rollout_restores_state():
     assert a1["info"]["step"] == b1["info"]["step"] == a0["info"]["step"] + 1
 
 
+
+def test_tune_launch_restores_state_and_picks_a_mode():
+    """The launch-mode tuner leaves the planner as it was (the next replan
+    equals the one it would have been) and keeps the faster mode; both modes
+    give the same bits."""
+    from paper_2607_06499_amd import binding as B
+
+    s = W.unicycle_dynamic_ahead(6, num_samples=2048)
+    pl = _planner(s.spec)
+    _set_U(pl, s.U0)
+    a0 = H.gpu_replan(pl, s.x0, s.obstacles)
+    state = pl.get_state()
+    a1 = H.gpu_replan(pl, s.x0, s.obstacles)
+    pl.set_state(state)
+    ug, ud = pl.tune_launch(H.to_dev(s.x0), H.to_dev(s.obstacles), reps=4)
+    assert ug > 0.0 and ud > 0.0
+    b1 = H.gpu_replan(pl, s.x0, s.obstacles)
+    for k in ("S", "col", "u_out", "U_new", "U_next"):
+        assert np.array_equal(a1[k], b1[k]), k
+    assert a1["info"]["step"] == b1["info"]["step"] == a0["info"]["step"] + 1
+    with pytest.raises(B.CeMppiError):
+        pl.tune_launch(H.to_dev(s.x0), H.to_dev(s.obstacles), reps=0)
+
 def test_lockstep_dynamic_loop():
     """unicycle_dynamic shaped scene, a few closed-loop steps in lockstep: at
     every step both sides start from the same state, nominal and history."""
@@ -382,6 +407,48 @@ def test_lockstep_dynamic_loop():
         fld.step(spec.dt)
     assert compared >= 6
 
+
+
+FULL = [
+    ("unicycle_static", lambda: W.unicycle_static(1)),
+    ("unicycle_dynamic", lambda: W.unicycle_dynamic(1)),
+    ("unicycle_dynamic_ahead", lambda: W.unicycle_dynamic_ahead(1)),
+    ("arm6_dynamic", lambda: W.arm6_dynamic(1)),
+]
+
+
+@pytest.mark.parametrize("name,make", FULL, ids=[f[0] for f in FULL])
+def test_full_size_workloads_match_oracle(name, make):
+    """The benchmark's single-planner workloads at their full sizes (K up to
+    8192, N up to 50) in the launch configuration the benchmark times (the
+    library default), three closed-loop steps in lockstep with the oracle:
+    every rollout record element by element, then the post-rollout stages."""
+    s = make()
+    spec = s.spec
+    pl = _planner(spec)
+    fld = s.field.copy()
+    x = s.x0.astype(np.float64)
+    U = s.U0.astype(np.float64)
+    hist = []
+    flagged = 0
+    for t in range(3):
+        obs = fld.observation()
+        hist.insert(0, obs[:, : spec.p].astype(np.float64))
+        hist = hist[: spec.history_len]
+        _set_U(pl, np.float32(U))
+        r = H.gpu_replan(pl, np.float32(x), obs)
+        o = oracle.replan(spec, np.float32(x), np.float32(U), obs, np.array(hist), step=t)
+        assert r["info"]["step"] == t
+        bnd = _compare_rollouts(r, o, spec)
+        flagged += int(bnd.sum())
+        if np.array_equal(r["col"], o["col"]):
+            _check_post(r, o, spec)
+        U = o["U_next"]
+        x = (oracle.unicycle_step(x, o["u_out"], spec.dt) if spec.dynamics == W.UNICYCLE
+             else _arm_step(x, o["u_out"], spec.dt))
+        fld.step(spec.dt)
+    print(f"{name}: K={spec.num_samples} N={spec.horizon}, {flagged} boundary rollouts flagged")
+    assert flagged <= 3 * max(4, spec.num_samples // 1000)
 
 def test_degenerate_branches():
     # every rollout collides
