@@ -352,12 +352,15 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   const float dt = c.dt;
   const float x0 = x_t[0], y0 = x_t[1], th0 = x_t[2];
   const float n0 = j < N ? b.U[j * 2] : 0.f, n1 = j < N ? b.U[j * 2 + 1] : 0.f;
-  // Paired rounds (64-lane segments, R >= 2): one Philox evaluation per lane
-  // serves two rounds.  Lane l owns counter block l & 31 of the rollout of
-  // round rr + (l >> 5) (a rollout has ceil(2N/4) <= 32 blocks); each lane
-  // then takes the words of its own block (j >> 1) from the owner lane, so
-  // every Gaussian is the one step_gaussians<2> would give.
-  constexpr bool PAIRED = SEG == 64 && R >= 2 && (R % 2) == 0;
+  // Paired rounds (R even): one Philox evaluation per lane serves two
+  // rounds.  A rollout needs ceil(2N/4) counter blocks: at most 32 with
+  // 64-lane segments, at most 16 with 32-lane ones (N <= 31), so the 64
+  // lanes own, in groups of OWN, every block of the SPW rollouts of round
+  // rr and of round rr + 1.  Each lane then takes the words of its own block
+  // (j >> 1) from the owner lane, so every Gaussian is the one
+  // step_gaussians<2> would give.
+  constexpr bool PAIRED = R >= 2 && (R % 2) == 0;
+  constexpr int OWN = SEG == 64 ? 32 : 16;
   uint32_t pw[4] = {0u, 0u, 0u, 0u};
   for (int rr = 0; rr < R; ++rr) {
   const int kloc = (rr * kRollWaves + wave) * SPW + sgi;
@@ -368,11 +371,12 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   uint32_t qw[4] = {0u, 0u, 0u, 0u};
   if constexpr (PAIRED) {
     if ((rr & 1) == 0) {
-      const int orr = rr + (lane >> 5), ob = lane & 31;
-      const int ok = bx * RPB + orr * kRollWaves + wave;
+      const int q = lane / OWN, ob = lane % OWN;
+      const int orr = rr + q / SPW, osg = q % SPW;
+      const int ok = bx * RPB + (orr * kRollWaves + wave) * SPW + osg;
       if (ok < c.K && ob < c.B && !bad) philox((uint32_t)ob, (uint32_t)ok, step, c.stream_id, c.seed_lo, c.seed_hi, pw);
     }
-    const int src = ((rr & 1) << 5) + (j >> 1);
+    const int src = ((rr & 1) * SPW + sgi) * OWN + (j >> 1);
 #pragma unroll
     for (int i = 0; i < 4; ++i) qw[i] = (uint32_t)__shfl((int)pw[i], src, kWave);
   }
@@ -475,8 +479,9 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
       // unit terminal displacement, Eq. (15)
       const float ex = ptx - x0, ey = pty - y0;
       const float den = sqrtf(__builtin_fmaf(ey, ey, ex * ex)) + c.norm_eps;
-      b.g[2 * k] = ex / den;
-      b.g[2 * k + 1] = ey / den;
+      const float inv = __builtin_amdgcn_rcpf(den);  // one v_rcp_f32 instead of two divisions
+      b.g[2 * k] = ex * inv;
+      b.g[2 * k + 1] = ey * inv;
     }
     rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 2);
   }
@@ -645,9 +650,10 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
       b.pF[3 * k + 2] = col ? pfz : 0.f;
       const float dx = ptx - s_p0[0], dy = pty - s_p0[1], dz = ptz - s_p0[2];
       const float den = sqrtf(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))) + c.norm_eps;
-      b.g[3 * k] = dx / den;
-      b.g[3 * k + 1] = dy / den;
-      b.g[3 * k + 2] = dz / den;
+      const float inv = __builtin_amdgcn_rcpf(den);
+      b.g[3 * k] = dx * inv;
+      b.g[3 * k + 1] = dy * inv;
+      b.g[3 * k + 2] = dz * inv;
     }
     rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 3);
   }
@@ -720,7 +726,8 @@ __global__ __launch_bounds__(kRollThreads) void k_reduce_records(Cfg c, Bufs b,
       for (int i = 0; i < P; ++i) e[i] = b.pT[(size_t)k * P + i] - s_p0[i];
       const float den =
           sqrtf(__builtin_fmaf(e[2], e[2], __builtin_fmaf(e[1], e[1], e[0] * e[0]))) + c.norm_eps;
-      for (int i = 0; i < P; ++i) b.g[(size_t)k * P + i] = e[i] / den;
+      const float inv = __builtin_amdgcn_rcpf(den);
+      for (int i = 0; i < P; ++i) b.g[(size_t)k * P + i] = e[i] * inv;
     }
     rollout_contrib(s_rec[threadIdx.x], act, col, f, closest, S, src, P);
   }
