@@ -478,8 +478,8 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
       b.pF[2 * k + 1] = col ? pfy : 0.f;
       // unit terminal displacement, Eq. (15)
       const float ex = ptx - x0, ey = pty - y0;
-      const float den = sqrtf(__builtin_fmaf(ey, ey, ex * ex)) + c.norm_eps;
-      const float inv = __builtin_amdgcn_rcpf(den);  // one v_rcp_f32 instead of two divisions
+      const float den = __builtin_amdgcn_sqrtf(__builtin_fmaf(ey, ey, ex * ex)) + c.norm_eps;
+      const float inv = __builtin_amdgcn_rcpf(den);  // v_sqrt_f32 and one v_rcp_f32
       b.g[2 * k] = ex * inv;
       b.g[2 * k + 1] = ey * inv;
     }
@@ -649,7 +649,8 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
       b.pF[3 * k + 1] = col ? pfy : 0.f;
       b.pF[3 * k + 2] = col ? pfz : 0.f;
       const float dx = ptx - s_p0[0], dy = pty - s_p0[1], dz = ptz - s_p0[2];
-      const float den = sqrtf(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))) + c.norm_eps;
+      const float den =
+          __builtin_amdgcn_sqrtf(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx))) + c.norm_eps;
       const float inv = __builtin_amdgcn_rcpf(den);
       b.g[3 * k] = dx * inv;
       b.g[3 * k + 1] = dy * inv;
