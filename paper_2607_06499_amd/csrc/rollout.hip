@@ -338,10 +338,20 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
   __shared__ float s_rec[kRollWaves * (kWave / SEG) * R][kPart];
-  prologue<0, CVM>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
+  // With one or two rounds the prologue (obstacles, finiteness, o*) runs
+  // after the first round's noise, dynamics and cost, which do not need it,
+  // so that its loads and barriers overlap that work; nothing is stored
+  // before it has run.  With more rounds it runs first (the late form costs
+  // registers, and so occupancy, in the persistent batched launch).
+  constexpr bool LATE = R <= 2;
   const uint32_t step = b.ctrl->step_lo;
-  const int bad = s_bad, closest = s_closest;
-  if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
+  int bad = 0, closest = -1;
+  if constexpr (!LATE) {
+    prologue<0, CVM>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
+    bad = s_bad;
+    closest = s_closest;
+    if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
+  }
   const bool cv = CVM == 2 ? c.cv != 0 : CVM == 1;
 
   constexpr int SPW = kWave / SEG;
@@ -365,7 +375,7 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   for (int rr = 0; rr < R; ++rr) {
   const int kloc = (rr * kRollWaves + wave) * SPW + sgi;
   const int k = bx * RPB + kloc;
-  const bool act = (k < c.K) && !bad;
+  const bool inr = k < c.K;
 
   // noise, perturbation and clamp (Eq. (3)); applied perturbation kept
   uint32_t qw[4] = {0u, 0u, 0u, 0u};
@@ -374,14 +384,14 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
       const int q = lane / OWN, ob = lane % OWN;
       const int orr = rr + q / SPW, osg = q % SPW;
       const int ok = bx * RPB + (orr * kRollWaves + wave) * SPW + osg;
-      if (ok < c.K && ob < c.B && !bad) philox((uint32_t)ob, (uint32_t)ok, step, c.stream_id, c.seed_lo, c.seed_hi, pw);
+      if (ok < c.K && ob < c.B) philox((uint32_t)ob, (uint32_t)ok, step, c.stream_id, c.seed_lo, c.seed_hi, pw);
     }
     const int src = ((rr & 1) * SPW + sgi) * OWN + (j >> 1);
 #pragma unroll
     for (int i = 0; i < 4; ++i) qw[i] = (uint32_t)__shfl((int)pw[i], src, kWave);
   }
-  float uv = 0.f, uw = 0.f;
-  if (act && j < N) {
+  float uv = 0.f, uw = 0.f, a0 = 0.f, a1 = 0.f;
+  if (inr && j < N) {
     float g[2];
     if constexpr (PAIRED) {
       const bool odd = (j & 1) != 0;
@@ -394,10 +404,8 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
     const float t0 = n0 + e0, t1 = n1 + e1;
     uv = fminf(fmaxf(t0, c.umin[0]), c.umax[0]);
     uw = fminf(fmaxf(t1, c.umin[1]), c.umax[1]);
-    const float a0 = uv == t0 ? e0 : uv - n0;
-    const float a1 = uw == t1 ? e1 : uw - n1;
-    float2* ep = reinterpret_cast<float2*>(b.eps + ((size_t)k * N + j) * 2);
-    *ep = make_float2(a0, a1);
+    a0 = uv == t0 ? e0 : uv - n0;
+    a1 = uw == t1 ? e1 : uw - n1;
   }
   // forward simulation, Eq. (4)/(21): heading and position are prefix sums
   const float th = th0 + seg_excl_scan<SEG>(uw * dt, j);
@@ -408,13 +416,25 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
 
   // cost, Eq. (5): stage terms in lanes 0..N-1, terminal term in lane N
   float l = 0.f;
-  if (act && j < N) {
+  if (inr && j < N) {
     l = c.Q[0] * sq(px - c.goal[0]) + c.Q[1] * sq(py - c.goal[1]) + c.Q[2] * sq(th - c.goal[2]) +
         c.R[0] * uv * uv + c.R[1] * uw * uw;
-  } else if (act && j == N) {
+  } else if (inr && j == N) {
     l = c.Qf[0] * sq(px - c.goal[0]) + c.Qf[1] * sq(py - c.goal[1]) + c.Qf[2] * sq(th - c.goal[2]);
   }
   const float S = seg_sum<SEG>(l);
+
+  if (LATE && rr == 0) {
+    prologue<0, CVM>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
+    bad = s_bad;
+    closest = s_closest;
+    if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
+  }
+  const bool act = inr && !bad;
+  if (act && j < N) {
+    float2* ep = reinterpret_cast<float2*>(b.eps + ((size_t)k * N + j) * 2);
+    *ep = make_float2(a0, a1);
+  }
 
   // collision of states 1..N against the obstacles: lowest index hit
   // pass 1: does this state touch any obstacle?  pass 2 (only in waves with
