@@ -288,23 +288,18 @@ __device__ void publish(const Cfg& c, const Bufs& b, const float* __restrict__ o
 // Per-rollout contribution to the block partial record.
 __device__ __forceinline__ void rollout_contrib(float* rec, bool active, int col, int first,
                                                 int closest, float S, const float* src, int P) {
-  for (int i = 0; i < kPart; ++i) rec[i] = 0.f;
-  rec[P_SMIN_ALL] = INFINITY;
-  rec[P_SMIN_FEAS] = INFINITY;
-  if (!active) return;
-  rec[P_SMIN_ALL] = S;
-  if (col) {
-    rec[P_NCOL] = 1.f;
-    const bool inA = first == closest;
-    rec[P_NREF] = inA ? 1.f : 0.f;
-    for (int i = 0; i < P; ++i) {
-      rec[P_SUM_COL + i] = src[i];
-      rec[P_SUM_REF + i] = inA ? src[i] : 0.f;
-    }
-  } else {
-    rec[P_NFEAS] = 1.f;
-    rec[P_SMIN_FEAS] = S;
-  }
+  // every field as one select, written as three 16-byte stores
+  const bool hit = active && col;
+  const bool inA = hit && first == closest;
+  const bool feas = active && !col;
+  float4* r4 = reinterpret_cast<float4*>(rec);
+  static_assert(kPart == 12 && P_NCOL == 0 && P_NREF == 1 && P_NFEAS == 2 && P_SMIN_ALL == 3 &&
+                    P_SMIN_FEAS == 4 && P_SUM_REF == 5 && P_SUM_COL == 8,
+                "record layout");
+  const float s0 = src[0], s1 = src[1], s2 = P == 3 ? src[2] : 0.f;
+  r4[0] = make_float4(hit ? 1.f : 0.f, inA ? 1.f : 0.f, feas ? 1.f : 0.f, active ? S : INFINITY);
+  r4[1] = make_float4(feas ? S : INFINITY, inA ? s0 : 0.f, inA ? s1 : 0.f, inA ? s2 : 0.f);
+  r4[2] = make_float4(hit ? s0 : 0.f, hit ? s1 : 0.f, hit ? s2 : 0.f, 0.f);
 }
 
 // Partial records of groups of kGroup consecutive rollouts, each summed in
@@ -337,7 +332,7 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
-  __shared__ float s_rec[kRollWaves * (kWave / SEG) * R][kPart];
+  __shared__ __align__(16) float s_rec[kRollWaves * (kWave / SEG) * R][kPart];
   // With one or two rounds the prologue (obstacles, finiteness, o*) runs
   // after the first round's noise, dynamics and cost, which do not need it,
   // so that its loads and barriers overlap that work; nothing is stored
@@ -374,7 +369,8 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   uint32_t pw[4] = {0u, 0u, 0u, 0u};
   for (int rr = 0; rr < R; ++rr) {
   const int kloc = (rr * kRollWaves + wave) * SPW + sgi;
-  const int k = bx * RPB + kloc;
+  // one rollout per wave with 64-lane segments: k is wave-uniform (scalar)
+  const int k = SEG == 64 ? __builtin_amdgcn_readfirstlane(bx * RPB + kloc) : bx * RPB + kloc;
   const bool inr = k < c.K;
 
   // noise, perturbation and clamp (Eq. (3)); applied perturbation kept
@@ -531,7 +527,7 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3], s_c0;
-  __shared__ float s_rec[RPB][kPart];
+  __shared__ __align__(16) float s_rec[RPB][kPart];
   prologue<1>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0, &s_c0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
@@ -547,7 +543,7 @@ __device__ __forceinline__ void rollout_arm_body(const Cfg& c, const Bufs& b, in
   for (int i = 0; i < 6; ++i) un[i] = j < N ? b.U[j * 6 + i] : 0.f;
   for (int rr = 0; rr < R; ++rr) {
   const int kloc = (rr * kRollWaves + wave) * SPW + sgi;
-  const int k = bx * RPB + kloc;
+  const int k = SEG == 64 ? __builtin_amdgcn_readfirstlane(bx * RPB + kloc) : bx * RPB + kloc;
   const bool act = (k < c.K) && !bad;
   const bool live = act && j < N;  // control u_j, state x_{j+1}
   const bool last = j == N - 1;    // state x_N: terminal weights
@@ -725,7 +721,7 @@ __global__ __launch_bounds__(kRollThreads) void k_reduce_records(Cfg c, Bufs b,
   __shared__ ObsLds L;
   __shared__ int s_bad, s_closest;
   __shared__ float s_p0[3];
-  __shared__ float s_rec[kMaxRpb][kPart];
+  __shared__ __align__(16) float s_rec[kMaxRpb][kPart];
   prologue<DYN>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
   const uint32_t step = b.ctrl->step_lo;
   const int bad = s_bad, closest = s_closest;
