@@ -190,6 +190,33 @@ __device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx
     ct->M = 0;
     ct->sel = -1;
     for (int i = 0; i < 3; ++i) ct->ref[i] = T.ref[i];
+    // Eq. (17) for o*, once per replan on the clustering branch (the
+    // selection reads it): the mean of H'-1 finite differences telescopes
+    // to (o_t - o_{t-H'+1}) / ((H'-1) dt)
+    float v[3] = {0.f, 0.f, 0.f};
+    int Hp = 0;
+    if (c.scene_mode == 1 && T.branch == 0) {
+      const int hc = ct->hist_count;
+      Hp = hc < c.H ? hc : c.H;
+      const int o = ct->closest;
+      if (Hp >= 2 && o >= 0) {
+        const int h0 = ct->hist_head;
+        const int h1 = (h0 - (Hp - 1) + 2 * c.H) % c.H;
+        const float* pa = b.hist + ((size_t)h0 * c.max_obs + o) * c.p;
+        const float* pz = b.hist + ((size_t)h1 * c.max_obs + o) * c.p;
+        const float den = (float)(Hp - 1) * c.dt;
+        v[0] = (pa[0] - pz[0]) / den;
+        v[1] = (pa[1] - pz[1]) / den;
+        if (c.p == 3) v[2] = (pa[2] - pz[2]) / den;
+      }
+    }
+    const float nv = sqrtf(__builtin_fmaf(v[2], v[2], __builtin_fmaf(v[1], v[1], v[0] * v[0])));
+    for (int i = 0; i < 3; ++i) {
+      ct->v_obs[i] = v[i];
+      ct->v_hat[i] = v[i] / (nv + c.norm_eps);
+    }
+    ct->dyn_h = Hp;
+    ct->dyn_ok = (c.scene_mode == 1 && Hp >= 2 && !(nv < c.v_obs_min)) ? 1 : 0;
   }
   if (T.branch != 0) return;
   const int k = bx * 256 + threadIdx.x;
@@ -842,49 +869,38 @@ struct Sel {
   float margin, smin, v[3], vh[3];
 };
 
-__device__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
-  __shared__ float s_k1[kUpdThreads], s_k2[kUpdThreads], s_m1[kUpdThreads];
-  __shared__ int s_i1[kUpdThreads];
-  __shared__ Sel s_sel;
+__device__ __forceinline__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
+  __shared__ float s_k1[kUpdThreads / kWave], s_k2[kUpdThreads / kWave], s_m1[kUpdThreads / kWave];
+  __shared__ int s_i1[kUpdThreads / kWave];
   const Ctrl* ct = b.ctrl;
-  if (threadIdx.x == 0) {
-    Sel s;
-    s.sel = -1;
-    s.rule = 0;
-    s.h_used = 0;
-    s.status_add = 0u;
-    s.margin = INFINITY;
-    s.smin = INFINITY;
-    for (int i = 0; i < 3; ++i) s.v[i] = s.vh[i] = 0.f;
-    if (M == 0) {
-      s.status_add = 4u;  // no cluster: update over all of V
-    } else if (c.scene_mode == 1) {
-      const int hc = ct->hist_count;
-      const int Hp = hc < c.H ? hc : c.H;
-      s.h_used = Hp;
-      const int o = ct->closest;
-      if (Hp >= 2 && o >= 0) {
-        // Eq. (17): the mean of H'-1 finite differences telescopes to
-        // (o_t - o_{t-H'+1}) / ((H'-1) dt)
-        const int h0 = ct->hist_head;
-        const int h1 = (h0 - (Hp - 1) + 2 * c.H) % c.H;
-        for (int i = 0; i < c.p; ++i) {
-          const float a = b.hist[((size_t)h0 * c.max_obs + o) * c.p + i];
-          const float z0 = b.hist[((size_t)h1 * c.max_obs + o) * c.p + i];
-          s.v[i] = (a - z0) / ((float)(Hp - 1) * c.dt);
-        }
-      }
-      const float nv =
-          sqrtf(__builtin_fmaf(s.v[2], s.v[2], __builtin_fmaf(s.v[1], s.v[1], s.v[0] * s.v[0])));
-      for (int i = 0; i < 3; ++i) s.vh[i] = s.v[i] / (nv + c.norm_eps);
-      if (Hp >= 2 && !(nv < c.v_obs_min)) s.rule = 1;
-      else s.status_add = 8u;
-    }
-    s_sel = s;
+  Sel s;
+  s.sel = -1;
+  s.rule = 0;
+  s.h_used = 0;
+  s.status_add = 0u;
+  s.margin = INFINITY;
+  s.smin = INFINITY;
+  s.v[0] = s.v[1] = s.v[2] = s.vh[0] = s.vh[1] = s.vh[2] = 0.f;
+  if (M == 0) {
+    s.status_add = 4u;  // no cluster: update over all of V
+    return s;
   }
-  __syncthreads();
-  Sel s = s_sel;
-  if (M == 0) return s;
+  if (c.scene_mode == 1) {
+    // the estimate of Eq. (17), computed once by the compaction kernel
+    s.h_used = ct->dyn_h;
+    s.v[0] = ct->v_obs[0];
+    s.v[1] = ct->v_obs[1];
+    s.v[2] = ct->v_obs[2];
+    s.vh[0] = ct->v_hat[0];
+    s.vh[1] = ct->v_hat[1];
+    s.vh[2] = ct->v_hat[2];
+    if (ct->dyn_ok) s.rule = 1;
+    else s.status_add = 8u;
+  }
+  // best key (ties to the lowest cluster), its minimum cost, and the second
+  // best key: per thread over a strided subset of the clusters, then wave
+  // butterflies and the four waves in order (min and the tie rule are exact,
+  // so the result does not depend on the combining order)
   float k1 = INFINITY, k2 = INFINITY, m1 = INFINITY;
   int i1 = kInt32Max;
   for (int cl = threadIdx.x; cl < M; cl += kUpdThreads) {
@@ -900,27 +916,38 @@ __device__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
       k2 = key;
     }
   }
-  s_k1[threadIdx.x] = k1;
-  s_k2[threadIdx.x] = k2;
-  s_i1[threadIdx.x] = i1;
-  s_m1[threadIdx.x] = m1;
-  __syncthreads();
-  for (int w = kUpdThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      const float a1 = s_k1[threadIdx.x], a2 = s_k2[threadIdx.x];
-      const float b1 = s_k1[threadIdx.x + w], b2 = s_k2[threadIdx.x + w];
-      const int ai = s_i1[threadIdx.x], bi = s_i1[threadIdx.x + w];
-      const bool takeb = b1 < a1 || (b1 == a1 && bi < ai);
-      s_k1[threadIdx.x] = takeb ? b1 : a1;
-      s_i1[threadIdx.x] = takeb ? bi : ai;
-      s_m1[threadIdx.x] = takeb ? s_m1[threadIdx.x + w] : s_m1[threadIdx.x];
-      s_k2[threadIdx.x] = fminf(fminf(a2, b2), takeb ? a1 : b1);
-    }
-    __syncthreads();
+  auto combine = [](float& a1, float& a2, int& ai, float& am, float b1, float b2, int bi, float bm) {
+    const bool takeb = b1 < a1 || (b1 == a1 && bi < ai);
+    const float n2 = fminf(fminf(a2, b2), takeb ? a1 : b1);
+    a1 = takeb ? b1 : a1;
+    ai = takeb ? bi : ai;
+    am = takeb ? bm : am;
+    a2 = n2;
+  };
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float b1 = __shfl_xor(k1, off, kWave), b2 = __shfl_xor(k2, off, kWave);
+    const int bi = __shfl_xor(i1, off, kWave);
+    const float bm = __shfl_xor(m1, off, kWave);
+    combine(k1, k2, i1, m1, b1, b2, bi, bm);
   }
-  s.sel = s_i1[0];
-  s.smin = s_m1[0];
-  s.margin = M > 1 ? s_k2[0] - s_k1[0] : INFINITY;
+  const int wv = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    s_k1[wv] = k1;
+    s_k2[wv] = k2;
+    s_i1[wv] = i1;
+    s_m1[wv] = m1;
+  }
+  __syncthreads();
+  k1 = s_k1[0];
+  k2 = s_k2[0];
+  i1 = s_i1[0];
+  m1 = s_m1[0];
+#pragma unroll
+  for (int w = 1; w < kUpdThreads / kWave; ++w) combine(k1, k2, i1, m1, s_k1[w], s_k2[w], s_i1[w], s_m1[w]);
+  s.sel = i1;
+  s.smin = m1;
+  s.margin = M > 1 ? k2 - k1 : INFINITY;
   __syncthreads();
   return s;
 }
@@ -957,7 +984,7 @@ __device__ __forceinline__ void update_body(const Cfg& c, const Bufs& b, int bx,
     }
   }
   Sel s;
-  if (branch == 0) {
+  if (branch == 0 && (a0 < ncand || bx == 0)) {
     s = select_cluster(c, b, M);
   } else {
     s.sel = -1;

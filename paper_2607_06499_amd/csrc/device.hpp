@@ -68,6 +68,7 @@ struct Ctrl {
   int32_t sel, sel_size, rule, h_used;
   float margin, smin_sel, wsum;
   float v_obs[3], v_hat[3];
+  int32_t dyn_h, dyn_ok;  // Eq. (17) estimate of this replan: H' and whether the dynamic rule applies
   uint32_t status;
   uint32_t step_used;
 };
