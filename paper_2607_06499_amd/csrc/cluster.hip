@@ -361,6 +361,12 @@ __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, 
   const int I = by, J0 = bx * COLG;
   if (I >= nt || J0 >= nt) return;
   const int J1 = min(J0 + COLG, nt);
+  if constexpr (SORTED) {
+    // a block whose column tiles are all apart from the row tile has no pair
+    bool any = false;
+    for (int J = J0; J < J1; ++J) any |= !tiles_apart(c, b, I, J);
+    if (!any) return;
+  }
   const ZT* z = reinterpret_cast<const ZT*>(SORTED ? b.zs : (zin ? zin : b.z));
   const int k = I * kTile + threadIdx.x;
   const ZT zk = k < V ? z[k] : ZVec<P>::far();
@@ -531,6 +537,15 @@ __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int b
   if (!adj_block_live(I, g, nt)) return;
   const ZT* z = reinterpret_cast<const ZT*>(SORTED ? b.zs : (zin ? zin : b.z));
   const int J0 = max(g * kColGroup, I), J1 = min(g * kColGroup + kColGroup, nt);
+  if constexpr (SORTED) {
+    // its slot stays zero: written here so the closure can read every slot
+    bool any = false;
+    for (int J = J0; J < J1; ++J) any |= !tiles_apart(c, b, I, J);
+    if (!any) {
+      if (threadIdx.x < kMaxTrees) b.tslot[((size_t)I * ngrp + g) * kMaxTrees + threadIdx.x] = 0ull;
+      return;
+    }
+  }
   // every operand of the block is requested before the first wait (sorted
   // positions first, then the per-point arrays at the original indices)
   const int k = I * kTile + threadIdx.x;
