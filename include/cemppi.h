@@ -267,7 +267,7 @@ enum { CE_LAUNCH_GRAPH = 0, CE_LAUNCH_DIRECT = 1 };
  * CE_LAUNCH_DIRECT: every kernel of the replan is launched on the caller's
  * stream.  Both run the same kernels with the same arguments and give the
  * same bits.  Which is faster depends on the host: a replay costs the device
- * a few microseconds more than ten direct launches, while direct launches
+ * a few microseconds more than the same direct launches, while direct launches
  * cost the host a few microseconds each (see ce_mppi_tune_launch). */
 ce_status ce_mppi_set_launch_mode(ce_mppi_planner* planner, int32_t mode);
 /* For callers that replan back to back: run `reps` replans on (x_t,

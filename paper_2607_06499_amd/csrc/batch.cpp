@@ -38,7 +38,7 @@ constexpr int kAreas = 4;  // area 0: the full member set; 1..3: subset ring
 struct Layout {
   size_t cnt_roll[3], cnt_p[2], cnt_all;          // table counts n
   size_t roll_slot[3], roll_pref[3][4];
-  size_t p_slot[2], compact[2], cc[2], stats[2], dyn_cnt[2], dyn_adj[2], dyn_roots[2];
+  size_t p_slot[2], compact[2], cc[2], dyn_cnt[2], dyn_adj[2];
   size_t all_slot, update, finish;
   size_t ints = 0;
   void make(int n) {
@@ -59,10 +59,8 @@ struct Layout {
       p_slot[kd] = take(n);
       compact[kd] = take(n + 1);
       cc[kd] = take(n + 1);
-      stats[kd] = take(n + 1);
       dyn_cnt[kd] = take(n + 1);
       dyn_adj[kd] = take(n + 1);
-      dyn_roots[kd] = take(n + 1);
     }
     all_slot = take(n);
     update = take(n + 1);
@@ -104,7 +102,7 @@ struct ce_mppi_batch {
   hipEvent_t up_done = nullptr;
   // totals of the full member set (upper bounds of any subset): grid sizes
   int roll_total[3][4] = {};
-  int compact_total[2] = {0, 0}, stats_total[2] = {0, 0}, update_total = 0, n_p[2] = {0, 0};
+  int compact_total[2] = {0, 0}, update_total = 0, n_p[2] = {0, 0};
   ce_mppi_batch_tuning tune{8, 8, 4, 4};
 };
 
@@ -171,7 +169,6 @@ void fill_tables(const ce_mppi_batch* B, const int* members, int count, int* h) 
     copy(lp[kd], L.p_slot[kd]);
     prefix(lp[kd], L.compact[kd], [](const ce_mppi_planner* P) { return (P->c.K + 255) / 256; });
     prefix(lp[kd], L.cc[kd], [](const ce_mppi_planner*) { return 1; });
-    prefix(lp[kd], L.stats[kd], [](const ce_mppi_planner*) { return kStatItems; });
     // the DBSCAN tables are written on the device by kb_plan
   }
   h[L.cnt_all] = count;
@@ -195,24 +192,19 @@ void area_tabs(const ce_mppi_batch* B, Area& a) {
     const int* nk = d + L.cnt_p[kd];
     T.compact[kd] = Tab{sl, d + L.compact[kd], nk};
     T.cc[kd] = Tab{sl, d + L.cc[kd], nk};
-    T.stats[kd] = Tab{sl, d + L.stats[kd], nk};
     T.cnt[kd] = Tab{sl, d + L.dyn_cnt[kd], nk};
     T.adj[kd] = Tab{sl, d + L.dyn_adj[kd], nk};
-    T.roots[kd] = Tab{sl, d + L.dyn_roots[kd], nk};
     T.plan.slot[kd] = sl;
     T.plan.n[kd] = nk;
     T.plan.pref_cnt[kd] = d + L.dyn_cnt[kd];
     T.plan.pref_adj[kd] = d + L.dyn_adj[kd];
-    T.plan.pref_roots[kd] = d + L.dyn_roots[kd];
     T.has[kd] = B->n_p[kd] > 0;
     T.grid_compact[kd] = std::max(1, std::min(B->compact_total[kd], 4 * cus));
     T.grid_cc[kd] = std::max(1, std::min(B->n_p[kd], cus));
-    T.grid_stats[kd] = std::max(1, std::min(B->stats_total[kd], 4 * cus));
   }
   T.update = Tab{d + L.all_slot, d + L.update, d + L.cnt_all};
   T.finish = Tab{d + L.all_slot, d + L.finish, d + L.cnt_all};
   T.grid_tile = B->tune.tile_blocks_per_cu * cus;
-  T.grid_roots = 2 * cus;
   T.grid_update = std::max(1, std::min(B->update_total, 4 * cus));
   T.grid_finish = std::max(1, std::min(B->n, cus));
   T.colg = B->tune.colg;
@@ -309,7 +301,6 @@ ce_status ce_mppi_batch_create(ce_mppi_planner* const* planners, int32_t n, ce_m
       B->roll_total[B->roll_kind[i]][ri] += (P->c.K + rpb - 1) / rpb;
     }
     B->compact_total[B->p_kind[i]] += (P->c.K + 255) / 256;
-    B->stats_total[B->p_kind[i]] += kStatItems;
     B->update_total += P->c.nblk_upd;
   }
   B->lay.make(n);

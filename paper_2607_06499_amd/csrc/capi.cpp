@@ -329,7 +329,7 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_tlo = cv.take<float4>((size_t)c.ntile), o_thi = cv.take<float4>((size_t)c.ntile);
   const size_t o_nc = cv.take<int>(K), o_mcn = cv.take<int>(K), o_root = cv.take<int>(K);
   const size_t o_lab = cv.take<int>(K);
-  const size_t o_rm = cv.take<unsigned long long>(nw);
+  const size_t o_cm = cv.take<unsigned long long>(nw), o_hm = cv.take<unsigned long long>(nw);
   const size_t o_tslot = cv.take<unsigned long long>((size_t)c.ntile * ((c.ntile + kColGroup - 1) / kColGroup) * kMaxTrees);
   const size_t o_ccost = cv.take<float>((size_t)c.mcap), o_cdir = cv.take<float>((size_t)c.mcap * 4);
   const size_t o_csize = cv.take<int>((size_t)c.mcap), o_csmin = cv.take<float>((size_t)c.mcap);
@@ -366,7 +366,8 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   b.mcn = reinterpret_cast<int*>(base + o_mcn);
   b.root = reinterpret_cast<int*>(base + o_root);
   b.label = reinterpret_cast<int*>(base + o_lab);
-  b.rootmask = reinterpret_cast<unsigned long long*>(base + o_rm);
+  b.coremask = reinterpret_cast<unsigned long long*>(base + o_cm);
+  b.hookmask = reinterpret_cast<unsigned long long*>(base + o_hm);
   b.tslot = reinterpret_cast<unsigned long long*>(base + o_tslot);
   b.c_cost = reinterpret_cast<float*>(base + o_ccost);
   b.c_dir = reinterpret_cast<float*>(base + o_cdir);

@@ -14,10 +14,12 @@
 //  2. mcn     tiled all-pairs lowest-index core neighbour; for a core point it
 //             is its hook target, for a non-core point it is exactly the
 //             border rule (join the cluster of the lowest-index core neighbour)
-//  3. roots   follow the hooks (indices strictly decrease) to a tree root;
-//             trees are numbered by root index
+//  3. roots   a core point with no core neighbour of lower index roots a
+//             tree (flag words from step 2); trees are numbered by root index
 //  4. trees   tiled pass over core-core neighbour pairs of different trees;
-//             each tile writes the tree adjacency bits it saw to its own slot
+//             each block first follows the hooks of its points (indices
+//             strictly decrease) to their roots, then writes the tree
+//             adjacency bits it saw to its own slot
 //  5. tree CC connected components of the (small) tree graph; the cluster of
 //             a component is ranked by its lowest root index, which is the
 //             lowest core index of the cluster
@@ -248,6 +250,7 @@ __device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx
   b.mcn[rank] = kInt32Max;
   b.root[rank] = -1;
   b.label[rank] = -1;
+  if ((rank & 63) == 0) b.hookmask[rank >> 6] = 0ull;
 }
 
 template <int P>
@@ -263,6 +266,7 @@ __global__ void k_init_points(Bufs b, int V) {
   b.mcn[a] = kInt32Max;
   b.root[a] = -1;
   b.label[a] = -1;
+  if ((a & 63) == 0) b.hookmask[a >> 6] = 0ull;
 }
 
 // number of points DBSCAN runs on: caller features (stage) or the feasible set
@@ -404,6 +408,10 @@ __global__ __launch_bounds__(kTile) void k_count(Cfg c, Bufs b, const float* __r
 // themselves).  This pass runs in the original order: column tiles ascend,
 // so the first hit of a row is its minimum within the block, and a block
 // stops once every row has one (in dense regions after the first tile).
+// The block whose columns hold the row tile also writes the tile's core
+// flags (one 64-bit word per wave), and every block flags the rows that have
+// a core neighbour of lower index: a core point without one is the root of
+// its hook tree.
 template <int P, int COLG = kColGroup>
 __device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
                                          const float* __restrict__ zin, int Vin) {
@@ -417,6 +425,8 @@ __device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, in
   const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
   const int k = I * kTile + threadIdx.x;
   const ZT zk = k < V ? z[k] : ZVec<P>::far();
+  const bool diag = J0 <= I && I < J1;
+  const int nck = (diag && k < V) ? b.ncount[k] : 0;
   ZT zl[COLG];
   int ncl[COLG];
 #pragma unroll
@@ -425,6 +435,10 @@ __device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, in
     const bool ok = J0 + u < J1 && l < V;
     zl[u] = ok ? z[l] : ZVec<P>::far();
     ncl[u] = ok ? b.ncount[l] : 0;
+  }
+  if (diag) {
+    const unsigned long long cm = __ballot(k < V && nck >= c.min_pts);
+    if ((threadIdx.x & (kWave - 1)) == 0 && k < V) b.coremask[k >> 6] = cm;
   }
   const float r2 = c.eps2;
   int m = kInt32Max;
@@ -445,6 +459,8 @@ __device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, in
     }
   }
   if (k < V && m != kInt32Max) atomicMin(&b.mcn[k], m);
+  const unsigned long long hk = __ballot(k < V && m < k);
+  if (hk && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&b.hookmask[k >> 6], hk);
 }
 
 template <int P>
@@ -452,38 +468,30 @@ __global__ __launch_bounds__(kTile) void k_mcn(Cfg c, Bufs b, const float* __res
   mcn_body<P, kCntGroup>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
 }
 
-// 3. roots: follow the hook chain of each core point (indices decrease, so the
-// walk ends at a point that hooks to itself); root flags go into 64-bit words.
-__device__ __forceinline__ void roots_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* zin, int Vin) {
-  const int V = dbscan_V(b, zin, Vin);
-  const int a = bx * 256 + threadIdx.x;
-  if (bx * 256 >= V) return;
-  bool isroot = false;
-  if (a < V) {
-    if (b.ncount[a] >= c.min_pts) {
-      int r = b.mcn[a];
-      while (true) {
-        const int n = b.mcn[r];
-        if (n == r) break;
-        r = n;
-      }
-      b.root[a] = r;
-      isroot = (r == a);
-    } else {
-      b.root[a] = -1;
+// 3. roots of the hook forest: each core point hooks to its lowest-index core
+// neighbour, so indices decrease along a chain and the walk ends at a point
+// that hooks to itself.  The chains of one thread advance together, all
+// their loads in flight at once.
+template <int NR>
+__device__ __forceinline__ void follow_roots(const int* __restrict__ mcn, int (&r)[NR]) {
+  while (true) {
+    int nx[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) nx[u] = r[u] >= 0 ? mcn[r[u]] : r[u];
+    bool more = false;
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      more |= nx[u] != r[u];
+      r[u] = nx[u];
     }
+    if (!more) break;
   }
-  const unsigned long long m = __ballot(isroot);
-  if ((threadIdx.x & 63) == 0 && a < V) b.rootmask[a >> 6] = m;
 }
 
-__global__ __launch_bounds__(256) void k_roots(Cfg c, Bufs b, const float* zin, int Vin) {
-  roots_body(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
-}
-
-// Tree numbering: exclusive prefix of root counts over the root-flag words,
-// computed by each block that needs it into LDS (the flag words are kept in
-// LDS too); returns the number of trees.
+// Tree numbering: exclusive prefix of root counts over the root-flag words
+// (core and not hooked to a lower index), computed by each block that needs
+// it into LDS (the flag words are kept in LDS too); returns the number of
+// trees.
 template <int NT>
 __device__ int tree_prefix(const Bufs& b, int V, int* s_woff, unsigned long long* s_rm) {
   const int nwords = (V + 63) >> 6;
@@ -491,7 +499,7 @@ __device__ int tree_prefix(const Bufs& b, int V, int* s_woff, unsigned long long
   const int lo = min((int)threadIdx.x * per, nwords), hi = min(lo + per, nwords);
   int mine = 0;
   for (int i = lo; i < hi; ++i) {
-    const unsigned long long m = b.rootmask[i];
+    const unsigned long long m = b.coremask[i] & ~b.hookmask[i];
     s_rm[i] = m;
     mine += __popcll(m);
   }
@@ -561,12 +569,24 @@ __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int b
     zl[u] = ok ? z[l] : ZVec<P>::far();
   }
   const int nck = k < V ? b.ncount[idk] : 0;
-  const int rk = k < V ? b.root[idk] : -1;
+  const int hk = k < V ? b.mcn[idk] : -1;
 #pragma unroll
   for (int u = 0; u < kColGroup; ++u) {
     ncl[u] = idl[u] >= 0 ? b.ncount[idl[u]] : 0;
-    rl[u] = idl[u] >= 0 ? b.root[idl[u]] : -1;
+    rl[u] = idl[u] >= 0 ? b.mcn[idl[u]] : -1;
   }
+  // roots of the row point (slot 0) and the column points, -1 if not core
+  int rt[kColGroup + 1];
+  rt[0] = nck >= c.min_pts ? hk : -1;
+#pragma unroll
+  for (int u = 0; u < kColGroup; ++u) rt[u + 1] = ncl[u] >= c.min_pts ? rl[u] : -1;
+  follow_roots(b.mcn, rt);
+  const int rk = rt[0];
+#pragma unroll
+  for (int u = 0; u < kColGroup; ++u) rl[u] = rt[u + 1];
+  // the block whose columns hold the row tile records the tile's roots for
+  // the closure and the labels
+  if (g * kColGroup <= I && I < g * kColGroup + kColGroup && k < V) b.root[idk] = rk;
   const int R = tree_prefix<kTile>(b, V, s_woff, s_rm);
   if (R < 2 || R > kMaxTrees) return;
   if (threadIdx.x < kMaxTrees) s_adj[threadIdx.x] = 0ull;
@@ -661,6 +681,90 @@ __device__ void uf_fallback(const Cfg& c, const Bufs& b, const float* zin, int V
   __syncthreads();
 }
 
+// Cluster statistics of Alg. 1 [Cluster stats] over one labelling chunk:
+// count, cost sum, direction sums (for Eq. (16)) and minimum cost of every
+// cluster.  Thread t holds the chunk's points a0 + u * kFinThreads + t (u
+// ascending) and sums them in that order; the thread sums go through an xor
+// butterfly within the wave, the wave results are added in wave order and
+// the chunks in ascending order, so every run gives the same totals.  The
+// running totals live in the cluster arrays: thread j < kStatClusters keeps
+// clusters j, j + kStatClusters, ...
+template <int P>
+__device__ void chunk_stats(const Bufs& b, bool first, int M, const int (&lab)[kLabBatch],
+                            const float (&Sa)[kLabBatch], const typename ZVec<P>::T (&ga)[kLabBatch],
+                            float (*s_red)[kStatClusters][6]) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (int c0 = 0; c0 < M; c0 += kStatClusters) {
+    const int ncl = min(kStatClusters, M - c0);
+    for (int j = 0; j < ncl; ++j) {
+      const int cl = c0 + j;
+      float sS = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, mn = INFINITY;
+      int n = 0;
+#pragma unroll
+      for (int u = 0; u < kLabBatch; ++u) {
+        const bool in = lab[u] == cl;
+        n += __popcll(__ballot(in));
+        if (in) {
+          sS += Sa[u];
+          g0 += ga[u].x;
+          g1 += ga[u].y;
+          if constexpr (P == 3) g2 += ga[u].z;
+          mn = fminf(mn, Sa[u]);
+        }
+      }
+      if (n) {  // wave-uniform
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+          sS += __shfl_xor(sS, off, kWave);
+          g0 += __shfl_xor(g0, off, kWave);
+          g1 += __shfl_xor(g1, off, kWave);
+          if constexpr (P == 3) g2 += __shfl_xor(g2, off, kWave);
+          mn = fminf(mn, __shfl_xor(mn, off, kWave));
+        }
+      }
+      if (lane == 0) {
+        float* r = s_red[w][j];
+        r[0] = sS;
+        r[1] = g0;
+        r[2] = g1;
+        r[3] = g2;
+        r[4] = mn;
+        r[5] = (float)n;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ncl) {
+      const int j = threadIdx.x, cl = c0 + j;
+      float sS = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, mn = INFINITY;
+      int n = 0;
+      if (!first) {
+        sS = b.c_cost[cl];
+        g0 = b.c_dir[4 * cl];
+        g1 = b.c_dir[4 * cl + 1];
+        g2 = b.c_dir[4 * cl + 2];
+        mn = b.c_smin[cl];
+        n = b.c_size[cl];
+      }
+      for (int v = 0; v < kFinThreads / kWave; ++v) {
+        const float* r = s_red[v][j];
+        sS += r[0];
+        g0 += r[1];
+        g1 += r[2];
+        g2 += r[3];
+        mn = fminf(mn, r[4]);
+        n += (int)r[5];
+      }
+      b.c_cost[cl] = sS;
+      b.c_dir[4 * cl] = g0;
+      b.c_dir[4 * cl + 1] = g1;
+      b.c_dir[4 * cl + 2] = g2;
+      b.c_smin[cl] = mn;
+      b.c_size[cl] = n;
+    }
+    __syncthreads();
+  }
+}
+
 template <int P>
 __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin, int ngrp, int* mout, int* lab_out, int* cnt_out) {
   __shared__ int s_woff[kMaxWords];
@@ -669,6 +773,7 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
   __shared__ unsigned long long s_part[kFinThreads / kWave][kMaxTrees];
   __shared__ int s_tc[kMaxTrees];
   __shared__ int s_M;
+  __shared__ float s_red[kFinThreads / kWave][kStatClusters][6];
   const int V = dbscan_V(b, zin, Vin);
   const int R = V > 0 ? tree_prefix<kFinThreads>(b, V, s_woff, s_rm) : 0;
   const bool overflow = R > kMaxTrees;
@@ -765,15 +870,23 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
   // its lowest-index core neighbour, noise -> -1.  In the fallback the
   // cluster number of a root sits in label[root] and is never overwritten
   // (a root's own label is that same number).  Each thread takes kLabBatch
-  // points at a time and issues all their loads before any store.
+  // points at a time and issues all their loads before any store.  On the
+  // feasible set of a replan the cluster statistics follow, chunk by chunk.
+  using ZT = typename ZVec<P>::T;
+  const bool stats = zin == nullptr && M > 0;
+  const ZT* gv = reinterpret_cast<const ZT*>(b.gv);
   for (int a0 = 0; a0 < V; a0 += kFinThreads * kLabBatch) {
     int nc[kLabBatch], x[kLabBatch], r[kLabBatch], lab[kLabBatch];
+    float Sa[kLabBatch];
+    ZT ga[kLabBatch];
 #pragma unroll
     for (int u = 0; u < kLabBatch; ++u) {
       const int a = a0 + u * kFinThreads + threadIdx.x;
       nc[u] = a < V ? b.ncount[a] : 0;
       const int mc = a < V ? b.mcn[a] : kInt32Max;
       x[u] = a >= V ? -1 : (nc[u] >= c.min_pts ? a : (mc != kInt32Max ? mc : -1));
+      Sa[u] = (stats && a < V) ? b.Sv[a] : 0.f;
+      ga[u] = (stats && a < V) ? gv[a] : ZT{};
     }
 #pragma unroll
     for (int u = 0; u < kLabBatch; ++u) r[u] = x[u] >= 0 ? b.root[x[u]] : -1;
@@ -792,85 +905,26 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
       if (lab_out) lab_out[a] = lab[u];
       if (cnt_out) cnt_out[a] = nc[u];
     }
+    if (stats) chunk_stats<P>(b, a0 == 0, M, lab, Sa, ga, s_red);
+  }
+  // means: cost (Alg. 1 [Cluster stats]) and normalised direction (Eq. (16))
+  if (stats && (int)threadIdx.x < kStatClusters) {
+    for (int cl = threadIdx.x; cl < M; cl += kStatClusters) {
+      const float cnt = (float)b.c_size[cl];
+      const float vx = b.c_dir[4 * cl] / cnt, vy = b.c_dir[4 * cl + 1] / cnt;
+      const float vz = P == 3 ? b.c_dir[4 * cl + 2] / cnt : 0.f;
+      const float nv = sqrtf(__builtin_fmaf(vz, vz, __builtin_fmaf(vy, vy, vx * vx))) + c.norm_eps;
+      b.c_cost[cl] = b.c_cost[cl] / cnt;
+      b.c_dir[4 * cl] = vx / nv;
+      b.c_dir[4 * cl + 1] = vy / nv;
+      b.c_dir[4 * cl + 2] = P == 3 ? vz / nv : 0.f;
+    }
   }
 }
 
 template <int P>
 __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const float* __restrict__ zin, int Vin, int ngrp, int* mout, int* lab_out, int* cnt_out) {
   tree_cc_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin, ngrp, mout, lab_out, cnt_out);
-}
-
-// ---------------------------------------------------------------------------
-// Cluster statistics with fixed-order block reductions: count, mean cost
-// (Alg. 1 [Cluster stats]), normalised mean direction (Eq. (16)), minimum
-// cost.  Block b handles clusters b, b + gridDim.x, ...
-template <int P>
-__device__ __forceinline__ void stats_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx) {
-  using ZT = typename ZVec<P>::T;
-  __shared__ float s_r[6][256];
-  const Ctrl* ct = b.ctrl;
-  const int branch = ct->branch;
-  const int V = branch == 0 ? ct->n_feas : 0;
-  const int M = branch == 0 ? ct->M : 0;
-  const ZT* gv = reinterpret_cast<const ZT*>(b.gv);
-  for (int cl = bx; cl < M; cl += nbx) {
-    float n = 0.f, sS = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, mn = INFINITY;
-    // thread t visits points t, t + 256, ... in increasing order, kStatBatch
-    // of them per pass with all their loads issued first
-    for (int a0 = threadIdx.x; a0 < V; a0 += 256 * kStatBatch) {
-      int lb[kStatBatch];
-      float Sa[kStatBatch];
-      ZT ga[kStatBatch];
-#pragma unroll
-      for (int u = 0; u < kStatBatch; ++u) {
-        const int a = a0 + u * 256;
-        lb[u] = a < V ? b.label[a] : -1;
-        Sa[u] = a < V ? b.Sv[a] : 0.f;
-        ga[u] = a < V ? gv[a] : ZT{};
-      }
-#pragma unroll
-      for (int u = 0; u < kStatBatch; ++u) {
-        if (lb[u] != cl) continue;
-        n += 1.f;
-        sS += Sa[u];
-        g0 += ga[u].x;
-        g1 += ga[u].y;
-        if constexpr (P == 3) g2 += ga[u].z;
-        mn = fminf(mn, Sa[u]);
-      }
-    }
-    s_r[0][threadIdx.x] = n;
-    s_r[1][threadIdx.x] = sS;
-    s_r[2][threadIdx.x] = g0;
-    s_r[3][threadIdx.x] = g1;
-    s_r[4][threadIdx.x] = g2;
-    s_r[5][threadIdx.x] = mn;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) {
-        for (int f = 0; f < 5; ++f) s_r[f][threadIdx.x] += s_r[f][threadIdx.x + w];
-        s_r[5][threadIdx.x] = fminf(s_r[5][threadIdx.x], s_r[5][threadIdx.x + w]);
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      const float cnt = s_r[0][0];
-      const float vx = s_r[2][0] / cnt, vy = s_r[3][0] / cnt, vz = s_r[4][0] / cnt;
-      const float nv = sqrtf(__builtin_fmaf(vz, vz, __builtin_fmaf(vy, vy, vx * vx))) + c.norm_eps;
-      b.c_size[cl] = (int)cnt;
-      b.c_cost[cl] = s_r[1][0] / cnt;
-      b.c_dir[4 * cl] = vx / nv;
-      b.c_dir[4 * cl + 1] = vy / nv;
-      b.c_dir[4 * cl + 2] = P == 3 ? vz / nv : 0.f;
-      b.c_smin[cl] = s_r[5][0];
-    }
-    __syncthreads();
-  }
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void k_stats(Cfg c, Bufs b) {
-  stats_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1168,7 +1222,7 @@ __global__ __launch_bounds__(kFinThreads) void kb_plan(CSlotStatic st, PlanOut o
     const int n = *o.n[kd];
     if (n == 0) continue;
     const int q = threadIdx.x;
-    int ncnt = 0, nadj = 0, nroot = 0;
+    int ncnt = 0, nadj = 0;
     if (q < n) {
       const SlotStatic& S = *(const SlotStatic*)(st + o.slot[kd][q]);
       const Ctrl* ct = S.b.ctrl;
@@ -1176,21 +1230,17 @@ __global__ __launch_bounds__(kFinThreads) void kb_plan(CSlotStatic st, PlanOut o
       const int nt = ntiles_of(V);
       ncnt = nt * ((nt + o.colg - 1) / o.colg);
       nadj = nt * ((nt + kColGroup - 1) / kColGroup);
-      nroot = (V + 255) / 256;
     }
-    int t1, t2, t3;
+    int t1, t2;
     const int e1 = block_excl_scan<kFinThreads>(ncnt, &t1);
     const int e2 = block_excl_scan<kFinThreads>(nadj, &t2);
-    const int e3 = block_excl_scan<kFinThreads>(nroot, &t3);
     if (q < n) {
       o.pref_cnt[kd][q] = e1;
       o.pref_adj[kd][q] = e2;
-      o.pref_roots[kd][q] = e3;
     }
     if (q == 0) {
       o.pref_cnt[kd][n] = t1;
       o.pref_adj[kd][n] = t2;
-      o.pref_roots[kd][n] = t3;
     }
   }
 }
@@ -1241,14 +1291,6 @@ __global__ __launch_bounds__(kTile) void kb_mcn(CSlotStatic st, Tab t) {
   });
 }
 
-__global__ __launch_bounds__(256) void kb_roots(CSlotStatic st, Tab t) {
-  __shared__ int s_pref[kMaxBatch + 1];
-  for_each_item(t, s_pref, [&](int slot, int local) {
-    CEMPPI_SLOT(slot);
-    roots_body(c, b, local, 0, 0, nullptr, 0);
-  });
-}
-
 template <int P>
 __global__ __launch_bounds__(kTile) void kb_tree_adj(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
@@ -1268,15 +1310,6 @@ __global__ __launch_bounds__(kFinThreads) void kb_tree_cc(CSlotStatic st, Tab t)
     CEMPPI_SLOT(slot);
     tree_cc_body<P>(c, b, 0, 0, 0, nullptr, 0, (c.ntile + kColGroup - 1) / kColGroup, nullptr,
                     nullptr, nullptr);
-  });
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void kb_stats(CSlotStatic st, Tab t) {
-  __shared__ int s_pref[kMaxBatch + 1];
-  for_each_item(t, s_pref, [&](int slot, int local) {
-    CEMPPI_SLOT(slot);
-    stats_body<P>(c, b, local, 0, kStatItems);
   });
 }
 
@@ -1306,15 +1339,12 @@ static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const floa
   const int ngrp = (ntile + kColGroup - 1) / kColGroup;
   const int ncnt = (ntile + kCntGroup - 1) / kCntGroup;
   dim3 tiles(ngrp, ntile), ctiles(ncnt, ntile), tb(kTile);
-  const int nr = (ntile * kTile + 255) / 256;
   L(k_count<P>, ctiles, tb, c, b, zin, Vin);
   L(k_mcn<P>, ctiles, tb, c, b, zin, Vin);
-  L(k_roots, dim3(nr), dim3(256), c, b, zin, Vin);
   L(k_tree_adj<P>, tiles, tb, c, b, zin, Vin, ngrp);
   L(k_tree_cc<P>, dim3(1), dim3(kFinThreads), c, b, zin, Vin, ngrp, mout, lab_out, cnt_out);
 }
 
-// Everything between the rollouts and the final combination.
 // Everything between the rollouts and the final combination, as one chain
 // (a graph fork into a clustering and a fallback branch was measured slower:
 // the cross-stream synchronisation of the branches costs more than the
@@ -1325,11 +1355,9 @@ void launch_post_rollout(Launcher& L, const Cfg& c, const Bufs& b) {
   if (c.p == 2) {
     L(k_compact<2>, dim3(nk), dim3(256), c, b);
     launch_dbscan_p<2>(L, c, b, nullptr, 0, c.ntile, none, none, none);
-    L(k_stats<2>, dim3(64), dim3(256), c, b);
   } else {
     L(k_compact<3>, dim3(nk), dim3(256), c, b);
     launch_dbscan_p<3>(L, c, b, nullptr, 0, c.ntile, none, none, none);
-    L(k_stats<3>, dim3(64), dim3(256), c, b);
   }
   L(k_update, dim3(c.nblk_upd), dim3(kUpdThreads), c, b);
 }
@@ -1402,8 +1430,6 @@ void launch_batch_post(Launcher& L, const SlotStatic* st, const SlotIO* io, cons
     if (kd == 0) launch_batch_dbscan<2>(L, cst, T, 0);
     else launch_batch_dbscan<3>(L, cst, T, 1);
   }
-  for (int kd = 0; kd < 2; ++kd)
-    if (T.has[kd]) L(kb_roots, dim3(T.grid_roots), dim3(256), cst, T.roots[kd]);
   for (int kd = 0; kd < 2; ++kd) {
     if (!T.has[kd]) continue;
     if (kd == 0) L(kb_tree_adj<2>, dim3(T.grid_tile), dim3(kTile), cst, T.adj[0]);
@@ -1413,11 +1439,6 @@ void launch_batch_post(Launcher& L, const SlotStatic* st, const SlotIO* io, cons
     if (!T.has[kd]) continue;
     if (kd == 0) L(kb_tree_cc<2>, dim3(T.grid_cc[0]), dim3(kFinThreads), cst, T.cc[0]);
     else L(kb_tree_cc<3>, dim3(T.grid_cc[1]), dim3(kFinThreads), cst, T.cc[1]);
-  }
-  for (int kd = 0; kd < 2; ++kd) {
-    if (!T.has[kd]) continue;
-    if (kd == 0) L(kb_stats<2>, dim3(T.grid_stats[0]), dim3(256), cst, T.stats[0]);
-    else L(kb_stats<3>, dim3(T.grid_stats[1]), dim3(256), cst, T.stats[1]);
   }
   L(kb_update, dim3(T.grid_update), dim3(kUpdThreads), cst, T.update);
   L(kb_finish, dim3(T.grid_finish), dim3(kFinThreads), cst, cio, T.finish);

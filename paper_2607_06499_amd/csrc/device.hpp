@@ -44,7 +44,7 @@ constexpr int kCntGroup = 2;   // column tiles per count / core-neighbour block 
 constexpr int kSortBins = 4096; // Morton cells of the DBSCAN spatial order
 constexpr int kOrBatch = 8;    // tree-slot loads in flight per lane
 constexpr int kLabBatch = 8;   // points per thread per labelling pass
-constexpr int kStatBatch = 4;  // points per thread per cluster-statistics pass
+constexpr int kStatClusters = 64;  // clusters per statistics pass of the labelling block
 
 constexpr int kInt32Max = 0x7fffffff;
 
@@ -134,7 +134,8 @@ struct Bufs {
   int* root;       // [K] tree root (core points), -1 otherwise
   unsigned long long* tslot;    // [ntile][ceil(ntile/kColGroup)][kMaxTrees] tree adjacency per block
   int* label;      // [K]
-  unsigned long long* rootmask;  // [ceil(K/64)] root flags
+  unsigned long long* coremask;  // [ceil(K/64)] core flags
+  unsigned long long* hookmask;  // [ceil(K/64)] core neighbour of lower index found
   // cluster statistics
   float* c_cost;   // [mcap] mean cost
   float* c_dir;    // [mcap][4] normalised mean direction
@@ -151,7 +152,6 @@ struct Bufs {
 // per-call inputs and outputs.  Kernels read slots through constant-address
 // pointers, so every field is a scalar load as with a kernel argument.
 constexpr int kMaxBatch = 1024;   // planners per batch
-constexpr int kStatItems = 16;    // cluster-statistics blocks per planner
 
 struct SlotStatic {
   Cfg c;
@@ -211,16 +211,15 @@ struct PlanOut {
   const int* n[2];      // their counts (device memory)
   int* pref_cnt[2];     // count and lowest-core-neighbour tiles
   int* pref_adj[2];     // tree-adjacency tiles
-  int* pref_roots[2];   // root-following blocks of 256 points
   int colg;             // column tiles per count/mcn item
 };
 
 struct BatchTabs {
-  Tab compact[2], cnt[2], adj[2], roots[2], cc[2], stats[2];
+  Tab compact[2], cnt[2], adj[2], cc[2];
   Tab update, finish;
   PlanOut plan;
-  int grid_compact[2], grid_cc[2], grid_stats[2], grid_update, grid_finish;
-  int grid_tile, grid_roots;
+  int grid_compact[2], grid_cc[2], grid_update, grid_finish;
+  int grid_tile;
   int colg;
   int has[2];  // the batch has planners with p = 2 / p = 3 (their phases are launched)
 };
