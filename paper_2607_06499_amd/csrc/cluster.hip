@@ -91,7 +91,8 @@ __device__ __forceinline__ bool is_min_field(int f) { return f == P_SMIN_ALL || 
 // thread t owns records t, t+256, ... (coalesced), each wave combines its
 // lanes by an xor butterfly (every lane ends with the same value), and the
 // four wave results are added in wave order.  Also returns the number of
-// feasible rollouts in records [0, upto).
+// feasible rollouts in records [0, upto).  A thread requests kRecBatch of its
+// records before adding any of them (in the same order).
 __device__ void reduce_partials(const Cfg& c, const Bufs& b, int upto, float* s_tot, int* s_before) {
   __shared__ float s_w[4][kPart + 1];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -100,12 +101,27 @@ __device__ void reduce_partials(const Cfg& c, const Bufs& b, int upto, float* s_
   for (int f = 0; f < kPart; ++f) acc[f] = is_min_field(f) ? INFINITY : 0.f;
   acc[kPart] = 0.f;
   const float4* rows = reinterpret_cast<const float4*>(b.part);
-  for (int i = tid; i < c.npart; i += 256) {
-    const float4 x = rows[3 * i], y = rows[3 * i + 1], z = rows[3 * i + 2];
-    const float v[kPart] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w, z.x, z.y, z.z, z.w};
+  for (int i0 = tid; i0 < c.npart; i0 += 256 * kRecBatch) {
+    float4 x[kRecBatch], y[kRecBatch], z[kRecBatch];
 #pragma unroll
-    for (int f = 0; f < kPart; ++f) acc[f] = is_min_field(f) ? fminf(acc[f], v[f]) : acc[f] + v[f];
-    if (i < upto) acc[kPart] += v[P_NFEAS];
+    for (int r = 0; r < kRecBatch; ++r) {
+      const int i = i0 + r * 256;
+      if (i < c.npart) {
+        x[r] = rows[3 * i];
+        y[r] = rows[3 * i + 1];
+        z[r] = rows[3 * i + 2];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRecBatch; ++r) {
+      const int i = i0 + r * 256;
+      if (i >= c.npart) break;
+      const float v[kPart] = {x[r].x, x[r].y, x[r].z, x[r].w, y[r].x, y[r].y,
+                              y[r].z, y[r].w, z[r].x, z[r].y, z[r].z, z[r].w};
+#pragma unroll
+      for (int f = 0; f < kPart; ++f) acc[f] = is_min_field(f) ? fminf(acc[f], v[f]) : acc[f] + v[f];
+      if (i < upto) acc[kPart] += v[P_NFEAS];
+    }
   }
 #pragma unroll
   for (int f = 0; f <= kPart; ++f) {
@@ -176,9 +192,23 @@ __device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx
   using ZT = typename ZVec<P>::T;
   __shared__ float s_tot[kPart + 1];
   __shared__ int s_before;
+  // the rollout's own record and the input flag are requested before the
+  // partials (they are only needed on the clustering branch)
+  // (unconditional loads at a clamped index keep them out of branches)
+  const int k = bx * 256 + threadIdx.x;
+  const bool ink = k < c.K;
+  const int kc = ink ? k : c.K - 1;
+  const int bad = b.ctrl->nonfinite;
+  const int colk = b.col[kc];
+  const float Sk = b.S[kc];
+  float pk[3] = {0.f, 0.f, 0.f}, gk[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    pk[i] = b.pT[(size_t)kc * P + i];
+    gk[i] = b.g[(size_t)kc * P + i];
+  }
   const int blk0 = (bx * 256) / kGroup;
   reduce_partials(c, b, blk0, s_tot, &s_before);
-  const int bad = b.ctrl->nonfinite;
   const Totals T = decide(c, s_tot, bad);
   if (bx == 0 && threadIdx.x == 0) {
     Ctrl* ct = b.ctrl;
@@ -221,16 +251,15 @@ __device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx
     ct->dyn_ok = (c.scene_mode == 1 && Hp >= 2 && !(nv < c.v_obs_min)) ? 1 : 0;
   }
   if (T.branch != 0) return;
-  const int k = bx * 256 + threadIdx.x;
-  const int feas = (k < c.K) ? !b.col[k] : 0;
+  const int feas = ink ? !colk : 0;
   int tot;
   const int local = block_excl_scan<256>(feas, &tot);
   if (!feas) return;
   const int rank = s_before + local;
   float d[3] = {0.f, 0.f, 0.f}, g[3] = {0.f, 0.f, 0.f};
   for (int i = 0; i < P; ++i) {
-    d[i] = b.pT[(size_t)k * P + i] - T.ref[i];
-    g[i] = b.g[(size_t)k * P + i];
+    d[i] = pk[i] - T.ref[i];
+    g[i] = gk[i];
   }
   const float nd = sqrtf(__builtin_fmaf(d[2], d[2], __builtin_fmaf(d[1], d[1], d[0] * d[0])));
   const float den = nd + c.norm_eps;
@@ -245,7 +274,7 @@ __device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx
   reinterpret_cast<ZT*>(b.z)[rank] = zz;
   reinterpret_cast<ZT*>(b.gv)[rank] = gg;
   b.vidx[rank] = k;
-  b.Sv[rank] = b.S[k];
+  b.Sv[rank] = Sk;
   b.ncount[rank] = 0;
   b.mcn[rank] = kInt32Max;
   b.root[rank] = -1;
@@ -938,7 +967,10 @@ struct Sel {
   float margin, smin, v[3], vh[3];
 };
 
-__device__ __forceinline__ Sel select_cluster(const Cfg& c, const Bufs& b, int M) {
+// The statistics of cluster threadIdx.x come preloaded (pre_*: requested by
+// the caller before the branch was known); further clusters are loaded here.
+__device__ __forceinline__ Sel select_cluster(const Cfg& c, const Bufs& b, int M, float pre_cost, float pre_mn,
+                                              float4 pre_dir) {
   __shared__ float s_k1[kUpdThreads / kWave], s_k2[kUpdThreads / kWave], s_m1[kUpdThreads / kWave];
   __shared__ int s_i1[kUpdThreads / kWave];
   const Ctrl* ct = b.ctrl;
@@ -973,8 +1005,9 @@ __device__ __forceinline__ Sel select_cluster(const Cfg& c, const Bufs& b, int M
   float k1 = INFINITY, k2 = INFINITY, m1 = INFINITY;
   int i1 = kInt32Max;
   for (int cl = threadIdx.x; cl < M; cl += kUpdThreads) {
-    const float cost = b.c_cost[cl], mn = b.c_smin[cl];
-    const float4 dir = reinterpret_cast<const float4*>(b.c_dir)[cl];
+    const bool first = cl == (int)threadIdx.x;
+    const float cost = first ? pre_cost : b.c_cost[cl], mn = first ? pre_mn : b.c_smin[cl];
+    const float4 dir = first ? pre_dir : reinterpret_cast<const float4*>(b.c_dir)[cl];
     const float key = s.rule == 0 ? cost : dir.x * s.vh[0] + dir.y * s.vh[1] + dir.z * s.vh[2];
     if (key < k1) {  // clusters are visited in increasing order: strict < keeps the lowest
       k2 = k1;
@@ -1014,6 +1047,10 @@ __device__ __forceinline__ Sel select_cluster(const Cfg& c, const Bufs& b, int M
   m1 = s_m1[0];
 #pragma unroll
   for (int w = 1; w < kUpdThreads / kWave; ++w) combine(k1, k2, i1, m1, s_k1[w], s_k2[w], s_i1[w], s_m1[w]);
+  if (i1 >= M) {  // no key compared below +inf (infinite or NaN keys): the lowest cluster
+    i1 = 0;
+    m1 = b.c_smin[0];
+  }
   s.sel = i1;
   s.smin = m1;
   s.margin = M > 1 ? k2 - k1 : INFINITY;
@@ -1030,31 +1067,41 @@ __device__ __forceinline__ void update_body(const Cfg& c, const Bufs& b, int bx,
   __shared__ int s_k[kUpdChunk];
   __shared__ float s_acc[kUpdThreads / kWave][kWave];
   const Ctrl* ct = b.ctrl;
+  // the candidate records of both branches are requested with the control
+  // words, before the branch is known (every array holds K entries)
+  const int a0 = bx * kUpdChunk;
+  const int a = a0 + (int)threadIdx.x;
+  const bool ina = threadIdx.x < kUpdChunk && a < c.K;
+  const int ac = ina ? a : 0;  // unconditional loads at a clamped index
+  const float S_all = b.S[ac];
+  const int lab_v = b.label[ac], k_v = b.vidx[ac];
+  const float S_v = b.Sv[ac];
+  // and the statistics of cluster threadIdx.x, for the selection
+  const int cq = (int)threadIdx.x < c.mcap ? (int)threadIdx.x : 0;
+  const float pre_cost = b.c_cost[cq], pre_mn = b.c_smin[cq];
+  const float4 pre_dir = reinterpret_cast<const float4*>(b.c_dir)[cq];
   const int branch = ct->branch;
   const bool bad = ct->nonfinite != 0;
   const int NM = c.NM;
   const bool over_all = branch != 0;
   const int M = branch == 0 ? ct->M : 0;
   const int ncand = over_all ? c.K : ct->n_feas;
-  // the candidate record is requested before the selection needs the block
-  const int a0 = bx * kUpdChunk;
-  const int a = a0 + (int)threadIdx.x;
-  const bool mine = threadIdx.x < kUpdChunk && !bad && a < ncand;
+  const bool mine = ina && !bad && a < ncand;
   int lab = -1, kk = 0;
   float Sa = 0.f;
   if (mine) {
     if (over_all) {
       kk = a;
-      Sa = b.S[a];
+      Sa = S_all;
     } else {
-      lab = b.label[a];
-      kk = b.vidx[a];
-      Sa = b.Sv[a];
+      lab = lab_v;
+      kk = k_v;
+      Sa = S_v;
     }
   }
   Sel s;
   if (branch == 0 && (a0 < ncand || bx == 0)) {
-    s = select_cluster(c, b, M);
+    s = select_cluster(c, b, M, pre_cost, pre_mn, pre_dir);
   } else {
     s.sel = -1;
     s.rule = 0;
@@ -1076,6 +1123,7 @@ __device__ __forceinline__ void update_body(const Cfg& c, const Bufs& b, int bx,
       cw->v_hat[i] = s.vh[i];
     }
     cw->sel_size = s.sel >= 0 ? b.c_size[s.sel] : 0;
+    cw->smin_sel = s.smin;
   }
   const int sel = s.sel;
   const float smin = over_all ? ct->smin_all : (sel >= 0 ? s.smin : ct->smin_feas);
@@ -1120,60 +1168,69 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
 __device__ __forceinline__ void finish_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, float* __restrict__ u_out, float* __restrict__ U_out, void* info_out) {
   __shared__ float s_sum[kFinThreads];
   __shared__ float s_tot[kMaxNM + 1];
-  const Ctrl* ct = b.ctrl;
-  const bool bad = ct->nonfinite != 0;
+  __shared__ float s_un[kMaxNM];
+  // the control words and the nominal are requested with the partials
+  const Ctrl cv = *b.ctrl;
+  const bool bad = cv.nonfinite != 0;
   const int NM = c.NM, W = NM + 1;
+  const int e_own = threadIdx.x;  // NM <= kMaxNM <= kFinThreads: one element per thread
   const int nb = c.nblk_upd;
-  // G threads per element, each summing a strided subset of the partials
-  const int G = kFinThreads / W > 0 ? kFinThreads / W : 1;
-  const int EP = kFinThreads / G;  // elements per pass
-  for (int e0 = 0; e0 < W; e0 += EP) {
-    const int el = threadIdx.x / G, g = threadIdx.x % G;
-    const int e = e0 + el;
-    float acc = 0.f;
-    if (el < EP && e < W) {
-#pragma unroll 8
-      for (int i = g; i < nb; i += G) acc += b.upart[(size_t)i * W + e];
-    }
-    s_sum[threadIdx.x] = acc;
-    __syncthreads();
-    if (g == 0 && el < EP && e < W) {
-      float t = 0.f;
-      for (int j = 0; j < G; ++j) t += s_sum[threadIdx.x + j];
-      s_tot[e] = t;
-    }
-    __syncthreads();
-  }
-  const float wsum = s_tot[NM];
-  for (int e = threadIdx.x; e < NM; e += kFinThreads) {
-    const float u = b.U[e];
-    const float un = bad ? u : u + s_tot[e] / wsum;
-    if (U_out) U_out[e] = un;
-    b.Unew[e] = un;
+  // G threads per element, each summing a strided subset of the partials;
+  // G = floor(kFinThreads / W) leaves at least W element groups, so one pass
+  // covers every element.  The first kFinBatch partials of a thread are
+  // requested at once, then the nominal: the rows past the last update block
+  // are zero padding (G * kFinBatch rows), so these loads need no tests.
+  const int G = kFinThreads / W;
+  const int el = threadIdx.x / G, g = threadIdx.x % G;
+  const bool live = el < W;
+  const int ec = live ? el : 0;
+  float v[kFinBatch];
+#pragma unroll
+  for (int q = 0; q < kFinBatch; ++q) v[q] = b.upart[(g + q * G) * W + ec];  // < 2^31
+  const float u_own = b.U[e_own < NM ? e_own : 0];
+  float acc = 0.f;
+#pragma unroll
+  for (int q = 0; q < kFinBatch; ++q) acc += v[q];
+  if (live)
+    for (int i = g + kFinBatch * G; i < nb; i += G) acc += b.upart[i * W + ec];
+  s_sum[threadIdx.x] = acc;
+  __syncthreads();
+  if (g == 0 && live) {
+    float t = 0.f;
+    for (int j = 0; j < G; ++j) t += s_sum[threadIdx.x + j];
+    s_tot[el] = t;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < NM; e += kFinThreads) {
-    const int j = e / c.m, i = e % c.m;
-    if (j == 0 && u_out) u_out[i] = b.Unew[e];
+  const float wsum = s_tot[NM];
+  if (e_own < NM) {
+    const float un = bad ? u_own : u_own + s_tot[e_own] / wsum;
+    if (U_out) U_out[e_own] = un;
+    b.Unew[e_own] = un;
+    s_un[e_own] = un;
+  }
+  __syncthreads();
+  if (e_own < NM) {
+    const int j = e_own / c.m, i = e_own % c.m;
+    if (j == 0 && u_out) u_out[i] = s_un[e_own];
     if (!bad) {
       const int src = j + 1 < c.N ? j + 1 : c.N - 1;
-      b.U[e] = b.Unew[src * c.m + i];
+      b.U[e_own] = s_un[src * c.m + i];
     }
   }
   if (threadIdx.x == 0) {
     Ctrl* cw = b.ctrl;
-    const int branch = cw->branch;
+    const int branch = cv.branch;
     const bool cl = branch == 0;
-    const bool hasM = cl && cw->M > 0;
-    const float smin = !cl ? cw->smin_all : (hasM ? b.c_smin[cw->sel] : cw->smin_feas);
+    const bool hasM = cl && cv.M > 0;
+    const float smin = !cl ? cv.smin_all : (hasM ? cv.smin_sel : cv.smin_feas);
     cw->wsum = wsum;
     // ring state for the next replan's rollout blocks
-    cw->hs_head = cw->hist_head;
-    cw->hs_count = cw->hist_count;
-    cw->hs_nobs = cw->hist_nobs;
+    cw->hs_head = cv.hist_head;
+    cw->hs_count = cv.hist_count;
+    cw->hs_nobs = cv.hist_nobs;
     if (!bad) {
-      const uint32_t lo = cw->step_lo + 1u;
-      if (lo == 0u) cw->step_hi += 1u;
+      const uint32_t lo = cv.step_lo + 1u;
+      cw->step_hi = lo == 0u ? cv.step_hi + 1u : cv.step_hi;
       cw->step_lo = lo;
     }
     if (info_out) {
@@ -1185,23 +1242,23 @@ __device__ __forceinline__ void finish_body(const Cfg& c, const Bufs& b, int bx,
       };
       Info* inf = reinterpret_cast<Info*>(info_out);
       inf->branch = branch;
-      inf->n_collide = bad ? 0 : cw->n_col;
-      inf->n_feasible = bad ? 0 : cw->n_feas;
-      inf->n_ref = cl ? cw->n_ref : 0;
-      inf->n_clusters = cl ? cw->M : 0;
-      inf->selected = hasM ? cw->sel : -1;
-      inf->selected_size = hasM ? cw->sel_size : 0;
-      inf->closest = cw->closest;
-      inf->rule = hasM ? cw->rule : 0;
-      inf->history_used = hasM ? cw->h_used : 0;
-      inf->status = cw->status;
-      inf->step = cw->step_used;
-      inf->margin = hasM ? cw->margin : INFINITY;
+      inf->n_collide = bad ? 0 : cv.n_col;
+      inf->n_feasible = bad ? 0 : cv.n_feas;
+      inf->n_ref = cl ? cv.n_ref : 0;
+      inf->n_clusters = cl ? cv.M : 0;
+      inf->selected = hasM ? cv.sel : -1;
+      inf->selected_size = hasM ? cv.sel_size : 0;
+      inf->closest = cv.closest;
+      inf->rule = hasM ? cv.rule : 0;
+      inf->history_used = hasM ? cv.h_used : 0;
+      inf->status = cv.status;
+      inf->step = cv.step_used;
+      inf->margin = hasM ? cv.margin : INFINITY;
       inf->s_min = smin;
       for (int i = 0; i < 3; ++i) {
-        inf->ref_point[i] = cl ? cw->ref[i] : 0.f;
-        inf->v_obs[i] = hasM ? cw->v_obs[i] : 0.f;
-        inf->v_obs_hat[i] = hasM ? cw->v_hat[i] : 0.f;
+        inf->ref_point[i] = cl ? cv.ref[i] : 0.f;
+        inf->v_obs[i] = hasM ? cv.v_obs[i] : 0.f;
+        inf->v_obs_hat[i] = hasM ? cv.v_hat[i] : 0.f;
       }
       inf->weight_sum = wsum;
     }

@@ -37,6 +37,7 @@ constexpr int kTile = 128;
 constexpr int kUpdChunk = 64;
 constexpr int kUpdThreads = 256;
 constexpr int kFinThreads = 1024;
+static_assert(kMaxNM <= kFinThreads, "the final combination holds one element per thread");
 // tree graph handled by the fast path
 constexpr int kMaxTrees = 64;
 constexpr int kColGroup = 2;   // column tiles per tree-adjacency block
@@ -44,6 +45,8 @@ constexpr int kCntGroup = 2;   // column tiles per count / core-neighbour block 
 constexpr int kSortBins = 4096; // Morton cells of the DBSCAN spatial order
 constexpr int kOrBatch = 8;    // tree-slot loads in flight per lane
 constexpr int kLabBatch = 8;   // points per thread per labelling pass
+constexpr int kRecBatch = 4;   // partial records per thread in flight at once
+constexpr int kFinBatch = 16;  // update partials per thread in flight at once (final combination)
 constexpr int kStatClusters = 64;  // clusters per statistics pass of the labelling block
 
 constexpr int kInt32Max = 0x7fffffff;
