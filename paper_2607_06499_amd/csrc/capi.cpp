@@ -334,8 +334,10 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_ccost = cv.take<float>((size_t)c.mcap), o_cdir = cv.take<float>((size_t)c.mcap * 4);
   const size_t o_csize = cv.take<int>((size_t)c.mcap), o_csmin = cv.take<float>((size_t)c.mcap);
   // update partials, then rows that stay zero so the final combination can
-  // request its first kFinBatch rows per thread without bounds tests
-  const size_t o_upart = cv.take<float>((size_t)(c.nblk_upd + (kFinThreads / (NM + 1)) * kFinBatch) * (NM + 1));
+  // request whole batches of rows (kFinRows per wave) without bounds tests,
+  // and the chunks of the last row that reach past its end
+  const size_t o_upart = cv.take<float>((size_t)(c.nblk_upd + (kFinThreads / kWave) * kFinRows) * (NM + 1) +
+                                        (size_t)kFinChunks * kWave);
   P->arena_bytes = cv.off;
   e = hipMalloc(&P->arena, P->arena_bytes);
   if (e != hipSuccess) {

@@ -1164,41 +1164,59 @@ __global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
 
 // Final combination (one block): sum of the update partials in a fixed order,
 // U_new = U + sum / sum(w), outputs, shift (last control repeated), step
-// counter and the info record.
-__device__ __forceinline__ void finish_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, float* __restrict__ u_out, float* __restrict__ U_out, void* info_out) {
-  __shared__ float s_sum[kFinThreads];
-  __shared__ float s_tot[kMaxNM + 1];
-  __shared__ float s_un[kMaxNM];
+// counter and the info record.  NCH = ceil((N m + 1) / 64) element chunks.
+struct FinLds {
+  float part[kFinThreads / kWave][kMaxNM + 1];
+  float tot[kMaxNM + 1];
+  float un[kMaxNM];
+};
+
+template <int NCH>
+__device__ __forceinline__ void finish_body(const Cfg& c, const Bufs& b, FinLds& sh, float* __restrict__ u_out, float* __restrict__ U_out, void* info_out) {
+  float (*s_part)[kMaxNM + 1] = sh.part;
+  float* s_tot = sh.tot;
+  float* s_un = sh.un;
   // the control words and the nominal are requested with the partials
   const Ctrl cv = *b.ctrl;
   const bool bad = cv.nonfinite != 0;
   const int NM = c.NM, W = NM + 1;
   const int e_own = threadIdx.x;  // NM <= kMaxNM <= kFinThreads: one element per thread
   const int nb = c.nblk_upd;
-  // G threads per element, each summing a strided subset of the partials;
-  // G = floor(kFinThreads / W) leaves at least W element groups, so one pass
-  // covers every element.  The first kFinBatch partials of a thread are
-  // requested at once, then the nominal: the rows past the last update block
-  // are zero padding (G * kFinBatch rows), so these loads need no tests.
-  const int G = kFinThreads / W;
-  const int el = threadIdx.x / G, g = threadIdx.x % G;
-  const bool live = el < W;
-  const int ec = live ? el : 0;
-  float v[kFinBatch];
+  // wave w sums the rows w, w + 16, ... in increasing order, lane l the
+  // elements l, l + 64, ... of each (whole rows: coalesced).  A batch of
+  // kFinRows rows per wave is requested at once; rows past the last update
+  // block are zero padding and the chunks past a row's end read the next
+  // row (those sums are never used), so the loads need no tests.
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  constexpr int NW = kFinThreads / kWave;
+  float acc[NCH];
 #pragma unroll
-  for (int q = 0; q < kFinBatch; ++q) v[q] = b.upart[(g + q * G) * W + ec];  // < 2^31
-  const float u_own = b.U[e_own < NM ? e_own : 0];
-  float acc = 0.f;
+  for (int ch = 0; ch < NCH; ++ch) acc[ch] = 0.f;
+  float u_own = 0.f;
+  for (int r0 = wv; r0 < nb; r0 += NW * kFinRows) {
+    float v[kFinRows][NCH];
 #pragma unroll
-  for (int q = 0; q < kFinBatch; ++q) acc += v[q];
-  if (live)
-    for (int i = g + kFinBatch * G; i < nb; i += G) acc += b.upart[i * W + ec];
-  s_sum[threadIdx.x] = acc;
+    for (int rb = 0; rb < kFinRows; ++rb)
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) v[rb][ch] = b.upart[(r0 + rb * NW) * W + ch * kWave + lane];  // < 2^31
+    if (r0 == wv) u_own = b.U[e_own < NM ? e_own : 0];
+#pragma unroll
+    for (int rb = 0; rb < kFinRows; ++rb)
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) acc[ch] += v[rb][ch];
+  }
+  if (nb <= wv) u_own = b.U[e_own < NM ? e_own : 0];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int e = ch * kWave + lane;
+    if (e < W) s_part[wv][e] = acc[ch];
+  }
   __syncthreads();
-  if (g == 0 && live) {
+  if (e_own < W) {
     float t = 0.f;
-    for (int j = 0; j < G; ++j) t += s_sum[threadIdx.x + j];
-    s_tot[el] = t;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += s_part[w][e_own];
+    s_tot[e_own] = t;
   }
   __syncthreads();
   const float wsum = s_tot[NM];
@@ -1265,8 +1283,10 @@ __device__ __forceinline__ void finish_body(const Cfg& c, const Bufs& b, int bx,
   }
 }
 
+template <int NCH>
 __global__ __launch_bounds__(kFinThreads) void k_finish(Cfg c, Bufs b, float* __restrict__ u_out, float* __restrict__ U_out, void* info_out) {
-  finish_body(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, u_out, U_out, info_out);
+  __shared__ FinLds sh;
+  finish_body<NCH>(c, b, sh, u_out, U_out, info_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1380,10 +1400,18 @@ __global__ __launch_bounds__(kUpdThreads) void kb_update(CSlotStatic st, Tab t) 
 
 __global__ __launch_bounds__(kFinThreads) void kb_finish(CSlotStatic st, CSlotIO io, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
+  __shared__ FinLds sh;
   for_each_item(t, s_pref, [&](int slot, int) {
     CEMPPI_SLOT(slot);
     const SlotIO& I = *(const SlotIO*)(io + slot);
-    finish_body(c, b, 0, 0, 0, I.u_out, I.U_out, I.info);
+    switch ((c.NM + 1 + kWave - 1) / kWave) {
+      case 1: finish_body<1>(c, b, sh, I.u_out, I.U_out, I.info); break;
+      case 2: finish_body<2>(c, b, sh, I.u_out, I.U_out, I.info); break;
+      case 3: finish_body<3>(c, b, sh, I.u_out, I.U_out, I.info); break;
+      case 4: finish_body<4>(c, b, sh, I.u_out, I.U_out, I.info); break;
+      case 5: finish_body<5>(c, b, sh, I.u_out, I.U_out, I.info); break;
+      default: finish_body<6>(c, b, sh, I.u_out, I.U_out, I.info); break;
+    }
   });
 }
 #undef CEMPPI_SLOT
@@ -1420,7 +1448,10 @@ void launch_post_rollout(Launcher& L, const Cfg& c, const Bufs& b) {
 }
 
 void launch_finish(Launcher& L, const Cfg& c, const Bufs& b, float* u_out, float* U_out, void* info) {
-  L(k_finish, dim3(1), dim3(kFinThreads), c, b, u_out, U_out, info);
+  static_assert(kFinChunks <= 6, "finish kernels exist for up to 6 element chunks");
+  using FFn = void (*)(Cfg, Bufs, float*, float*, void*);
+  static const FFn fins[6] = {k_finish<1>, k_finish<2>, k_finish<3>, k_finish<4>, k_finish<5>, k_finish<6>};
+  L(fins[(c.NM + 1 + kWave - 1) / kWave - 1], dim3(1), dim3(kFinThreads), c, b, u_out, U_out, info);
 }
 
 void launch_stage_dbscan(Launcher& L, const Cfg& c, const Bufs& b, const float* z, int V,

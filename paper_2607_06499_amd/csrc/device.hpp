@@ -46,7 +46,8 @@ constexpr int kSortBins = 4096; // Morton cells of the DBSCAN spatial order
 constexpr int kOrBatch = 8;    // tree-slot loads in flight per lane
 constexpr int kLabBatch = 8;   // points per thread per labelling pass
 constexpr int kRecBatch = 4;   // partial records per thread in flight at once
-constexpr int kFinBatch = 16;  // update partials per thread in flight at once (final combination)
+constexpr int kFinRows = 8;    // update-partial rows per wave in flight at once (final combination)
+constexpr int kFinChunks = (kMaxNM + 1 + 63) / 64;  // 64-element chunks of a partial row, at most
 constexpr int kStatClusters = 64;  // clusters per statistics pass of the labelling block
 
 constexpr int kInt32Max = 0x7fffffff;
