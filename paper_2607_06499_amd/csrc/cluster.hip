@@ -4,8 +4,10 @@
 // [Selection], Eq. (14)-(18)) and the path-integral update with the shift
 // (Eq. (6)-(7), Eq. (19)-(20), Alg. 1 [Execute]).
 //
-// No kernel here communicates between its own workgroups: every reduction
-// that several blocks need is recomputed by each of them from the previous
+// No block of a kernel waits for another.  Blocks combine results only
+// through integer atomics whose outcome does not depend on their order
+// (neighbour counts, minima, bit ORs); every floating-point reduction that
+// several blocks need is recomputed by each of them from the previous
 // kernel's outputs in a fixed order (so results are deterministic), and the
 // work that needs a single view runs in a one-block kernel.
 //
@@ -18,8 +20,8 @@
 //             tree (flag words from step 2); trees are numbered by root index
 //  4. trees   tiled pass over core-core neighbour pairs of different trees;
 //             each block first follows the hooks of its points (indices
-//             strictly decrease) to their roots, then writes the tree
-//             adjacency bits it saw to its own slot
+//             strictly decrease) to their roots, then ORs the tree
+//             adjacency bits it saw into the 64 rows of the tree graph
 //  5. tree CC connected components of the (small) tree graph; the cluster of
 //             a component is ranked by its lowest root index, which is the
 //             lowest core index of the cluster
@@ -280,6 +282,7 @@ __device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx
   b.root[rank] = -1;
   b.label[rank] = -1;
   if ((rank & 63) == 0) b.hookmask[rank >> 6] = 0ull;
+  if (rank < kMaxTrees) b.tadj[rank] = 0ull;  // rows of trees 0 .. min(V, 64) - 1
 }
 
 template <int P>
@@ -296,6 +299,7 @@ __global__ void k_init_points(Bufs b, int V) {
   b.root[a] = -1;
   b.label[a] = -1;
   if ((a & 63) == 0) b.hookmask[a >> 6] = 0ull;
+  if (a < kMaxTrees) b.tadj[a] = 0ull;
 }
 
 // number of points DBSCAN runs on: caller features (stage) or the feasible set
@@ -553,7 +557,8 @@ constexpr int kMaxWords = (65536 + 63) / 64;
 // 4. tree adjacency over the upper triangle of tiles (J >= I; the closure
 // makes the relation symmetric): for every core-core neighbour pair (row k,
 // column l) of different trees set bit tree(l) in the row of tree(k).  Block
-// (g, I) writes the rows it saw to its own slot (no cross-block atomics).
+// (g, I) gathers its rows in LDS and ORs the nonzero ones into the global
+// rows (an exact, order-independent reduction).
 __device__ __forceinline__ bool adj_block_live(int I, int g, int nt) {
   const int J0 = g * kColGroup;
   return I < nt && J0 < nt && J0 + kColGroup > I;
@@ -561,7 +566,7 @@ __device__ __forceinline__ bool adj_block_live(int I, int g, int nt) {
 
 template <int P, bool SORTED = false>
 __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
-                                              const float* __restrict__ zin, int Vin, int ngrp) {
+                                              const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
   __shared__ ZT s_z[kTile];
   __shared__ uint2 s_bit[kTile];  // tree bit of the column point as two words, 0 if not core
@@ -575,13 +580,9 @@ __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int b
   const ZT* z = reinterpret_cast<const ZT*>(SORTED ? b.zs : (zin ? zin : b.z));
   const int J0 = max(g * kColGroup, I), J1 = min(g * kColGroup + kColGroup, nt);
   if constexpr (SORTED) {
-    // its slot stays zero: written here so the closure can read every slot
     bool any = false;
     for (int J = J0; J < J1; ++J) any |= !tiles_apart(c, b, I, J);
-    if (!any) {
-      if (threadIdx.x < kMaxTrees) b.tslot[((size_t)I * ngrp + g) * kMaxTrees + threadIdx.x] = 0ull;
-      return;
-    }
+    if (!any) return;
   }
   // every operand of the block is requested before the first wait (sorted
   // positions first, then the per-point arrays at the original indices)
@@ -652,12 +653,13 @@ __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int b
     if (mask) atomicOr(&s_adj[tk], mask);
   }
   __syncthreads();
-  if (threadIdx.x < R) b.tslot[((size_t)I * ngrp + g) * kMaxTrees + threadIdx.x] = s_adj[threadIdx.x];
+  // OR is exact and commutative: the rows do not depend on the block order
+  if (threadIdx.x < R && s_adj[threadIdx.x]) atomicOr(&b.tadj[threadIdx.x], s_adj[threadIdx.x]);
 }
 
 template <int P>
-__global__ __launch_bounds__(kTile) void k_tree_adj(Cfg c, Bufs b, const float* __restrict__ zin, int Vin, int ngrp) {
-  tree_adj_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin, ngrp);
+__global__ __launch_bounds__(kTile) void k_tree_adj(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  tree_adj_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
 }
 
 // 5. connected components of the tree graph and canonical cluster numbers
@@ -795,11 +797,10 @@ __device__ void chunk_stats(const Bufs& b, bool first, int M, const int (&lab)[k
 }
 
 template <int P>
-__device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin, int ngrp, int* mout, int* lab_out, int* cnt_out) {
+__device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin, int* mout, int* lab_out, int* cnt_out) {
   __shared__ int s_woff[kMaxWords];
   __shared__ unsigned long long s_rm[kMaxWords];
   __shared__ unsigned long long s_adj[kMaxTrees];
-  __shared__ unsigned long long s_part[kFinThreads / kWave][kMaxTrees];
   __shared__ int s_tc[kMaxTrees];
   __shared__ int s_M;
   __shared__ float s_red[kFinThreads / kWave][kStatClusters][6];
@@ -814,38 +815,9 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
   if (threadIdx.x < kMaxTrees) s_tc[threadIdx.x] = 0;
   __syncthreads();
   if (R >= 2 && !overflow) {
-    // OR the live slots.  Rows are padded to Rp = 2^ceil(log2 R) lanes: thread
-    // t owns row t % Rp of slots t / Rp, t / Rp + 1024 / Rp, ... (kOrBatch
-    // loads in flight), then the lanes of one row are OR-ed across the wave
-    // and the 16 waves' rows across LDS.
-    const int nt = ntiles_of(V);
-    const int nslot = nt * ngrp;
-    int Rp = 2;
-    while (Rp < R) Rp <<= 1;
-    const int row = threadIdx.x & (Rp - 1), grp = threadIdx.x / Rp, ngr = kFinThreads / Rp;
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    unsigned long long acc = 0ull;
-    if (row < R) {
-      for (int t0 = grp; t0 < nslot; t0 += ngr * kOrBatch) {
-        unsigned long long v[kOrBatch];
-#pragma unroll
-        for (int u = 0; u < kOrBatch; ++u) {
-          const int t = t0 + u * ngr;
-          const int I = t / ngrp, g = t - I * ngrp;
-          v[u] = (t < nslot && adj_block_live(I, g, nt)) ? b.tslot[(size_t)t * kMaxTrees + row] : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < kOrBatch; ++u) acc |= v[u];
-      }
-    }
-    for (int off = Rp; off < kWave; off <<= 1) acc |= __shfl_xor(acc, off, kWave);
-    if (lane < Rp) s_part[w][lane] = acc;
-    __syncthreads();
-    if (threadIdx.x < R) {
-      unsigned long long a = 0ull;
-      for (int i = 0; i < kFinThreads / kWave; ++i) a |= s_part[i][threadIdx.x];
-      s_adj[threadIdx.x] = a;
-    }
+    // the tree graph: row t holds the trees adjacent to tree t (OR-ed by
+    // the tree-adjacency blocks)
+    if (threadIdx.x < R) s_adj[threadIdx.x] = b.tadj[threadIdx.x];
     __syncthreads();
     if (threadIdx.x < kWave) {
       const int r = threadIdx.x;
@@ -952,8 +924,8 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
 }
 
 template <int P>
-__global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const float* __restrict__ zin, int Vin, int ngrp, int* mout, int* lab_out, int* cnt_out) {
-  tree_cc_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin, ngrp, mout, lab_out, cnt_out);
+__global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const float* __restrict__ zin, int Vin, int* mout, int* lab_out, int* cnt_out) {
+  tree_cc_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin, mout, lab_out, cnt_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1375,8 +1347,7 @@ __global__ __launch_bounds__(kTile) void kb_tree_adj(CSlotStatic st, Tab t) {
     CEMPPI_SLOT(slot);
     const int nt = ntiles_of(dbscan_V(b, nullptr, 0));
     const int ng = (nt + kColGroup - 1) / kColGroup;
-    tree_adj_body<P, true>(c, b, local % ng, local / ng, 0, nullptr, 0,
-                           (c.ntile + kColGroup - 1) / kColGroup);
+    tree_adj_body<P, true>(c, b, local % ng, local / ng, 0, nullptr, 0);
   });
 }
 
@@ -1385,8 +1356,7 @@ __global__ __launch_bounds__(kFinThreads) void kb_tree_cc(CSlotStatic st, Tab t)
   __shared__ int s_pref[kMaxBatch + 1];
   for_each_item(t, s_pref, [&](int slot, int) {
     CEMPPI_SLOT(slot);
-    tree_cc_body<P>(c, b, 0, 0, 0, nullptr, 0, (c.ntile + kColGroup - 1) / kColGroup, nullptr,
-                    nullptr, nullptr);
+    tree_cc_body<P>(c, b, 0, 0, 0, nullptr, 0, nullptr, nullptr, nullptr);
   });
 }
 
@@ -1426,8 +1396,8 @@ static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const floa
   dim3 tiles(ngrp, ntile), ctiles(ncnt, ntile), tb(kTile);
   L(k_count<P>, ctiles, tb, c, b, zin, Vin);
   L(k_mcn<P>, ctiles, tb, c, b, zin, Vin);
-  L(k_tree_adj<P>, tiles, tb, c, b, zin, Vin, ngrp);
-  L(k_tree_cc<P>, dim3(1), dim3(kFinThreads), c, b, zin, Vin, ngrp, mout, lab_out, cnt_out);
+  L(k_tree_adj<P>, tiles, tb, c, b, zin, Vin);
+  L(k_tree_cc<P>, dim3(1), dim3(kFinThreads), c, b, zin, Vin, mout, lab_out, cnt_out);
 }
 
 // Everything between the rollouts and the final combination, as one chain
@@ -1462,9 +1432,9 @@ void launch_stage_dbscan(Launcher& L, const Cfg& c, const Bufs& b, const float* 
   if (V == 0) {
     // no points: only the cluster count (0) is produced
     if (c.p == 2)
-      L(k_tree_cc<2>, dim3(1), dim3(kFinThreads), c, b, z, 0, 1, mout, (int*)nullptr, (int*)nullptr);
+      L(k_tree_cc<2>, dim3(1), dim3(kFinThreads), c, b, z, 0, mout, (int*)nullptr, (int*)nullptr);
     else
-      L(k_tree_cc<3>, dim3(1), dim3(kFinThreads), c, b, z, 0, 1, mout, (int*)nullptr, (int*)nullptr);
+      L(k_tree_cc<3>, dim3(1), dim3(kFinThreads), c, b, z, 0, mout, (int*)nullptr, (int*)nullptr);
     return;
   }
   const int ntile = (V + kTile - 1) / kTile;

@@ -43,7 +43,6 @@ constexpr int kMaxTrees = 64;
 constexpr int kColGroup = 2;   // column tiles per tree-adjacency block
 constexpr int kCntGroup = 2;   // column tiles per count / core-neighbour block (early exit)
 constexpr int kSortBins = 4096; // Morton cells of the DBSCAN spatial order
-constexpr int kOrBatch = 8;    // tree-slot loads in flight per lane
 constexpr int kLabBatch = 8;   // points per thread per labelling pass
 constexpr int kRecBatch = 4;   // partial records per thread in flight at once
 constexpr int kFinRows = 8;    // update-partial rows per wave in flight at once (final combination)
@@ -136,7 +135,7 @@ struct Bufs {
   int* ncount;     // [K]
   int* mcn;        // [K] lowest-index core neighbour (kInt32Max if none)
   int* root;       // [K] tree root (core points), -1 otherwise
-  unsigned long long* tslot;    // [ntile][ceil(ntile/kColGroup)][kMaxTrees] tree adjacency per block
+  unsigned long long* tadj;     // [kMaxTrees] tree adjacency rows (OR of every tree-adjacency block)
   int* label;      // [K]
   unsigned long long* coremask;  // [ceil(K/64)] core flags
   unsigned long long* hookmask;  // [ceil(K/64)] core neighbour of lower index found
