@@ -320,7 +320,8 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_U = cv.take<float>(NM), o_Unew = cv.take<float>(NM), o_hist = cv.take<float>(hist);
   const size_t o_S = cv.take<float>(K), o_col = cv.take<int>(K), o_first = cv.take<int>(K);
   const size_t o_pT = cv.take<float>(K * p), o_pF = cv.take<float>(K * p), o_g = cv.take<float>(K * p);
-  const size_t o_eps = cv.take<float>(K * NM);
+  // (plus the chunks of the last row that the update kernel reads past its end)
+  const size_t o_eps = cv.take<float>(K * NM + (size_t)kFinChunks * kWave);
   // room for the groups of the widest block (kMaxR rounds of 2 rollouts per wave)
   const size_t o_part = cv.take<float>((size_t)(c.npart + kMaxRpb * kMaxR / kGroup) * kPart);
   const size_t o_vidx = cv.take<int>(K), o_z = cv.take<float>(K * zs), o_gv = cv.take<float>(K * zs);

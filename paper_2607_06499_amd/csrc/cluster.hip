@@ -1031,13 +1031,59 @@ __device__ __forceinline__ Sel select_cluster(const Cfg& c, const Bufs& b, int M
 }
 
 // ---------------------------------------------------------------------------
+// Weighted sums of one update block: wave w takes candidates w * PER ..
+// w * PER + PER - 1 (in order), lane l the elements l, l + 64, ... (NCH
+// chunks, two chunks of every row requested at once; a chunk past the row's
+// end reads the next row, or the slack after the last, and is not used);
+// element N m is the weight sum.  The four waves are added in order.
+struct UpdLds {
+  float w[kUpdChunk];
+  int k[kUpdChunk];
+  float acc[kUpdThreads / kWave][kFinChunks * kWave];
+};
+
+template <int NCH>
+__device__ __forceinline__ void update_sums(const Bufs& b, int NM, float* part, UpdLds& L) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  constexpr int PER = kUpdChunk / (kUpdThreads / kWave);
+#pragma unroll
+  for (int c0 = 0; c0 < NCH; c0 += 2) {
+    constexpr int CB = 2;
+    float v[PER][CB];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const float* row = b.eps + (size_t)L.k[wv * PER + i] * NM + lane;
+#pragma unroll
+      for (int q = 0; q < CB; ++q) v[i][q] = c0 + q < NCH ? row[(c0 + q) * kWave] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      if (c0 + q >= NCH) break;
+      const int e = (c0 + q) * kWave + lane;
+      float acc = 0.f;
+      if (e < NM) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) acc += L.w[wv * PER + i] * v[i][q];
+      } else if (e == NM) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) acc += L.w[wv * PER + i];
+      }
+      L.acc[wv][e] = acc;
+    }
+  }
+  __syncthreads();
+  float (*s_acc)[kFinChunks * kWave] = L.acc;
+  for (int e = threadIdx.x; e <= NM; e += kUpdThreads)
+    part[e] = ((s_acc[0][e] + s_acc[1][e]) + s_acc[2][e]) + s_acc[3][e];
+}
+
 // Update partials, Eq. (19)-(20) (Eq. (6)-(7) on the fallback branches):
 // block b takes kUpdChunk candidates (16 per wave); lane = element of the
 // [N][m] sequence; the four waves' sums are combined in a fixed order.
-__device__ __forceinline__ void update_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx) {
-  __shared__ float s_w[kUpdChunk];
-  __shared__ int s_k[kUpdChunk];
-  __shared__ float s_acc[kUpdThreads / kWave][kWave];
+template <int NCH>
+__device__ __forceinline__ void update_body(const Cfg& c, const Bufs& b, UpdLds& L, int bx) {
+  float* s_w = L.w;
+  int* s_k = L.k;
   const Ctrl* ct = b.ctrl;
   // the candidate records of both branches are requested with the control
   // words, before the branch is known (every array holds K entries)
@@ -1107,31 +1153,14 @@ __device__ __forceinline__ void update_body(const Cfg& c, const Bufs& b, int bx,
     s_k[threadIdx.x] = kk;  // a valid row whenever the weight is nonzero
   }
   __syncthreads();
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  constexpr int PER = kUpdChunk / (kUpdThreads / kWave);
   float* part = b.upart + (size_t)bx * (NM + 1);
-  for (int e0 = 0; e0 < NM + 1; e0 += kWave) {
-    const int e = e0 + lane;
-    float acc = 0.f;
-    if (e < NM) {
-#pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int ci = wv * PER + i;
-        acc += s_w[ci] * b.eps[(size_t)s_k[ci] * NM + e];
-      }
-    } else if (e == NM) {
-#pragma unroll
-      for (int i = 0; i < PER; ++i) acc += s_w[wv * PER + i];
-    }
-    s_acc[wv][lane] = acc;
-    __syncthreads();
-    if (wv == 0 && e <= NM) part[e] = ((s_acc[0][lane] + s_acc[1][lane]) + s_acc[2][lane]) + s_acc[3][lane];
-    __syncthreads();
-  }
+  update_sums<NCH>(b, NM, part, L);
 }
 
+template <int NCH>
 __global__ __launch_bounds__(kUpdThreads) void k_update(Cfg c, Bufs b) {
-  update_body(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+  __shared__ UpdLds L;
+  update_body<NCH>(c, b, L, (int)blockIdx.x);
 }
 
 // Final combination (one block): sum of the update partials in a fixed order,
@@ -1362,9 +1391,17 @@ __global__ __launch_bounds__(kFinThreads) void kb_tree_cc(CSlotStatic st, Tab t)
 
 __global__ __launch_bounds__(kUpdThreads) void kb_update(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
+  __shared__ UpdLds L;
   for_each_item(t, s_pref, [&](int slot, int local) {
     CEMPPI_SLOT(slot);
-    update_body(c, b, local, 0, 0);
+    switch ((c.NM + 1 + kWave - 1) / kWave) {
+      case 1: update_body<1>(c, b, L, local); break;
+      case 2: update_body<2>(c, b, L, local); break;
+      case 3: update_body<3>(c, b, L, local); break;
+      case 4: update_body<4>(c, b, L, local); break;
+      case 5: update_body<5>(c, b, L, local); break;
+      default: update_body<6>(c, b, L, local); break;
+    }
   });
 }
 
@@ -1414,7 +1451,9 @@ void launch_post_rollout(Launcher& L, const Cfg& c, const Bufs& b) {
     L(k_compact<3>, dim3(nk), dim3(256), c, b);
     launch_dbscan_p<3>(L, c, b, nullptr, 0, c.ntile, none, none, none);
   }
-  L(k_update, dim3(c.nblk_upd), dim3(kUpdThreads), c, b);
+  using UFn = void (*)(Cfg, Bufs);
+  static const UFn upds[6] = {k_update<1>, k_update<2>, k_update<3>, k_update<4>, k_update<5>, k_update<6>};
+  L(upds[(c.NM + 1 + kWave - 1) / kWave - 1], dim3(c.nblk_upd), dim3(kUpdThreads), c, b);
 }
 
 void launch_finish(Launcher& L, const Cfg& c, const Bufs& b, float* u_out, float* U_out, void* info) {
