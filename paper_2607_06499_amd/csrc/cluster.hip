@@ -386,12 +386,30 @@ __device__ __forceinline__ void sort_body(const Cfg& c, const Bufs& b, const flo
   }
 }
 
+// AND of a predicate over the NT threads of a block (a barrier for all of
+// them).  Each wave posts whether any of its lanes is false; consecutive
+// calls must be separated by another barrier of the block (the tiled passes
+// stage a tile between calls), so one word per wave suffices.  (The
+// library's block-wide AND reads the block size from the dispatch packet,
+// one more memory round trip per kernel.)
+template <int NT>
+__device__ __forceinline__ bool block_and(bool p, int* s_w) {
+  const unsigned long long f = __ballot(!p);
+  if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = f != 0ull ? 1 : 0;
+  __syncthreads();
+  int any = 0;
+#pragma unroll
+  for (int i = 0; i < NT / kWave; ++i) any |= s_w[i];
+  return any == 0;
+}
+
 // 1. neighbour counts: for each row point, its neighbours among the block's
 // column points (closed ball, itself included), in sorted order.
 template <int P, int COLG = kColGroup, bool SORTED = false>
 __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
                                            const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
+  __shared__ int s_all[kTile / kWave];
   __shared__ ZT s_z[kTile];
   const int V = dbscan_V(b, zin, Vin);
   const int nt = ntiles_of(V);
@@ -423,7 +441,7 @@ __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, 
     if (SORTED && tiles_apart(c, b, I, J)) continue;
     // only the core test needs the count: once every row of the block has
     // minPts neighbours in this chunk, the rest of the chunk cannot change it
-    if (__syncthreads_and(k >= V || cnt >= c.min_pts)) break;
+    if (block_and<kTile>(k >= V || cnt >= c.min_pts, s_all)) break;
     s_z[threadIdx.x] = zl[u];
     __syncthreads();
     const int ncol = min(kTile, V - J * kTile);
@@ -449,6 +467,7 @@ template <int P, int COLG = kColGroup>
 __device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
                                          const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
+  __shared__ int s_all[kTile / kWave];
   __shared__ ZT s_z[kTile];
   const int V = dbscan_V(b, zin, Vin);
   const int nt = ntiles_of(V);
@@ -479,7 +498,7 @@ __device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, in
   for (int u = 0; u < COLG; ++u) {
     const int J = J0 + u;
     if (J >= J1) break;
-    if (__syncthreads_and(k >= V || m != kInt32Max)) break;
+    if (block_and<kTile>(k >= V || m != kInt32Max, s_all)) break;
     // non-core columns are parked far away: they can never be a neighbour here
     s_z[threadIdx.x] = ncl[u] >= c.min_pts ? zl[u] : ZVec<P>::far();
     __syncthreads();
@@ -682,7 +701,7 @@ __device__ void uf_fallback(const Cfg& c, const Bufs& b, const float* zin, int V
       x = p;
     }
   };
-  for (int a = threadIdx.x; a < V; a += blockDim.x) {
+  for (int a = threadIdx.x; a < V; a += kFinThreads) {
     if (b.ncount[a] < c.min_pts) continue;
     const ZT za = z[a];
     for (int l = a + 1; l < V; ++l) {
@@ -707,7 +726,7 @@ __device__ void uf_fallback(const Cfg& c, const Bufs& b, const float* zin, int V
     }
   }
   __syncthreads();
-  for (int a = threadIdx.x; a < V; a += blockDim.x)
+  for (int a = threadIdx.x; a < V; a += kFinThreads)
     if (b.ncount[a] >= c.min_pts) parent[a] = find(a);
   __syncthreads();
 }
@@ -1331,7 +1350,7 @@ __global__ __launch_bounds__(kFinThreads) void kb_plan(CSlotStatic st, PlanOut o
 template <int P>
 __global__ __launch_bounds__(256) void kb_compact(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
-  for_each_item(t, s_pref, [&](int slot, int local) {
+  for_each_item<256>(t, s_pref, [&](int slot, int local) {
     CEMPPI_SLOT(slot);
     compact_body<P>(c, b, local, 0, 0);
   });
@@ -1341,7 +1360,7 @@ __global__ __launch_bounds__(256) void kb_compact(CSlotStatic st, Tab t) {
 template <int P>
 __global__ __launch_bounds__(kFinThreads) void kb_sort(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
-  for_each_item(t, s_pref, [&](int slot, int) {
+  for_each_item<kFinThreads>(t, s_pref, [&](int slot, int) {
     CEMPPI_SLOT(slot);
     sort_body<P>(c, b, nullptr, 0);
   });
@@ -1350,7 +1369,7 @@ __global__ __launch_bounds__(kFinThreads) void kb_sort(CSlotStatic st, Tab t) {
 template <int P, int COLG>
 __global__ __launch_bounds__(kTile) void kb_count(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
-  for_each_item(t, s_pref, [&](int slot, int local) {
+  for_each_item<kTile>(t, s_pref, [&](int slot, int local) {
     CEMPPI_SLOT(slot);
     const int nt = ntiles_of(dbscan_V(b, nullptr, 0));
     const int ng = (nt + COLG - 1) / COLG;
@@ -1361,7 +1380,7 @@ __global__ __launch_bounds__(kTile) void kb_count(CSlotStatic st, Tab t) {
 template <int P, int COLG>
 __global__ __launch_bounds__(kTile) void kb_mcn(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
-  for_each_item(t, s_pref, [&](int slot, int local) {
+  for_each_item<kTile>(t, s_pref, [&](int slot, int local) {
     CEMPPI_SLOT(slot);
     const int nt = ntiles_of(dbscan_V(b, nullptr, 0));
     const int ng = (nt + COLG - 1) / COLG;
@@ -1372,7 +1391,7 @@ __global__ __launch_bounds__(kTile) void kb_mcn(CSlotStatic st, Tab t) {
 template <int P>
 __global__ __launch_bounds__(kTile) void kb_tree_adj(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
-  for_each_item(t, s_pref, [&](int slot, int local) {
+  for_each_item<kTile>(t, s_pref, [&](int slot, int local) {
     CEMPPI_SLOT(slot);
     const int nt = ntiles_of(dbscan_V(b, nullptr, 0));
     const int ng = (nt + kColGroup - 1) / kColGroup;
@@ -1383,7 +1402,7 @@ __global__ __launch_bounds__(kTile) void kb_tree_adj(CSlotStatic st, Tab t) {
 template <int P>
 __global__ __launch_bounds__(kFinThreads) void kb_tree_cc(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
-  for_each_item(t, s_pref, [&](int slot, int) {
+  for_each_item<kFinThreads>(t, s_pref, [&](int slot, int) {
     CEMPPI_SLOT(slot);
     tree_cc_body<P>(c, b, 0, 0, 0, nullptr, 0, nullptr, nullptr, nullptr);
   });
@@ -1392,7 +1411,7 @@ __global__ __launch_bounds__(kFinThreads) void kb_tree_cc(CSlotStatic st, Tab t)
 __global__ __launch_bounds__(kUpdThreads) void kb_update(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
   __shared__ UpdLds L;
-  for_each_item(t, s_pref, [&](int slot, int local) {
+  for_each_item<kUpdThreads>(t, s_pref, [&](int slot, int local) {
     CEMPPI_SLOT(slot);
     switch ((c.NM + 1 + kWave - 1) / kWave) {
       case 1: update_body<1>(c, b, L, local); break;
@@ -1408,7 +1427,7 @@ __global__ __launch_bounds__(kUpdThreads) void kb_update(CSlotStatic st, Tab t) 
 __global__ __launch_bounds__(kFinThreads) void kb_finish(CSlotStatic st, CSlotIO io, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
   __shared__ FinLds sh;
-  for_each_item(t, s_pref, [&](int slot, int) {
+  for_each_item<kFinThreads>(t, s_pref, [&](int slot, int) {
     CEMPPI_SLOT(slot);
     const SlotIO& I = *(const SlotIO*)(io + slot);
     switch ((c.NM + 1 + kWave - 1) / kWave) {

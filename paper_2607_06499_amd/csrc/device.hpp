@@ -182,11 +182,13 @@ struct Tab {
 };
 
 // Persistent loop over the items of a table: block i takes items i, i +
-// gridDim.x, ...; f(slot, local item) runs with every thread of the block.
-template <typename F>
+// gridDim.x, ...; f(slot, local item) runs with every thread of the block
+// (NT threads: a compile-time block size, so the kernel does not read the
+// dispatch packet for it).
+template <int NT, typename F>
 __device__ __forceinline__ void for_each_item(const Tab& t, int* s_pref, F&& f) {
   const int n = __builtin_amdgcn_readfirstlane(*t.n);
-  for (int i = threadIdx.x; i <= n; i += blockDim.x) s_pref[i] = t.pref[i];
+  for (int i = threadIdx.x; i <= n; i += NT) s_pref[i] = t.pref[i];
   __syncthreads();
   const int total = s_pref[n];
   for (int it = blockIdx.x; it < total; it += gridDim.x) {

@@ -262,7 +262,7 @@ __device__ void publish(const Cfg& c, const Bufs& b, const float* __restrict__ o
   __syncthreads();
   const int nh = s_nh;
   if (!bad) {
-    for (int t = threadIdx.x; t < n_obs * c.p; t += blockDim.x) {
+    for (int t = threadIdx.x; t < n_obs * c.p; t += kRollThreads) {
       const int i = t / c.p, d = t % c.p;
       b.hist[((size_t)nh * c.max_obs + i) * c.p + d] = obs[i * (c.p + 1) + d];
     }
@@ -309,7 +309,7 @@ __device__ __forceinline__ void rollout_contrib(float* rec, bool active, int col
 __device__ __forceinline__ void write_group_partials(const Bufs& b, float (*recs)[kPart], int rpb, int bx) {
   __syncthreads();
   const int ng = rpb / kGroup;
-  for (int t = threadIdx.x; t < ng * kPart; t += blockDim.x) {
+  for (int t = threadIdx.x; t < ng * kPart; t += kRollThreads) {
     const int g = t / kPart, f = t - g * kPart;
     const bool mn = f == P_SMIN_ALL || f == P_SMIN_FEAS;
     float acc = mn ? INFINITY : 0.f;
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_arm(Cfg c, Bufs b, con
 template <int SEG, int R>
 __global__ __launch_bounds__(kRollThreads) void kb_rollout_unicycle(CSlotStatic st, CSlotIO io, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
-  for_each_item(t, s_pref, [&](int slot, int local) {
+  for_each_item<kRollThreads>(t, s_pref, [&](int slot, int local) {
     const SlotStatic& S = *(const SlotStatic*)(st + slot);
     const SlotIO& I = *(const SlotIO*)(io + slot);
     rollout_unicycle_body<SEG, R>(S.c, S.b, local, 0, 0, I.x_t, I.obs, I.n_obs);
@@ -699,7 +699,7 @@ __global__ __launch_bounds__(kRollThreads) void kb_rollout_unicycle(CSlotStatic 
 template <int R>
 __global__ __launch_bounds__(kRollThreads) void kb_rollout_arm(CSlotStatic st, CSlotIO io, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
-  for_each_item(t, s_pref, [&](int slot, int local) {
+  for_each_item<kRollThreads>(t, s_pref, [&](int slot, int local) {
     const SlotStatic& S = *(const SlotStatic*)(st + slot);
     const SlotIO& I = *(const SlotIO*)(io + slot);
     // the segment width is the member's own (a block-uniform branch)
