@@ -200,10 +200,23 @@ def _dbscan_cases():
     cases.append(("sphere3d", v.astype(np.float32),
                   W.PlannerSpec(dynamics=W.ARM6, num_samples=1200, dbscan_eps=0.35, dbscan_min_pts=16,
                                 dh=W.arm_dh([0.2] * 6))))
+    # full-size feature sets (64 and 40 tiles): one dense arc of unit
+    # features, as the rollouts give, and seven blobs of unequal spread in
+    # uniform noise (several hook trees per cluster, long hook chains)
+    th = rng.normal(0.7, 0.35, 8184)
+    z = np.stack([np.cos(th), np.sin(th)], 1).astype(np.float32)
+    cases.append(("arc_8184", z, W.PlannerSpec(num_samples=8192, dbscan_eps=0.25, dbscan_min_pts=20)))
+    cen = rng.uniform(-1, 1, (7, 2))
+    pts = [cc + rng.normal(0, 0.02 + 0.01 * i, (450 + 40 * i, 2)) for i, cc in enumerate(cen)]
+    pts.append(rng.uniform(-1, 1, (5000 - sum(len(q) for q in pts), 2)))
+    z = np.concatenate(pts)
+    rng.shuffle(z)
+    cases.append(("blobs_5000", z.astype(np.float32),
+                  W.PlannerSpec(num_samples=5000, dbscan_eps=0.05, dbscan_min_pts=12)))
     return cases
 
 
-@pytest.mark.parametrize("case", range(9))
+@pytest.mark.parametrize("case", range(10))
 def test_stage_dbscan_bit_exact(case):
     cases = _dbscan_cases()
     if case >= len(cases):
