@@ -474,9 +474,9 @@ def run_serve(seed, torch, B, rates=(2000.0, 5000.0, 10000.0, 20000.0), seconds=
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the CE-MPPI planners are "
+        print(json.dumps({"error": "bench.py measures one GPU: the CE-MPPI planners are "
                                    "independent, so more GPUs would each run their own share of "
-                                   "planners (see the design notes); run with --gpus 1"}))
+                                   "planners with no data crossing between them; run with --gpus 1"}))
         sys.exit(2)
     import torch
 

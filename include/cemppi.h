@@ -49,7 +49,7 @@ enum {
   CE_EINVAL = 1,       /* invalid argument or configuration                    */
   CE_ENOMEM = 2,       /* device allocation failed                             */
   CE_EDEVICE = 3,      /* HIP runtime error or no usable GPU                   */
-  CE_EUNSUPPORTED = 4, /* valid request this build does not support            */
+  CE_EUNSUPPORTED = 4, /* valid request the library does not support           */
   CE_EBUSY = 5         /* resource in use (e.g. server full)                   */
 };
 
