@@ -6,7 +6,11 @@ import numpy as np
 
 from paper_2607_06499_amd import binding as B
 
-# Tolerances (see the design notes for their derivation)
+# Tolerances.  FP32 kernels against the FP64 oracle on the same noise: a
+# horizon of N <= 63 steps accumulates O(N) FP32 roundings (about 6e-8
+# each) in the states and O(N) more in the cost sums, well under 1e-4
+# relative; the Gaussians come from hardware log/sqrt/sin/cos with a
+# measured worst case of 3.2e-7 against FP64, under 2e-6.
 TRAJ_RTOL = 1e-4        # trajectories, costs: |d| <= 1e-4 * max(|ref|, 1)
 GAUSS_TOL = 2e-6        # standard normals: |d| <= 2e-6 * max(|g|, 1)
 BOUNDARY = 2e-5         # rollouts within 2e-5 (relative) of a contact boundary are flagged
