@@ -6,7 +6,7 @@
  * Alg. 1, Sec. III) as slow scalar loops, in the paper's order, so that it
  * can be read against the equations.  No blocking, fusion or reordering.
  *
- * Readings where the paper is silent (each listed with the design notes):
+ * Readings where the paper is silent:
  *  - noise: Philox4x32-10 counter layout (block, rollout, step, stream) and
  *    Box-Muller on 24-bit uniforms; Sigma given as its Cholesky factor L;
  *  - controls are clamped to the bounds and the applied perturbation
