@@ -12,7 +12,10 @@
  *  - controls are clamped to the bounds and the applied perturbation
  *    (clamped control minus nominal) enters the update;
  *  - collisions are checked on the states j = 1..N against obstacles frozen
- *    at their current positions;
+ *    at their current positions, or, with the constant-velocity flag, moved
+ *    by j dt times each obstacle's own Eq. (17) velocity;
+ *  - the pose cost (flag) uses the geodesic angle between the end-effector
+ *    and goal orientations, and its contact term shares the collision test;
  *  - the reference point averages the colliding rollouts whose first hit is
  *    the obstacle closest to x_t, and all colliding rollouts if none is;
  *  - DBSCAN: closed eps-ball, minPts counts the point itself, a border
