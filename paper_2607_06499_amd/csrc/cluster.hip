@@ -404,13 +404,20 @@ __device__ __forceinline__ bool block_and(bool p, int* s_w) {
 }
 
 // 1. neighbour counts: for each row point, its neighbours among the block's
-// column points (closed ball, itself included), in sorted order.
-template <int P, int COLG = kColGroup, bool SORTED = false>
+// column points (closed ball, itself included), in sorted order.  With CS > 1,
+// CS threads share a row (thread = row + kTile * split), each taking 1/CS of
+// every column tile: more waves for the latency of the LDS loop when the
+// feasible set is small.
+template <int P, int COLG = kColGroup, bool SORTED = false, int CS = 1>
 __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
                                            const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
-  __shared__ int s_all[kTile / kWave];
+  constexpr int NT = kTile * CS, SPAN = kTile / CS;
+  __shared__ int s_all[NT / kWave];
   __shared__ ZT s_z[kTile];
+  __shared__ int s_part[CS][kTile];
+  const int r = CS > 1 ? (int)(threadIdx.x & (kTile - 1)) : (int)threadIdx.x;
+  const int q = CS > 1 ? (int)(threadIdx.x / kTile) : 0;
   const int V = dbscan_V(b, zin, Vin);
   const int nt = ntiles_of(V);
   const int I = by, J0 = bx * COLG;
@@ -423,17 +430,17 @@ __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, 
     if (!any) return;
   }
   const ZT* z = reinterpret_cast<const ZT*>(SORTED ? b.zs : (zin ? zin : b.z));
-  const int k = I * kTile + threadIdx.x;
+  const int k = I * kTile + r;
   const ZT zk = k < V ? z[k] : ZVec<P>::far();
   const int ok_k = SORTED ? (k < V ? b.sid[k] : 0) : k;
   ZT zl[COLG];
 #pragma unroll
   for (int u = 0; u < COLG; ++u) {
-    const int l = (J0 + u) * kTile + threadIdx.x;
-    zl[u] = (J0 + u < J1 && l < V) ? z[l] : ZVec<P>::far();
+    const int l = (J0 + u) * kTile + r;
+    zl[u] = (q == 0 && J0 + u < J1 && l < V) ? z[l] : ZVec<P>::far();
   }
   const float r2 = c.eps2;
-  int cnt = 0;
+  int cnt = 0;  // this split's count
 #pragma unroll
   for (int u = 0; u < COLG; ++u) {
     const int J = J0 + u;
@@ -441,18 +448,36 @@ __device__ __forceinline__ void count_body(const Cfg& c, const Bufs& b, int bx, 
     if (SORTED && tiles_apart(c, b, I, J)) continue;
     // only the core test needs the count: once every row of the block has
     // minPts neighbours in this chunk, the rest of the chunk cannot change it
-    if (block_and<kTile>(k >= V || cnt >= c.min_pts, s_all)) break;
-    s_z[threadIdx.x] = zl[u];
+    int tot = cnt;
+    if constexpr (CS > 1) {
+      s_part[q][r] = cnt;
+      __syncthreads();
+      tot = 0;
+#pragma unroll
+      for (int i = 0; i < CS; ++i) tot += s_part[i][r];
+    }
+    if (block_and<NT>(k >= V || tot >= c.min_pts, s_all)) break;
+    if (q == 0) s_z[r] = zl[u];
     __syncthreads();
     const int ncol = min(kTile, V - J * kTile);
-    for (int t = 0; t < ncol; ++t) cnt += ZVec<P>::d2(zk, s_z[t]) <= r2 ? 1 : 0;
+    const int t1 = CS > 1 ? min(ncol, (q + 1) * SPAN) : ncol;
+    for (int t = q * SPAN; t < t1; ++t) cnt += ZVec<P>::d2(zk, s_z[t]) <= r2 ? 1 : 0;
   }
-  if (k < V && cnt) atomicAdd(&b.ncount[ok_k], cnt);
+  if constexpr (CS > 1) {
+    s_part[q][r] = cnt;
+    __syncthreads();
+    if (q == 0) {
+      cnt = 0;
+#pragma unroll
+      for (int i = 0; i < CS; ++i) cnt += s_part[i][r];
+    }
+  }
+  if (q == 0 && k < V && cnt) atomicAdd(&b.ncount[ok_k], cnt);
 }
 
-template <int P>
-__global__ __launch_bounds__(kTile) void k_count(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
-  count_body<P, kCntGroup>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
+template <int P, int CS>
+__global__ __launch_bounds__(kTile * CS) void k_count(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  count_body<P, kCntGroup, false, CS>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
 }
 
 // 2. lowest-index core neighbour of every point (core points include
@@ -463,61 +488,84 @@ __global__ __launch_bounds__(kTile) void k_count(Cfg c, Bufs b, const float* __r
 // flags (one 64-bit word per wave), and every block flags the rows that have
 // a core neighbour of lower index: a core point without one is the root of
 // its hook tree.
-template <int P, int COLG = kColGroup>
+template <int P, int COLG = kColGroup, int CS = 1>
 __device__ __forceinline__ void mcn_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
                                          const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
-  __shared__ int s_all[kTile / kWave];
+  constexpr int NT = kTile * CS, SPAN = kTile / CS;
+  __shared__ int s_all[NT / kWave];
   __shared__ ZT s_z[kTile];
+  __shared__ int s_part[CS][kTile];
+  // CS threads share a row as in the count pass; the row's hit is the
+  // lowest of its splits' first hits
+  const int r = CS > 1 ? (int)(threadIdx.x & (kTile - 1)) : (int)threadIdx.x;
+  const int q = CS > 1 ? (int)(threadIdx.x / kTile) : 0;
   const int V = dbscan_V(b, zin, Vin);
   const int nt = ntiles_of(V);
   const int I = by, J0 = bx * COLG;
   if (I >= nt || J0 >= nt) return;
   const int J1 = min(J0 + COLG, nt);
   const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
-  const int k = I * kTile + threadIdx.x;
+  const int k = I * kTile + r;
   const ZT zk = k < V ? z[k] : ZVec<P>::far();
   const bool diag = J0 <= I && I < J1;
-  const int nck = (diag && k < V) ? b.ncount[k] : 0;
+  const int nck = (q == 0 && diag && k < V) ? b.ncount[k] : 0;
   ZT zl[COLG];
   int ncl[COLG];
 #pragma unroll
   for (int u = 0; u < COLG; ++u) {
-    const int l = (J0 + u) * kTile + threadIdx.x;
-    const bool ok = J0 + u < J1 && l < V;
+    const int l = (J0 + u) * kTile + r;
+    const bool ok = q == 0 && J0 + u < J1 && l < V;
     zl[u] = ok ? z[l] : ZVec<P>::far();
     ncl[u] = ok ? b.ncount[l] : 0;
   }
-  if (diag) {
+  if (diag && q == 0) {
     const unsigned long long cm = __ballot(k < V && nck >= c.min_pts);
     if ((threadIdx.x & (kWave - 1)) == 0 && k < V) b.coremask[k >> 6] = cm;
   }
   const float r2 = c.eps2;
-  int m = kInt32Max;
+  int m = kInt32Max;  // this split's first hit
+  // lowest hit of the row over its splits (a barrier when CS > 1: every
+  // thread calls it)
+  auto row_min = [&]() {
+    int mm = m;
+    if constexpr (CS > 1) {
+      s_part[q][r] = m;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < CS; ++i) mm = min(mm, s_part[i][r]);
+    }
+    return mm;
+  };
 #pragma unroll
   for (int u = 0; u < COLG; ++u) {
     const int J = J0 + u;
     if (J >= J1) break;
-    if (block_and<kTile>(k >= V || m != kInt32Max, s_all)) break;
+    const int mm = row_min();
+    if (block_and<NT>(k >= V || mm != kInt32Max, s_all)) break;
     // non-core columns are parked far away: they can never be a neighbour here
-    s_z[threadIdx.x] = ncl[u] >= c.min_pts ? zl[u] : ZVec<P>::far();
+    if (q == 0) s_z[r] = ncl[u] >= c.min_pts ? zl[u] : ZVec<P>::far();
     __syncthreads();
     if (m == kInt32Max) {
       const int ncol = min(kTile, V - J * kTile);
-      for (int t = 0; t < ncol; ++t) {
+      const int t1 = CS > 1 ? min(ncol, (q + 1) * SPAN) : ncol;
+      for (int t = q * SPAN; t < t1; ++t) {
         const bool h = ZVec<P>::d2(zk, s_z[t]) <= r2;
         m = (h && m == kInt32Max) ? J * kTile + t : m;
       }
     }
   }
-  if (k < V && m != kInt32Max) atomicMin(&b.mcn[k], m);
-  const unsigned long long hk = __ballot(k < V && m < k);
-  if (hk && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&b.hookmask[k >> 6], hk);
+  m = row_min();
+  if (q == 0) {
+    if (k < V && m != kInt32Max) atomicMin(&b.mcn[k], m);
+    const unsigned long long hk = __ballot(k < V && m < k);
+    if (hk && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&b.hookmask[k >> 6], hk);
+  }
 }
 
-template <int P>
-__global__ __launch_bounds__(kTile) void k_mcn(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
-  mcn_body<P, kCntGroup>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
+template <int P, int CS>
+__global__ __launch_bounds__(kTile * CS) void k_mcn(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  mcn_body<P, kCntGroup, CS>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
 }
 
 // 3. roots of the hook forest: each core point hooks to its lowest-index core
@@ -583,10 +631,14 @@ __device__ __forceinline__ bool adj_block_live(int I, int g, int nt) {
   return I < nt && J0 < nt && J0 + kColGroup > I;
 }
 
-template <int P, bool SORTED = false>
+template <int P, bool SORTED = false, int CS = 1>
 __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx,
                                               const float* __restrict__ zin, int Vin) {
   using ZT = typename ZVec<P>::T;
+  constexpr int NT = kTile * CS, SPAN = kTile / CS;
+  // CS threads share a row as in the count pass; split 0 stages the columns
+  const int r = CS > 1 ? (int)(threadIdx.x & (kTile - 1)) : (int)threadIdx.x;
+  const int q = CS > 1 ? (int)(threadIdx.x / kTile) : 0;
   __shared__ ZT s_z[kTile];
   __shared__ uint2 s_bit[kTile];  // tree bit of the column point as two words, 0 if not core
   __shared__ int s_woff[kMaxWords];
@@ -605,15 +657,15 @@ __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int b
   }
   // every operand of the block is requested before the first wait (sorted
   // positions first, then the per-point arrays at the original indices)
-  const int k = I * kTile + threadIdx.x;
+  const int k = I * kTile + r;
   const int idk = SORTED ? (k < V ? b.sid[k] : 0) : k;
   const ZT zk0 = k < V ? z[k] : ZVec<P>::far();
   int idl[kColGroup], ncl[kColGroup], rl[kColGroup];
   ZT zl[kColGroup];
 #pragma unroll
   for (int u = 0; u < kColGroup; ++u) {
-    const int l = (J0 + u) * kTile + threadIdx.x;
-    const bool ok = J0 + u < J1 && l < V;
+    const int l = (J0 + u) * kTile + r;
+    const bool ok = q == 0 && J0 + u < J1 && l < V;
     idl[u] = ok ? (SORTED ? b.sid[l] : l) : -1;
     zl[u] = ok ? z[l] : ZVec<P>::far();
   }
@@ -635,8 +687,8 @@ __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int b
   for (int u = 0; u < kColGroup; ++u) rl[u] = rt[u + 1];
   // the block whose columns hold the row tile records the tile's roots for
   // the closure and the labels
-  if (g * kColGroup <= I && I < g * kColGroup + kColGroup && k < V) b.root[idk] = rk;
-  const int R = tree_prefix<kTile>(b, V, s_woff, s_rm);
+  if (q == 0 && g * kColGroup <= I && I < g * kColGroup + kColGroup && k < V) b.root[idk] = rk;
+  const int R = tree_prefix<NT>(b, V, s_woff, s_rm);
   if (R < 2 || R > kMaxTrees) return;
   if (threadIdx.x < kMaxTrees) s_adj[threadIdx.x] = 0ull;
   const int tk = nck >= c.min_pts ? tree_id(s_rm, s_woff, rk) : -1;
@@ -650,15 +702,18 @@ __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int b
     if (SORTED && tiles_apart(c, b, I, J)) continue;
     const int tl = ncl[u] >= c.min_pts ? tree_id(s_rm, s_woff, rl[u]) : -1;
     __syncthreads();
-    s_z[threadIdx.x] = tl >= 0 ? zl[u] : ZVec<P>::far();
-    s_bit[threadIdx.x] = tl < 0 ? make_uint2(0u, 0u)
-                                : (tl < 32 ? make_uint2(1u << tl, 0u) : make_uint2(0u, 1u << (tl - 32)));
+    if (q == 0) {
+      s_z[r] = tl >= 0 ? zl[u] : ZVec<P>::far();
+      s_bit[r] = tl < 0 ? make_uint2(0u, 0u)
+                        : (tl < 32 ? make_uint2(1u << tl, 0u) : make_uint2(0u, 1u << (tl - 32)));
+    }
     __syncthreads();
     if (tk >= 0) {
       // branch-free: both LDS words are read for every column
       const int ncol = min(kTile, V - J * kTile);
+      const int t1 = CS > 1 ? min(ncol, (q + 1) * SPAN) : ncol;
 #pragma unroll 8
-      for (int t = 0; t < ncol; ++t) {
+      for (int t = q * SPAN; t < t1; ++t) {
         const uint2 bt = s_bit[t];
         const uint32_t h = ZVec<P>::d2(zk, s_z[t]) <= r2 ? 0xffffffffu : 0u;
         mlo |= bt.x & h;
@@ -676,9 +731,9 @@ __device__ __forceinline__ void tree_adj_body(const Cfg& c, const Bufs& b, int b
   if (threadIdx.x < R && s_adj[threadIdx.x]) atomicOr(&b.tadj[threadIdx.x], s_adj[threadIdx.x]);
 }
 
-template <int P>
-__global__ __launch_bounds__(kTile) void k_tree_adj(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
-  tree_adj_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
+template <int P, int CS>
+__global__ __launch_bounds__(kTile * CS) void k_tree_adj(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  tree_adj_body<P, false, CS>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
 }
 
 // 5. connected components of the tree graph and canonical cluster numbers
@@ -1449,10 +1504,22 @@ static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const floa
                             int ntile, int* lab_out, int* cnt_out, int* mout) {
   const int ngrp = (ntile + kColGroup - 1) / kColGroup;
   const int ncnt = (ntile + kCntGroup - 1) / kCntGroup;
-  dim3 tiles(ngrp, ntile), ctiles(ncnt, ntile), tb(kTile);
-  L(k_count<P>, ctiles, tb, c, b, zin, Vin);
-  L(k_mcn<P>, ctiles, tb, c, b, zin, Vin);
-  L(k_tree_adj<P>, tiles, tb, c, b, zin, Vin);
+  dim3 tiles(ngrp, ntile), ctiles(ncnt, ntile);
+  // planners of at most kSplitTiles tiles (K <= 4096) split every row over
+  // kSplit threads: their few blocks would otherwise leave the loop latency
+  // exposed; larger ones launch enough blocks, and more threads would cost
+  // the branches that skip the passes
+  if (c.ntile <= kSplitTiles) {
+    const dim3 tb(kTile * kSplit);
+    L(k_count<P, kSplit>, ctiles, tb, c, b, zin, Vin);
+    L(k_mcn<P, kSplit>, ctiles, tb, c, b, zin, Vin);
+    L(k_tree_adj<P, kSplit>, tiles, tb, c, b, zin, Vin);
+  } else {
+    const dim3 tb(kTile);
+    L(k_count<P, 1>, ctiles, tb, c, b, zin, Vin);
+    L(k_mcn<P, 1>, ctiles, tb, c, b, zin, Vin);
+    L(k_tree_adj<P, 1>, tiles, tb, c, b, zin, Vin);
+  }
   L(k_tree_cc<P>, dim3(1), dim3(kFinThreads), c, b, zin, Vin, mout, lab_out, cnt_out);
 }
 

@@ -42,6 +42,8 @@ static_assert(kMaxNM <= kFinThreads, "the final combination holds one element pe
 constexpr int kMaxTrees = 64;
 constexpr int kColGroup = 2;   // column tiles per tree-adjacency block
 constexpr int kCntGroup = 2;   // column tiles per count / core-neighbour block (early exit)
+constexpr int kSplit = 4;       // threads per row in the tiled passes of small single planners
+constexpr int kSplitTiles = 32; // planners of at most this many tiles use them
 constexpr int kSortBins = 4096; // Morton cells of the DBSCAN spatial order
 constexpr int kLabBatch = 8;   // points per thread per labelling pass
 constexpr int kRecBatch = 4;   // partial records per thread in flight at once
