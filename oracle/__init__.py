@@ -21,6 +21,8 @@ from .oracle import (  # noqa: F401
     rot_quat,
     quat_angle,
     closest_obstacle,
+    closest_obstacle_margin,
+    select_cluster,
     obstacle_velocity,
     dbscan,
     weighted_update,

@@ -292,39 +292,6 @@ double orc_quat_angle(const double a[4], const double b[4]) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Single-precision decisions                                         */
-/* ------------------------------------------------------------------ */
-
-/* Squared distance of two points in single precision:
- * d_i = fl(a_i - b_i), s = fma(d_{p-1}, d_{p-1}, ... fma(d_1, d_1, d_0*d_0)). */
-static float dec32_dist2(const double* a, const double* b, int32_t p) {
-  float d0 = (float)a[0] - (float)b[0];
-  float s = d0 * d0;
-  for (int32_t i = 1; i < p; ++i) {
-    float di = (float)a[i] - (float)b[i];
-    s = fmaf(di, di, s);
-  }
-  return s;
-}
-
-/* DBSCAN neighbourhood predicate: squared distance <= fl(eps*eps). */
-int32_t dec32_within(const double* a, const double* b, int32_t p, float r2) {
-  return dec32_dist2(a, b, p) <= r2 ? 1 : 0;
-}
-
-/* Contact predicate between a point (or sphere centre) with radius ra and an
- * obstacle with radius rb: squared distance <= fl(fl(ra + rb)^2). */
-static int32_t dec32_contact(const double* a, const double* b, int32_t p, double ra, double rb) {
-  float R = (float)ra + (float)rb;
-  return dec32_dist2(a, b, p) <= R * R ? 1 : 0;
-}
-
-/* Surface clearance used to find the closest obstacle: fl(sqrt(d2)) - r. */
-static float dec32_clearance(const double* a, const double* b, int32_t p, double rb) {
-  return sqrtf(dec32_dist2(a, b, p)) - (float)rb;
-}
-
-/* ------------------------------------------------------------------ */
 /* Cost terms, Eq. (5) with the instances of Sec. III                  */
 /* ------------------------------------------------------------------ */
 
@@ -421,10 +388,10 @@ static int32_t state_contact(const orc_problem* P, const double* x, const double
         o[1] += tj * vel[2 * i + 1];
       }
       double R = P->robot_radius + obs[3 * i + 2];
-      double d = sqrt(sqdist(x, o, 2));
-      double c = fabs(d - R) / (R > 0.0 ? R : 1.0);
+      double d2 = sqdist(x, o, 2);
+      double c = fabs(sqrt(d2) - R) / (R > 0.0 ? R : 1.0);
       if (c < *clear) *clear = c;
-      if (hit < 0 && dec32_contact(x, o, 2, P->robot_radius, obs[3 * i + 2])) hit = i;
+      if (hit < 0 && d2 <= R * R) hit = i;
     }
   } else {
     double org[7][3];
@@ -437,10 +404,10 @@ static int32_t state_contact(const orc_problem* P, const double* x, const double
         for (int c = 0; c < 3; ++c) o[c] += tj * vel[3 * i + c];
       for (int32_t s = 0; s < P->n_link_spheres; ++s) {
         double R = P->link_sphere_radius + obs[4 * i + 3];
-        double d = sqrt(sqdist(cen + 3 * s, o, 3));
-        double c = fabs(d - R) / (R > 0.0 ? R : 1.0);
+        double d2 = sqdist(cen + 3 * s, o, 3);
+        double c = fabs(sqrt(d2) - R) / (R > 0.0 ? R : 1.0);
         if (c < *clear) *clear = c;
-        if (hit < 0 && dec32_contact(cen + 3 * s, o, 3, P->link_sphere_radius, obs[4 * i + 3])) hit = i;
+        if (hit < 0 && d2 <= R * R) hit = i;
       }
     }
   }
@@ -507,38 +474,47 @@ void orc_simulate(const orc_problem* P, const double* x0, const double* ut, cons
                       clearance);
 }
 
+/* Surface clearance of obstacle i from the robot at x0: distance to the
+ * centre minus the obstacle radius (for the arm, the minimum over the link
+ * spheres of the distance to their centres). */
+static double clearance_of(const orc_problem* P, const double* x0, const double* obs, int32_t i) {
+  if (P->dynamics == ORC_UNICYCLE) return sqrt(sqdist(x0, obs + 3 * i, 2)) - obs[3 * i + 2];
+  double org[7][3];
+  double cen[3 * 64];
+  orc_arm_frames(x0, P->dh, org, NULL);
+  orc_arm_spheres(org, P->n_link_spheres, cen);
+  double ci = INFINITY;
+  for (int32_t s = 0; s < P->n_link_spheres; ++s) {
+    double c = sqrt(sqdist(cen + 3 * s, obs + 4 * i, 3)) - obs[4 * i + 3];
+    if (c < ci) ci = c;
+  }
+  return ci;
+}
+
 /* Closest obstacle o* to the current robot (the reference obstacle of
  * Sec. I and Sec. II-B.2): smallest surface clearance, ties to the lowest
- * index; for the arm the clearance is the minimum over link spheres. */
-int32_t orc_closest_obstacle(const orc_problem* P, const double* x0, const double* obs, int32_t n_obs) {
+ * index.  *margin (may be NULL) receives the second-smallest clearance minus
+ * the smallest (INFINITY with fewer than two obstacles). */
+int32_t orc_closest_obstacle_margin(const orc_problem* P, const double* x0, const double* obs,
+                                    int32_t n_obs, double* margin) {
   int32_t best = -1;
-  float bestc = INFINITY;
-  if (P->dynamics == ORC_UNICYCLE) {
-    for (int32_t i = 0; i < n_obs; ++i) {
-      float c = dec32_clearance(x0, obs + 3 * i, 2, obs[3 * i + 2]);
-      if (best < 0 || c < bestc) {
-        best = i;
-        bestc = c;
-      }
-    }
-  } else {
-    double org[7][3];
-    double cen[3 * 64];
-    orc_arm_frames(x0, P->dh, org, NULL);
-    orc_arm_spheres(org, P->n_link_spheres, cen);
-    for (int32_t i = 0; i < n_obs; ++i) {
-      float ci = INFINITY;
-      for (int32_t s = 0; s < P->n_link_spheres; ++s) {
-        float c = dec32_clearance(cen + 3 * s, obs + 4 * i, 3, obs[4 * i + 3]);
-        if (c < ci) ci = c;
-      }
-      if (best < 0 || ci < bestc) {
-        best = i;
-        bestc = ci;
-      }
+  double bestc = INFINITY, second = INFINITY;
+  for (int32_t i = 0; i < n_obs; ++i) {
+    double c = clearance_of(P, x0, obs, i);
+    if (best < 0 || c < bestc) {
+      second = bestc;
+      best = i;
+      bestc = c;
+    } else if (c < second) {
+      second = c;
     }
   }
+  if (margin) *margin = n_obs > 1 ? second - bestc : INFINITY;
   return best;
+}
+
+int32_t orc_closest_obstacle(const orc_problem* P, const double* x0, const double* obs, int32_t n_obs) {
+  return orc_closest_obstacle_margin(P, x0, obs, n_obs, NULL);
 }
 
 /* Obstacle velocity, Sec. II-B.3, Eq. (17): the mean of the H'-1 finite
@@ -567,13 +543,16 @@ void orc_obstacle_velocity(const double* hist, int32_t h_avail, int32_t n_obs, i
  * whose lowest core index is the c-th smallest; a non-core point with a
  * core neighbour joins the cluster of its lowest-index core neighbour;
  * everything else is noise (-1).  Returns the number of clusters. */
+static int32_t within(const double* a, const double* b, int32_t p, double r2) {
+  return sqdist(a, b, p) <= r2 ? 1 : 0;
+}
+
 int32_t orc_dbscan(const double* z, int32_t V, int32_t p, double eps, int32_t min_pts,
                    int32_t* ncount, int32_t* core, int32_t* label) {
-  float e = (float)eps;
-  float r2 = e * e;
+  const double r2 = eps * eps;
   for (int32_t k = 0; k < V; ++k) {
     int32_t c = 0;
-    for (int32_t l = 0; l < V; ++l) c += dec32_within(z + (size_t)k * p, z + (size_t)l * p, p, r2);
+    for (int32_t l = 0; l < V; ++l) c += within(z + (size_t)k * p, z + (size_t)l * p, p, r2);
     ncount[k] = c;
     core[k] = c >= min_pts ? 1 : 0;
     label[k] = -1;
@@ -588,7 +567,7 @@ int32_t orc_dbscan(const double* z, int32_t V, int32_t p, double eps, int32_t mi
     while (head < tail) {
       int32_t a = queue[head++];
       for (int32_t l = 0; l < V; ++l) {
-        if (core[l] && label[l] < 0 && dec32_within(z + (size_t)a * p, z + (size_t)l * p, p, r2)) {
+        if (core[l] && label[l] < 0 && within(z + (size_t)a * p, z + (size_t)l * p, p, r2)) {
           label[l] = M;
           queue[tail++] = l;
         }
@@ -600,7 +579,7 @@ int32_t orc_dbscan(const double* z, int32_t V, int32_t p, double eps, int32_t mi
   for (int32_t k = 0; k < V; ++k) {
     if (core[k]) continue;
     for (int32_t l = 0; l < V; ++l) {
-      if (core[l] && dec32_within(z + (size_t)k * p, z + (size_t)l * p, p, r2)) {
+      if (core[l] && within(z + (size_t)k * p, z + (size_t)l * p, p, r2)) {
         label[k] = label[l];
         break;
       }
@@ -640,6 +619,100 @@ void orc_weighted_update(int32_t n_set, const int32_t* set, const double* S, con
 }
 
 /* ------------------------------------------------------------------ */
+/* Cluster statistics and selection, Alg. 1 [Cluster stats] and        */
+/* [Selection], Eq. (14)-(18)                                          */
+/* ------------------------------------------------------------------ */
+
+/* On the labels of the nV feasible rollouts (0..M-1, -1 noise; M >= 1) with
+ * their costs S_v and unit terminal displacements g ([nV][p], Eq. (15)):
+ * per cluster the size, the mean cost (Alg. 1) and the normalised mean
+ * direction (Eq. (16)); then the cluster of minimum mean cost (Eq. (14)), or,
+ * in a dynamic scene whose closest obstacle has a usable velocity estimate
+ * (Eq. (17)), the cluster whose direction has the smallest dot product with
+ * the obstacle's normalised velocity (Eq. (18)).  Ties go to the lowest
+ * label.  Fills the cluster arrays, selected, selected_size, rule, h_used,
+ * margin, v_obs, v_obs_hat and the DYN_STATIC status bit of *out; returns the
+ * selected label. */
+int32_t orc_select_cluster(const orc_problem* P, int32_t nV, const int32_t* lab, int32_t M,
+                           const double* S_v, const double* g, const double* hist, int32_t h_avail,
+                           int32_t n_obs, int32_t closest, orc_out* out) {
+  int32_t n, m, p;
+  orc_dims(P->dynamics, &n, &m, &p);
+  double* mc = (double*)calloc((size_t)M, sizeof(double));
+  double* vd = (double*)calloc((size_t)M * 3, sizeof(double));
+  int32_t* sz = (int32_t*)calloc((size_t)M, sizeof(int32_t));
+  for (int32_t a = 0; a < nV; ++a) {
+    int32_t c = lab[a];
+    if (c < 0) continue;
+    mc[c] += S_v[a];
+    for (int32_t i = 0; i < p; ++i) vd[(size_t)c * 3 + i] += g[(size_t)a * p + i];
+    sz[c] += 1;
+  }
+  for (int32_t c = 0; c < M; ++c) {
+    mc[c] /= (double)sz[c];
+    double nv = 0.0;
+    for (int32_t i = 0; i < p; ++i) {
+      vd[(size_t)c * 3 + i] /= (double)sz[c];
+      nv += vd[(size_t)c * 3 + i] * vd[(size_t)c * 3 + i];
+    }
+    nv = sqrt(nv);
+    for (int32_t i = 0; i < p; ++i) vd[(size_t)c * 3 + i] /= (nv + P->norm_eps);
+  }
+
+  int32_t rule = ORC_STATIC;
+  double vhat[3] = {0.0, 0.0, 0.0};
+  if (P->scene_mode == ORC_DYNAMIC) {
+    int32_t Hp = h_avail < P->history_len ? h_avail : P->history_len;
+    out->h_used = Hp;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (closest >= 0)
+      orc_obstacle_velocity(hist, h_avail, n_obs, p, closest, P->history_len, P->dt, v);
+    double nv = 0.0;
+    for (int32_t i = 0; i < p; ++i) nv += v[i] * v[i];
+    nv = sqrt(nv);
+    for (int32_t i = 0; i < p; ++i) {
+      out->v_obs[i] = v[i];
+      vhat[i] = v[i] / (nv + P->norm_eps);
+      out->v_obs_hat[i] = vhat[i];
+    }
+    if (Hp >= 2 && closest >= 0 && !(nv < P->v_obs_min)) rule = ORC_DYNAMIC;
+    else out->status |= ORC_ST_DYN_STATIC;
+  }
+  out->rule = rule;
+  int32_t best = 0;
+  double kbest = INFINITY, second = INFINITY;
+  for (int32_t c = 0; c < M; ++c) {
+    double key = 0.0;
+    if (rule == ORC_STATIC) {
+      key = mc[c];
+    } else {
+      for (int32_t i = 0; i < p; ++i) key += vd[(size_t)c * 3 + i] * vhat[i];
+    }
+    if (c == 0 || key < kbest) {
+      if (c > 0) second = kbest;
+      kbest = key;
+      best = c;
+    } else if (key < second) {
+      second = key;
+    }
+  }
+  out->margin = M > 1 ? second - kbest : INFINITY;
+  out->selected = best;
+  out->selected_size = sz[best];
+  int32_t cap = out->c_cap < M ? out->c_cap : M;
+  for (int32_t c = 0; c < cap; ++c) {
+    if (out->c_mean_cost) out->c_mean_cost[c] = mc[c];
+    if (out->c_size) out->c_size[c] = sz[c];
+    if (out->c_dir)
+      for (int32_t i = 0; i < p; ++i) out->c_dir[(size_t)c * p + i] = vd[(size_t)c * 3 + i];
+  }
+  free(mc);
+  free(vd);
+  free(sz);
+  return best;
+}
+
+/* ------------------------------------------------------------------ */
 /* Alg. 1                                                              */
 /* ------------------------------------------------------------------ */
 
@@ -668,7 +741,12 @@ static void post_rollouts(const orc_problem* P, const double* x_t, const double*
   }
   out->n_col = nC;
   out->n_feas = nV;
-  out->closest = orc_closest_obstacle(P, x_t, obs, n_obs);
+  {
+    double cm = INFINITY;
+    int32_t c = orc_closest_obstacle_margin(P, x_t, obs, n_obs, &cm);
+    out->closest_margin = cm;
+    out->closest = out->closest_force >= -1 ? out->closest_force : c;
+  }
 
   int32_t* set = (int32_t*)malloc(sizeof(int32_t) * (size_t)K);
   int32_t n_set = 0;
@@ -739,80 +817,12 @@ static void post_rollouts(const orc_problem* P, const double* x_t, const double*
       out->status |= ORC_ST_NO_CLUSTER;
       for (int32_t a = 0; a < nV; ++a) set[n_set++] = Vi[a];
     } else {
-      /* [Cluster stats] mean cost (Alg. 1) and mean direction, Eq. (16) */
-      double* mc = (double*)calloc((size_t)M, sizeof(double));
-      double* vd = (double*)calloc((size_t)M * 3, sizeof(double));
-      int32_t* sz = (int32_t*)calloc((size_t)M, sizeof(int32_t));
-      for (int32_t a = 0; a < nV; ++a) {
-        int32_t c = lab[a];
-        if (c < 0) continue;
-        mc[c] += S[Vi[a]];
-        for (int32_t i = 0; i < p; ++i) vd[(size_t)c * 3 + i] += g[(size_t)a * p + i];
-        sz[c] += 1;
-      }
-      for (int32_t c = 0; c < M; ++c) {
-        mc[c] /= (double)sz[c];
-        double nv = 0.0;
-        for (int32_t i = 0; i < p; ++i) {
-          vd[(size_t)c * 3 + i] /= (double)sz[c];
-          nv += vd[(size_t)c * 3 + i] * vd[(size_t)c * 3 + i];
-        }
-        nv = sqrt(nv);
-        for (int32_t i = 0; i < p; ++i) vd[(size_t)c * 3 + i] /= (nv + P->norm_eps);
-      }
-
-      /* [Selection] static: Eq. (14); dynamic: Eq. (17)-(18) */
-      int32_t rule = ORC_STATIC;
-      double vhat[3] = {0.0, 0.0, 0.0};
-      if (P->scene_mode == ORC_DYNAMIC) {
-        int32_t Hp = h_avail < P->history_len ? h_avail : P->history_len;
-        out->h_used = Hp;
-        double v[3];
-        orc_obstacle_velocity(hist, h_avail, n_obs, p, out->closest, P->history_len, P->dt, v);
-        double nv = 0.0;
-        for (int32_t i = 0; i < p; ++i) nv += v[i] * v[i];
-        nv = sqrt(nv);
-        for (int32_t i = 0; i < p; ++i) {
-          out->v_obs[i] = v[i];
-          vhat[i] = v[i] / (nv + P->norm_eps);
-          out->v_obs_hat[i] = vhat[i];
-        }
-        if (Hp >= 2 && !((float)nv < (float)P->v_obs_min)) rule = ORC_DYNAMIC;
-        else out->status |= ORC_ST_DYN_STATIC;
-      }
-      out->rule = rule;
-      double* key = (double*)malloc(sizeof(double) * (size_t)M);
-      for (int32_t c = 0; c < M; ++c) {
-        if (rule == ORC_STATIC) {
-          key[c] = mc[c];
-        } else {
-          double dot = 0.0;
-          for (int32_t i = 0; i < p; ++i) dot += vd[(size_t)c * 3 + i] * vhat[i];
-          key[c] = dot;
-        }
-      }
-      int32_t best = 0;
-      for (int32_t c = 1; c < M; ++c)
-        if ((float)key[c] < (float)key[best]) best = c;
-      double second = INFINITY;
-      for (int32_t c = 0; c < M; ++c)
-        if (c != best && key[c] < second) second = key[c];
-      out->margin = M > 1 ? second - key[best] : INFINITY;
-      out->selected = best;
-      out->selected_size = sz[best];
+      double* Sv = (double*)malloc(sizeof(double) * (size_t)nV);
+      for (int32_t a = 0; a < nV; ++a) Sv[a] = S[Vi[a]];
+      int32_t best = orc_select_cluster(P, nV, lab, M, Sv, g, hist, h_avail, n_obs, out->closest, out);
+      free(Sv);
       for (int32_t a = 0; a < nV; ++a)
         if (lab[a] == best) set[n_set++] = Vi[a];
-      int32_t cap = out->c_cap < M ? out->c_cap : M;
-      for (int32_t c = 0; c < cap; ++c) {
-        if (out->c_mean_cost) out->c_mean_cost[c] = mc[c];
-        if (out->c_size) out->c_size[c] = sz[c];
-        if (out->c_dir)
-          for (int32_t i = 0; i < p; ++i) out->c_dir[(size_t)c * p + i] = vd[(size_t)c * 3 + i];
-      }
-      free(key);
-      free(mc);
-      free(vd);
-      free(sz);
     }
   }
 
@@ -858,6 +868,7 @@ static void init_out(orc_out* out) {
   out->h_used = 0;
   out->status = 0;
   out->margin = INFINITY;
+  out->closest_margin = INFINITY;
   out->s_min = 0.0;
   for (int i = 0; i < 3; ++i) out->ref_point[i] = out->v_obs[i] = out->v_obs_hat[i] = 0.0;
 }

@@ -9,13 +9,15 @@
  * calls it, and it shares no code, header, table or helper with the GPU
  * library.
  *
- * Precision.  Every value is computed in double precision.  The only
- * exceptions are the points where a floating-point comparison decides an
- * integer result (collision flag, DBSCAN neighbourhood, closest obstacle,
- * the two cluster argmins, the dynamic-rule threshold): there the oracle
- * takes the decision in single precision with a fixed operation order
- * (helpers named dec32_*), the precision of the GPU kernels, so that both
- * sides decide identically whenever their operands agree.
+ * Precision.  Every value and every decision is computed in double
+ * precision from the single-precision parameters promoted exactly: the
+ * collision flag (squared distance against the squared sum of radii), the
+ * DBSCAN neighbourhood (squared distance against eps squared), the closest
+ * obstacle, the dynamic-rule threshold and the two cluster argmins.  A
+ * single-precision implementation can decide differently only where the
+ * compared quantities lie within its rounding of each other; the oracle
+ * reports the quantities that let a caller find those cases (boundary
+ * clearance per rollout, the closest-obstacle margin, the selection margin).
  *
  * Layouts are row-major and dense.  All arrays are owned by the caller.
  */
@@ -113,6 +115,8 @@ typedef struct orc_out {
   double* c_mean_cost; /* [c_cap]    mean cost per cluster                        */
   double* c_dir;       /* [c_cap][p] normalised mean direction, Eq. (16)          */
   int32_t* c_size;     /* [c_cap]                                                 */
+  int32_t closest_force; /* in: -2 computes o*; -1 or an obstacle index is taken as o*
+                            (resolves a near tie the way another implementation did)  */
   double* weight;      /* [K]        normalised update weight of each rollout     */
   double* U_new;       /* [N][m]     updated nominal sequence                     */
   double* U_next;      /* [N][m]     shifted warm start for the next replan       */
@@ -122,6 +126,7 @@ typedef struct orc_out {
   int32_t closest, rule, h_used;
   uint32_t status;
   double margin;
+  double closest_margin; /* second-smallest minus smallest surface clearance at x_t */
   double ref_point[3];
   double v_obs[3];
   double v_obs_hat[3];
@@ -163,12 +168,22 @@ void orc_simulate_moving(const orc_problem* P, const double* x0, const double* u
                          double* p_first, double* clearance);
 
 int32_t orc_closest_obstacle(const orc_problem* P, const double* x0, const double* obs, int32_t n_obs);
+int32_t orc_closest_obstacle_margin(const orc_problem* P, const double* x0, const double* obs,
+                                    int32_t n_obs, double* margin);
 void orc_obstacle_velocity(const double* hist, int32_t h_avail, int32_t n_obs, int32_t p, int32_t idx,
                            int32_t H, double dt, double v[3]);
 
 int32_t orc_dbscan(const double* z, int32_t V, int32_t p, double eps, int32_t min_pts,
                    int32_t* ncount, int32_t* core, int32_t* label);
-int32_t dec32_within(const double* a, const double* b, int32_t p, float r2);
+
+/* Cluster statistics and selection (Alg. 1 [Cluster stats], [Selection],
+ * Eq. (14)-(18)) on given labels of the nV feasible rollouts (M >= 1
+ * clusters), their costs S_v [nV] and directions g [nV][p]; closest is o*.
+ * Writes the cluster arrays and the selection fields of *out (c_cap and the
+ * array pointers must be set); returns the selected label. */
+int32_t orc_select_cluster(const orc_problem* P, int32_t nV, const int32_t* label, int32_t M,
+                           const double* S_v, const double* g, const double* hist, int32_t h_avail,
+                           int32_t n_obs, int32_t closest, orc_out* out);
 
 void orc_weighted_update(int32_t n_set, const int32_t* set, const double* S, const double* eps_eff,
                          int32_t N, int32_t m, double lambda, const double* U, double* U_new,

@@ -84,6 +84,7 @@ class OrcOut(C.Structure):
         ("c_mean_cost", _p(C.c_double)),
         ("c_dir", _p(C.c_double)),
         ("c_size", _p(C.c_int32)),
+        ("closest_force", C.c_int32),
         ("weight", _p(C.c_double)),
         ("U_new", _p(C.c_double)),
         ("U_next", _p(C.c_double)),
@@ -100,6 +101,7 @@ class OrcOut(C.Structure):
         ("h_used", C.c_int32),
         ("status", C.c_uint32),
         ("margin", C.c_double),
+        ("closest_margin", C.c_double),
         ("ref_point", C.c_double * 3),
         ("v_obs", C.c_double * 3),
         ("v_obs_hat", C.c_double * 3),
@@ -153,6 +155,14 @@ def load():
     lib.orc_quat_angle.restype = C.c_double
     lib.orc_closest_obstacle.argtypes = [_p(OrcProblem), _f64p, _f64p, C.c_int32]
     lib.orc_closest_obstacle.restype = C.c_int32
+    lib.orc_closest_obstacle_margin.argtypes = [_p(OrcProblem), _f64p, _f64p, C.c_int32,
+                                                _p(C.c_double)]
+    lib.orc_closest_obstacle_margin.restype = C.c_int32
+    lib.orc_select_cluster.argtypes = [
+        _p(OrcProblem), C.c_int32, _i32p, C.c_int32, _f64p, _f64p, _f64p, C.c_int32, C.c_int32,
+        C.c_int32, _p(OrcOut),
+    ]
+    lib.orc_select_cluster.restype = C.c_int32
     lib.orc_obstacle_velocity.argtypes = [
         _f64p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, _f64p,
     ]
@@ -339,6 +349,53 @@ def closest_obstacle(spec, x0, obs) -> int:
                                        obs.shape[0])
 
 
+def closest_obstacle_margin(spec, x0, obs):
+    """(o*, second-smallest minus smallest surface clearance)."""
+    P = make_problem(spec)
+    _, _, p = dims(P.dynamics)
+    obs = _f64(obs).reshape(-1, p + 1)
+    mg = C.c_double()
+    i = load().orc_closest_obstacle_margin(C.byref(P), _f64(x0),
+                                           np.ascontiguousarray(obs.ravel()) if obs.size else np.zeros(1),
+                                           obs.shape[0], C.byref(mg))
+    return i, mg.value
+
+
+def select_cluster(spec, labels, S_v, g, obs, hist=None, closest: int = 0, c_cap: int = 4096):
+    """Cluster statistics and selection on given labels of the feasible set
+    (S_v [V] costs, g [V][p] directions); obs/hist as in replan."""
+    lib = load()
+    P = make_problem(spec)
+    _, _, p = dims(P.dynamics)
+    lab = np.ascontiguousarray(np.asarray(labels, dtype=np.int32))
+    V = len(lab)
+    M = int(lab.max()) + 1 if V else 0
+    if M == 0:
+        raise ValueError("select_cluster needs at least one cluster")
+    obs = _f64(obs).reshape(-1, p + 1) if np.size(obs) else np.zeros((0, p + 1))
+    n_obs = obs.shape[0]
+    if hist is None:
+        hist = obs[None, :, :p]
+    hist = _f64(hist).reshape(-1, n_obs, p) if n_obs else np.zeros((1, 0, p))
+    r = dict(c_mean_cost=np.zeros(c_cap), c_dir=np.zeros((c_cap, p)), c_size=np.zeros(c_cap, np.int32))
+    o = OrcOut()
+    for name, arr in r.items():
+        setattr(o, name, _ptr(arr, C.c_int32 if arr.dtype == np.int32 else C.c_double))
+    o.c_cap = c_cap
+    o.status = 0
+    o.h_used = 0
+    o.margin = np.inf
+    sel = lib.orc_select_cluster(C.byref(P), V, lab, M, _f64(S_v), np.ascontiguousarray(_f64(g).ravel()),
+                                 np.ascontiguousarray(hist.ravel()) if hist.size else np.zeros(1),
+                                 hist.shape[0], n_obs, int(closest), C.byref(o))
+    for name in ("c_mean_cost", "c_dir", "c_size"):
+        r[name] = r[name][:min(M, c_cap)]
+    r.update(selected=sel, selected_size=o.selected_size, rule=o.rule, h_used=o.h_used,
+             status=o.status, margin=o.margin, n_clusters=M,
+             v_obs=np.array(o.v_obs[:p]), v_obs_hat=np.array(o.v_obs_hat[:p]))
+    return r
+
+
 def obstacle_velocity(hist, idx: int, H: int, dt: float) -> np.ndarray:
     """hist [h_avail][n_obs][p], newest first."""
     hist = _f64(hist)
@@ -377,11 +434,14 @@ def weighted_update(set_idx, S, eps_eff, lam, U):
 
 
 # ---------------------------------------------------------------- full replan
-def replan(spec, x_t, U, obs, hist=None, step: int = 0, c_cap: int = 4096, rollouts=None):
+def replan(spec, x_t, U, obs, hist=None, step: int = 0, c_cap: int = 4096, rollouts=None,
+           closest=None):
     """Run Alg. 1 once.  obs [n_obs][p+1]; hist [h_avail][n_obs][p] newest
     first (defaults to the current positions alone).  With ``rollouts`` (a
     dict of S, col, first_obs, p_term, p_first, eps_eff) the rollout stage is
-    skipped and those records are used.  Returns a dict."""
+    skipped and those records are used.  ``closest`` (an obstacle index, or
+    -1) replaces the computed o*, to resolve a near tie the way another
+    implementation did.  Returns a dict."""
     lib = load()
     P = make_problem(spec)
     n, m, p = dims(P.dynamics)
@@ -405,6 +465,7 @@ def replan(spec, x_t, U, obs, hist=None, step: int = 0, c_cap: int = 4096, rollo
         ct = C.c_int32 if arr.dtype == np.int32 else C.c_double
         setattr(o, name, _ptr(arr, ct))
     o.c_cap = c_cap
+    o.closest_force = -2 if closest is None else int(closest)
     obs_flat = np.ascontiguousarray(obs.ravel()) if n_obs else np.zeros(1)
     hist_flat = np.ascontiguousarray(hist.ravel()) if hist.size else np.zeros(1)
     if rollouts is None:
@@ -429,7 +490,7 @@ def replan(spec, x_t, U, obs, hist=None, step: int = 0, c_cap: int = 4096, rollo
     for name in ("c_mean_cost", "c_dir", "c_size"):
         r[name] = r[name][:min(M, c_cap)]
     for name in ("branch", "n_col", "n_feas", "n_ref", "n_clusters", "selected", "selected_size",
-                 "closest", "rule", "h_used", "status", "margin", "s_min"):
+                 "closest", "rule", "h_used", "status", "margin", "closest_margin", "s_min"):
         r[name] = getattr(o, name)
     r["ref_point"] = np.array(o.ref_point[:p])
     r["v_obs"] = np.array(o.v_obs[:p])

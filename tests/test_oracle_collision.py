@@ -10,8 +10,8 @@ def _spec(N=20, dt=0.1, robot_radius=0.0):
                          robot_radius=robot_radius).rounded()
 
 
-def _run(orc, obs, N=20, robot_radius=0.0, x0=(0.0, 0.0, 0.0), v=1.0):
-    spec = _spec(N, 0.1, robot_radius)
+def _run(orc, obs, N=20, robot_radius=0.0, x0=(0.0, 0.0, 0.0), v=1.0, dt=0.1):
+    spec = _spec(N, dt, robot_radius)
     return orc.simulate(spec, np.array(x0), np.tile([v, 0.0], (N, 1)),
                         np.asarray(obs, np.float32).reshape(-1, 3))
 
@@ -34,9 +34,13 @@ def test_first_contact_step_and_lowest_index(orc):
 
 def test_outside_tangent_inside(orc):
     assert _run(orc, [(0.5, 0.5, 0.3)])["col"] == 0            # min distance 0.5 > 0.3
-    # tangent at x_5 = 0.5: distance equals the radius -> contact (closed ball)
-    r = _run(orc, [(0.5, 0.3, 0.3)], N=8)
-    assert r["col"] == 1 and np.allclose(r["p_first"], [0.5, 0.0], atol=1e-6)
+    # tangent at x_4 = 0.5 (dt = 1/8: every position and radius is exact):
+    # distance equals the radius -> contact (closed ball); a radius one ulp
+    # smaller leaves the rollout free
+    r = _run(orc, [(0.5, 0.25, 0.25)], N=8, dt=0.125)
+    assert r["col"] == 1 and np.allclose(r["p_first"], [0.5, 0.0], atol=0.0)
+    r = _run(orc, [(0.5, 0.25, float(np.nextafter(np.float32(0.25), np.float32(0))))], N=8, dt=0.125)
+    assert r["col"] == 0
     # robot radius adds to the obstacle radius
     assert _run(orc, [(0.5, 0.5, 0.3)], robot_radius=0.25)["col"] == 1
     # the start state is not checked; the first state after it is
@@ -78,3 +82,29 @@ def test_arm_collision_against_link_spheres(orc):
     o = cen[3] + np.array([0.0, 0.0, 0.05 + 0.07 + 1e-3])
     r = orc.simulate(spec, x0, ut, np.array([[*o, 0.07]], np.float32))
     assert r["col"] == 0
+
+
+def test_closest_obstacle_margin(orc):
+    spec = _spec()
+    x0 = np.array([0.0, 0.0, 0.0])
+    # clearances 2.9, 0.5, 0.75, 3.8: o* = 1, margin 0.25
+    obs = np.array([(-3.0, 0.0, 0.1), (1.0, 0.0, 0.5), (0.0, 2.0, 1.25), (0.0, -4, 0.2)], np.float32)
+    i, mg = orc.closest_obstacle_margin(spec, x0, obs)
+    assert i == 1 and abs(mg - 0.25) < 1e-7
+    # an exact tie: margin 0, lowest index
+    obs = np.array([(0.0, 2.0, 1.5), (1.0, 0.0, 0.5)], np.float32)
+    i, mg = orc.closest_obstacle_margin(spec, x0, obs)
+    assert i == 0 and mg == 0.0
+    i, mg = orc.closest_obstacle_margin(spec, x0, obs[:1])
+    assert i == 0 and mg == np.inf
+
+
+def test_contact_decided_in_double_precision(orc):
+    # positions j/8 and the radii are exact: a gap of 1e-12 m separates contact
+    # from no contact (single precision would call both a contact)
+    spec = _spec(8, 0.125)
+    ut = np.tile([1.0, 0.0], (8, 1))
+    for dy, col in ((1e-12, 0), (-1e-12, 1), (0.0, 1)):
+        r = orc.simulate(spec, np.zeros(3), ut, np.array([[0.5, 0.25 + dy, 0.25]]))
+        assert r["col"] == col, dy
+        assert r["clearance"] < 1e-10

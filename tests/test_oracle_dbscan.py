@@ -124,3 +124,20 @@ def test_empty_and_degenerate(orc):
     assert M == 1 and np.all(lab == 0) and np.all(cnt == 5)
     lab, core, cnt, M = orc.dbscan(pts, 0.3, 6)
     assert M == 0 and np.all(lab == -1)
+
+
+def test_neighbourhood_decided_in_double_precision(orc):
+    # eps promoted from single precision; a pair at exactly eps is inside, a
+    # pair 1e-12 farther is outside (single precision could not separate them)
+    eps = float(np.float32(0.25))
+    pts = np.array([[0.0, 0.0], [eps, 0.0], [0.0, 3.0], [eps + 1e-12, 3.0]])
+    lab, core, cnt, M = orc.dbscan(pts, eps, 2)
+    assert list(cnt) == [2, 2, 1, 1]
+    assert list(lab) == [0, 0, -1, -1] and M == 1
+    # the same in three dimensions, along a diagonal: |d|^2 = 3 (eps/sqrt3)^2
+    d = eps / np.sqrt(3.0)
+    p3 = np.array([[0.0, 0.0, 0.0], [d, d, d], [5.0, 5.0, 5.0], [5.0 + d * (1 + 1e-9), 5.0 + d, 5.0 + d]])
+    _, _, cnt3, _ = orc.dbscan(p3, eps, 2)
+    inside = 3 * d * d <= eps * eps
+    assert list(cnt3[:2]) == ([2, 2] if inside else [1, 1])
+    assert list(cnt3[2:]) == [1, 1]
