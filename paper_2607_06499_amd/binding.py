@@ -330,9 +330,30 @@ class Planner:
         self.U_out = torch.zeros(self.N, self.m, dtype=torch.float32, device=dev)
         self.info_buf = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
 
+    @classmethod
+    def borrowed(cls, handle: int, spec, device: int = 0) -> "Planner":
+        """A view of a planner owned elsewhere (a server session): the same
+        calls, but close() leaves the planner alone."""
+        import torch
+
+        self = cls.__new__(cls)
+        self.spec = spec
+        self.device = torch.device("cuda", device)
+        self.cfg = config_from_spec(spec, device)
+        self.n, self.m, self.p = _dims(int(spec.dynamics))
+        self.N, self.K = int(spec.horizon), int(spec.num_samples)
+        self.handle = handle
+        self._borrowed = True
+        dev = self.device
+        self.u_out = torch.zeros(self.m, dtype=torch.float32, device=dev)
+        self.U_out = torch.zeros(self.N, self.m, dtype=torch.float32, device=dev)
+        self.info_buf = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+        return self
+
     def close(self):
         if getattr(self, "handle", None):
-            ce_mppi_destroy(self.handle)
+            if not getattr(self, "_borrowed", False):
+                ce_mppi_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -619,6 +640,13 @@ class Server:
                                                xs.ctypes.data, ob.ctypes.data, no.ctypes.data,
                                                lat.ctypes.data, u.ctypes.data))
         return lat, u
+
+    def session_planner(self, session: int, spec) -> "Planner":
+        """The planner of a session (owned by the server) as a Planner view."""
+        h = load().ce_mppi_server_session_planner(self.handle, int(session))
+        if not h:
+            raise CeMppiError("ce_mppi_server_session_planner", CE_EINVAL, "unknown session")
+        return Planner.borrowed(h, spec, self.device)
 
     def stats(self) -> dict:
         st = CeMppiServerStats()

@@ -304,6 +304,40 @@ def arm6_dynamic(seed: int = 1, num_samples: int = 4096) -> Scene:
     return Scene(spec, x0, np.zeros((32, 6), np.float32), ObstacleField(c, r, v, lo, hi), "arm6_dynamic")
 
 
+def unicycle_crossing(seed: int = 1, side: int = 1, num_samples: int = 2048, distance: float = 1.5,
+                      speed: float = 0.5) -> Scene:
+    """unicycle_static robot with a single obstacle (r = 0.3) `distance` m
+    straight ahead, crossing the path at `speed` m/s towards the robot's left
+    (side +1) or right (side -1); constant nominal (0.7, 0), dynamic rule with
+    H = 3.  The feasible rollouts pass on both sides, so DBSCAN finds two
+    clusters at some steps and Eq. (18) chooses between them."""
+    s = unicycle_static_ahead(seed, num_samples)
+    h = math.pi / 4
+    left = np.array([-math.sin(h), math.cos(h)])
+    s.field.c = (np.asarray(s.x0[:2], np.float64) + distance * np.array([math.cos(h), math.sin(h)]))[None]
+    s.field.r = np.array([0.3])
+    s.field.v = (side * speed * left)[None]
+    U0 = np.zeros_like(s.U0)
+    U0[:, 0] = 0.7
+    spec = s.spec.replace(scene_mode=DYNAMIC, history_len=3)
+    return Scene(spec, s.x0, U0, s.field, "unicycle_crossing")
+
+
+def arm6_dynamic_ahead(anchor, seed: int = 1, num_samples: int = 4096, gap: float = 0.03) -> Scene:
+    """arm6_dynamic with obstacle 0 (r = 0.08) placed `gap` m from a link
+    sphere of centre `anchor` (the caller's choice, e.g. the end-effector
+    sphere at the start pose) and moving into the arm at 0.1 m/s: a share of
+    the rollouts touch it, so Alg. 1 takes the clustering branch."""
+    s = arm6_dynamic(seed, num_samples)
+    n = np.array([1.0, 0.3, 0.2])
+    n /= np.linalg.norm(n)
+    r0 = 0.08
+    s.field.c[0] = np.asarray(anchor, np.float64) + (s.spec.link_sphere_radius + r0 + gap) * n
+    s.field.r[0] = r0
+    s.field.v[0] = -0.1 * n
+    return Scene(s.spec, s.x0, s.U0, s.field, "arm6_dynamic_ahead")
+
+
 # ---------------------------------------------------------------- paper presets
 def paper_unicycle_preset(scenario: int = 1, seed: int = 1) -> Scene:
     """Unicycle planner with the simulation parameters of Sec. III-A: K=300,

@@ -1,12 +1,15 @@
 """Batched form: every member of a batch gets bitwise the result of its own
 single-planner replan (same configuration, nominal, history and step), for
 members of uneven size and of every kind, over consecutive steps and under
-every tuning the autotuner may pick."""
+every tuning the autotuner may pick; and every member matches the FP64
+oracle's replan on its inputs, stage by stage."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2607_06499_amd import workloads as W
 from tests import harness as H
+from tests import test_gpu_parity as P
 
 pytestmark = pytest.mark.gpu
 
@@ -67,26 +70,57 @@ def _compare(B, batched, single, tag):
             assert torch.equal(a.debug(B.DBG_LABEL, V), b.debug(B.DBG_LABEL, V)), (tag, i)
 
 
-def test_batch_matches_single_replans():
+def test_batch_matches_single_replans_and_oracle():
     B, scenes, batched, single, xs, obs, batch = _setup()
+    host_obs = [np.asarray(sc.obstacles, np.float32).copy() for sc in scenes]
+    hists = [[] for _ in scenes]
+    Us = [np.asarray(sc.U0, np.float64) for sc in scenes]
     kinds = set()
+    summary = []
     for step, tune in enumerate(TUNINGS):
         if tune is not None:
             batch.set_tuning(*tune)
+        # every step starts from the oracle's nominal (both forms get it)
+        for i, (sc, a, b) in enumerate(zip(scenes, batched, single)):
+            U32 = np.float32(Us[i])
+            a.set_nominal(H.to_dev(U32))
+            b.set_nominal(H.to_dev(U32))
+            hists[i].insert(0, host_obs[i][:, : sc.spec.p].astype(np.float64))
+            hists[i] = hists[i][: sc.spec.history_len]
         batch.replan()
         for b, x, o in zip(single, xs, obs):
             b.replan(x, o)
         _compare(B, batched, single, f"step {step} tuning {tune}")
+        # each member against the oracle on the same inputs
+        for i, (sc, a) in enumerate(zip(scenes, batched)):
+            spec = sc.spec
+            U32 = np.float32(Us[i])
+            hs = np.array(hists[i]) if len(host_obs[i]) else None
+            r = H.collect_outputs(a)
+            o = oracle.replan(spec, sc.x0, U32, host_obs[i], hs, step=step)
+            bnd = P._compare_rollouts(r, o, spec)
+            o, nflip = P._resolve(spec, sc.x0, U32, host_obs[i], hs, step, o, r, bnd)
+            st = P._check_post(r, o, spec, U32, host_obs[i], hist=hs, tag=f"member {i} step {step}")
+            summary.append((i, step, st["branch"], st.get("V"), st.get("M")))
+            Us[i] = o["U_next"]
         kinds |= {a.info()["branch"] for a in batched}
         # the obstacles move between steps (in place: both forms read the same
         # tensors), so the constant-velocity members predict real motion
         H.torch_mod().cuda.synchronize()
-        for o in obs:
+        for o, ho in zip(obs, host_obs):
             if o is not None:
                 o[:, 0] += 0.02
                 o[:, 1] -= 0.01
+                ho[:, 0] += np.float32(0.02)
+                ho[:, 1] -= np.float32(0.01)
+        H.torch_mod().cuda.synchronize()
+        for o, ho in zip(obs, host_obs):
+            if o is not None:
+                assert np.array_equal(o.cpu().numpy(), ho)
+    print("member, step, branch, V, M:", summary)
     # the members exercised the clustering branch and a fallback branch
     assert 0 in kinds and len(kinds) >= 2
+    assert sum(1 for x in summary if x[2] == 0) >= 8
     batch.close()
 
 

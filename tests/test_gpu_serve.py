@@ -1,12 +1,15 @@
 """Served form: continuous batching over resident sessions.  Each request's
 result equals, bitwise, the result of replanning its session alone with the
-same sequence of requests; admission is bounded by device memory; the plain
-form launches one request at a time."""
+same sequence of requests, and matches the FP64 oracle stage by stage;
+admission is bounded by device memory; the plain form launches one request
+at a time."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2607_06499_amd import workloads as W
 from tests import harness as H
+from tests import test_gpu_parity as P
 
 pytestmark = pytest.mark.gpu
 
@@ -73,6 +76,51 @@ def test_mixed_results_equal_alone():
             torch.cuda.synchronize()
             assert np.array_equal(uu.cpu().numpy(), u[i, :m]), (k, int(i))
         pl.close()
+
+
+def test_served_requests_match_oracle():
+    """Rounds of one request per session, submitted together so that they
+    share launches; before each round every session's nominal is set to the
+    oracle's (lockstep).  Each request is compared with the oracle's replan
+    of its session through every stage (the session planner's buffers hold
+    that request's replan)."""
+    from paper_2607_06499_amd import binding as B
+
+    scenes = _scenes()[:9]
+    srv = B.Server(max_batch=16, max_inflight=3)
+    for s in scenes:
+        srv.open_session(s.spec, s.U0)
+    srv.start()
+    views = [srv.session_planner(i, s.spec) for i, s in enumerate(scenes)]
+    Us = [np.asarray(s.U0, np.float64) for s in scenes]
+    hists = [[] for _ in scenes]
+    torch = H.torch_mod()
+    branches = []
+    for rnd in range(3):
+        for i, (sc, v) in enumerate(zip(scenes, views)):
+            v.set_nominal(H.to_dev(np.float32(Us[i])))
+            hists[i].insert(0, np.asarray(sc.obstacles, np.float64)[:, : sc.spec.p])
+            hists[i] = hists[i][: sc.spec.history_len]
+        torch.cuda.synchronize()
+        tickets = [srv.submit(i, sc.x0, sc.obstacles) for i, sc in enumerate(scenes)]
+        res = [srv.wait(t, i) for i, t in enumerate(tickets)]
+        for i, (sc, v) in enumerate(zip(scenes, views)):
+            u, info, lat = res[i]
+            assert info["step"] == rnd and lat > 0.0
+            spec = sc.spec
+            U32 = np.float32(Us[i])
+            hs = np.array(hists[i])
+            r = H.collect_outputs(v, info=info, u_out=u[: spec.m])
+            o = oracle.replan(spec, sc.x0, U32, sc.obstacles, hs, step=rnd)
+            bnd = P._compare_rollouts(r, o, spec)
+            o, _ = P._resolve(spec, sc.x0, U32, sc.obstacles, hs, rnd, o, r, bnd)
+            st = P._check_post(r, o, spec, U32, sc.obstacles, hist=hs, tag=f"session {i} request {rnd}")
+            branches.append(st["branch"])
+            Us[i] = o["U_next"]
+    stats = srv.stats()
+    srv.close()
+    assert stats["served"] == 3 * len(scenes) and stats["mean_batch"] > 1.0, stats
+    assert 0 in branches, branches
 
 
 def test_admission_bounded_by_memory():
