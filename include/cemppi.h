@@ -259,6 +259,36 @@ ce_status ce_mppi_replan_from_rollouts(ce_mppi_planner* planner, const float* x_
 ce_status ce_mppi_stage_dbscan(ce_mppi_planner* planner, const float* z, int32_t V, int32_t* ncount,
                                int32_t* label, int32_t* n_clusters, void* stream);
 
+/* ---- allocation-free DBSCAN ----
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  It runs the
+ * kernels of ce_mppi_stage_dbscan (same conventions, same results bit for bit)
+ * without a planner: their per-point work arrays live in one file-scope
+ * device array of the library (about 530 KB per GPU, held until the process
+ * ends), so the call allocates nothing and calls no hipMalloc, hipFree or
+ * allocating library routine.  The first call on a device looks up that
+ * device's copy of the array (hipGetSymbolAddress).
+ *
+ *   device     HIP device ordinal; stream must belong to it
+ *   z          device, [V][p] features (float), p = 2 or 3
+ *   V          0..CE_MPPI_NOALLOC_MAX_POINTS; larger V is rejected (CE_EINVAL)
+ *   eps        neighbourhood radius (closed ball), finite and > 0
+ *   min_pts    minimum neighbourhood size, the point itself included, >= 1
+ *   ncount     device, [V] neighbour counts (exact below min_pts, between
+ *              min_pts and the exact count for core points), or NULL
+ *   label      device, [V] cluster label 0..M-1 (numbered by the lowest core
+ *              index), -1 noise
+ *   n_clusters device, one int32 (M), or NULL
+ * Asynchronous on stream.  Every call on a GPU shares that GPU's array and
+ * overwrites what the previous call left there: calls that overlap on one GPU
+ * (other streams or threads) race, so the caller must order them.  Errors:
+ * CE_EINVAL (sizes, parameters, NULL pointers, device ordinal), CE_EDEVICE. */
+#define CE_MPPI_NOALLOC_MAX_POINTS 16384
+ce_status ce_mppi_dbscan_noalloc(int32_t device, const float* z, int32_t V, int32_t p, float eps,
+                                 int32_t min_pts, int32_t* ncount, int32_t* label,
+                                 int32_t* n_clusters, void* stream);
+
 /* ---- launch mode and timing ---- */
 enum { CE_LAUNCH_GRAPH = 0, CE_LAUNCH_DIRECT = 1 };
 /* CE_LAUNCH_GRAPH (default): the first replan records the planner's kernel

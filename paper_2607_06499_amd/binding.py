@@ -16,6 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcemppi.so")
 
 ABI_VERSION = 1
+NOALLOC_MAX_POINTS = 16384
 CE_OK, CE_EINVAL, CE_ENOMEM, CE_EDEVICE, CE_EUNSUPPORTED, CE_EBUSY = range(6)
 DYN_UNICYCLE, DYN_ARM6 = 0, 1
 SCENE_STATIC, SCENE_DYNAMIC = 0, 1
@@ -181,6 +182,8 @@ def load():
         "ce_mppi_replan_from_rollouts": [_vp, _vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp,
                                          _vp, _vp, _vp, _vp],
         "ce_mppi_stage_dbscan": [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp],
+        "ce_mppi_dbscan_noalloc": [C.c_int32, _vp, C.c_int32, C.c_int32, C.c_float, C.c_int32, _vp, _vp,
+                                   _vp, _vp],
         "ce_mppi_set_launch_mode": [_vp, C.c_int32],
         "ce_mppi_tune_launch": [_vp, _vp, _vp, C.c_int32, _vp, C.c_int32, _vp,
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)],
@@ -495,6 +498,25 @@ class Planner:
         _check("ce_mppi_debug_get", load().ce_mppi_debug_get(self.handle, int(which), out.data_ptr(),
                                                               nbytes, _stream_handle(None)))
         return out[:count] if count else out[:0]
+
+
+def dbscan_noalloc(z, eps: float, min_pts: int, device: int = 0, stream=None):
+    """ce_mppi_dbscan_noalloc on a [V][p] float32 device tensor; returns
+    (label, ncount, n_clusters) device tensors (allocated here, by the caller
+    of the entry point)."""
+    import torch
+
+    z = z.contiguous()
+    V, p = int(z.shape[0]), int(z.shape[1])
+    dev = torch.device("cuda", device)
+    lab = torch.empty(V, dtype=torch.int32, device=dev)
+    cnt = torch.empty(V, dtype=torch.int32, device=dev)
+    M = torch.empty(1, dtype=torch.int32, device=dev)
+    _check("ce_mppi_dbscan_noalloc", load().ce_mppi_dbscan_noalloc(
+        int(device), z.data_ptr() if V else None, V, p, float(eps), int(min_pts),
+        cnt.data_ptr() if V else None, lab.data_ptr() if V else None, M.data_ptr(),
+        _stream_handle(stream)))
+    return lab, cnt, M
 
 
 class Batch:

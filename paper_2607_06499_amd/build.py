@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcemppi.so")
-SOURCES = ["rollout.hip", "cluster.hip", "capi.cpp", "batch.cpp", "server.cpp"]
+SOURCES = ["rollout.hip", "cluster.hip", "capi.cpp", "batch.cpp", "server.cpp", "noalloc.hip"]
 ARCH = os.environ.get("CEMPPI_OFFLOAD_ARCH", "gfx950")
 
 
