@@ -322,6 +322,14 @@ ce_status ce_mppi_timing_enable(ce_mppi_planner* planner, int32_t capacity);
 ce_status ce_mppi_timing_read(ce_mppi_planner* planner, double* rollout_ms, double* post_ms,
                               double* total_ms, int32_t* count);
 
+/* The same per timed replan, in order: host arrays of cap entries receive
+ * the rollout, post-rollout and total times (ms) of the first
+ * min(cap, count) timed replans; *count (may be NULL) receives the number of
+ * timed replans.  Waits for the events.  Errors: CE_EINVAL for NULL arrays
+ * with cap > 0 or cap < 0; CE_EDEVICE. */
+ce_status ce_mppi_timing_read_each(ce_mppi_planner* planner, int32_t cap, double* rollout_ms,
+                                   double* post_ms, double* total_ms, int32_t* count);
+
 /* Time the rollout phase alone: `reps` back-to-back launches of the rollout
  * kernel of a replan on (x_t, obstacles) between two HIP events on `stream`;
  * *ms_per_launch receives the mean time per launch.  Device pointers as in
@@ -422,14 +430,29 @@ ce_status ce_mppi_batch_autotune(ce_mppi_batch* batch, const ce_mppi_batch_io* i
  * launches running at once on their own streams.  Every request's result is
  * bitwise the one a plain ce_mppi_replan of its session would give for the
  * same sequence of requests.  Sessions are admitted while their device memory
- * (the planner arena) fits memory_budget. */
+ * (the planner arena) fits memory_budget; every buffer a request needs
+ * (staging, outputs) is allocated at start, so requests are admitted as
+ * launch slots free up, without allocating.
+ *
+ * A launch of one or two requests runs each through its session's own
+ * single-planner replan (ce_mppi_replan, in the launch mode ce_mppi_tune_launch
+ * picks for each session at start) instead of the batched chain: fewer
+ * kernels, the same results.
+ *
+ * CE_SERVE_PLAIN is the one-request-per-launch form for comparison: the
+ * scheduler serves one request at a time with ce_mppi_replan on the
+ * session's planner (the single-planner kernels, in the launch mode that
+ * ce_mppi_tune_launch picks for each session at start); max_batch and
+ * max_inflight must be 1. */
 typedef struct ce_mppi_server ce_mppi_server;
+
+enum { CE_SERVE_BATCHED = 0, CE_SERVE_PLAIN = 1 };
 
 typedef struct ce_mppi_server_config {
   int32_t device;
   int32_t max_batch;       /* requests per launch, 1..CE_MPPI_MAX_BATCH (1: one per launch) */
   int32_t max_inflight;    /* launches in flight, 1..3                                      */
-  int32_t reserved;        /* must be 0                                                     */
+  int32_t mode;            /* CE_SERVE_BATCHED (0) or CE_SERVE_PLAIN                        */
   uint64_t memory_budget;  /* device bytes the sessions may hold; 0: 90 % of free memory    */
 } ce_mppi_server_config;
 

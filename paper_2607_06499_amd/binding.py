@@ -26,6 +26,7 @@ BRANCH_CLUSTER, BRANCH_FALLBACK, BRANCH_ALL_COLLIDE = 0, 1, 2
 STATUS_FALLBACK, STATUS_ALL_COLLIDE, STATUS_NO_CLUSTER, STATUS_DYN_STATIC, STATUS_NONFINITE = (
     1, 2, 4, 8, 16)
 LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
+SERVE_BATCHED, SERVE_PLAIN = 0, 1
 (DBG_COST, DBG_COLLIDE, DBG_FIRST_OBS, DBG_P_TERM, DBG_P_FIRST, DBG_EPS, DBG_V_IDX, DBG_Z, DBG_G,
  DBG_NCOUNT, DBG_LABEL, DBG_CLUSTER_COST, DBG_CLUSTER_DIR, DBG_CLUSTER_SIZE, DBG_TREES) = range(15)
 
@@ -124,7 +125,7 @@ class CeMppiServerConfig(C.Structure):
         ("device", C.c_int32),
         ("max_batch", C.c_int32),
         ("max_inflight", C.c_int32),
-        ("reserved", C.c_int32),
+        ("mode", C.c_int32),
         ("memory_budget", C.c_uint64),
     ]
 
@@ -191,6 +192,7 @@ def load():
         "ce_mppi_timing_read": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_double), C.POINTER(C.c_int32)],
         "ce_mppi_time_rollout": [_vp, _vp, _vp, C.c_int32, C.c_int32, _vp, C.POINTER(C.c_double)],
+        "ce_mppi_timing_read_each": [_vp, C.c_int32, _vp, _vp, _vp, C.POINTER(C.c_int32)],
         "ce_mppi_batch_create": [C.POINTER(_vp), C.c_int32, C.POINTER(_vp)],
         "ce_mppi_batch_replan": [_vp, C.POINTER(CeMppiBatchIO), _vp],
         "ce_mppi_batch_replan_subset": [_vp, C.POINTER(C.c_int32), C.c_int32, C.POINTER(CeMppiBatchIO),
@@ -451,6 +453,18 @@ class Planner:
             self.handle, C.byref(r), C.byref(q), C.byref(a), C.byref(n)))
         return dict(rollout_ms=r.value, post_ms=q.value, total_ms=a.value, count=n.value)
 
+    def timing_read_each(self, cap: int):
+        """Per timed replan (rollout_ms, post_ms, total_ms) arrays."""
+        r = np.zeros(cap)
+        q = np.zeros(cap)
+        t = np.zeros(cap)
+        n = C.c_int32()
+        _check("ce_mppi_timing_read_each",
+               load().ce_mppi_timing_read_each(self.handle, int(cap), r.ctypes.data, q.ctypes.data,
+                                               t.ctypes.data, C.byref(n)))
+        k = min(cap, n.value)
+        return r[:k], q[:k], t[:k]
+
     def time_rollout(self, x_t, obstacles=None, reps: int = 100, stream=None) -> float:
         """Mean ms per launch of the rollout kernel alone (state restored)."""
         n_obs = 0 if obstacles is None else int(obstacles.shape[0])
@@ -604,8 +618,11 @@ class Server:
     (``ce_mppi_server_*``).  Inputs and outputs are host numpy arrays."""
 
     def __init__(self, device: int = 0, max_batch: int = 256, max_inflight: int = 3,
-                 memory_budget: int = 0):
-        cfg = CeMppiServerConfig(int(device), int(max_batch), int(max_inflight), 0, int(memory_budget))
+                 memory_budget: int = 0, mode: int = 0):
+        """mode: SERVE_BATCHED (continuous batching) or SERVE_PLAIN (one request
+        at a time through ce_mppi_replan; max_batch = max_inflight = 1)."""
+        cfg = CeMppiServerConfig(int(device), int(max_batch), int(max_inflight), int(mode),
+                                 int(memory_budget))
         h = _vp()
         _check("ce_mppi_server_create", load().ce_mppi_server_create(C.byref(cfg), C.byref(h)))
         self.handle = h.value

@@ -569,6 +569,29 @@ ce_status ce_mppi_timing_read(ce_mppi_planner* P, double* rollout_ms, double* po
   return CE_OK;
 }
 
+ce_status ce_mppi_timing_read_each(ce_mppi_planner* P, int32_t cap, double* rollout_ms,
+                                   double* post_ms, double* total_ms, int32_t* count) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  if (cap < 0 || (cap > 0 && (!rollout_ms || !post_ms || !total_ms)))
+    return fail(CE_EINVAL, "bad output arrays");
+  DeviceGuard guard(P->cfg.device);
+  const Timing& t = P->t;
+  const int n = t.n < cap ? t.n : cap;
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = hipEventSynchronize(t.ev[3 * i + 2]);
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&x, t.ev[3 * i], t.ev[3 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&y, t.ev[3 * i + 1], t.ev[3 * i + 2]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&z, t.ev[3 * i], t.ev[3 * i + 2]);
+    if (e != hipSuccess) return hip_fail(e, "timing_read_each");
+    rollout_ms[i] = x;
+    post_ms[i] = y;
+    total_ms[i] = z;
+  }
+  if (count) *count = t.n;
+  return CE_OK;
+}
+
 ce_status ce_mppi_time_rollout(ce_mppi_planner* P, const float* x_t, const float* obstacles,
                                int32_t n_obs, int32_t reps, void* stream, double* ms_per_launch) {
   if (!P || !x_t || !ms_per_launch) return fail(CE_EINVAL, "NULL argument");

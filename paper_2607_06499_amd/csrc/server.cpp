@@ -43,6 +43,11 @@ double seconds_since(Clock::time_point t0) {
 constexpr int kInStride = 12 + kMaxObs * 4;  // floats: state, then obstacle rows
 constexpr int kOutFloats = kMaxCtrl;         // u_out
 constexpr int kMaxInflight = 3;
+// Launches of at most this many requests run each request's own
+// single-planner replan (eight kernels, back to back on the launch stream)
+// instead of the batched chain, whose per-phase persistent kernels cost more
+// than they share at these sizes; both give the same bits.
+constexpr int kSingleMax = 2;
 
 struct Request {
   uint64_t ticket = 0;
@@ -144,8 +149,17 @@ hipError_t start_launch(ce_mppi_server* S, Launch& L, std::vector<Request*>& tak
   hipError_t e = hipMemcpyAsync(L.d_in, L.h_in, sizeof(float) * kInStride * count,
                                 hipMemcpyHostToDevice, L.stream);
   if (e != hipSuccess) return e;
-  if (ce_mppi_batch_replan_subset(S->batch, members.data(), count, io.data(), L.stream) != CE_OK)
+  if (S->cfg.mode == CE_SERVE_PLAIN || count <= kSingleMax) {
+    // each request through its session's own single-planner replan
+    for (int q = 0; q < count; ++q) {
+      const ce_mppi_batch_io& a = io[q];
+      if (ce_mppi_replan(S->sessions[members[q]], a.x_t, a.obstacles, a.n_obs, a.u_out, nullptr,
+                         static_cast<ce_mppi_info*>(a.info), L.stream) != CE_OK)
+        return hipErrorUnknown;
+    }
+  } else if (ce_mppi_batch_replan_subset(S->batch, members.data(), count, io.data(), L.stream) != CE_OK) {
     return hipErrorUnknown;
+  }
   e = hipMemcpyAsync(L.h_out, L.d_out, sizeof(float) * kOutFloats * count, hipMemcpyDeviceToHost,
                      L.stream);
   if (e == hipSuccess)
@@ -258,7 +272,10 @@ ce_status ce_mppi_server_create(const ce_mppi_server_config* cfg, ce_mppi_server
     return set_error(CE_EINVAL, "max_batch out of range 1..1024");
   if (cfg->max_inflight < 1 || cfg->max_inflight > kMaxInflight)
     return set_error(CE_EINVAL, "max_inflight out of range 1..3");
-  if (cfg->reserved != 0) return set_error(CE_EINVAL, "reserved must be 0");
+  if (cfg->mode != CE_SERVE_BATCHED && cfg->mode != CE_SERVE_PLAIN)
+    return set_error(CE_EINVAL, "unknown mode");
+  if (cfg->mode == CE_SERVE_PLAIN && (cfg->max_batch != 1 || cfg->max_inflight != 1))
+    return set_error(CE_EINVAL, "the plain form serves one request at a time (max_batch = max_inflight = 1)");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
     return set_error(CE_EDEVICE, "no HIP device available");
@@ -342,10 +359,26 @@ ce_status ce_mppi_server_start(ce_mppi_server* S) {
     S->batch = nullptr;
     return set_hip_error(e, "server_start");
   }
-  // warm-up: one launch through every subset area, so that graph builds and
-  // first kernel loads happen before the first request (session 0 replans a
-  // zero state without obstacles; its state is saved before and restored)
   {
+    // every session builds its replan graph and picks its faster launch mode
+    // before the first request (tune_launch restores each session's state)
+    Launch& L = S->launch[0];
+    e = hipMemsetAsync(L.d_in, 0, sizeof(float) * kInStride, L.stream);
+    for (size_t q = 0; q < S->sessions.size() && st == CE_OK && e == hipSuccess; ++q)
+      st = ce_mppi_tune_launch(S->sessions[q], L.d_in, nullptr, 0, L.d_out, 8, L.stream, nullptr,
+                               nullptr);
+    if (st == CE_OK && e == hipSuccess) e = hipStreamSynchronize(L.stream);
+    if (st != CE_OK || e != hipSuccess) {
+      free_launches(S);
+      ce_mppi_batch_destroy(S->batch);
+      S->batch = nullptr;
+      return st != CE_OK ? st : set_hip_error(e, "server warm-up");
+    }
+  }
+  if (S->cfg.mode == CE_SERVE_BATCHED) {
+    // warm-up: one launch through every subset area, so that graph builds and
+    // first kernel loads happen before the first request (session 0 replans a
+    // zero state without obstacles; its state is saved before and restored)
     size_t bytes = 0;
     st = ce_mppi_state_size(S->sessions[0], &bytes);
     std::vector<char> saved(bytes);

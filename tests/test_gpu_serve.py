@@ -140,14 +140,39 @@ def test_admission_bounded_by_memory():
 
 
 def test_plain_form_is_one_request_per_launch():
+    """The plain served form: one request at a time through ce_mppi_replan of
+    its session (single-planner kernels), bitwise equal to replanning the
+    session alone; the batched server with max_batch = 1 also launches one
+    request at a time."""
     from paper_2607_06499_amd import binding as B
 
     scenes = _scenes()[:4]
-    srv = B.Server(max_batch=1, max_inflight=1)
+    with pytest.raises(B.CeMppiError):
+        B.Server(max_batch=4, max_inflight=1, mode=B.SERVE_PLAIN)
+    srv = B.Server(max_batch=1, max_inflight=1, mode=B.SERVE_PLAIN)
     for s in scenes:
         srv.open_session(s.spec, s.U0)
     srv.start()
     t, sess, x, ob, no = _trace(scenes, 40, rate=20_000.0, seed=5)
+    lat, u = srv.run_trace(t, sess, x, ob, no)
+    st = srv.stats()
+    srv.close()
+    assert st["launches"] == 40 and st["mean_batch"] == 1.0 and st["max_inflight"] == 1
+    torch = H.torch_mod()
+    for k, sc in enumerate(scenes):
+        pl = B.Planner(sc.spec)
+        pl.set_nominal(H.to_dev(sc.U0))
+        xd = H.to_dev(np.asarray(sc.x0, np.float32))
+        od = H.to_dev(np.asarray(sc.obstacles, np.float32))
+        for i in np.flatnonzero(sess == k):
+            uu, _, _ = pl.replan(xd, od)
+            torch.cuda.synchronize()
+            assert np.array_equal(uu.cpu().numpy(), u[i, : pl.m]), (k, int(i))
+        pl.close()
+    srv = B.Server(max_batch=1, max_inflight=1)
+    for s in scenes:
+        srv.open_session(s.spec, s.U0)
+    srv.start()
     lat, u = srv.run_trace(t, sess, x, ob, no)
     st = srv.stats()
     srv.close()
