@@ -870,8 +870,30 @@ __device__ void chunk_stats(const Bufs& b, bool first, int M, const int (&lab)[k
   }
 }
 
+// Point data of one labelling chunk (points a0 + u * kFinThreads + threadIdx.x):
+// neighbour count, the point whose root gives the label (itself if core,
+// its lowest-index core neighbour if border, -1 if noise), and with stats
+// its cost and direction.
+template <int P>
+__device__ __forceinline__ void label_loads(const Cfg& c, const Bufs& b, int a0, int V, bool stats,
+                                            int (&nc)[kLabBatch], int (&x)[kLabBatch], float (&Sa)[kLabBatch],
+                                            typename ZVec<P>::T (&ga)[kLabBatch]) {
+  using ZT = typename ZVec<P>::T;
+  const ZT* gv = reinterpret_cast<const ZT*>(b.gv);
+#pragma unroll
+  for (int u = 0; u < kLabBatch; ++u) {
+    const int a = a0 + u * kFinThreads + threadIdx.x;
+    nc[u] = a < V ? b.ncount[a] : 0;
+    const int mc = a < V ? b.mcn[a] : kInt32Max;
+    x[u] = a >= V ? -1 : (nc[u] >= c.min_pts ? a : (mc != kInt32Max ? mc : -1));
+    Sa[u] = (stats && a < V) ? b.Sv[a] : 0.f;
+    ga[u] = (stats && a < V) ? gv[a] : ZT{};
+  }
+}
+
 template <int P>
 __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx, const float* __restrict__ zin, int Vin, int* mout, int* lab_out, int* cnt_out) {
+  using ZT = typename ZVec<P>::T;
   __shared__ int s_woff[kMaxWords];
   __shared__ unsigned long long s_rm[kMaxWords];
   __shared__ unsigned long long s_adj[kMaxTrees];
@@ -879,6 +901,17 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
   __shared__ int s_M;
   __shared__ float s_red[kFinThreads / kWave][kStatClusters][6];
   const int V = dbscan_V(b, zin, Vin);
+  // the first labelling chunk's point data and roots do not depend on the
+  // tree numbering or the closure: they are requested first, so their loads
+  // overlap those steps (the union-find fallback rewrites the roots; it
+  // reloads them)
+  const bool stats_pts = zin == nullptr;
+  int nc0[kLabBatch], x0[kLabBatch], r0[kLabBatch];
+  float S0[kLabBatch];
+  ZT g0[kLabBatch];
+  label_loads<P>(c, b, 0, V, stats_pts, nc0, x0, S0, g0);
+#pragma unroll
+  for (int u = 0; u < kLabBatch; ++u) r0[u] = x0[u] >= 0 ? b.root[x0[u]] : -1;
   const int R = V > 0 ? tree_prefix<kFinThreads>(b, V, s_woff, s_rm) : 0;
   const bool overflow = R > kMaxTrees;
   if (threadIdx.x == 0) {
@@ -923,6 +956,8 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
     // exact fallback; clusters = components ranked by their root (lowest core
     // index), the number of each root parked in label[root]
     uf_fallback<P>(c, b, zin, V);
+#pragma unroll
+    for (int u = 0; u < kLabBatch; ++u) r0[u] = x0[u] >= 0 ? b.root[x0[u]] : -1;
     int base = 0;
     for (int a0 = 0; a0 < V; a0 += kFinThreads) {
       const int a = a0 + threadIdx.x;
@@ -947,24 +982,25 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
   // (a root's own label is that same number).  Each thread takes kLabBatch
   // points at a time and issues all their loads before any store.  On the
   // feasible set of a replan the cluster statistics follow, chunk by chunk.
-  using ZT = typename ZVec<P>::T;
-  const bool stats = zin == nullptr && M > 0;
-  const ZT* gv = reinterpret_cast<const ZT*>(b.gv);
+  const bool stats = stats_pts && M > 0;
   for (int a0 = 0; a0 < V; a0 += kFinThreads * kLabBatch) {
     int nc[kLabBatch], x[kLabBatch], r[kLabBatch], lab[kLabBatch];
     float Sa[kLabBatch];
     ZT ga[kLabBatch];
+    if (a0 == 0) {
 #pragma unroll
-    for (int u = 0; u < kLabBatch; ++u) {
-      const int a = a0 + u * kFinThreads + threadIdx.x;
-      nc[u] = a < V ? b.ncount[a] : 0;
-      const int mc = a < V ? b.mcn[a] : kInt32Max;
-      x[u] = a >= V ? -1 : (nc[u] >= c.min_pts ? a : (mc != kInt32Max ? mc : -1));
-      Sa[u] = (stats && a < V) ? b.Sv[a] : 0.f;
-      ga[u] = (stats && a < V) ? gv[a] : ZT{};
+      for (int u = 0; u < kLabBatch; ++u) {
+        nc[u] = nc0[u];
+        x[u] = x0[u];
+        r[u] = r0[u];
+        Sa[u] = S0[u];
+        ga[u] = g0[u];
+      }
+    } else {
+      label_loads<P>(c, b, a0, V, stats_pts, nc, x, Sa, ga);
+#pragma unroll
+      for (int u = 0; u < kLabBatch; ++u) r[u] = x[u] >= 0 ? b.root[x[u]] : -1;
     }
-#pragma unroll
-    for (int u = 0; u < kLabBatch; ++u) r[u] = x[u] >= 0 ? b.root[x[u]] : -1;
 #pragma unroll
     for (int u = 0; u < kLabBatch; ++u) {
       if (r[u] < 0) lab[u] = -1;
