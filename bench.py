@@ -4,21 +4,23 @@
 Workload (default): the dynamic 2-D scene -- unicycle, K=8192 rollouts,
 horizon N=50, dt=0.05 s, 24 moving circular obstacles in a 20x20 m box,
 dynamic selection rule, DBSCAN eps=0.25 / minPts=20 -- driven through a
-closed loop.  A step is one replan (the whole hot path).  The loop's states
-and observations are recorded first (untimed), uploaded to the GPU, and the
-planner (reset to its initial state) then replans over them back to back:
-inputs are resident in HBM when the timed region starts, and the timed
-replans reproduce the recorded loop bit for bit.
+closed loop of 50 + 400 replans.  The loop is recorded first (untimed, host
+plant), its inputs uploaded to the GPU; a step is then one replay of the
+400-replan segment from the planner state it started from (the state restore
+included), so every step holds the loop's clustering and fallback replans in
+their natural mix.  Inputs are resident in HBM when the timed region starts,
+and the replays reproduce the recorded loop bit for bit.
 
 Prints one JSON line: replans/s (value), rollout-steps/s, p50/p99 latency,
-the branch mix, the roofline of the rollout kernel and the CPU oracle
-baseline.
+per-branch latency and device time, the roofline of the rollout kernel and
+the CPU oracle baseline (one thread and every host core).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -30,22 +32,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "CE-MPPI replans/s + rollout-steps/s at K=8192; p50/p99 replan latency"
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (datasheet)
+# MI355X FP32 vector: 256 CUs x 2.4 GHz x 64 lanes x 2 (FMA) = 78.6 TFLOP/s
+# without packed FP32 instructions (this build disables them); the datasheet's
+# 157.3 TFLOP/s counts the packed (two-wide) FMA
+PEAK_FP32_TFLOPS = 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+LOOP_WARM, LOOP_LEN = 50, 400
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=10,
+                    help="timed steps: replays of the recorded closed-loop segment")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed replays before them")
+    ap.add_argument("--loop", type=int, default=LOOP_LEN, help="replans per replay (the timed segment)")
+    ap.add_argument("--loop-warm", type=int, default=LOOP_WARM,
+                    help="closed-loop replans recorded before the timed segment")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--workload", default="unicycle_dynamic",
                     choices=["unicycle_dynamic", "unicycle_dynamic_ahead", "unicycle_static",
                              "unicycle_static_ahead", "arm6_dynamic", "unicycle_dynamic_cv",
                              "arm6_pose", "batch_uneven", "served_sessions"])
-    ap.add_argument("--cpu-seconds", type=float, default=20.0,
-                    help="budget of the CPU-oracle baseline sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="budget of each CPU-oracle baseline sample (one thread, then every core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the clustering-branch companion measurement")
@@ -76,9 +87,10 @@ def scene_for(name, seed):
             "arm6_pose": W.arm6_pose}[name](seed)
 
 
-def record_loop(pl, scene, T, torch):
+def record_loop(pl, scene, T, torch, snap_at=0):
     """Run the closed loop for T replans (host plant), returning the inputs
-    each replan saw, the applied controls and the per-replan info."""
+    each replan saw, the applied controls, the per-replan info and the
+    planner state before replan snap_at."""
     from paper_2607_06499_amd import plant
     from paper_2607_06499_amd.binding import DBG_TREES
 
@@ -86,9 +98,12 @@ def record_loop(pl, scene, T, torch):
     fld = scene.field.copy()
     x = scene.x0.astype(np.float64)
     X, OBS, UO, INFO = [], [], [], []
+    snap = None
     xd = torch.zeros(spec.n, dtype=torch.float32, device="cuda")
     od = torch.zeros(max(fld.n, 1), spec.p + 1, dtype=torch.float32, device="cuda")
-    for _ in range(T):
+    for t in range(T):
+        if t == snap_at:
+            snap = pl.get_state()
         xf = np.asarray(x, np.float32)
         obs = fld.observation()
         X.append(xf)
@@ -105,49 +120,72 @@ def record_loop(pl, scene, T, torch):
         INFO.append(info)
         x = plant.step(spec.dynamics, x, un, spec.dt)
         fld.step(spec.dt)
-    return np.stack(X), np.stack(OBS), np.stack(UO), INFO
+    return np.stack(X), np.stack(OBS), np.stack(UO), INFO, snap
 
 
-def timed_replays(pl, lib, Xd, Od, n_obs, W, K, torch):
-    """Back-to-back replans over the recorded inputs: W warm-up, K timed."""
+def timed_passes(pl, lib, Xd, Od, n_obs, t0, L, snap, W, K, torch):
+    """W untimed and K timed replays of the L recorded replans from t0, each
+    from the planner state snap (the restore is inside the timed region)."""
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
     h = pl.handle
     u_ptr = pl.u_out.data_ptr()
-    xs = [Xd[t].data_ptr() for t in range(W + K)]
-    os_ = [Od[t].data_ptr() for t in range(W + K)]
+    xs = [Xd[t].data_ptr() for t in range(t0, t0 + L)]
+    os_ = [Od[t].data_ptr() for t in range(t0, t0 + L)]
     f = lib.ce_mppi_replan
-    for t in range(W):
-        f(h, xs[t], os_[t], n_obs, u_ptr, None, None, sh)
+
+    def one_pass():
+        pl.set_state(snap)
+        for t in range(L):
+            f(h, xs[t], os_[t], n_obs, u_ptr, None, None, sh)
+
+    for _ in range(W):
+        one_pass()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
+    t_start = time.perf_counter()
     e0.record(stream)
-    for t in range(W, W + K):
-        f(h, xs[t], os_[t], n_obs, u_ptr, None, None, sh)
+    for _ in range(K):
+        one_pass()
     e1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = time.perf_counter() - t_start
     return wall, e0.elapsed_time(e1) / 1e3
 
 
-def latency_replays(pl, lib, Xd, Od, n_obs, W, K, torch, Uo):
-    """One replan at a time, host wall clock from the call to u_out ready."""
+def latency_replay(pl, lib, Xd, Od, n_obs, t0, L, snap, torch, Uo):
+    """One replan at a time, host wall clock from the call to u_out ready, and
+    a bit-for-bit check against the recorded loop."""
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
     h = pl.handle
     f = lib.ce_mppi_replan
+    pl.set_state(snap)
     lat = []
-    outs = torch.zeros(W + K, pl.m, dtype=torch.float32, device="cuda")
-    for t in range(W + K):
-        t0 = time.perf_counter()
-        f(h, Xd[t].data_ptr(), Od[t].data_ptr(), n_obs, outs[t].data_ptr(), None, None, sh)
+    outs = torch.zeros(L, pl.m, dtype=torch.float32, device="cuda")
+    for t in range(L):
+        ts = time.perf_counter()
+        f(h, Xd[t0 + t].data_ptr(), Od[t0 + t].data_ptr(), n_obs, outs[t].data_ptr(), None, None, sh)
         stream.synchronize()
-        if t >= W:
-            lat.append(time.perf_counter() - t0)
-    same = bool(np.array_equal(outs.cpu().numpy(), Uo[: W + K]))
+        lat.append(time.perf_counter() - ts)
+    same = bool(np.array_equal(outs.cpu().numpy(), Uo[t0: t0 + L]))
     return np.array(lat), same
+
+
+def device_times(pl, lib, Xd, Od, n_obs, t0, L, snap, torch):
+    """Per replan of the segment: device time of the rollout kernel, of the
+    rest and of the whole replan (HIP events around direct launches)."""
+    pl.set_state(snap)
+    pl.timing_enable(L)
+    sh = int(torch.cuda.current_stream().cuda_stream)
+    for t in range(t0, t0 + L):
+        lib.ce_mppi_replan(pl.handle, Xd[t].data_ptr(), Od[t].data_ptr(), n_obs, pl.u_out.data_ptr(),
+                           None, None, sh)
+    torch.cuda.synchronize()
+    r, q, a = pl.timing_read_each(L)
+    pl.timing_enable(0)
+    return r, q, a
 
 
 def copy_calibration(torch, mib: int, reps: int = 5):
@@ -168,28 +206,31 @@ def source_digest(paths):
     return h.hexdigest()[:16]
 
 
-def traffic_record(kernel_sources):
-    """HBM traffic per launch from the committed counter summary, if it was
-    taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "rollout_unicycle_k8192_n50_traffic.json")
+def profile_record(name, kernel_sources):
+    """A committed counter summary (profiles/<name>), if it was taken on the
+    current kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
-        return None, None
+        return None
     rec = json.load(open(path))
     if rec.get("source_digest") != source_digest(kernel_sources):
-        return None, rec
-    return rec.get("hbm_bytes_per_launch"), rec
+        return None
+    return rec
 
 
-def cpu_baseline(scene, X, OBS, W, budget_s, hist_len):
+def _oracle_worker(args):
+    """Oracle replans of the recorded loop from its start (its own nominal
+    sequence), one after another, until the budget is spent: (count, s)."""
+    spec, U0, X, OBS, hist_len, budget_s, start_evt = args
     import oracle
 
-    spec = scene.spec
-    U = scene.U0.astype(np.float64)
+    oracle.load()
+    if start_evt is not None:
+        start_evt.wait()
+    U = np.asarray(U0, np.float64)
     hist = []
     n = 0
     t0 = time.perf_counter()
-    # the oracle replays the same loop from its start (its own nominal
-    # sequence), one replan after another, until the budget is spent
     for t in range(len(X)):
         hist.insert(0, OBS[t][:, : spec.p].astype(np.float64))
         hist = hist[:hist_len]
@@ -198,76 +239,82 @@ def cpu_baseline(scene, X, OBS, W, budget_s, hist_len):
         n += 1
         if time.perf_counter() - t0 >= budget_s and n >= 2:
             break
-    dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit="replans/s", cores=1, kind="oracle",
-                sample=f"first {n} replans of the same closed loop (K={spec.num_samples}, "
-                       f"N={spec.horizon}), single-threaded FP64 C oracle, "
-                       f"{spec.num_samples * spec.horizon * n / dt:.3g} rollout-steps/s")
+    return n, time.perf_counter() - t0
 
 
-def run_workload(name, seed, W, K, torch, B, want_timing=True, rollout_reps=2000):
-    scene = scene_for(name, seed)
+def _pool_worker(args):
+    return _oracle_worker(args)
+
+
+def host_cpu():
+    """Host CPU model and the cores this process may use (the box's share)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail, os.cpu_count() or avail
+
+
+def cpu_baseline(scene, X, OBS, budget_s, hist_len, max_workers=16):
+    """The FP64 C oracle as it stands on this host: one thread, then one
+    worker process per core (up to the box's share), every worker replaying
+    the same closed loop; the rate is the sum of the workers' rates while
+    they run together."""
     spec = scene.spec
-    lib = B.load()
-    pl = B.Planner(spec)
-    pl.set_nominal(torch.as_tensor(scene.U0).cuda())
-    state0 = pl.get_state()
-    X, OBS, Uo, INFO = record_loop(pl, scene, W + K, torch)
-    Xd = torch.as_tensor(X).cuda()
-    Od = torch.as_tensor(OBS).cuda()
-    n_obs = OBS.shape[1]
-    # throughput, in both launch modes (graph replay, direct launches): which
-    # one is faster depends on the host of this box; the faster is reported
-    walls = {}
-    for mode, code in (("graph", B.LAUNCH_GRAPH), ("direct", B.LAUNCH_DIRECT)):
-        pl.set_launch_mode(code)
-        pl.set_state(state0)
-        walls[mode] = timed_replays(pl, lib, Xd, Od, n_obs, W, K, torch)
-    best = min(walls, key=lambda m: walls[m][0])
-    wall, gpu = walls[best]
-    pl.set_launch_mode(B.LAUNCH_GRAPH if best == "graph" else B.LAUNCH_DIRECT)
-    launch = {"mode": best, "us_per_replan_graph": round(1e6 * walls["graph"][0] / K, 2),
-              "us_per_replan_direct": round(1e6 * walls["direct"][0] / K, 2)}
-    # latency (and a bit-for-bit replay check)
-    pl.set_state(state0)
-    lat, same = latency_replays(pl, lib, Xd, Od, n_obs, W, K, torch, Uo)
-    timing = None
-    kernel_ms = None
-    if want_timing:
-        # the rollout kernel alone, back to back on the replan stream, on the
-        # first timed replan's inputs (the planner state is restored after)
-        pl.set_state(state0)
-        kernel_ms = pl.time_rollout(Xd[W], Od[W], reps=rollout_reps)
-        pl.set_state(state0)
-        pl.timing_enable(W + K)
-        for t in range(W + K):
-            lib.ce_mppi_replan(pl.handle, Xd[t].data_ptr(), Od[t].data_ptr(), n_obs,
-                               pl.u_out.data_ptr(), None, None, int(torch.cuda.current_stream().cuda_stream))
-        torch.cuda.synchronize()
-        timing = pl.timing_read()
-        timing["count"] = max(timing["count"], 1)
-        pl.timing_enable(0)
-    branches = [i["branch"] for i in INFO[W:]]
-    mix = {"cluster": branches.count(0), "fallback": branches.count(1),
-           "all_collide": branches.count(2)}
-    ncl = [i["n_feasible"] for i in INFO[W:] if i["branch"] == 0]
-    trees = [i["trees"] for i in INFO[W:] if i["branch"] == 0]
-    tstat = {"mean": round(float(np.mean(trees)), 1) if trees else 0.0,
-             "max": int(max(trees)) if trees else 0,
-             "union_find_fallback": int(sum(i["tree_fallback"] for i in INFO[W:] if i["branch"] == 0))}
-    pl.close()
-    return dict(scene=scene, X=X, OBS=OBS, wall=wall, gpu=gpu, lat=lat, same=same, timing=timing, launch=launch,
-                kernel_ms=kernel_ms, mix=mix, mean_V=float(np.mean(ncl)) if ncl else 0.0, trees=tstat)
+    model, avail, total = host_cpu()
+    n1, t1 = _oracle_worker((spec, scene.U0, X, OBS, hist_len, budget_s, None))
+    cores = max(1, min(avail, max_workers))
+    ctx = mp.get_context("spawn")
+    with ctx.Manager() as mgr:
+        evt = mgr.Event()
+        with ctx.Pool(cores) as pool:
+            res = pool.map_async(_pool_worker, [(spec, scene.U0, X, OBS, hist_len, budget_s, evt)] * cores)
+            time.sleep(1.0)  # let the workers import and load the oracle
+            evt.set()
+            out = res.get()
+    rate_all = sum(n / dt for n, dt in out)
+    steps = spec.num_samples * spec.horizon
+    return dict(value=round(rate_all, 3), unit="replans/s", cores=cores, kind="oracle",
+                sample=f"the recorded closed loop (K={spec.num_samples}, N={spec.horizon}) replayed from "
+                       f"its start by the single-threaded FP64 C oracle in {cores} worker processes "
+                       f"for about {budget_s:g} s each ({sum(n for n, _ in out)} replans in all)",
+                one_thread=dict(value=round(n1 / t1, 3), unit="replans/s", cores=1, replans=n1,
+                                rollout_steps_per_s=round(steps * n1 / t1, 1)),
+                rollout_steps_per_s=round(steps * rate_all, 1),
+                host={"cpu_model": model, "cores_available": avail, "cores_total": total})
+
+
+def live_obstacles(spec, x, obs):
+    """Obstacles the unicycle rollout kernel keeps after its exact broad phase
+    (frozen obstacles): every state lies within max|v| N dt of p(x_t), so an
+    obstacle whose surface is farther (plus a margin) is never tested."""
+    if spec.dynamics != 0:
+        return len(obs)
+    vmax = max(abs(float(spec.u_min[0])), abs(float(spec.u_max[0])))
+    if not np.isfinite(vmax):
+        return len(obs)
+    reach = vmax * spec.horizon * float(spec.dt)
+    d = np.hypot(obs[:, 0] - x[0], obs[:, 1] - x[1])
+    ext = reach + float(spec.robot_radius) + obs[:, 2]
+    return int(np.sum(d <= ext + 1e-3 * ext + 1e-3))
 
 
 def rollout_flops(spec, n_obs):
-    """Algorithmic FP32 flops of one rollout launch: 25 + 5 n_obs per
-    unicycle rollout-step (noise transform, clamp, dynamics, cost, 5 per
-    obstacle test); forward kinematics 480, link spheres 48, 8 per
-    sphere-obstacle test and 40 for noise and cost per arm rollout-step.
-    Constant-velocity obstacles add the displacement of each tested obstacle
-    (4 flops in 2-D, 6 in 3-D); the pose cost adds 62 per arm rollout-step
-    (orientation error 60, distance 2)."""
+    """Algorithmic FP32 flops of one rollout launch with n_obs obstacles
+    tested: 25 + 5 n_obs per unicycle rollout-step (noise transform 6, clamp
+    4, dynamics 6, cost 9, 5 per obstacle test); forward kinematics 480, link
+    spheres 48, 8 per sphere-obstacle test and 40 for noise and cost per arm
+    rollout-step.  Constant-velocity obstacles add the displacement of each
+    tested obstacle (4 flops in 2-D, 6 in 3-D); the pose cost adds 62 per arm
+    rollout-step (orientation error 60, distance 2)."""
     steps = spec.num_samples * spec.horizon
     cv = bool(getattr(spec, "flags", 0) & 2)
     pose = bool(getattr(spec, "flags", 0) & 1)
@@ -276,20 +323,84 @@ def rollout_flops(spec, n_obs):
     return steps * (480 + 48 + (14 if cv else 8) * n_obs * spec.n_link_spheres + 40 + (62 if pose else 0))
 
 
-def companion(name, seed, W, K, torch, B, label):
+def _ms(a):
+    return round(float(a) * 1e3, 4)
+
+
+def run_workload(name, seed, loop_warm, L, W, K, torch, B, want_timing=True, rollout_reps=2000):
+    scene = scene_for(name, seed)
+    spec = scene.spec
+    lib = B.load()
+    pl = B.Planner(spec)
+    pl.set_nominal(torch.as_tensor(scene.U0).cuda())
+    X, OBS, Uo, INFO, snap = record_loop(pl, scene, loop_warm + L, torch, snap_at=loop_warm)
+    Xd = torch.as_tensor(X).cuda()
+    Od = torch.as_tensor(OBS).cuda()
+    n_obs = OBS.shape[1]
+    t0 = loop_warm
+    # throughput, in both launch modes (graph replay, direct launches): which
+    # one is faster depends on the host of this box; the faster is reported
+    walls = {}
+    for mode, code in (("graph", B.LAUNCH_GRAPH), ("direct", B.LAUNCH_DIRECT)):
+        pl.set_launch_mode(code)
+        walls[mode] = timed_passes(pl, lib, Xd, Od, n_obs, t0, L, snap, W, K, torch)
+    best = min(walls, key=lambda m: walls[m][0])
+    wall, gpu = walls[best]
+    pl.set_launch_mode(B.LAUNCH_GRAPH if best == "graph" else B.LAUNCH_DIRECT)
+    launch = {"mode": best, "us_per_replan_graph": round(1e6 * walls["graph"][0] / (K * L), 2),
+              "us_per_replan_direct": round(1e6 * walls["direct"][0] / (K * L), 2)}
+    lat, same = latency_replay(pl, lib, Xd, Od, n_obs, t0, L, snap, torch, Uo)
+    dev = device_times(pl, lib, Xd, Od, n_obs, t0, L, snap, torch) if want_timing else None
+    kernel_ms = None
+    if want_timing:
+        # the rollout kernel alone, back to back on the replan stream, on the
+        # first timed replan's inputs (the planner state is restored after)
+        pl.set_state(snap)
+        kernel_ms = pl.time_rollout(Xd[t0], Od[t0], reps=rollout_reps)
+    info = INFO[t0: t0 + L]
+    branches = np.array([i["branch"] for i in info])
+    mix = {"cluster": int(np.sum(branches == 0)), "fallback": int(np.sum(branches == 1)),
+           "all_collide": int(np.sum(branches == 2))}
+    per_branch = {}
+    for bname, code in (("cluster", 0), ("fallback", 1), ("all_collide", 2)):
+        sel = branches == code
+        if not sel.any():
+            continue
+        e = {"replans": int(sel.sum()),
+             "latency_ms": {"p50": _ms(np.percentile(lat[sel], 50)), "p99": _ms(np.percentile(lat[sel], 99)),
+                            "mean": _ms(np.mean(lat[sel]))}}
+        if dev is not None:
+            e["device_us"] = {"rollout": round(float(np.mean(dev[0][sel])) * 1e3, 2),
+                              "after_rollout": round(float(np.mean(dev[1][sel])) * 1e3, 2),
+                              "replan": round(float(np.mean(dev[2][sel])) * 1e3, 2)}
+        if code == 0:
+            e["mean_feasible"] = round(float(np.mean([i["n_feasible"] for i, b in zip(info, branches) if b == 0])), 1)
+        per_branch[bname] = e
+    trees = [i["trees"] for i in info if i["branch"] == 0]
+    tstat = {"mean": round(float(np.mean(trees)), 1) if trees else 0.0,
+             "max": int(max(trees)) if trees else 0,
+             "union_find_fallback": int(sum(i["tree_fallback"] for i in info if i["branch"] == 0))}
+    n_live = live_obstacles(spec, X[t0], OBS[t0])
+    pl.close()
+    return dict(scene=scene, X=X, OBS=OBS, wall=wall, gpu=gpu, lat=lat, same=same, launch=launch,
+                kernel_ms=kernel_ms, mix=mix, per_branch=per_branch, trees=tstat, n_live=n_live,
+                L=L, K=K, W=W, loop_warm=loop_warm)
+
+
+def companion(name, seed, loop_warm, L, K, torch, B, label):
     """Throughput, latency and rollout roofline of another single-planner
-    workload (same protocol as the headline)."""
-    r = run_workload(name, seed, W, K, torch, B, rollout_reps=500)
+    workload (same protocol as the headline: K replays of an L-replan loop)."""
+    r = run_workload(name, seed, loop_warm, L, 1, K, torch, B, rollout_reps=500)
     spec = r["scene"].spec
-    n_obs = r["OBS"].shape[1]
-    flops = rollout_flops(spec, n_obs)
+    flops = rollout_flops(spec, r["n_live"])
+    rate = K * L / r["wall"]
     return {
-        "workload": label, "replans_per_s": round(K / r["wall"], 1),
-        "rollout_steps_per_s": round(K / r["wall"] * spec.num_samples * spec.horizon, 1),
-        "latency_ms": {"p50": round(float(np.percentile(r["lat"], 50)) * 1e3, 4),
-                       "p99": round(float(np.percentile(r["lat"], 99)) * 1e3, 4)},
-        "branch_mix": r["mix"], "replay_bit_exact": r["same"], "launch": r["launch"],
-        "rollout_kernel_ms": round(r["kernel_ms"], 5),
+        "workload": label, "replans_per_s": round(rate, 1),
+        "rollout_steps_per_s": round(rate * spec.num_samples * spec.horizon, 1),
+        "latency_ms": {"p50": _ms(np.percentile(r["lat"], 50)), "p99": _ms(np.percentile(r["lat"], 99))},
+        "branch_mix": r["mix"], "per_branch": r["per_branch"], "replay_bit_exact": r["same"],
+        "launch": r["launch"], "rollout_kernel_ms": round(r["kernel_ms"], 5),
+        "obstacles_tested": r["n_live"],
         "rollout_tflops": round(flops / (r["kernel_ms"] * 1e-3) / 1e12, 4),
     }
 
@@ -424,15 +535,16 @@ def run_batch(seed, W, K, torch, B, autotune=True, n_planners=256):
 def run_serve(seed, torch, B, rates=(2000.0, 5000.0, 10000.0, 20000.0), seconds=0.75):
     """Served form: 512 resident sessions, Poisson-arrival replan requests at
     each rate through the continuous-batching server and through the plain
-    form (one request per launch, one launch at a time), on the same trace.
-    Latency is request arrival to completion."""
+    form (one request at a time, each through ce_mppi_replan of its session:
+    the single-planner kernels in the launch mode tuned per session), on the
+    same trace.  Latency is request arrival to completion."""
     from paper_2607_06499_amd import workloads as WL
 
     sess = WL.served_sessions(seed)
     scenes = [s.scene for s in sess]
 
-    def make(max_batch, max_inflight):
-        srv = B.Server(max_batch=max_batch, max_inflight=max_inflight)
+    def make(max_batch, max_inflight, mode):
+        srv = B.Server(max_batch=max_batch, max_inflight=max_inflight, mode=mode)
         for sc in scenes:
             srv.open_session(sc.spec, sc.U0)
         srv.start()
@@ -456,8 +568,9 @@ def run_serve(seed, torch, B, rates=(2000.0, 5000.0, 10000.0, 20000.0), seconds=
             no[i] = len(o)
             ob[i, : o.size] = o.ravel()
         row = {"offered_req_per_s": rate, "requests": n}
-        for name, mb, fl in (("continuous_batching", 256, 3), ("plain_one_per_launch", 1, 1)):
-            srv = make(mb, fl)
+        for name, mb, fl, mode in (("continuous_batching", 256, 3, B.SERVE_BATCHED),
+                                   ("plain_one_per_launch", 1, 1, B.SERVE_PLAIN)):
+            srv = make(mb, fl, mode)
             t0 = time.perf_counter()
             lat, _ = srv.run_trace(t, sid, x, ob, no)
             wall = time.perf_counter() - t0
@@ -505,23 +618,47 @@ def main():
                           "config": {"workload": rb["workload"]}, **{k: v for k, v in rb.items()
                                                                      if k != "workload"}}))
         return
-    res = run_workload(args.workload, args.seed, W, K, torch, B, rollout_reps=args.rollout_reps)
+    res = run_workload(args.workload, args.seed, args.loop_warm, args.loop, W, K, torch, B,
+                       rollout_reps=args.rollout_reps)
     if args.calibrate_copy_mib:
         copy_calibration(torch, args.calibrate_copy_mib)
     spec = res["scene"].spec
-    replans_per_s = K / res["wall"]
+    L = args.loop
+    replans_per_s = K * L / res["wall"]
     rollout_steps = spec.num_samples * spec.horizon
     lat = res["lat"]
-    # roofline of the rollout kernel: algorithmic FP32 flops per rollout-step
-    # 25 + 5 n_obs (noise transform, clamp, dynamics, cost, 5 per obstacle)
+    # roofline of the rollout kernel on the first timed replan's inputs:
+    # algorithmic flops with the obstacles the exact broad phase keeps
     n_obs = res["OBS"].shape[1]
-    flops = rollout_flops(spec, n_obs)
+    flops = rollout_flops(spec, res["n_live"])
     t_roll = res["kernel_ms"] * 1e-3
-    t_roll_launch = res["timing"]["rollout_ms"] / res["timing"]["count"] * 1e-3
     achieved = flops / t_roll / 1e12
     ksrc = [os.path.join(ROOT, "paper_2607_06499_amd", "csrc", f)
             for f in ("rollout.hip", "device.hpp")]
-    traffic, _ = traffic_record(ksrc)
+    traffic_rec = profile_record("rollout_unicycle_k8192_n50_traffic.json", ksrc)
+    valu_rec = profile_record("rollout_unicycle_k8192_n50_valu.json", ksrc)
+    roofline = {
+        "bound": "alu", "kernel": "rollout",
+        "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP32_TFLOPS, 6),
+        "traffic": traffic_rec.get("hbm_bytes_per_launch") if traffic_rec else None,
+        "kernel_ms": round(t_roll * 1e3, 5),
+        "algorithmic_flop_per_launch": flops,
+        "obstacles_tested": res["n_live"], "obstacles": n_obs,
+        "peak_note": "FP32 vector without packed instructions (disabled in this build); "
+                     f"the packed datasheet peak is {PEAK_FP32_PACKED_TFLOPS}",
+        "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 6),
+    }
+    if valu_rec:
+        # executed FP32 work and VALU issue from the committed counter run
+        cf = valu_rec["fp32_flop_per_launch"]
+        roofline["counters"] = {
+            "fp32_flop_per_launch": cf,
+            "fp32_tflops_at_kernel_ms": round(cf / t_roll / 1e12, 4),
+            "valu_issue_utilisation": valu_rec["valu_issue_utilisation"],
+            "valu_insts_per_launch": valu_rec["valu_insts_per_launch"],
+            "source": "profiles/rollout_unicycle_k8192_n50_valu.json",
+        }
     out = {
         "metric": METRIC,
         "value": round(replans_per_s, 2),
@@ -536,66 +673,60 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: unicycle K={spec.num_samples} N={spec.horizon} "
-                        f"dt={spec.dt:g} {n_obs} obstacles, "
-                        f"{'dynamic' if spec.scene_mode else 'static'} rule, "
-                        f"closed loop of {W + K} replans (seed {args.seed})"
+            "workload": (f"{args.workload}: unicycle K={spec.num_samples} N={spec.horizon} "
+                         f"dt={spec.dt:g} {n_obs} moving obstacles, "
+                         f"{'dynamic' if spec.scene_mode else 'static'} rule, closed loop of "
+                         f"{args.loop_warm} + {L} replans (seed {args.seed}); a step replays the "
+                         f"{L}-replan segment")
             if spec.dynamics == 0 else
-            f"{args.workload}: 6-joint arm K={spec.num_samples} N={spec.horizon} {n_obs} spheres",
-            "K": spec.num_samples, "N": spec.horizon, "n_obs": n_obs,
-            "branch_mix": res["mix"], "mean_feasible_when_clustering": round(res["mean_V"], 1),
+            f"{args.workload}: 6-joint arm K={spec.num_samples} N={spec.horizon} {n_obs} spheres; "
+            f"a step replays {L} closed-loop replans",
+            "K": spec.num_samples, "N": spec.horizon, "n_obs": n_obs, "replans_per_step": L,
+            "branch_mix": res["mix"],
             "dbscan_trees": res["trees"],
             "launch": res["launch"],
         },
         "rollout_steps_per_s": round(replans_per_s * rollout_steps, 1),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
-                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 4)},
+        "latency_ms": {"p50": _ms(np.percentile(lat, 50)), "p99": _ms(np.percentile(lat, 99))},
+        "per_branch": res["per_branch"],
         "gpu_ms_per_step": round(1e3 * res["gpu"] / K, 4),
         "replay_bit_exact": res["same"],
-        "roofline": {
-            "bound": "alu", "kernel": "rollout",
-            "achieved": round(achieved, 4), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 6),
-            "traffic": traffic,
-            "kernel_ms": round(t_roll * 1e3, 5),
-            "kernel_ms_in_replan_with_launch": round(t_roll_launch * 1e3, 5),
-            "algorithmic_flop_per_launch": flops,
-        },
+        "roofline": roofline,
     }
     if not args.no_probe and args.workload == "unicycle_dynamic":
-        pr = run_workload("unicycle_dynamic_ahead", args.seed, W, K, torch, B, want_timing=False)
+        pr = run_workload("unicycle_dynamic_ahead", args.seed, 0, 40, 1, max(K, 5), torch, B)
         out["clustering_branch"] = {
-            "workload": "unicycle_dynamic_ahead: same planner, obstacle ahead in the robot's path",
-            "replans_per_s": round(K / pr["wall"], 2),
-            "latency_ms": {"p50": round(float(np.percentile(pr["lat"], 50)) * 1e3, 4),
-                           "p99": round(float(np.percentile(pr["lat"], 99)) * 1e3, 4)},
-            "branch_mix": pr["mix"], "mean_feasible": round(pr["mean_V"], 1),
-            "dbscan_trees": pr["trees"],
+            "workload": "unicycle_dynamic_ahead: same planner, obstacle ahead in the robot's path "
+                        "(replays of a 40-replan loop)",
+            "replans_per_s": round(pr["K"] * pr["L"] / pr["wall"], 2),
+            "latency_ms": {"p50": _ms(np.percentile(pr["lat"], 50)), "p99": _ms(np.percentile(pr["lat"], 99))},
+            "branch_mix": pr["mix"], "per_branch": pr["per_branch"], "dbscan_trees": pr["trees"],
         }
     if not args.no_companions and args.workload == "unicycle_dynamic":
-        out["static_2d"] = companion("unicycle_static", args.seed, W, 200, torch, B,
+        cK = max(2, min(K, 3))
+        out["static_2d"] = companion("unicycle_static", args.seed, 0, 200, cK, torch, B,
                                      "unicycle_static: K=1024 N=30 dt=0.1, 8 static obstacles, "
-                                     "closed loop of 200 timed replans")
-        out["static_2d_ahead"] = companion("unicycle_static_ahead", args.seed, W, 200, torch, B,
-                                           "unicycle_static_ahead: obstacle 1.2 m ahead, clustering "
-                                           "branch")
-        out["arm_6dof"] = companion("arm6_dynamic", args.seed, W, K, torch, B,
+                                     "replays of a 200-replan closed loop")
+        out["static_2d_ahead"] = companion("unicycle_static_ahead", args.seed, 0, 200, cK, torch, B,
+                                           "unicycle_static_ahead: obstacle 1.2 m ahead, replays of a "
+                                           "200-replan closed loop")
+        out["arm_6dof"] = companion("arm6_dynamic", args.seed, 0, 400, cK, torch, B,
                                     "arm6_dynamic: K=4096 N=32 dt=0.05, 16 moving spheres, "
-                                    "8 link spheres, closed loop")
+                                    "8 link spheres, replays of a 400-replan closed loop")
         out["dynamic_2d_const_vel"] = companion(
-            "unicycle_dynamic_cv", args.seed, W, K, torch, B,
+            "unicycle_dynamic_cv", args.seed, args.loop_warm, L, cK, torch, B,
             "unicycle_dynamic_cv: the headline scene with constant-velocity obstacle prediction "
             "inside the rollouts")
         out["arm_6dof_pose"] = companion(
-            "arm6_pose", args.seed, W, K, torch, B,
+            "arm6_pose", args.seed, 0, 400, cK, torch, B,
             "arm6_pose: arm6_dynamic with the real-robot pose cost (10, 3, 1000) and "
-            "constant-velocity obstacles")
+            "constant-velocity obstacles, replays of a 400-replan closed loop")
     if not args.no_batch and args.workload == "unicycle_dynamic":
         out["batched_form"] = run_batch(args.seed, 5, args.batch_steps, torch, B)
     if not args.no_serve and args.workload == "unicycle_dynamic":
         out["served_form"] = run_serve(args.seed, torch, B)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(res["scene"], res["X"], res["OBS"], W, args.cpu_seconds,
+        out["cpu_baseline"] = cpu_baseline(res["scene"], res["X"], res["OBS"], args.cpu_seconds,
                                            spec.history_len)
     print(json.dumps(out))
 
