@@ -22,7 +22,9 @@
  *  - A planner owns its device state (nominal control sequence, obstacle
  *    history, step counter, scratch), all allocated in ce_mppi_create.
  *    ce_mppi_replan allocates nothing.  A planner must not have two calls in
- *    flight on different streams at once; different planners are independent.
+ *    flight on different streams at once (ce_mppi_replan and
+ *    ce_mppi_replan_from_rollouts return CE_EBUSY when they can see it);
+ *    different planners are independent.
  */
 #ifndef CEMPPI_H
 #define CEMPPI_H
@@ -178,8 +180,12 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out);
  *   info      device, one ce_mppi_info, or NULL
  * The planner keeps the shifted warm start (last control repeated) and
  * increments its step counter.  A non-finite x_t or obstacle value makes the
- * call a no-op apart from u_out = U[0] and info.status.  Errors: CE_EINVAL
- * (NULL planner/x_t/u_out, n_obs outside 0..max_obstacles), CE_EDEVICE. */
+ * call a no-op apart from u_out = U[0] and info.status.  A planner has at most
+ * one replan in flight: a call on a stream other than the planner's previous
+ * replan (single or batched) while that stream still has work queued returns
+ * CE_EBUSY without enqueuing anything; synchronise that stream first.
+ * Errors: CE_EINVAL (NULL planner/x_t/u_out, n_obs outside 0..max_obstacles),
+ * CE_EBUSY, CE_EDEVICE. */
 ce_status ce_mppi_replan(ce_mppi_planner* planner, const float* x_t, const float* obstacles,
                          int32_t n_obs, float* u_out, float* U_out, ce_mppi_info* info,
                          void* stream);
@@ -195,6 +201,16 @@ ce_status ce_mppi_set_nominal(ce_mppi_planner* planner, const float* U, void* st
 ce_status ce_mppi_get_nominal(const ce_mppi_planner* planner, float* U, void* stream);
 /* Empty the obstacle history. */
 ce_status ce_mppi_reset_history(ce_mppi_planner* planner, void* stream);
+/* Replace the obstacle history (the {o_{t-h}} of Eq. (17)): hist is device
+ * memory [h_count][n_obs][p] of obstacle centres, newest first; the planner
+ * keeps the newest min(h_count, history_len) entries, exactly as if they had
+ * been pushed by that many replans with n_obs obstacles (h_count = 0 empties
+ * it).  The next replan pushes its own observation on top, and a different
+ * obstacle count there restarts the history as usual.  Synchronises the
+ * stream.  Errors: CE_EINVAL (h_count < 0, n_obs outside 0..max_obstacles,
+ * NULL hist with entries), CE_EDEVICE. */
+ce_status ce_mppi_set_history(ce_mppi_planner* planner, const float* hist, int32_t h_count,
+                              int32_t n_obs, void* stream);
 /* Set the step counter (the Philox step word of the next replan). */
 ce_status ce_mppi_set_step(ce_mppi_planner* planner, uint64_t step, void* stream);
 /* Checkpoint: size in bytes of the serialised state (U, history, counters). */

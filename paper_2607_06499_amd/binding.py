@@ -174,6 +174,7 @@ def load():
         "ce_mppi_set_nominal": [_vp, _vp, _vp],
         "ce_mppi_get_nominal": [_vp, _vp, _vp],
         "ce_mppi_reset_history": [_vp, _vp],
+        "ce_mppi_set_history": [_vp, _vp, C.c_int32, C.c_int32, _vp],
         "ce_mppi_set_step": [_vp, C.c_uint64, _vp],
         "ce_mppi_state_size": [_vp, C.POINTER(C.c_size_t)],
         "ce_mppi_get_state": [_vp, _vp, C.c_size_t, _vp],
@@ -387,6 +388,17 @@ class Planner:
 
     def reset_history(self, stream=None):
         _check("ce_mppi_reset_history", load().ce_mppi_reset_history(self.handle, _stream_handle(stream)))
+
+    def set_history(self, hist, stream=None):
+        """hist: [h_count][n_obs][p] device tensor of obstacle centres, newest first."""
+        import torch
+
+        hist = torch.as_tensor(hist, dtype=torch.float32).to(self.device).contiguous()
+        h_count = int(hist.shape[0])
+        n_obs = int(hist.shape[1]) if hist.dim() == 3 else 0
+        _check("ce_mppi_set_history",
+               load().ce_mppi_set_history(self.handle, hist.data_ptr() if hist.numel() else None, h_count,
+                                          n_obs, _stream_handle(stream)))
 
     def set_step(self, step: int, stream=None):
         _check("ce_mppi_set_step", load().ce_mppi_set_step(self.handle, int(step), _stream_handle(stream)))

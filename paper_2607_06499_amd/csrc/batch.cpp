@@ -394,6 +394,7 @@ ce_status ce_mppi_batch_replan(ce_mppi_batch* B, const ce_mppi_batch_io* io, voi
   }
   e = hipGraphLaunch(a.exec, hs);
   if (e != hipSuccess) return set_hip_error(e, "batch graph launch");
+  for (int i = 0; i < B->n; ++i) mark_stream(B->pl[i], hs);
   return CE_OK;
 }
 
@@ -435,6 +436,7 @@ ce_status ce_mppi_batch_replan_subset(ce_mppi_batch* B, const int32_t* members, 
   if (e == hipSuccess) e = hipEventRecord(a.done, hs);
   if (e != hipSuccess) return set_hip_error(e, "batch subset launch");
   a.used = true;
+  for (int q = 0; q < count; ++q) mark_stream(B->pl[members[q]], hs);
   return CE_OK;
 }
 

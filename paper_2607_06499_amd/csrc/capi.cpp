@@ -485,14 +485,38 @@ void ce_mppi_destroy(ce_mppi_planner* P) {
   delete P;
 }
 
-ce_status ce_mppi_replan(ce_mppi_planner* P, const float* x_t, const float* obstacles, int32_t n_obs,
-                         float* u_out, float* U_out, ce_mppi_info* info, void* stream) {
+}  // extern "C"
+
+namespace {
+// A replan on a stream other than the previous replan's while that stream
+// still has work queued: the previous replan may still be running.
+ce_status check_not_busy(ce_mppi_planner* P, hipStream_t s) {
+  if (!P->used || s == P->last_stream) return CE_OK;
+  const hipError_t q = hipStreamQuery(P->last_stream);
+  if (q == hipSuccess) return CE_OK;
+  if (q == hipErrorNotReady)
+    return fail(CE_EBUSY, "the planner's previous replan may still be in flight on another stream");
+  return hip_fail(q, "hipStreamQuery");
+}
+}  // namespace
+
+namespace cemppi {
+void mark_stream(ce_mppi_planner* P, hipStream_t s) {
+  P->last_stream = s;
+  P->used = true;
+}
+}  // namespace cemppi
+
+namespace cemppi {
+ce_status replan_unchecked(ce_mppi_planner* P, const float* x_t, const float* obstacles,
+                                   int32_t n_obs, float* u_out, float* U_out, ce_mppi_info* info,
+                                   hipStream_t s) {
   if (!P) return fail(CE_EINVAL, "planner is NULL");
   if (!x_t || !u_out) return fail(CE_EINVAL, "x_t and u_out must not be NULL");
   if (n_obs < 0 || n_obs > P->c.max_obs) return fail(CE_EINVAL, "n_obs outside 0..max_obstacles");
   if (n_obs > 0 && !obstacles) return fail(CE_EINVAL, "obstacles is NULL with n_obs > 0");
   DeviceGuard guard(P->cfg.device);
-  hipStream_t s = S(stream);
+  mark_stream(P, s);
   Timing& t = P->t;
   hipError_t e = hipSuccess;
   if (t.cap > 0 && t.n < t.cap) {
@@ -518,6 +542,19 @@ ce_status ce_mppi_replan(ce_mppi_planner* P, const float* x_t, const float* obst
   if (e != hipSuccess) return hip_fail(e, "replan launch");
   return CE_OK;
 }
+}  // namespace cemppi
+
+extern "C" {
+
+ce_status ce_mppi_replan(ce_mppi_planner* P, const float* x_t, const float* obstacles, int32_t n_obs,
+                         float* u_out, float* U_out, ce_mppi_info* info, void* stream) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  DeviceGuard guard(P->cfg.device);
+  const ce_status st = check_not_busy(P, S(stream));
+  if (st != CE_OK) return st;
+  return replan_unchecked(P, x_t, obstacles, n_obs, u_out, U_out, info, S(stream));
+}
+
 
 ce_status ce_mppi_set_launch_mode(ce_mppi_planner* P, int32_t mode) {
   if (!P) return fail(CE_EINVAL, "planner is NULL");
@@ -684,6 +721,9 @@ ce_status ce_mppi_replan_from_rollouts(ce_mppi_planner* P, const float* x_t, con
   const Bufs& b = P->b;
   const size_t K = (size_t)c.K;
   hipStream_t s = S(stream);
+  ce_status busy = check_not_busy(P, s);
+  if (busy != CE_OK) return busy;
+  mark_stream(P, s);
   hipError_t e = hipMemcpyAsync(b.S, S_in, K * 4, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(b.col, collide, K * 4, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(b.first, first_obs, K * 4, hipMemcpyDeviceToDevice, s);
@@ -798,6 +838,35 @@ ce_status ce_mppi_reset_history(ce_mppi_planner* P, void* stream) {
   ps.hist_count = 0;
   ps.hist_nobs = -1;
   return write_persist(P, ps, S(stream));
+}
+
+ce_status ce_mppi_set_history(ce_mppi_planner* P, const float* hist, int32_t h_count, int32_t n_obs,
+                              void* stream) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  const Cfg& c = P->c;
+  if (h_count < 0 || n_obs < 0 || n_obs > c.max_obs)
+    return fail(CE_EINVAL, "h_count must be >= 0 and n_obs within 0..max_obstacles");
+  if (h_count > 0 && n_obs > 0 && !hist) return fail(CE_EINVAL, "hist is NULL");
+  DeviceGuard guard(P->cfg.device);
+  hipStream_t s = S(stream);
+  const int keep = h_count < c.H ? h_count : c.H;
+  // entry i (0 = newest) goes to ring slot head - i
+  const int head = keep > 0 ? keep - 1 : c.H - 1;
+  const size_t row = (size_t)n_obs * c.p;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < keep && row > 0 && e == hipSuccess; ++i) {
+    const int slot = ((head - i) % c.H + c.H) % c.H;
+    e = hipMemcpyAsync(P->b.hist + (size_t)slot * c.max_obs * c.p, hist + (size_t)i * row,
+                       row * sizeof(float), hipMemcpyDeviceToDevice, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "set_history");
+  Persist ps;
+  ce_status st = read_persist(P, ps, s);
+  if (st != CE_OK) return st;
+  ps.hist_head = head;
+  ps.hist_count = keep;
+  ps.hist_nobs = keep > 0 ? n_obs : -1;
+  return write_persist(P, ps, s);
 }
 
 ce_status ce_mppi_set_step(ce_mppi_planner* P, uint64_t step, void* stream) {

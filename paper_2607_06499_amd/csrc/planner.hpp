@@ -47,9 +47,20 @@ struct ce_mppi_planner {
   int launch_mode = CE_LAUNCH_GRAPH;
   cemppi::ReplanGraph g;
   cemppi::Timing t;
+  // stream of the last replan (or batch replan) of this planner
+  hipStream_t last_stream = nullptr;
+  bool used = false;
 };
 
 namespace cemppi {
+
+// Record the stream a planner was last replanned on (single or batched).
+void mark_stream(ce_mppi_planner* P, hipStream_t s);
+
+// ce_mppi_replan without the in-flight check, for callers that order the
+// planner's replans themselves (the server); records the stream used.
+ce_status replan_unchecked(ce_mppi_planner* P, const float* x_t, const float* obstacles, int32_t n_obs,
+                           float* u_out, float* U_out, ce_mppi_info* info, hipStream_t s);
 
 // Error reporting into the thread's last-error string (defined in capi.cpp).
 ce_status set_error(ce_status s, const std::string& msg);

@@ -153,8 +153,9 @@ hipError_t start_launch(ce_mppi_server* S, Launch& L, std::vector<Request*>& tak
     // each request through its session's own single-planner replan
     for (int q = 0; q < count; ++q) {
       const ce_mppi_batch_io& a = io[q];
-      if (ce_mppi_replan(S->sessions[members[q]], a.x_t, a.obstacles, a.n_obs, a.u_out, nullptr,
-                         static_cast<ce_mppi_info*>(a.info), L.stream) != CE_OK)
+      // the scheduler orders each session's requests (one in flight at most)
+      if (replan_unchecked(S->sessions[members[q]], a.x_t, a.obstacles, a.n_obs, a.u_out, nullptr,
+                           static_cast<ce_mppi_info*>(a.info), L.stream) != CE_OK)
         return hipErrorUnknown;
     }
   } else if (ce_mppi_batch_replan_subset(S->batch, members.data(), count, io.data(), L.stream) != CE_OK) {
