@@ -37,6 +37,7 @@ METRIC = "CE-MPPI replans/s + rollout-steps/s at K=8192; p50/p99 replan latency"
 # 157.3 TFLOP/s counts the packed (two-wide) FMA
 PEAK_FP32_TFLOPS = 78.6
 PEAK_FP32_PACKED_TFLOPS = 157.3
+N_CU, CLOCK_HZ = 256, 2.4e9
 PEAK_HBM_GBS = 8000.0
 LOOP_WARM, LOOP_LEN = 50, 400
 
@@ -651,12 +652,17 @@ def main():
     }
     if valu_rec:
         # executed FP32 work and VALU issue from the committed counter run
+        # at the live kernel time: the issue ceiling is one wave64 VALU
+        # instruction per CU per cycle (four 16-lane SIMDs, four cycles each)
         cf = valu_rec["fp32_flop_per_launch"]
+        vi = valu_rec["valu_insts_per_launch"]
         roofline["counters"] = {
             "fp32_flop_per_launch": cf,
             "fp32_tflops_at_kernel_ms": round(cf / t_roll / 1e12, 4),
-            "valu_issue_utilisation": valu_rec["valu_issue_utilisation"],
-            "valu_insts_per_launch": valu_rec["valu_insts_per_launch"],
+            "fp32_frac_of_peak": round(cf / t_roll / 1e12 / PEAK_FP32_TFLOPS, 4),
+            "valu_insts_per_launch": vi,
+            "valu_issue_utilisation": round(vi / (N_CU * CLOCK_HZ * t_roll), 4),
+            "fp32_share_of_valu": valu_rec["fp32_share_of_valu"],
             "source": "profiles/rollout_unicycle_k8192_n50_valu.json",
         }
     out = {
