@@ -332,6 +332,8 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_lab = cv.take<int>(K);
   const size_t o_cm = cv.take<unsigned long long>(nw), o_hm = cv.take<unsigned long long>(nw);
   const size_t o_tadj = cv.take<unsigned long long>(kMaxTrees);
+  const bool with_adj = c.K <= kAdjMaxK;
+  const size_t o_adj = cv.take<uint4>(with_adj ? (size_t)c.ntile * c.ntile * kTile : 0);
   const size_t o_ccost = cv.take<float>((size_t)c.mcap), o_cdir = cv.take<float>((size_t)c.mcap * 4);
   const size_t o_csize = cv.take<int>((size_t)c.mcap), o_csmin = cv.take<float>((size_t)c.mcap);
   // update partials, then rows that stay zero so the final combination can
@@ -374,6 +376,7 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   b.coremask = reinterpret_cast<unsigned long long*>(base + o_cm);
   b.hookmask = reinterpret_cast<unsigned long long*>(base + o_hm);
   b.tadj = reinterpret_cast<unsigned long long*>(base + o_tadj);
+  b.adj = with_adj ? reinterpret_cast<uint4*>(base + o_adj) : nullptr;
   b.c_cost = reinterpret_cast<float*>(base + o_ccost);
   b.c_dir = reinterpret_cast<float*>(base + o_cdir);
   b.c_size = reinterpret_cast<int*>(base + o_csize);

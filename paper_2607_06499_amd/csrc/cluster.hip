@@ -27,6 +27,9 @@
 //             lowest core index of the cluster
 // With more than 64 trees, steps 4-5 are replaced by an exact
 // single-workgroup union-find over the core graph.
+// A single planner of at most kAdjMaxK rollouts runs steps 1, 2 and 4 on an
+// eps-adjacency bitmap instead (1b, 2b, 4b below): one tiled pass evaluates
+// each pair once and stores the outcome, the other two read bits.
 #include "device.hpp"
 #include "launch.hpp"
 
@@ -55,6 +58,7 @@ template <>
 struct ZVec<2> {
   using T = float2;
   static __device__ __forceinline__ T far() { return make_float2(1e30f, 1e30f); }
+  static __device__ __forceinline__ T nfar() { return make_float2(-1e30f, -1e30f); }
   static __device__ __forceinline__ float d2(T a, T b) { return dist2_2(a.x, a.y, b.x, b.y); }
   static __device__ __forceinline__ int key(T a) {
     return (int)(spread2((unsigned)morton_q(a.x, 64)) | (spread2((unsigned)morton_q(a.y, 64)) << 1));
@@ -65,6 +69,7 @@ template <>
 struct ZVec<3> {
   using T = float4;
   static __device__ __forceinline__ T far() { return make_float4(1e30f, 1e30f, 1e30f, 0.f); }
+  static __device__ __forceinline__ T nfar() { return make_float4(-1e30f, -1e30f, -1e30f, 0.f); }
   static __device__ __forceinline__ float d2(T a, T b) { return dist2_3(a.x, a.y, a.z, b.x, b.y, b.z); }
   static __device__ __forceinline__ int key(T a) {
     return (int)(spread3((unsigned)morton_q(a.x, 16)) | (spread3((unsigned)morton_q(a.y, 16)) << 1) |
@@ -613,6 +618,43 @@ __device__ int tree_prefix(const Bufs& b, int V, int* s_woff, unsigned long long
   return tot;
 }
 
+// The same numbering in two steps, so that a kernel can request the flag
+// words together with its other operands: root_words loads this thread's
+// words (the partition of tree_prefix, at most PER words), tree_prefix_of
+// numbers them.
+template <int NT, int PER>
+__device__ __forceinline__ void root_words(const Bufs& b, int V, unsigned long long (&w)[PER], int& lo,
+                                           int& hi) {
+  const int nwords = (V + 63) >> 6;
+  const int per = (nwords + NT - 1) / NT;
+  lo = min((int)threadIdx.x * per, nwords);
+  hi = min(lo + per, nwords);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) w[i] = lo + i < hi ? (b.coremask[lo + i] & ~b.hookmask[lo + i]) : 0ull;
+}
+
+template <int NT, int PER>
+__device__ int tree_prefix_of(const unsigned long long (&w)[PER], int lo, int hi, int* s_woff,
+                              unsigned long long* s_rm) {
+  int mine = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i)
+    if (lo + i < hi) {
+      s_rm[lo + i] = w[i];
+      mine += __popcll(w[i]);
+    }
+  int tot;
+  int off = block_excl_scan<NT>(mine, &tot);
+#pragma unroll
+  for (int i = 0; i < PER; ++i)
+    if (lo + i < hi) {
+      s_woff[lo + i] = off;
+      off += __popcll(w[i]);
+    }
+  __syncthreads();
+  return tot;
+}
+
 __device__ __forceinline__ int tree_id(const unsigned long long* s_rm, const int* s_woff, int r) {
   const int w = r >> 6, bit = r & 63;
   const unsigned long long below = bit ? (s_rm[w] & ((1ull << bit) - 1ull)) : 0ull;
@@ -736,6 +778,278 @@ __global__ __launch_bounds__(kTile * CS) void k_tree_adj(Cfg c, Bufs b, const fl
   tree_adj_body<P, false, CS>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, zin, Vin);
 }
 
+// ---------------------------------------------------------------------------
+// DBSCAN on the eps-adjacency bitmap (single planner, K <= kAdjMaxK).  The
+// three distance passes above each evaluate about half of all pairs; here one
+// tiled pass evaluates every pair once and keeps the outcome as bits, and the
+// core-neighbour and tree-adjacency passes read bits.  adj[J * stride + k]
+// (stride = ntile * kTile) holds row k's neighbours in column tile J: bit b of
+// component i is the pair (k, J * kTile + 32 i + b).  Every decision is the
+// FP32 predicate of the distance passes (the distance of (k, l) and of (l, k)
+// is the same number), so the clusters are the same.
+
+// v_writelane_b32: the returned register equals `old` except in lane `lane`,
+// which takes the wave-uniform `v`
+extern "C" __device__ int lane_write(int v, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// 1b. pairs of the upper triangle of tiles (J >= I), each once.  Block (g, I)
+// takes row tile I against the column tiles J >= I of group g (COLG tiles);
+// with CS > 1, CS threads share a row, each taking 1/CS of every column tile.
+// A thread's hits are its row's word of tile J; for J > I the wave's ballot of
+// column t (that column's neighbours among the wave's 64 rows) is moved into
+// lane t with writelane and stored as half of the column's word of tile I.
+// Counts are the popcounts of both (exact, not capped at minPts).
+template <int P, int COLG, int CS>
+__global__ __launch_bounds__(kTile * CS) void k_adj(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  using ZT = typename ZVec<P>::T;
+  constexpr int SPAN = kTile / CS, NW = SPAN / 32, NSET = (SPAN + 63) / 64;
+  static_assert(SPAN % 32 == 0, "row words are 32-bit");
+  __shared__ ZT s_z[kTile];
+  __shared__ int s_cc[2][kTile];
+  __shared__ int s_rc[CS][kTile];
+  const int r = (int)(threadIdx.x & (kTile - 1)), q = (int)(threadIdx.x / kTile);
+  const int lane = (int)(threadIdx.x & (kWave - 1)), half = r / kWave;
+  const int V = dbscan_V(b, zin, Vin);
+  const int nt = ntiles_of(V);
+  const int I = (int)blockIdx.y, g = (int)blockIdx.x;
+  const int J0 = max(g * COLG, I), J1 = min(g * COLG + COLG, nt);
+  if (I >= nt || J0 >= J1) return;
+  const ZT* z = reinterpret_cast<const ZT*>(zin ? zin : b.z);
+  const size_t stride = (size_t)c.ntile * kTile;
+  const int k = I * kTile + r;
+  // rows past V sit at +1e30, columns past V at -1e30: no pair with either
+  // is a hit (the squared distance overflows to infinity)
+  const ZT zk = k < V ? z[k] : ZVec<P>::far();
+  ZT zl[COLG];
+#pragma unroll
+  for (int u = 0; u < COLG; ++u) {
+    const int l = (J0 + u) * kTile + r;
+    zl[u] = (q == 0 && J0 + u < J1 && l < V) ? z[l] : ZVec<P>::nfar();
+  }
+  const float r2 = c.eps2;
+  int cnt = 0;
+#pragma unroll
+  for (int u = 0; u < COLG; ++u) {
+    const int J = J0 + u;
+    if (J >= J1) break;
+    if (u > 0) __syncthreads();  // the previous tile's readers are done
+    if (q == 0) s_z[r] = zl[u];
+    __syncthreads();
+    uint32_t w[NW];
+    int clo[NSET], chi[NSET];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = 0u;
+#pragma unroll
+    for (int s = 0; s < NSET; ++s) clo[s] = chi[s] = 0;
+#pragma unroll
+    for (int t = 0; t < SPAN; ++t) {
+      const bool h = ZVec<P>::d2(zk, s_z[q * SPAN + t]) <= r2;
+      w[t >> 5] |= h ? (1u << (t & 31)) : 0u;
+      const unsigned long long bal = __ballot(h);
+      clo[t >> 6] = lane_write((int)(uint32_t)bal, t & 63, clo[t >> 6]);
+      chi[t >> 6] = lane_write((int)(uint32_t)(bal >> 32), t & 63, chi[t >> 6]);
+    }
+    uint32_t* rw = reinterpret_cast<uint32_t*>(b.adj + (size_t)J * stride + k) + q * NW;
+    if constexpr (NW == 4)
+      *reinterpret_cast<uint4*>(rw) = make_uint4(w[0], w[1], w[2], w[3]);
+    else if constexpr (NW == 2)
+      *reinterpret_cast<uint2*>(rw) = make_uint2(w[0], w[1]);
+    else
+      rw[0] = w[0];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) cnt += __popc(w[i]);
+    if (J > I) {
+#pragma unroll
+      for (int s = 0; s < NSET; ++s) {
+        const int t = 64 * s + lane;
+        if (t < SPAN) {
+          const int tc = q * SPAN + t;  // column within the tile
+          uint2* cw = reinterpret_cast<uint2*>(b.adj + (size_t)I * stride + J * kTile + tc) + half;
+          *cw = make_uint2((uint32_t)clo[s], (uint32_t)chi[s]);
+          s_cc[half][tc] = __popc((uint32_t)clo[s]) + __popc((uint32_t)chi[s]);
+        }
+      }
+      __syncthreads();
+      if ((int)threadIdx.x < kTile) {
+        const int l = J * kTile + (int)threadIdx.x;
+        const int cc = s_cc[0][threadIdx.x] + s_cc[1][threadIdx.x];
+        if (l < V && cc) atomicAdd(&b.ncount[l], cc);
+      }
+    }
+  }
+  if constexpr (CS > 1) {
+    s_rc[q][r] = cnt;
+    __syncthreads();
+    if (q == 0)
+#pragma unroll
+      for (int i = 1; i < CS; ++i) cnt += s_rc[i][r];
+  }
+  if (q == 0 && k < V && cnt) atomicAdd(&b.ncount[k], cnt);
+}
+
+// 2b. lowest-index core neighbour from the bitmap.  A block takes 64 rows with
+// kMcnSplit threads each.  The core flags of all V points go to LDS first
+// (wave ballots of the counts); thread q of a row takes the column tiles q,
+// q + kMcnSplit, ... (all its words requested at once) and keeps its lowest
+// core hit, and the row's minimum is a butterfly over its kMcnSplit lanes.
+// Also writes the rows' core and hook words (one 64-bit word per block).
+__global__ __launch_bounds__(kMcnThreads) void k_mcn_bits(Cfg c, Bufs b, const float* __restrict__ zin,
+                                                        int Vin) {
+  constexpr int NWV = kMcnThreads / kWave;
+  __shared__ unsigned long long s_core[kMaxWords];
+  __shared__ int s_m[64];
+  const int V = dbscan_V(b, zin, Vin);
+  const int base = (int)blockIdx.x * 64;
+  if (base >= V) return;
+  const int lane = (int)(threadIdx.x & (kWave - 1)), wv = (int)(threadIdx.x / kWave);
+  const int nt = ntiles_of(V);
+  const size_t stride = (size_t)c.ntile * kTile;
+  const int rr = (int)threadIdx.x / kMcnSplit, q = (int)threadIdx.x % kMcnSplit;
+  const int k = base + rr;
+  // the row words do not depend on the core flags: requested first
+  uint4 a[kMcnLoads];
+#pragma unroll
+  for (int u = 0; u < kMcnLoads; ++u) {
+    const int J = q + u * kMcnSplit;
+    a[u] = (k < V && J < nt) ? b.adj[(size_t)J * stride + k] : make_uint4(0u, 0u, 0u, 0u);
+  }
+  const int nw = (V + 63) >> 6;
+  for (int w0 = wv; w0 < nw; w0 += NWV * 8) {
+    int n[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int pt = (w0 + u * NWV) * 64 + lane;
+      n[u] = pt < V ? b.ncount[pt] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const unsigned long long m = __ballot(n[u] >= c.min_pts);
+      const int w = w0 + u * NWV;
+      if (lane == 0 && w < nw) s_core[w] = m;
+    }
+  }
+  __syncthreads();
+  // descending, so the last hit kept is the one of the lowest tile (the
+  // flag words past V may be stale in LDS: the row has no bit there)
+  int m = kInt32Max;
+#pragma unroll
+  for (int u = kMcnLoads - 1; u >= 0; --u) {
+    const int J = q + u * kMcnSplit;
+    if (J >= nt) continue;
+    const unsigned long long lo = (((unsigned long long)a[u].y << 32) | a[u].x) & s_core[2 * J];
+    const unsigned long long hi = (((unsigned long long)a[u].w << 32) | a[u].z) & s_core[2 * J + 1];
+    if (lo) m = J * kTile + __ffsll((long long)lo) - 1;
+    else if (hi) m = J * kTile + 64 + __ffsll((long long)hi) - 1;
+  }
+#pragma unroll
+  for (int off = 1; off < kMcnSplit; off <<= 1) m = min(m, __shfl_xor(m, off, kWave));
+  if (q == 0) {
+    if (k < V) b.mcn[k] = m;
+    s_m[rr] = m;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    const int kk = base + lane;
+    const unsigned long long hk = __ballot(kk < V && s_m[lane] < kk);
+    if (lane == 0) {
+      b.hookmask[base >> 6] = hk;
+      b.coremask[base >> 6] = s_core[base >> 6];
+    }
+  }
+}
+
+// 4b. tree adjacency from the bitmap: block (g, I) as in the distance pass
+// (upper triangle of tiles, roots followed the same way).  For each column
+// tile the block gathers, per tree, the mask of the tile's core columns in it
+// (one ballot per tree present in a wave's 64 columns); a core row sets the
+// bit of every other tree whose mask meets its word of the tile.
+template <int COLG>
+__global__ __launch_bounds__(kTile) void k_tree_adj_bits(Cfg c, Bufs b, const float* __restrict__ zin,
+                                                         int Vin) {
+  __shared__ int s_woff[kMaxWords];
+  __shared__ unsigned long long s_rm[kMaxWords];
+  __shared__ unsigned long long s_adj[kMaxTrees];
+  __shared__ unsigned long long s_cm[kMaxTrees][2];
+  __shared__ unsigned long long s_pres[2];
+  const int V = dbscan_V(b, zin, Vin);
+  const int nt = ntiles_of(V);
+  const int I = (int)blockIdx.y, g = (int)blockIdx.x;
+  const int J0 = max(g * COLG, I), J1 = min(g * COLG + COLG, nt);
+  if (I >= nt || J0 >= J1) return;
+  const size_t stride = (size_t)c.ntile * kTile;
+  const int r = (int)threadIdx.x, lane = r & (kWave - 1), half = r / kWave;
+  const int k = I * kTile + r;
+  // every operand of the block is requested before the first wait
+  uint4 aw[COLG];
+  int ncl[COLG], rl[COLG];
+#pragma unroll
+  for (int u = 0; u < COLG; ++u) {
+    const int J = J0 + u, l = J * kTile + r;
+    const bool ok = J < J1 && l < V;
+    aw[u] = (J < J1 && k < V) ? b.adj[(size_t)J * stride + k] : make_uint4(0u, 0u, 0u, 0u);
+    ncl[u] = ok ? b.ncount[l] : 0;
+    rl[u] = ok ? b.mcn[l] : -1;
+  }
+  const int nck = k < V ? b.ncount[k] : 0;
+  const int hk = k < V ? b.mcn[k] : -1;
+  constexpr int PERW = (kAdjMaxK / 64 + kTile - 1) / kTile;
+  unsigned long long rw[PERW];
+  int wlo, whi;
+  root_words<kTile, PERW>(b, V, rw, wlo, whi);
+  int rt[COLG + 1];
+  rt[0] = nck >= c.min_pts ? hk : -1;
+#pragma unroll
+  for (int u = 0; u < COLG; ++u) rt[u + 1] = ncl[u] >= c.min_pts ? rl[u] : -1;
+  follow_roots(b.mcn, rt);
+  const int rk = rt[0];
+  if (g * COLG <= I && I < g * COLG + COLG && k < V) b.root[k] = rk;
+  const int R = tree_prefix_of<kTile, PERW>(rw, wlo, whi, s_woff, s_rm);
+  if (R < 2 || R > kMaxTrees) return;
+  if (threadIdx.x < kMaxTrees) s_adj[threadIdx.x] = 0ull;
+  const int tk = nck >= c.min_pts ? tree_id(s_rm, s_woff, rk) : -1;
+  unsigned long long mask = 0ull;
+#pragma unroll
+  for (int u = 0; u < COLG; ++u) {
+    const int J = J0 + u;
+    if (J >= J1) break;
+    const int tl = ncl[u] >= c.min_pts ? tree_id(s_rm, s_woff, rt[u + 1]) : -1;
+    __syncthreads();  // the previous tile's masks are read
+    if (threadIdx.x < kMaxTrees) {
+      s_cm[threadIdx.x][0] = 0ull;
+      s_cm[threadIdx.x][1] = 0ull;
+    }
+    __syncthreads();
+    {
+      int rem = tl;
+      unsigned long long pres = 0ull;
+      while (true) {
+        const unsigned long long act = __ballot(rem >= 0);
+        if (!act) break;
+        const int T = __shfl(rem, __ffsll((long long)act) - 1, kWave);
+        const unsigned long long bal = __ballot(rem == T);
+        if (lane == 0) s_cm[T][half] = bal;
+        pres |= 1ull << T;
+        if (rem == T) rem = -1;
+      }
+      if (lane == 0) s_pres[half] = pres;
+    }
+    __syncthreads();
+    if (tk >= 0) {
+      unsigned long long pres = (s_pres[0] | s_pres[1]) & ~(1ull << tk);
+      const unsigned long long lo = ((unsigned long long)aw[u].y << 32) | aw[u].x;
+      const unsigned long long hi = ((unsigned long long)aw[u].w << 32) | aw[u].z;
+      while (pres) {
+        const int T = __ffsll((long long)pres) - 1;
+        pres &= pres - 1ull;
+        if ((lo & s_cm[T][0]) | (hi & s_cm[T][1])) mask |= 1ull << T;
+      }
+    }
+  }
+  if (tk >= 0 && mask) atomicOr(&s_adj[tk], mask);
+  __syncthreads();
+  if (threadIdx.x < R && s_adj[threadIdx.x]) atomicOr(&b.tadj[threadIdx.x], s_adj[threadIdx.x]);
+}
+
 // 5. connected components of the tree graph and canonical cluster numbers
 // (one 1024-thread block), or the exact fallback for more than 64 trees.
 template <int P>
@@ -797,7 +1111,7 @@ __device__ void uf_fallback(const Cfg& c, const Bufs& b, const float* zin, int V
 template <int P>
 __device__ void chunk_stats(const Bufs& b, bool first, int M, const int (&lab)[kLabBatch],
                             const float (&Sa)[kLabBatch], const typename ZVec<P>::T (&ga)[kLabBatch],
-                            float (*s_red)[kStatClusters][6]) {
+                            float (*s_red)[kStatClusters][6], float (*s_tot)[6]) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   for (int c0 = 0; c0 < M; c0 += kStatClusters) {
     const int ncl = min(kStatClusters, M - c0);
@@ -865,6 +1179,13 @@ __device__ void chunk_stats(const Bufs& b, bool first, int M, const int (&lab)[k
       b.c_dir[4 * cl + 2] = g2;
       b.c_smin[cl] = mn;
       b.c_size[cl] = n;
+      if (c0 == 0) {  // the first kStatClusters clusters' totals stay in LDS for the means
+        s_tot[j][0] = sS;
+        s_tot[j][1] = g0;
+        s_tot[j][2] = g1;
+        s_tot[j][3] = g2;
+        s_tot[j][5] = (float)n;
+      }
     }
     __syncthreads();
   }
@@ -900,6 +1221,7 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
   __shared__ int s_tc[kMaxTrees];
   __shared__ int s_M;
   __shared__ float s_red[kFinThreads / kWave][kStatClusters][6];
+  __shared__ float s_tot[kStatClusters][6];
   const int V = dbscan_V(b, zin, Vin);
   // the first labelling chunk's point data and roots do not depend on the
   // tree numbering or the closure: they are requested first, so their loads
@@ -910,9 +1232,13 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
   float S0[kLabBatch];
   ZT g0[kLabBatch];
   label_loads<P>(c, b, 0, V, stats_pts, nc0, x0, S0, g0);
+  unsigned long long rw[1];
+  int wlo, whi;
+  root_words<kFinThreads, 1>(b, V, rw, wlo, whi);
+  const unsigned long long tadj0 = threadIdx.x < kMaxTrees ? b.tadj[threadIdx.x] : 0ull;
 #pragma unroll
   for (int u = 0; u < kLabBatch; ++u) r0[u] = x0[u] >= 0 ? b.root[x0[u]] : -1;
-  const int R = V > 0 ? tree_prefix<kFinThreads>(b, V, s_woff, s_rm) : 0;
+  const int R = V > 0 ? tree_prefix_of<kFinThreads, 1>(rw, wlo, whi, s_woff, s_rm) : 0;
   const bool overflow = R > kMaxTrees;
   if (threadIdx.x == 0) {
     b.ctrl->n_trees = R;
@@ -924,7 +1250,7 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
   if (R >= 2 && !overflow) {
     // the tree graph: row t holds the trees adjacent to tree t (OR-ed by
     // the tree-adjacency blocks)
-    if (threadIdx.x < R) s_adj[threadIdx.x] = b.tadj[threadIdx.x];
+    if (threadIdx.x < R) s_adj[threadIdx.x] = tadj0;
     __syncthreads();
     if (threadIdx.x < kWave) {
       const int r = threadIdx.x;
@@ -1016,16 +1342,21 @@ __device__ __forceinline__ void tree_cc_body(const Cfg& c, const Bufs& b, int bx
       if (lab_out) lab_out[a] = lab[u];
       if (cnt_out) cnt_out[a] = nc[u];
     }
-    if (stats) chunk_stats<P>(b, a0 == 0, M, lab, Sa, ga, s_red);
+    if (stats) chunk_stats<P>(b, a0 == 0, M, lab, Sa, ga, s_red, s_tot);
   }
-  // means: cost (Alg. 1 [Cluster stats]) and normalised direction (Eq. (16))
+  // means: cost (Alg. 1 [Cluster stats]) and normalised direction (Eq. (16)),
+  // from the totals in LDS (clusters past kStatClusters from global memory)
   if (stats && (int)threadIdx.x < kStatClusters) {
     for (int cl = threadIdx.x; cl < M; cl += kStatClusters) {
-      const float cnt = (float)b.c_size[cl];
-      const float vx = b.c_dir[4 * cl] / cnt, vy = b.c_dir[4 * cl + 1] / cnt;
-      const float vz = P == 3 ? b.c_dir[4 * cl + 2] / cnt : 0.f;
+      const bool lds = cl < kStatClusters;
+      const float cnt = lds ? s_tot[cl][5] : (float)b.c_size[cl];
+      const float sx = lds ? s_tot[cl][1] : b.c_dir[4 * cl], sy = lds ? s_tot[cl][2] : b.c_dir[4 * cl + 1];
+      const float sz = lds ? s_tot[cl][3] : b.c_dir[4 * cl + 2];
+      const float sc = lds ? s_tot[cl][0] : b.c_cost[cl];
+      const float vx = sx / cnt, vy = sy / cnt;
+      const float vz = P == 3 ? sz / cnt : 0.f;
       const float nv = sqrtf(__builtin_fmaf(vz, vz, __builtin_fmaf(vy, vy, vx * vx))) + c.norm_eps;
-      b.c_cost[cl] = b.c_cost[cl] / cnt;
+      b.c_cost[cl] = sc / cnt;
       b.c_dir[4 * cl] = vx / nv;
       b.c_dir[4 * cl + 1] = vy / nv;
       b.c_dir[4 * cl + 2] = P == 3 ? vz / nv : 0.f;
@@ -1545,7 +1876,16 @@ static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const floa
   // kSplit threads: their few blocks would otherwise leave the loop latency
   // exposed; larger ones launch enough blocks, and more threads would cost
   // the branches that skip the passes
-  if (c.ntile <= kSplitTiles) {
+  if (b.adj) {
+    // bitmap passes
+    // one column tile per block and four threads per row at every size (A/B
+    // on the clustering replan at K = 8192: 7.6 us against 8.3-16.4 us for
+    // one or two threads per row or two or four tiles per block)
+    const int nag = (ntile + kAdjGroup - 1) / kAdjGroup;
+    L(k_adj<P, kAdjGroup, kSplit>, dim3(nag, ntile), dim3(kTile * kSplit), c, b, zin, Vin);
+    L(k_mcn_bits, dim3(2 * ntile), dim3(kMcnThreads), c, b, zin, Vin);
+    L(k_tree_adj_bits<kColGroup>, tiles, dim3(kTile), c, b, zin, Vin);
+  } else if (c.ntile <= kSplitTiles) {
     const dim3 tb(kTile * kSplit);
     L(k_count<P, kSplit>, ctiles, tb, c, b, zin, Vin);
     L(k_mcn<P, kSplit>, ctiles, tb, c, b, zin, Vin);

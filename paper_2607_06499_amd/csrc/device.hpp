@@ -45,6 +45,14 @@ constexpr int kCntGroup = 2;   // column tiles per count / core-neighbour block 
 constexpr int kSplit = 4;       // threads per row in the tiled passes of small single planners
 constexpr int kSplitTiles = 32; // planners of at most this many tiles use them
 constexpr int kSortBins = 4096; // Morton cells of the DBSCAN spatial order
+// eps-adjacency bitmap of the single-planner DBSCAN: planners of at most
+// kAdjMaxK rollouts keep one (ceil(K/kTile)^2 * kTile * 16 bytes: 8 MiB at
+// K = 8192, 32 MiB at the limit); larger ones use the distance passes
+constexpr int kAdjMaxK = 16384;
+constexpr int kAdjGroup = 1;       // column tiles per bitmap block
+constexpr int kMcnThreads = 1024;  // core-neighbour pass on the bitmap: 64 rows per block
+constexpr int kMcnSplit = kMcnThreads / 64;  // threads per row there
+constexpr int kMcnLoads = (kAdjMaxK / kTile + kMcnSplit - 1) / kMcnSplit;  // row words per thread
 constexpr int kLabBatch = 8;   // points per thread per labelling pass
 constexpr int kRecBatch = 4;   // partial records per thread in flight at once
 constexpr int kFinRows = 8;    // update-partial rows per wave in flight at once (final combination)
@@ -138,6 +146,7 @@ struct Bufs {
   int* mcn;        // [K] lowest-index core neighbour (kInt32Max if none)
   int* root;       // [K] tree root (core points), -1 otherwise
   unsigned long long* tadj;     // [kMaxTrees] tree adjacency rows (OR of every tree-adjacency block)
+  uint4* adj;      // [ntile][ntile * kTile] eps-adjacency words (null: distance passes)
   int* label;      // [K]
   unsigned long long* coremask;  // [ceil(K/64)] core flags
   unsigned long long* hookmask;  // [ceil(K/64)] core neighbour of lower index found
