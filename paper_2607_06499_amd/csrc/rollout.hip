@@ -321,6 +321,22 @@ __device__ __forceinline__ void write_group_partials(const Bufs& b, float (*recs
   }
 }
 
+// Unicycle perturbation (Eq. (3)) of one control step: e = L g, the clamp to
+// the bounds, and the applied perturbation (clamped control - nominal); all
+// zero when `on` is false.
+__device__ __forceinline__ void perturb_clamp(const Cfg& c, float n0, float n1, float g0, float g1, bool on,
+                                              float& uv, float& uw, float& a0, float& a1) {
+  const float e0 = c.L[0] * g0;
+  const float e1 = c.L[2] * g0 + c.L[3] * g1;
+  const float t0 = n0 + e0, t1 = n1 + e1;
+  const float v = fminf(fmaxf(t0, c.umin[0]), c.umax[0]);
+  const float w = fminf(fmaxf(t1, c.umin[1]), c.umax[1]);
+  uv = on ? v : 0.f;
+  uw = on ? w : 0.f;
+  a0 = on ? (v == t0 ? e0 : v - n0) : 0.f;
+  a1 = on ? (w == t1 ? e1 : w - n1) : 0.f;
+}
+
 // ---------------------------------------------------------------------------
 // Unicycle rollouts (Sec. III-A): state (x, y, theta), control (v, omega).
 // R rounds per wave: each wave runs R rollouts per block item, the nominal
@@ -366,70 +382,84 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   // step_gaussians<2> would give.
   constexpr bool PAIRED = R >= 2 && (R % 2) == 0;
   constexpr int OWN = SEG == 64 ? 32 : 16;
-  uint32_t pw[4] = {0u, 0u, 0u, 0u};
-  for (int rr = 0; rr < R; ++rr) {
-  const int kloc = (rr * kRollWaves + wave) * SPW + sgi;
-  // one rollout per wave with 64-lane segments: k is wave-uniform (scalar)
-  const int k = SEG == 64 ? __builtin_amdgcn_readfirstlane(bx * RPB + kloc) : bx * RPB + kloc;
-  const bool inr = k < c.K;
+  // Rounds go RS at a time.  With paired Philox the two rounds that share an
+  // evaluation also share one instruction stream up to the cost, so their
+  // dependent chains (the DPP scans, the transcendentals) interleave; the
+  // arithmetic of each rollout is unchanged.
+  constexpr int RS = PAIRED ? 2 : 1;
+  for (int r0 = 0; r0 < R; r0 += RS) {
+  int kloc[RS], k[RS];
+  bool inr[RS];
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    kloc[s] = ((r0 + s) * kRollWaves + wave) * SPW + sgi;
+    // one rollout per wave with 64-lane segments: k is wave-uniform (scalar)
+    k[s] = SEG == 64 ? __builtin_amdgcn_readfirstlane(bx * RPB + kloc[s]) : bx * RPB + kloc[s];
+    inr[s] = k[s] < c.K;
+  }
 
   // noise, perturbation and clamp (Eq. (3)); applied perturbation kept
-  uint32_t qw[4] = {0u, 0u, 0u, 0u};
+  float uv[RS], uw[RS], a0[RS], a1[RS];
   if constexpr (PAIRED) {
-    if ((rr & 1) == 0) {
+    uint32_t pw[4] = {0u, 0u, 0u, 0u};
+    {
       const int q = lane / OWN, ob = lane % OWN;
-      const int orr = rr + q / SPW, osg = q % SPW;
+      const int orr = r0 + q / SPW, osg = q % SPW;
       const int ok = bx * RPB + (orr * kRollWaves + wave) * SPW + osg;
       if (ok < c.K && ob < c.B) philox((uint32_t)ob, (uint32_t)ok, step, c.stream_id, c.seed_lo, c.seed_hi, pw);
     }
-    const int src = ((rr & 1) * SPW + sgi) * OWN + (j >> 1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) qw[i] = (uint32_t)__shfl((int)pw[i], src, kWave);
-  }
-  float uv = 0.f, uw = 0.f, a0 = 0.f, a1 = 0.f;
-  if (inr && j < N) {
-    float g[2];
-    if constexpr (PAIRED) {
+    for (int s = 0; s < RS; ++s) {
+      const int src = (s * SPW + sgi) * OWN + (j >> 1);
+      uint32_t qw[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) qw[i] = (uint32_t)__shfl((int)pw[i], src, kWave);
       const bool odd = (j & 1) != 0;
-      box_muller(odd ? qw[2] : qw[0], odd ? qw[3] : qw[1], g[0], g[1]);
-    } else {
-      step_gaussians<2>(c, step, k, j, g);
+      float g0, g1;
+      box_muller(odd ? qw[2] : qw[0], odd ? qw[3] : qw[1], g0, g1);
+      perturb_clamp(c, n0, n1, g0, g1, inr[s] && j < N, uv[s], uw[s], a0[s], a1[s]);
     }
-    const float e0 = c.L[0] * g[0];
-    const float e1 = c.L[2] * g[0] + c.L[3] * g[1];
-    const float t0 = n0 + e0, t1 = n1 + e1;
-    uv = fminf(fmaxf(t0, c.umin[0]), c.umax[0]);
-    uw = fminf(fmaxf(t1, c.umin[1]), c.umax[1]);
-    a0 = uv == t0 ? e0 : uv - n0;
-    a1 = uw == t1 ? e1 : uw - n1;
+  } else {
+    uv[0] = uw[0] = a0[0] = a1[0] = 0.f;
+    if (inr[0] && j < N) {
+      float g[2];
+      step_gaussians<2>(c, step, k[0], j, g);
+      perturb_clamp(c, n0, n1, g[0], g[1], true, uv[0], uw[0], a0[0], a1[0]);
+    }
   }
   // forward simulation, Eq. (4)/(21): heading and position are prefix sums
-  const float th = th0 + seg_excl_scan<SEG>(uw * dt, j);
-  float sn, cs;
-  __sincosf(th, &sn, &cs);
-  const float px = x0 + seg_excl_scan<SEG>(uv * cs * dt, j);
-  const float py = y0 + seg_excl_scan<SEG>(uv * sn * dt, j);
-
-  // cost, Eq. (5): stage terms in lanes 0..N-1, terminal term in lane N
-  float l = 0.f;
-  if (inr && j < N) {
-    l = c.Q[0] * sq(px - c.goal[0]) + c.Q[1] * sq(py - c.goal[1]) + c.Q[2] * sq(th - c.goal[2]) +
-        c.R[0] * uv * uv + c.R[1] * uw * uw;
-  } else if (inr && j == N) {
-    l = c.Qf[0] * sq(px - c.goal[0]) + c.Qf[1] * sq(py - c.goal[1]) + c.Qf[2] * sq(th - c.goal[2]);
+  float th[RS], sn[RS], cs[RS], px[RS], py[RS], S[RS];
+#pragma unroll
+  for (int s = 0; s < RS; ++s) th[s] = th0 + seg_excl_scan<SEG>(uw[s] * dt, j);
+#pragma unroll
+  for (int s = 0; s < RS; ++s) __sincosf(th[s], &sn[s], &cs[s]);
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    px[s] = x0 + seg_excl_scan<SEG>(uv[s] * cs[s] * dt, j);
+    py[s] = y0 + seg_excl_scan<SEG>(uv[s] * sn[s] * dt, j);
   }
-  const float S = seg_sum<SEG>(l);
+  // cost, Eq. (5): stage terms in lanes 0..N-1, terminal term in lane N
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    const float lx = sq(px[s] - c.goal[0]), ly = sq(py[s] - c.goal[1]), lth = sq(th[s] - c.goal[2]);
+    const float ls = c.Q[0] * lx + c.Q[1] * ly + c.Q[2] * lth + c.R[0] * uv[s] * uv[s] + c.R[1] * uw[s] * uw[s];
+    const float lt = c.Qf[0] * lx + c.Qf[1] * ly + c.Qf[2] * lth;
+    const float l = !inr[s] ? 0.f : (j < N ? ls : (j == N ? lt : 0.f));
+    S[s] = seg_sum<SEG>(l);
+  }
 
-  if (LATE && rr == 0) {
+  if (LATE && r0 == 0) {
     prologue<0, CVM>(c, b, x_t, obs, n_obs, L, s_bad, s_closest, s_p0);
     bad = s_bad;
     closest = s_closest;
     if (bx == 0) publish(c, b, obs, n_obs, bad, closest, s_p0, step);
   }
-  const bool act = inr && !bad;
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+  const bool act = inr[s] && !bad;
   if (act && j < N) {
-    float2* ep = reinterpret_cast<float2*>(b.eps + ((size_t)k * N + j) * 2);
-    *ep = make_float2(a0, a1);
+    float2* ep = reinterpret_cast<float2*>(b.eps + ((size_t)k[s] * N + j) * 2);
+    *ep = make_float2(a0[s], a1[s]);
   }
 
   // collision of states 1..N against the obstacles: lowest index hit
@@ -439,17 +469,18 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   const bool chk = act && j >= 1 && j <= N;
   const int n_live = L.n_live;
   const float tj = (float)j * dt;
+  const float qx = px[s], qy = py[s];
   bool any = false;
   if (chk) {
     if (cv) {
       for (int i = 0; i < n_live; ++i) {
         const float4 o = L.live[i], v = L.vlive[i];
-        any |= dist2_2(px, py, __builtin_fmaf(tj, v.x, o.x), __builtin_fmaf(tj, v.y, o.y)) <= o.w;
+        any |= dist2_2(qx, qy, __builtin_fmaf(tj, v.x, o.x), __builtin_fmaf(tj, v.y, o.y)) <= o.w;
       }
     } else {
       for (int i = 0; i < n_live; ++i) {
         const float4 o = L.live[i];
-        any |= dist2_2(px, py, o.x, o.y) <= o.w;
+        any |= dist2_2(qx, qy, o.x, o.y) <= o.w;
       }
     }
   }
@@ -458,13 +489,13 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
     if (cv) {
       for (int i = n_live - 1; i >= 0; --i) {
         const float4 o = L.live[i], v = L.vlive[i];
-        hit = dist2_2(px, py, __builtin_fmaf(tj, v.x, o.x), __builtin_fmaf(tj, v.y, o.y)) <= o.w
+        hit = dist2_2(qx, qy, __builtin_fmaf(tj, v.x, o.x), __builtin_fmaf(tj, v.y, o.y)) <= o.w
                   ? L.idx[i] : hit;
       }
     } else {
       for (int i = n_live - 1; i >= 0; --i) {
         const float4 o = L.live[i];
-        hit = dist2_2(px, py, o.x, o.y) <= o.w ? L.idx[i] : hit;
+        hit = dist2_2(qx, qy, o.x, o.y) <= o.w ? L.idx[i] : hit;
       }
     }
   }
@@ -476,30 +507,32 @@ __device__ __forceinline__ void rollout_unicycle_body(const Cfg& c, const Bufs& 
   const int f1 = m1 ? __ffsll((long long)m1) - 1 : 0;
   const int col = (sgi == 0 ? m0 : m1) != 0ull;
   const int f = seg_pick_i<SEG>(hit, f0, f1);
-  const float pfx = seg_pick<SEG>(px, f0, f1), pfy = seg_pick<SEG>(py, f0, f1);
+  const float pfx = seg_pick<SEG>(qx, f0, f1), pfy = seg_pick<SEG>(qy, f0, f1);
   const int ln = N < SEG ? N : SEG - 1;
-  const float ptx = seg_bcast<SEG>(px, ln), pty = seg_bcast<SEG>(py, ln);
+  const float ptx = seg_bcast<SEG>(qx, ln), pty = seg_bcast<SEG>(qy, ln);
 
   float src[2];
   src[0] = c.ref_mode == 1 ? pfx : ptx;
   src[1] = c.ref_mode == 1 ? pfy : pty;
   if (j == 0) {
+    const int kk = k[s];
     if (act) {
-      b.S[k] = S;
-      b.col[k] = col;
-      b.first[k] = col ? f : -1;
-      b.pT[2 * k] = ptx;
-      b.pT[2 * k + 1] = pty;
-      b.pF[2 * k] = col ? pfx : 0.f;
-      b.pF[2 * k + 1] = col ? pfy : 0.f;
+      b.S[kk] = S[s];
+      b.col[kk] = col;
+      b.first[kk] = col ? f : -1;
+      b.pT[2 * kk] = ptx;
+      b.pT[2 * kk + 1] = pty;
+      b.pF[2 * kk] = col ? pfx : 0.f;
+      b.pF[2 * kk + 1] = col ? pfy : 0.f;
       // unit terminal displacement, Eq. (15)
       const float ex = ptx - x0, ey = pty - y0;
       const float den = __builtin_amdgcn_sqrtf(__builtin_fmaf(ey, ey, ex * ex)) + c.norm_eps;
       const float inv = __builtin_amdgcn_rcpf(den);  // v_sqrt_f32 and one v_rcp_f32
-      b.g[2 * k] = ex * inv;
-      b.g[2 * k + 1] = ey * inv;
+      b.g[2 * kk] = ex * inv;
+      b.g[2 * kk + 1] = ey * inv;
     }
-    rollout_contrib(s_rec[kloc], act, col, col ? f : -1, closest, S, src, 2);
+    rollout_contrib(s_rec[kloc[s]], act, col, col ? f : -1, closest, S[s], src, 2);
+  }
   }
   }
   write_group_partials(b, s_rec, RPB, bx);
