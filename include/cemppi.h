@@ -239,8 +239,9 @@ enum {
   CE_DBG_CLUSTER_COST = 11, /* float [M]         mean cost per cluster             */
   CE_DBG_CLUSTER_DIR = 12,  /* float [M][p]      normalised mean direction Eq.(16) */
   CE_DBG_CLUSTER_SIZE = 13, /* int32 [M]                                           */
-  CE_DBG_TREES = 14,        /* int32 [2]  hook-forest trees, 1 if the exact         */
-                            /*            union-find fallback ran (> 64 trees)      */
+  CE_DBG_TREES = 14,        /* int32 [2]  hook-forest trees (angular runs of core  */
+                            /*            buckets on the window path), 1 if the     */
+                            /*            exact union-find fallback ran (> 64 trees) */
   CE_DBG_COUNT_ = 15
 };
 /* Copy the named buffer into device memory dst of `bytes` bytes (at most the
@@ -274,6 +275,38 @@ ce_status ce_mppi_replan_from_rollouts(ce_mppi_planner* planner, const float* x_
  * ncount (may be NULL), label; n_clusters (device int32, may be NULL). */
 ce_status ce_mppi_stage_dbscan(ce_mppi_planner* planner, const float* z, int32_t V, int32_t* ncount,
                                int32_t* label, int32_t* n_clusters, void* stream);
+
+/* ---- DBSCAN path (Sec. II-B.2) ----
+ *
+ * Every path computes the same clustering: closed eps-ball, minPts counting
+ * the point itself, a border point in the cluster of its lowest-index core
+ * neighbour, clusters numbered by their lowest core index.  The neighbour
+ * relation is the same FP32 distance test on every path, so counts, labels,
+ * cluster statistics and the replan's outputs are identical bit for bit;
+ * only the work differs.
+ *   CE_DBSCAN_WINDOW  2-D features bucketed by angle around the unit ring on
+ *                     which the features of Eq. (13) lie: ring points inside
+ *                     a point's inner angular window are neighbours and those
+ *                     outside its outer window are not, so only the buckets
+ *                     between the windows, and features off the ring, are
+ *                     tested pair by pair.  About O(V) window lookups plus
+ *                     the boundary tests, where the others take V^2/2 pairs.
+ *                     Needs p = 2, K <= 16384 and eps in roughly [0.01, 1.4].
+ *   CE_DBSCAN_BITMAP  one tiled pass over the V^2/2 pairs into an
+ *                     eps-adjacency bitmap that the later passes read;
+ *                     K <= 16384.
+ *   CE_DBSCAN_TILED   tiled distance passes (any K, p = 2 or 3).
+ *   CE_DBSCAN_AUTO    (default) the first of these that the planner supports.
+ * The mode applies to replans and to ce_mppi_stage_dbscan; a change rebuilds
+ * the replan graph at the next replan.  The batched form always uses its own
+ * spatially sorted distance passes.  Errors: CE_EINVAL (NULL planner,
+ * unknown mode), CE_EUNSUPPORTED (the path is not available for this
+ * planner; the mode is unchanged). */
+enum { CE_DBSCAN_AUTO = 0, CE_DBSCAN_WINDOW = 1, CE_DBSCAN_BITMAP = 2, CE_DBSCAN_TILED = 3 };
+ce_status ce_mppi_set_dbscan_mode(ce_mppi_planner* planner, int32_t mode);
+/* The path replans and stage calls use now (CE_DBSCAN_WINDOW, _BITMAP or
+ * _TILED) into *path.  Errors: CE_EINVAL for NULL arguments. */
+ce_status ce_mppi_get_dbscan_path(const ce_mppi_planner* planner, int32_t* path);
 
 /* ---- allocation-free DBSCAN ----
  *

@@ -26,6 +26,7 @@ BRANCH_CLUSTER, BRANCH_FALLBACK, BRANCH_ALL_COLLIDE = 0, 1, 2
 STATUS_FALLBACK, STATUS_ALL_COLLIDE, STATUS_NO_CLUSTER, STATUS_DYN_STATIC, STATUS_NONFINITE = (
     1, 2, 4, 8, 16)
 LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
+DBSCAN_AUTO, DBSCAN_WINDOW, DBSCAN_BITMAP, DBSCAN_TILED = 0, 1, 2, 3
 SERVE_BATCHED, SERVE_PLAIN = 0, 1
 (DBG_COST, DBG_COLLIDE, DBG_FIRST_OBS, DBG_P_TERM, DBG_P_FIRST, DBG_EPS, DBG_V_IDX, DBG_Z, DBG_G,
  DBG_NCOUNT, DBG_LABEL, DBG_CLUSTER_COST, DBG_CLUSTER_DIR, DBG_CLUSTER_SIZE, DBG_TREES) = range(15)
@@ -187,6 +188,8 @@ def load():
         "ce_mppi_dbscan_noalloc": [C.c_int32, _vp, C.c_int32, C.c_int32, C.c_float, C.c_int32, _vp, _vp,
                                    _vp, _vp],
         "ce_mppi_set_launch_mode": [_vp, C.c_int32],
+        "ce_mppi_set_dbscan_mode": [_vp, C.c_int32],
+        "ce_mppi_get_dbscan_path": [_vp, C.POINTER(C.c_int32)],
         "ce_mppi_tune_launch": [_vp, _vp, _vp, C.c_int32, _vp, C.c_int32, _vp,
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "ce_mppi_timing_enable": [_vp, C.c_int32],
@@ -445,6 +448,15 @@ class Planner:
     # -- launch mode and timing
     def set_launch_mode(self, mode: int):
         _check("ce_mppi_set_launch_mode", load().ce_mppi_set_launch_mode(self.handle, int(mode)))
+
+    # -- DBSCAN path
+    def set_dbscan_mode(self, mode: int):
+        _check("ce_mppi_set_dbscan_mode", load().ce_mppi_set_dbscan_mode(self.handle, int(mode)))
+
+    def dbscan_path(self) -> int:
+        v = C.c_int32()
+        _check("ce_mppi_get_dbscan_path", load().ce_mppi_get_dbscan_path(self.handle, C.byref(v)))
+        return int(v.value)
 
     def tune_launch(self, x_t, obstacles=None, reps: int = 50, stream=None):
         """Time both launch modes on these inputs and keep the faster;

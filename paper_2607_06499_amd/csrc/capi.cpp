@@ -125,6 +125,47 @@ ce_status validate(const ce_mppi_config* c) {
   return CE_OK;
 }
 
+// Angular windows of the 2-D DBSCAN (cluster.hip, k_wplace .. k_wcc), in
+// double precision.  Ring points have |z| in [s_lo, s_hi]: the features of
+// Eq. (13) are unit directions scaled by |d| / (|d| + eps_n), so this holds
+// for every feasible rollout whose terminal point is more than about 1 mm
+// from the reference point (others are tested against every point).  For a
+// pair of ring points at angular separation phi,
+//   4 s_lo^2 sin^2(phi/2) <= |a - b|^2 <= (s_hi - s_lo)^2 + 4 s_hi^2 sin^2(phi/2):
+// below the inner angle the pair is surely within eps (FP32 rounding of the
+// distance test is far inside the 1e-4 relative margin), above the outer
+// angle surely not.  The windows lose the error of two computed angles
+// (atan2f, the shift by pi and the scaling to buckets: well under 1e-5 rad
+// each) and 1e-2 bucket for the rounding of u +- w.  Leaves w_g = 0 (path
+// off) where the windows do not fit: 3-D features, K beyond the key's slot
+// bits, an inner window under five buckets (eps below about 0.01) or an
+// outer window of a quarter turn or more (eps above about 1.4).
+void set_windows(Cfg& c) {
+  const double pi = 3.14159265358979323846, beta = 2.0 * pi / kWinBins;
+  const double delta = 1e-3;
+  const double s_lo = (1.0 - delta) * (1.0 - 1e-6), s_hi = (1.0 + 2e-6) * (1.0 + 1e-6);
+  const double e2 = (double)c.eps2;
+  const double e_ang = 2e-5;
+  c.w_scale = (float)(kWinBins / (2.0 * pi));
+  c.w_r2lo = (float)((1.0 - delta) * (1.0 - delta));
+  c.w_r2hi = (float)((1.0 + 2e-6) * (1.0 + 2e-6));
+  c.w_in = c.w_out = 0.f;
+  c.w_g = c.w_gout = 0;
+  const double ain = (e2 * (1.0 - 1e-4) - (s_hi - s_lo) * (s_hi - s_lo)) / (4.0 * s_hi * s_hi);
+  const double aout = e2 * (1.0 + 1e-4) / (4.0 * s_lo * s_lo);
+  if (c.p != 2 || c.K > kWinMaxK || !(ain > 0.0) || !(aout < 0.5)) return;
+  const double din = 2.0 * std::asin(std::sqrt(ain)), dout = 2.0 * std::asin(std::sqrt(aout));
+  const double win = (din - e_ang) / beta - 1e-2, wout = (dout + e_ang) / beta + 1e-2;
+  const int g = (int)std::floor(win) - 1, gout = (int)std::floor(wout) + 1;
+  // runs need gaps of at least four buckets (at most kWinMaxRuns runs), and
+  // only adjacent runs may be linked
+  if (g < 3 || 2 * g + 2 <= gout) return;
+  c.w_in = (float)win;
+  c.w_out = (float)wout;
+  c.w_g = g;
+  c.w_gout = gout;
+}
+
 void build_cfg(const ce_mppi_config* u, Cfg& c) {
   std::memset(&c, 0, sizeof(c));
   c.dyn = u->dynamics;
@@ -225,6 +266,8 @@ void build_cfg(const ce_mppi_config* u, Cfg& c) {
   c.ntile = (c.K + kTile - 1) / kTile;
   c.nblk_upd = (c.K + kUpdChunk - 1) / kUpdChunk;
   c.mcap = c.K;
+  set_windows(c);
+  c.dbpath = c.w_g > 0 ? 0 : (c.K <= kAdjMaxK ? 1 : 2);
 }
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -334,6 +377,13 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_tadj = cv.take<unsigned long long>(kMaxTrees);
   const bool with_adj = c.K <= kAdjMaxK;
   const size_t o_adj = cv.take<uint4>(with_adj ? (size_t)c.ntile * c.ntile * kTile : 0);
+  const bool with_win = c.w_g > 0;
+  const size_t wk = with_win ? K : 0;
+  const size_t o_wcnt = cv.take<int>(with_win ? kWinBins + 1 : 0);
+  const size_t o_wstart = cv.take<int>(with_win ? kWinBins + 2 : 0);
+  const size_t o_wbmin = cv.take<int>(with_win ? kWinBins : 0);
+  const size_t o_wkey = cv.take<int>(wk), o_wnc = cv.take<int>(wk);
+  const size_t o_wuf = cv.take<int>(with_win ? 3 * (kWinMaxRuns + K) : 0);
   const size_t o_ccost = cv.take<float>((size_t)c.mcap), o_cdir = cv.take<float>((size_t)c.mcap * 4);
   const size_t o_csize = cv.take<int>((size_t)c.mcap), o_csmin = cv.take<float>((size_t)c.mcap);
   // update partials, then rows that stay zero so the final combination can
@@ -377,6 +427,12 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   b.hookmask = reinterpret_cast<unsigned long long*>(base + o_hm);
   b.tadj = reinterpret_cast<unsigned long long*>(base + o_tadj);
   b.adj = with_adj ? reinterpret_cast<uint4*>(base + o_adj) : nullptr;
+  b.wcnt = with_win ? reinterpret_cast<int*>(base + o_wcnt) : nullptr;
+  b.wstart = with_win ? reinterpret_cast<int*>(base + o_wstart) : nullptr;
+  b.wbmin = with_win ? reinterpret_cast<int*>(base + o_wbmin) : nullptr;
+  b.wkey = with_win ? reinterpret_cast<int*>(base + o_wkey) : nullptr;
+  b.wnc = with_win ? reinterpret_cast<int*>(base + o_wnc) : nullptr;
+  b.wuf = with_win ? reinterpret_cast<int*>(base + o_wuf) : nullptr;
   b.c_cost = reinterpret_cast<float*>(base + o_ccost);
   b.c_dir = reinterpret_cast<float*>(base + o_cdir);
   b.c_size = reinterpret_cast<int*>(base + o_csize);
@@ -558,6 +614,38 @@ ce_status ce_mppi_replan(ce_mppi_planner* P, const float* x_t, const float* obst
   return replan_unchecked(P, x_t, obstacles, n_obs, u_out, U_out, info, S(stream));
 }
 
+
+ce_status ce_mppi_set_dbscan_mode(ce_mppi_planner* P, int32_t mode) {
+  if (!P) return fail(CE_EINVAL, "planner is NULL");
+  Cfg& c = P->c;
+  int path;
+  switch (mode) {
+    case CE_DBSCAN_AUTO: path = P->b.wcnt ? 0 : (P->b.adj ? 1 : 2); break;
+    case CE_DBSCAN_WINDOW:
+      if (!P->b.wcnt)
+        return fail(CE_EUNSUPPORTED, "angular windows need 2-D features, K <= 16384 and eps in [0.01, 1.4]");
+      path = 0;
+      break;
+    case CE_DBSCAN_BITMAP:
+      if (!P->b.adj) return fail(CE_EUNSUPPORTED, "the eps-adjacency bitmap needs K <= 16384");
+      path = 1;
+      break;
+    case CE_DBSCAN_TILED: path = 2; break;
+    default: return fail(CE_EINVAL, "unknown DBSCAN mode");
+  }
+  if (path != c.dbpath) {
+    DeviceGuard guard(P->cfg.device);
+    drop_graph(P->g);  // the recorded chain holds the previous path's kernels
+    c.dbpath = path;
+  }
+  return CE_OK;
+}
+
+ce_status ce_mppi_get_dbscan_path(const ce_mppi_planner* P, int32_t* path) {
+  if (!P || !path) return fail(CE_EINVAL, "planner or path is NULL");
+  *path = P->c.dbpath == 0 ? CE_DBSCAN_WINDOW : (P->c.dbpath == 1 ? CE_DBSCAN_BITMAP : CE_DBSCAN_TILED);
+  return CE_OK;
+}
 
 ce_status ce_mppi_set_launch_mode(ce_mppi_planner* P, int32_t mode) {
   if (!P) return fail(CE_EINVAL, "planner is NULL");

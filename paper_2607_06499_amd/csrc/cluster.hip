@@ -194,7 +194,29 @@ __device__ __forceinline__ Totals decide(const Cfg& c, const float* tot, int bad
 // Pruning (Eq. (9)-(10)), reference point (Eq. (11)), stable compaction of V
 // in ascending rollout order, features z (Eq. (13)) and the DBSCAN arrays.
 // Block 0 publishes the totals.
-template <int P>
+// ---------------------------------------------------------------------------
+// Angular buckets of the windowed DBSCAN (k_wplace .. k_wcc below).  The
+// bucket coordinate of a feature is its angle mapped to [0, kWinBins]; a
+// ring point has a squared norm within [w_r2lo, w_r2hi]; every other point
+// goes to the extra bucket kWinBins ("off the ring").
+__device__ __forceinline__ float win_u(const Cfg& c, float2 z) {
+  return fmaxf(0.f, (atan2f(z.y, z.x) + 3.14159265f) * c.w_scale);
+}
+__device__ __forceinline__ int win_bucket(float u) { return min((int)u, kWinBins - 1); }
+__device__ __forceinline__ bool win_ring(const Cfg& c, float2 z) {
+  const float n2 = __builtin_fmaf(z.y, z.y, z.x * z.x);
+  return n2 >= c.w_r2lo && n2 <= c.w_r2hi;
+}
+// bucket and slot of point `rank`: the slot is its arrival order in the
+// bucket (any order serves: no result depends on the order inside a bucket)
+__device__ __forceinline__ void win_bin(const Cfg& c, const Bufs& b, float2 zz, int rank) {
+  const int bkt = win_ring(c, zz) ? win_bucket(win_u(c, zz)) : kWinBins;
+  const int slot = atomicAdd(&b.wcnt[bkt], 1);
+  b.wkey[rank] = (bkt << kWinShift) | slot;
+}
+__device__ __forceinline__ void win_bin(const Cfg&, const Bufs&, float4, int) {}
+
+template <int P, bool BIN = false>
 __device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx, int by, int nbx) {
   using ZT = typename ZVec<P>::T;
   __shared__ float s_tot[kPart + 1];
@@ -279,6 +301,7 @@ __device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx
     gg = make_float4(g[0], g[1], g[2], 0.f);
   }
   reinterpret_cast<ZT*>(b.z)[rank] = zz;
+  if constexpr (BIN) win_bin(c, b, zz, rank);
   reinterpret_cast<ZT*>(b.gv)[rank] = gg;
   b.vidx[rank] = k;
   b.Sv[rank] = Sk;
@@ -290,9 +313,9 @@ __device__ __forceinline__ void compact_body(const Cfg& c, const Bufs& b, int bx
   if (rank < kMaxTrees) b.tadj[rank] = 0ull;  // rows of trees 0 .. min(V, 64) - 1
 }
 
-template <int P>
+template <int P, bool BIN>
 __global__ __launch_bounds__(256) void k_compact(Cfg c, Bufs b) {
-  compact_body<P>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+  compact_body<P, BIN>(c, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 // per-point DBSCAN state for a stage call on caller features
@@ -1370,6 +1393,559 @@ __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const fl
 }
 
 // ---------------------------------------------------------------------------
+// DBSCAN on angular windows: single planners with 2-D features (exact,
+// deterministic; the labels and statistics are those of the tiled passes).
+//
+// The features of Eq. (13) are unit directions scaled by |d| / (|d| + eps_n),
+// so nearly all of them lie on the unit ring.  For two ring points with norms
+// s, t in [s_lo, s_hi] and angular separation phi,
+//   4 s_lo^2 sin^2(phi/2) <= |a - b|^2 = (s - t)^2 + 4 s t sin^2(phi/2)
+//                         <= (s_hi - s_lo)^2 + 4 s_hi^2 sin^2(phi/2).
+// With the error of the computed angles taken off, every ring point of a
+// bucket inside the inner window of a point (u +- w_in in bucket units) is
+// its neighbour and no ring point outside the outer window (u +- w_out) is.
+// Only the ring points of the one or two buckets between the windows at each
+// end, and the points off the ring, are decided by the distance test: the
+// same FP32 expression as in every other DBSCAN pass, so the neighbour graph
+// is the same, and so are the counts, the core flags and the labels.
+//  W0 bin    (in the compaction) each feature's bucket and its slot there
+//  W1 place  bucket starts; the features sorted by bucket (zs, sid)
+//  W2 count  count = ring points of the inner window (two bucket starts) +
+//            hits among the boundary buckets and the off-ring points: exact;
+//            the lowest core index of every bucket (atomic minimum)
+//  W3 mcn    lowest-index core neighbour of every non-core point: a range
+//            minimum of the bucket minima over the inner window, then the
+//            boundary buckets and the off-ring points
+//  W4 cc     core buckets at most w_g apart hold core points that are
+//            neighbours for certain, so a run of such buckets is connected;
+//            two adjacent runs more than w_gout apart are not, and runs in
+//            between are linked if one core pair across the gap is; off-ring
+//            core points join through their own tests (union-find).
+//            Components are numbered by their lowest core index; labels and
+//            cluster statistics as in k_tree_cc.
+// Work: O(V) window lookups and O(V * points of the boundary buckets) tests,
+// against V^2 / 2 pair tests for the bitmap.
+
+__device__ __forceinline__ int wmod(int j) { return j & (kWinBins - 1); }
+
+// Buckets around a ring point at bucket coordinate u, as unwrapped indices
+// (bucket j stands for j mod kWinBins): the inner window [sl, sh] and the
+// boundary buckets [lb0, lb1], [rb0, rb1]; the three cover every bucket at
+// most once.  all: the inner window is the whole circle.
+struct WinRange {
+  int sl, sh, lb0, lb1, rb0, rb1;
+  bool all;
+};
+__device__ __forceinline__ WinRange win_range(const Cfg& c, float u) {
+  WinRange r;
+  r.sl = (int)ceilf(u - c.w_in);
+  r.sh = (int)floorf(u + c.w_in) - 1;
+  r.all = r.sh - r.sl + 1 >= kWinBins;
+  if (r.sh < r.sl) r.sh = r.sl - 1;
+  const int cl = (int)floorf(u - c.w_out), ch = (int)floorf(u + c.w_out);
+  r.lb0 = max(cl, r.sh + 1 - kWinBins);
+  r.lb1 = r.sl - 1;
+  r.rb0 = r.sh + 1;
+  r.rb1 = min(ch, r.lb0 + kWinBins - 1);
+  return r;
+}
+
+// sorted positions of the buckets j0..j1 (unwrapped, at most kWinBins of
+// them): [p0, p1) and [q0, q1)
+__device__ __forceinline__ void win_pos(const int* __restrict__ ws, int j0, int j1, int& p0, int& p1,
+                                        int& q0, int& q1) {
+  p0 = p1 = q0 = q1 = 0;
+  if (j1 < j0) return;
+  const int n = j1 - j0 + 1, m = wmod(j0);
+  p0 = ws[m];
+  if (m + n <= kWinBins) {
+    p1 = ws[m + n];
+  } else {
+    p1 = ws[kWinBins];
+    q1 = ws[m + n - kWinBins];
+  }
+}
+
+// number of neighbours of zk among the sorted positions [p0, p1)
+__device__ __forceinline__ int win_hits(float2 zk, const float2* __restrict__ zs, int p0, int p1, float r2) {
+  int n = 0;
+  int q = p0;
+  for (; q + 4 <= p1; q += 4) {
+    const float2 a = zs[q], b = zs[q + 1], d = zs[q + 2], e = zs[q + 3];
+    n += (ZVec<2>::d2(zk, a) <= r2 ? 1 : 0) + (ZVec<2>::d2(zk, b) <= r2 ? 1 : 0) +
+         (ZVec<2>::d2(zk, d) <= r2 ? 1 : 0) + (ZVec<2>::d2(zk, e) <= r2 ? 1 : 0);
+  }
+  for (; q < p1; ++q) n += ZVec<2>::d2(zk, zs[q]) <= r2 ? 1 : 0;
+  return n;
+}
+
+// lowest index among the core neighbours of zk at sorted positions [p0, p1)
+__device__ __forceinline__ int win_core_min(float2 zk, const Bufs& b, int p0, int p1, float r2, int min_pts,
+                                            int m) {
+  const float2* zs = reinterpret_cast<const float2*>(b.zs);
+  int q = p0;
+  for (; q + 2 <= p1; q += 2) {
+    const float2 a = zs[q], d = zs[q + 1];
+    const int na = b.wnc[q], nd = b.wnc[q + 1];
+    const int ia = b.sid[q], id = b.sid[q + 1];
+    if (na >= min_pts && ZVec<2>::d2(zk, a) <= r2) m = min(m, ia);
+    if (nd >= min_pts && ZVec<2>::d2(zk, d) <= r2) m = min(m, id);
+  }
+  if (q < p1 && b.wnc[q] >= min_pts && ZVec<2>::d2(zk, zs[q]) <= r2) m = min(m, b.sid[q]);
+  return m;
+}
+
+// W1.  Every block scans the bucket counts into LDS; block 0 publishes the
+// starts and clears the bucket minima of W2.
+__global__ __launch_bounds__(kFinThreads) void k_wplace(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  constexpr int PER = kWinBins / kFinThreads;
+  __shared__ int s_start[kWinBins + 1];
+  const int V = dbscan_V(b, zin, Vin);
+  const int base = (int)blockIdx.x * kFinThreads;
+  if (base >= V) return;
+  const float2* z = reinterpret_cast<const float2*>(zin ? zin : b.z);
+  const int t = (int)threadIdx.x, k = base + t;
+  const bool in = k < V;
+  const int key = in ? b.wkey[k] : 0;
+  const float2 zk = in ? z[k] : make_float2(0.f, 0.f);
+  int cnt[PER], sum = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    cnt[i] = b.wcnt[t * PER + i];
+    sum += cnt[i];
+  }
+  int tot;
+  int off = block_excl_scan<kFinThreads>(sum, &tot);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    s_start[t * PER + i] = off;
+    off += cnt[i];
+  }
+  if (t == 0) s_start[kWinBins] = tot;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      b.wstart[t * PER + i] = s_start[t * PER + i];
+      b.wbmin[t * PER + i] = kInt32Max;
+    }
+    if (t == 0) {
+      b.wstart[kWinBins] = tot;
+      b.wstart[kWinBins + 1] = V;
+    }
+  }
+  const int pos = s_start[key >> kWinShift] + (key & (kWinMaxK - 1));
+  if (in && pos < V) {  // (always: the counts hold exactly the V keys)
+    reinterpret_cast<float2*>(b.zs)[pos] = zk;
+    b.sid[pos] = k;
+  }
+}
+
+// W2.  One thread per sorted position.
+__global__ __launch_bounds__(256) void k_wcount(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  const int V = dbscan_V(b, zin, Vin);
+  const int pos = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (pos >= V) return;
+  const float2* zs = reinterpret_cast<const float2*>(b.zs);
+  const int* ws = b.wstart;
+  const int nring = ws[kWinBins];
+  const float2 zk = zs[pos];
+  const int k = b.sid[pos];
+  const float r2 = c.eps2;
+  int cnt;
+  if (pos < nring) {
+    const int key = b.wkey[k];
+    const WinRange r = win_range(c, win_u(c, zk));
+    if (r.all) {
+      cnt = nring;
+    } else {
+      int p0, p1, q0, q1;
+      win_pos(ws, r.sl, r.sh, p0, p1, q0, q1);
+      cnt = (p1 - p0) + (q1 - q0);
+      win_pos(ws, r.lb0, r.lb1, p0, p1, q0, q1);
+      cnt += win_hits(zk, zs, p0, p1, r2) + win_hits(zk, zs, q0, q1, r2);
+      win_pos(ws, r.rb0, r.rb1, p0, p1, q0, q1);
+      cnt += win_hits(zk, zs, p0, p1, r2) + win_hits(zk, zs, q0, q1, r2);
+    }
+    cnt += win_hits(zk, zs, nring, V, r2);
+    if (cnt >= c.min_pts) atomicMin(&b.wbmin[key >> kWinShift], k);
+  } else {
+    cnt = win_hits(zk, zs, 0, V, r2);
+  }
+  b.ncount[k] = cnt;
+  b.wnc[pos] = cnt;
+}
+
+// Range minimum over the bucket minima: within-chunk prefix and suffix
+// minima (chunks of 64 buckets) and a sparse table over the chunk minima.
+struct WinRmq {
+  int pre[kWinBins], suf[kWinBins];
+  int sp[7][kWinBins / 64];
+};
+template <int NT>
+__device__ __forceinline__ void win_rmq_build(const Bufs& b, WinRmq& q) {
+  constexpr int NCH = kWinBins / 64, NW = NT / kWave, PER = NCH / NW;
+  const int lane = (int)(threadIdx.x & (kWave - 1)), wv = (int)(threadIdx.x / kWave);
+  int v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) v[i] = b.wbmin[(wv + i * NW) * 64 + lane];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int ch = wv + i * NW;
+    int pre = v[i], suf = v[i];
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int a = __shfl_up(pre, (unsigned)d, kWave);
+      const int s = __shfl_down(suf, (unsigned)d, kWave);
+      if (lane >= d) pre = min(pre, a);
+      if (lane + d < kWave) suf = min(suf, s);
+    }
+    q.pre[ch * 64 + lane] = pre;
+    q.suf[ch * 64 + lane] = suf;
+    if (lane == kWave - 1) q.sp[0][ch] = pre;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int lev = 1; lev < 7; ++lev) {
+    const int t = (int)threadIdx.x;
+    if (t + (1 << lev) <= NCH) q.sp[lev][t] = min(q.sp[lev - 1][t], q.sp[lev - 1][t + (1 << (lev - 1))]);
+    __syncthreads();
+  }
+}
+// minimum over buckets l..r (0 <= l <= r < kWinBins)
+__device__ __forceinline__ int win_rmq(const WinRmq& q, const int* __restrict__ gmin, int l, int r) {
+  const int cl = l >> 6, cr = r >> 6;
+  if (cl == cr) {
+    int m = kInt32Max;
+    for (int i = l; i <= r; ++i) m = min(m, gmin[i]);
+    return m;
+  }
+  int m = min(q.suf[l], q.pre[r]);
+  if (cr - cl >= 2) {
+    const int a = cl + 1, e = cr - 1, lev = 31 - __clz(e - a + 1);
+    m = min(m, min(q.sp[lev][a], q.sp[lev][e - (1 << lev) + 1]));
+  }
+  return m;
+}
+// over the unwrapped buckets j0..j1 (at most kWinBins of them)
+__device__ __forceinline__ int win_rmq_range(const WinRmq& q, const int* __restrict__ gmin, int j0, int j1) {
+  if (j1 < j0) return kInt32Max;
+  const int n = j1 - j0 + 1, m0 = wmod(j0);
+  if (m0 + n <= kWinBins) return win_rmq(q, gmin, m0, m0 + n - 1);
+  return min(win_rmq(q, gmin, m0, kWinBins - 1), win_rmq(q, gmin, 0, m0 + n - 1 - kWinBins));
+}
+
+// W3.  One thread per sorted position; core points keep their label from
+// their component and are skipped.
+__global__ __launch_bounds__(256) void k_wmcn(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  __shared__ WinRmq s_q;
+  const int V = dbscan_V(b, zin, Vin);
+  if ((int)blockIdx.x * 256 >= V) return;
+  const int pos = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  const bool in = pos < V;
+  const float2* zs = reinterpret_cast<const float2*>(b.zs);
+  const int* ws = b.wstart;
+  // the point's operands are requested before the table is built
+  const int nring = ws[kWinBins];
+  const float2 zk = in ? zs[pos] : make_float2(0.f, 0.f);
+  const int nk = in ? b.wnc[pos] : c.min_pts;
+  const int k = in ? b.sid[pos] : 0;
+  win_rmq_build<256>(b, s_q);
+  if (!in || nk >= c.min_pts) return;
+  const float r2 = c.eps2;
+  int m = kInt32Max;
+  if (pos < nring) {
+    const WinRange r = win_range(c, win_u(c, zk));
+    if (r.all) {
+      m = s_q.sp[6][0];
+    } else {
+      m = win_rmq_range(s_q, b.wbmin, r.sl, r.sh);
+      int p0, p1, q0, q1;
+      win_pos(ws, r.lb0, r.lb1, p0, p1, q0, q1);
+      m = win_core_min(zk, b, p0, p1, r2, c.min_pts, m);
+      m = win_core_min(zk, b, q0, q1, r2, c.min_pts, m);
+      win_pos(ws, r.rb0, r.rb1, p0, p1, q0, q1);
+      m = win_core_min(zk, b, p0, p1, r2, c.min_pts, m);
+      m = win_core_min(zk, b, q0, q1, r2, c.min_pts, m);
+    }
+    m = win_core_min(zk, b, nring, V, r2, c.min_pts, m);
+  } else {
+    m = win_core_min(zk, b, 0, V, r2, c.min_pts, m);
+  }
+  b.mcn[k] = m;
+}
+
+// union-find over the nodes of W4 (runs, then off-ring points), in global
+// memory, within one workgroup: parents always point to a lower node.  Words
+// that atomics update are read with atomic loads.
+__device__ __forceinline__ int ld_wg(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int win_find(int* parent, int x) {
+  while (true) {
+    const int p = ld_wg(&parent[x]);
+    if (p == x) return x;
+    x = p;
+  }
+}
+__device__ __forceinline__ void win_union(int* parent, int x, int y) {
+  while (true) {
+    x = win_find(parent, x);
+    y = win_find(parent, y);
+    if (x == y) return;
+    if (x > y) {
+      const int t = x;
+      x = y;
+      y = t;
+    }
+    int expected = y;
+    if (__hip_atomic_compare_exchange_strong(&parent[y], &expected, x, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+      return;
+  }
+}
+
+// W4.  One 1024-thread block.
+__global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float* __restrict__ zin, int Vin,
+                                                     int* mout, int* lab_out, int* cnt_out) {
+  using ZT = float2;
+  constexpr int PER = kWinBins / kFinThreads;  // buckets per thread
+  constexpr int NBW = kWinMaxK / 32;           // words of the component-minimum bitmap
+  static_assert(kWinMaxRuns <= kFinThreads, "one run per thread");
+  __shared__ int s_lab[kWinBins];              // bucket -> run, then cluster label (-1: no core point)
+  __shared__ int s_run[kWinMaxRuns];           // run -> lowest core index, then cluster label
+  __shared__ int s_mj[kWinMaxRuns], s_mp[kWinMaxRuns];  // gaps that may link two runs
+  __shared__ unsigned s_bits[NBW];
+  __shared__ int s_boff[NBW];
+  __shared__ int s_nmaybe;
+  __shared__ float s_red[kFinThreads / kWave][kStatClusters][6];
+  __shared__ float s_tot[kStatClusters][6];
+  const int V = dbscan_V(b, zin, Vin);
+  const int t = (int)threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+  if (V == 0) {
+    if (t == 0) {
+      b.ctrl->n_trees = 0;
+      b.ctrl->tree_overflow = 0;
+      b.ctrl->M = 0;
+      if (mout) *mout = 0;
+    }
+    return;
+  }
+  const bool stats_pts = zin == nullptr;
+  const float2* zs = reinterpret_cast<const float2*>(b.zs);
+  const int* ws = b.wstart;
+  // the first labelling chunk's point data are requested first
+  int nc0[kLabBatch], x0[kLabBatch], key0[kLabBatch];
+  float S0[kLabBatch];
+  ZT g0[kLabBatch];
+  label_loads<2>(c, b, 0, V, stats_pts, nc0, x0, S0, g0);
+  int bm[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) bm[i] = b.wbmin[t * PER + i];
+  const int nring = ws[kWinBins];
+#pragma unroll
+  for (int u = 0; u < kLabBatch; ++u) key0[u] = x0[u] >= 0 ? b.wkey[x0[u]] : -1;
+  const int noff = V - nring;
+  s_run[t] = kInt32Max;
+  if (t < NBW) s_bits[t] = 0u;
+  if (t == 0) s_nmaybe = 0;
+  // the core bucket before each core bucket (cyclic) and the gap to it
+  int mine = -1;
+#pragma unroll
+  for (int i = 0; i < PER; ++i)
+    if (bm[i] != kInt32Max) mine = t * PER + i;
+  int last;
+  int pv = block_excl_max<kFinThreads>(mine, &last);
+  int st[PER], prv[PER], nst_mine = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = t * PER + i;
+    st[i] = 0;
+    prv[i] = 0;
+    if (bm[i] != kInt32Max) {
+      prv[i] = pv >= 0 ? pv : last - kWinBins;
+      st[i] = j - prv[i] > c.w_g ? 1 : 0;
+      pv = j;
+    }
+    nst_mine += st[i];
+  }
+  int nst;
+  const int st_before = block_excl_scan<kFinThreads>(nst_mine, &nst);
+  const int nR = last < 0 ? 0 : max(nst, 1);
+  // run of a core bucket: the starts at or before it, less one; the buckets
+  // before the first start close the circle with the last run
+  int cum = st_before;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = t * PER + i;
+    if (bm[i] != kInt32Max) {
+      cum += st[i];
+      const int run = nst == 0 ? 0 : (cum > 0 ? cum - 1 : nst - 1);
+      s_lab[j] = run;
+      atomicMin(&s_run[run], bm[i]);
+      if (st[i] && nR >= 2 && j - prv[i] <= c.w_gout) {
+        const int q = atomicAdd(&s_nmaybe, 1);
+        s_mj[q] = j;
+        s_mp[q] = prv[i];
+      }
+    } else {
+      s_lab[j] = -1;
+    }
+  }
+  __syncthreads();
+  const int nmaybe = s_nmaybe;
+  const bool uf = nmaybe > 0 || noff > 0;
+  const int stride = kWinMaxRuns + c.K;
+  int* parent = b.wuf;
+  int* cmin = b.wuf + stride;
+  int* olab = b.wuf + 2 * stride;
+  const int nn = nR + noff;  // union-find nodes: runs, then off-ring points by sorted position
+  if (uf) {
+    for (int i = t; i < nn; i += kFinThreads) {
+      parent[i] = i;
+      cmin[i] = i < nR ? s_run[i]
+                       : (b.wnc[nring + i - nR] >= c.min_pts ? b.sid[nring + i - nR] : kInt32Max);
+    }
+    __syncthreads();
+    const float r2 = c.eps2;
+    // a gap that may link two runs: core pairs across it, one wave per gap
+    for (int gi = wv; gi < nmaybe; gi += kFinThreads / kWave) {
+      const int j = s_mj[gi], pj = s_mp[gi];
+      int a0, a1, a2, a3, c0, c1, c2, c3;
+      win_pos(ws, j - c.w_gout, pj, a0, a1, a2, a3);
+      win_pos(ws, j, pj + c.w_gout, c0, c1, c2, c3);
+      const int na = (a1 - a0) + (a3 - a2), nb = (c1 - c0) + (c3 - c2);
+      bool hit = false;
+      for (int ia = 0; ia < na && !hit; ++ia) {
+        const int pa = ia < a1 - a0 ? a0 + ia : a2 + ia - (a1 - a0);
+        if (b.wnc[pa] < c.min_pts) continue;
+        const float2 za = zs[pa];
+        bool h = false;
+        for (int ib = lane; ib < nb; ib += kWave) {
+          const int pb = ib < c1 - c0 ? c0 + ib : c2 + ib - (c1 - c0);
+          h |= b.wnc[pb] >= c.min_pts && ZVec<2>::d2(za, zs[pb]) <= r2;
+        }
+        hit = __ballot(h) != 0ull;
+      }
+      if (hit && lane == 0) win_union(parent, s_lab[wmod(pj)], s_lab[j]);
+    }
+    // off-ring core points: every core neighbour, one wave per point
+    for (int o = wv; o < noff; o += kFinThreads / kWave) {
+      const int po = nring + o;
+      if (b.wnc[po] < c.min_pts) continue;
+      const float2 zo = zs[po];
+      for (int q = lane; q < V; q += kWave) {
+        if (q == po || b.wnc[q] < c.min_pts || !(ZVec<2>::d2(zo, zs[q]) <= r2)) continue;
+        const int node = q < nring ? s_lab[b.wkey[b.sid[q]] >> kWinShift] : nR + (q - nring);
+        win_union(parent, nR + o, node);
+      }
+    }
+    __syncthreads();
+    // (nodes that are not roots keep their own minimum; roots only decrease)
+    for (int i = t; i < nn; i += kFinThreads) {
+      const int r = win_find(parent, i), m = ld_wg(&cmin[i]);
+      if (m != kInt32Max && r != i) atomicMin(&cmin[r], m);
+    }
+    __syncthreads();
+    for (int i = t; i < nn; i += kFinThreads) {
+      const int m = ld_wg(&cmin[i]);
+      if (ld_wg(&parent[i]) == i && m != kInt32Max) atomicOr(&s_bits[m >> 5], 1u << (m & 31));
+    }
+  } else if (t < nR) {
+    atomicOr(&s_bits[s_run[t] >> 5], 1u << (s_run[t] & 31));
+  }
+  __syncthreads();
+  // clusters are the components ranked by their lowest core index
+  const unsigned wbits = t < NBW ? s_bits[t] : 0u;
+  int M;
+  const int boff = block_excl_scan<kFinThreads>(__popc(wbits), &M);
+  if (t < NBW) s_boff[t] = boff;
+  __syncthreads();
+  auto rank_of = [&](int x) {
+    const int w = x >> 5, bit = x & 31;
+    return s_boff[w] + __popc(s_bits[w] & (bit ? (0xffffffffu >> (32 - bit)) : 0u));
+  };
+  if (t < nR) s_run[t] = rank_of(uf ? ld_wg(&cmin[win_find(parent, t)]) : s_run[t]);
+  if (uf)
+    for (int o = t; o < noff; o += kFinThreads)
+      olab[o] = b.wnc[nring + o] >= c.min_pts ? rank_of(ld_wg(&cmin[win_find(parent, nR + o)])) : -1;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = t * PER + i;
+    if (s_lab[j] >= 0) s_lab[j] = s_run[s_lab[j]];
+  }
+  if (t == 0) {
+    b.ctrl->n_trees = nR;
+    b.ctrl->tree_overflow = 0;
+    b.ctrl->M = M;
+    if (mout) *mout = M;
+  }
+  __syncthreads();
+  // labels: core -> its component, border -> the component of its
+  // lowest-index core neighbour, noise -> -1; statistics as in k_tree_cc
+  const bool stats = stats_pts && M > 0;
+  for (int a0 = 0; a0 < V; a0 += kFinThreads * kLabBatch) {
+    int nc[kLabBatch], x[kLabBatch], key[kLabBatch], lab[kLabBatch];
+    float Sa[kLabBatch];
+    ZT ga[kLabBatch];
+    if (a0 == 0) {
+#pragma unroll
+      for (int u = 0; u < kLabBatch; ++u) {
+        nc[u] = nc0[u];
+        x[u] = x0[u];
+        key[u] = key0[u];
+        Sa[u] = S0[u];
+        ga[u] = g0[u];
+      }
+    } else {
+      label_loads<2>(c, b, a0, V, stats_pts, nc, x, Sa, ga);
+#pragma unroll
+      for (int u = 0; u < kLabBatch; ++u) key[u] = x[u] >= 0 ? b.wkey[x[u]] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kLabBatch; ++u) {
+      const int bk = key[u] >> kWinShift;
+      lab[u] = key[u] < 0 ? -1 : (bk < kWinBins ? s_lab[bk] : olab[key[u] & (kWinMaxK - 1)]);
+    }
+#pragma unroll
+    for (int u = 0; u < kLabBatch; ++u) {
+      const int a = a0 + u * kFinThreads + t;
+      if (a >= V) continue;
+      b.label[a] = lab[u];
+      if (lab_out) lab_out[a] = lab[u];
+      if (cnt_out) cnt_out[a] = nc[u];
+    }
+    if (stats) chunk_stats<2>(b, a0 == 0, M, lab, Sa, ga, s_red, s_tot);
+  }
+  if (stats && t < kStatClusters) {
+    for (int cl = t; cl < M; cl += kStatClusters) {
+      const bool lds = cl < kStatClusters;
+      const float cnt = lds ? s_tot[cl][5] : (float)b.c_size[cl];
+      const float sx = lds ? s_tot[cl][1] : b.c_dir[4 * cl], sy = lds ? s_tot[cl][2] : b.c_dir[4 * cl + 1];
+      const float sc = lds ? s_tot[cl][0] : b.c_cost[cl];
+      const float vx = sx / cnt, vy = sy / cnt;
+      const float nv = sqrtf(__builtin_fmaf(vy, vy, vx * vx)) + c.norm_eps;
+      b.c_cost[cl] = sc / cnt;
+      b.c_dir[4 * cl] = vx / nv;
+      b.c_dir[4 * cl + 1] = vy / nv;
+      b.c_dir[4 * cl + 2] = 0.f;
+    }
+  }
+  // the bucket counts start from zero at the next call
+#pragma unroll
+  for (int i = 0; i < PER; ++i) b.wcnt[t * PER + i] = 0;
+  if (t == 0) b.wcnt[kWinBins] = 0;
+}
+
+// bucket and slot of caller features (stage calls; replans bin in the compaction)
+__global__ __launch_bounds__(256) void k_wbin(Cfg c, Bufs b, const float* __restrict__ zin, int V) {
+  const int a = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (a >= V) return;
+  win_bin(c, b, reinterpret_cast<const float2*>(zin)[a], a);
+}
+
+// ---------------------------------------------------------------------------
 // Selection (Eq. (14), or Eq. (17)-(18) for the dynamic rule), computed the
 // same way by every update block: each thread scans a strided subset of the
 // clusters keeping its best and second-best key, then a fixed tree merges
@@ -1866,9 +2442,22 @@ __global__ __launch_bounds__(kFinThreads) void kb_finish(CSlotStatic st, CSlotIO
 
 // ---------------------------------------------------------------------------
 // launchers
+// the angular-window path runs (single planners with 2-D features whose
+// windows are valid; the no-allocation entry point has no window buffers)
+static bool use_window(const Cfg& c, const Bufs& b) { return c.p == 2 && c.dbpath == 0 && b.wcnt; }
+
 template <int P>
 static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const float* zin, int Vin,
                             int ntile, int* lab_out, int* cnt_out, int* mout) {
+  if (P == 2 && use_window(c, b)) {
+    // grids sized for every point the call may have (K for a replan)
+    const int cap = ntile * kTile;
+    L(k_wplace, dim3((cap + kFinThreads - 1) / kFinThreads), dim3(kFinThreads), c, b, zin, Vin);
+    L(k_wcount, dim3((cap + 255) / 256), dim3(256), c, b, zin, Vin);
+    L(k_wmcn, dim3((cap + 255) / 256), dim3(256), c, b, zin, Vin);
+    L(k_wcc, dim3(1), dim3(kFinThreads), c, b, zin, Vin, mout, lab_out, cnt_out);
+    return;
+  }
   const int ngrp = (ntile + kColGroup - 1) / kColGroup;
   const int ncnt = (ntile + kCntGroup - 1) / kCntGroup;
   dim3 tiles(ngrp, ntile), ctiles(ncnt, ntile);
@@ -1876,7 +2465,7 @@ static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const floa
   // kSplit threads: their few blocks would otherwise leave the loop latency
   // exposed; larger ones launch enough blocks, and more threads would cost
   // the branches that skip the passes
-  if (b.adj) {
+  if (b.adj && c.dbpath != 2) {
     // bitmap passes
     // one column tile per block and four threads per row at every size (A/B
     // on the clustering replan at K = 8192: 7.6 us against 8.3-16.4 us for
@@ -1907,10 +2496,11 @@ void launch_post_rollout(Launcher& L, const Cfg& c, const Bufs& b) {
   const int nk = (c.K + 255) / 256;
   int* none = nullptr;
   if (c.p == 2) {
-    L(k_compact<2>, dim3(nk), dim3(256), c, b);
+    if (use_window(c, b)) L(k_compact<2, true>, dim3(nk), dim3(256), c, b);
+    else L(k_compact<2, false>, dim3(nk), dim3(256), c, b);
     launch_dbscan_p<2>(L, c, b, nullptr, 0, c.ntile, none, none, none);
   } else {
-    L(k_compact<3>, dim3(nk), dim3(256), c, b);
+    L(k_compact<3, false>, dim3(nk), dim3(256), c, b);
     launch_dbscan_p<3>(L, c, b, nullptr, 0, c.ntile, none, none, none);
   }
   using UFn = void (*)(Cfg, Bufs);
@@ -1940,6 +2530,7 @@ void launch_stage_dbscan(Launcher& L, const Cfg& c, const Bufs& b, const float* 
   }
   const int ntile = (V + kTile - 1) / kTile;
   L(k_init_points, dim3((V + 255) / 256), dim3(256), b, V);
+  if (use_window(c, b)) L(k_wbin, dim3((V + 255) / 256), dim3(256), c, b, z, V);
   if (c.p == 2)
     launch_dbscan_p<2>(L, c, b, z, V, ntile, label, ncount, mout);
   else

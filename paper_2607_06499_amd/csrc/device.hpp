@@ -53,6 +53,15 @@ constexpr int kAdjGroup = 1;       // column tiles per bitmap block
 constexpr int kMcnThreads = 1024;  // core-neighbour pass on the bitmap: 64 rows per block
 constexpr int kMcnSplit = kMcnThreads / 64;  // threads per row there
 constexpr int kMcnLoads = (kAdjMaxK / kTile + kMcnSplit - 1) / kMcnSplit;  // row words per thread
+// angular-window DBSCAN of single planners with 2-D features (the unit
+// directions of Eq. (13)): points on the unit ring are binned by angle into
+// kWinBins buckets; the compacted index of a point and its slot in its bucket
+// share one key (bucket << kWinShift | slot), so V <= 2^kWinShift
+constexpr int kWinBins = 4096;
+constexpr int kWinShift = 14;
+constexpr int kWinMaxK = 1 << kWinShift;
+constexpr int kWinMaxRuns = 1024;  // runs of core buckets (at most kWinBins / (gap + 1) with gap >= 3)
+static_assert(kWinMaxK >= kAdjMaxK, "the windowed path covers every planner with a bitmap");
 constexpr int kLabBatch = 8;   // points per thread per labelling pass
 constexpr int kRecBatch = 4;   // partial records per thread in flight at once
 constexpr int kFinRows = 8;    // update-partial rows per wave in flight at once (final combination)
@@ -116,6 +125,15 @@ struct Cfg {
   int ntile;       // ceil(K / kTile)
   int nblk_upd;    // update kernel blocks
   int mcap;        // cluster capacity
+  // DBSCAN path: 0 angular windows, 1 eps-adjacency bitmap, 2 distance passes
+  int dbpath;
+  // angular windows (dbpath 0): bucket coordinate u = (atan2(z) + pi) * w_scale;
+  // ring points have |z|^2 in [w_r2lo, w_r2hi]; from a point at u, every ring
+  // point of the buckets inside u +- w_in is a neighbour and none outside
+  // u +- w_out is; occupied buckets at most w_g apart are linked for certain,
+  // more than w_gout apart never
+  float w_scale, w_in, w_out, w_r2lo, w_r2hi;
+  int w_g, w_gout;
 };
 
 // Device buffers of one planner (kernel argument).
@@ -156,6 +174,14 @@ struct Bufs {
   int* c_size;     // [mcap]
   float* c_smin;   // [mcap]
   // update partials
+  // angular-window DBSCAN (null unless the planner has p = 2 and K <= kWinMaxK);
+  // the sorted features and their indices use zs and sid
+  int* wcnt;       // [kWinBins + 1] points per bucket (the last: off the ring); zero between calls
+  int* wstart;     // [kWinBins + 2] first sorted position of each bucket; [kWinBins] = ring points
+  int* wkey;       // [K] bucket << kWinShift | slot, by compacted index
+  int* wbmin;      // [kWinBins] lowest core index in each bucket (kInt32Max if none)
+  int* wnc;        // [K] neighbour counts by sorted position
+  int* wuf;        // [3][kWinMaxRuns + K] union-find parents, component minima, off-ring labels
   float* upart;    // [nblk_upd][NM + 1]
   float* Unew;     // [N][m] updated sequence before the shift
 };
@@ -436,6 +462,33 @@ __device__ __forceinline__ int block_excl_scan(int v, int* total) {
   __syncthreads();
   *total = tot;
   return base + inc - v;
+}
+
+// block-wide (blockDim.x == NT) exclusive max-scan of one int per thread
+// (identity -1); returns the maximum over the lower threads and writes the
+// block maximum.
+template <int NT>
+__device__ __forceinline__ int block_excl_max(int v, int* total) {
+  __shared__ int s_w[NT / kWave];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int t = __shfl_up(inc, (unsigned)d, kWave);
+    if (lane >= d) inc = max(inc, t);
+  }
+  const int below = __shfl_up(inc, 1u, kWave);
+  if (lane == kWave - 1) s_w[w] = inc;
+  __syncthreads();
+  int base = -1, tot = -1;
+#pragma unroll
+  for (int i = 0; i < NT / kWave; ++i) {
+    if (i < w) base = max(base, s_w[i]);
+    tot = max(tot, s_w[i]);
+  }
+  __syncthreads();
+  *total = tot;
+  return lane > 0 ? max(base, below) : base;
 }
 
 }  // namespace cemppi

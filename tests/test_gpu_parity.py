@@ -319,26 +319,34 @@ def test_stage_dbscan_matches_definition(case):
     name, z, spec = cases[case]
     spec = spec.rounded()
     pl = _planner(spec)
-    lab, cnt, M = pl.stage_dbscan(H.to_dev(z))
-    lab = lab.cpu().numpy()
-    cnt = cnt.cpu().numpy()
     from paper_2607_06499_amd import binding as B
 
-    n_trees, overflow = pl.debug(B.DBG_TREES, 2).cpu().tolist()
-    print(f"{name}: V={len(z)} trees={n_trees} overflow={overflow}")
     eps = float(np.float32(spec.dbscan_eps))
     z64 = z.astype(np.float64)
     olab, ocore, ocnt, oM = oracle.dbscan(z64, eps, spec.dbscan_min_pts)
-    st = H.dbscan_check(z64, eps, spec.dbscan_min_pts, cnt, lab, 0.5 * H.STAGE_BAND * eps, exact_ref=olab,
-                        tag=name)
-    print(f"{name}: {st}")
-    if st["flagged_pairs"] == 0:
-        assert H.counts_agree(cnt, ocnt, spec.dbscan_min_pts), name
-        assert int(M.cpu().item()) == oM, name
-    assert int(M.cpu().item()) == (int(lab.max()) + 1 if len(lab) and lab.max() >= 0 else 0)
-    assert overflow == (1 if n_trees > 64 else 0)
-    if name == "90_groups":
-        assert overflow == 1
+    # the planner's default path, and the bitmap too where the default is
+    # the angular windows
+    paths = [pl.dbscan_path()] + ([B.DBSCAN_BITMAP] if pl.dbscan_path() == B.DBSCAN_WINDOW else [])
+    for path in paths:
+        pl.set_dbscan_mode(path)
+        lab, cnt, M = pl.stage_dbscan(H.to_dev(z))
+        lab = lab.cpu().numpy()
+        cnt = cnt.cpu().numpy()
+        n_trees, overflow = pl.debug(B.DBG_TREES, 2).cpu().tolist()
+        print(f"{name} path {path}: V={len(z)} trees={n_trees} overflow={overflow}")
+        st = H.dbscan_check(z64, eps, spec.dbscan_min_pts, cnt, lab, 0.5 * H.STAGE_BAND * eps,
+                            exact_ref=olab, tag=name)
+        print(f"{name}: {st}")
+        if st["flagged_pairs"] == 0:
+            assert H.counts_agree(cnt, ocnt, spec.dbscan_min_pts), name
+            assert int(M.cpu().item()) == oM, name
+        assert int(M.cpu().item()) == (int(lab.max()) + 1 if len(lab) and lab.max() >= 0 else 0)
+        if path == B.DBSCAN_WINDOW:
+            assert overflow == 0
+        else:
+            assert overflow == (1 if n_trees > 64 else 0)
+            if name == "90_groups":
+                assert overflow == 1
 
 
 def test_stage_dbscan_empty_and_single():
