@@ -71,6 +71,8 @@ def parse():
                     help="timed batch steps of the batched-form measurement")
     ap.add_argument("--rollout-reps", type=int, default=2000,
                     help="back-to-back rollout launches timed for the roofline")
+    ap.add_argument("--dbscan", default="auto", choices=["auto", "window", "bitmap", "tiled"],
+                    help="DBSCAN path of the single-planner workloads (auto: the planner's default)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (profiler calibration)")
     return ap.parse_args()
@@ -328,11 +330,17 @@ def _ms(a):
     return round(float(a) * 1e3, 4)
 
 
-def run_workload(name, seed, loop_warm, L, W, K, torch, B, want_timing=True, rollout_reps=2000):
+DBSCAN_NAMES = {1: "window", 2: "bitmap", 3: "tiled"}
+
+
+def run_workload(name, seed, loop_warm, L, W, K, torch, B, want_timing=True, rollout_reps=2000,
+                 dbscan_mode=0):
     scene = scene_for(name, seed)
     spec = scene.spec
     lib = B.load()
     pl = B.Planner(spec)
+    pl.set_dbscan_mode(dbscan_mode)
+    dbscan_path = DBSCAN_NAMES[pl.dbscan_path()]
     pl.set_nominal(torch.as_tensor(scene.U0).cuda())
     X, OBS, Uo, INFO, snap = record_loop(pl, scene, loop_warm + L, torch, snap_at=loop_warm)
     Xd = torch.as_tensor(X).cuda()
@@ -385,7 +393,7 @@ def run_workload(name, seed, loop_warm, L, W, K, torch, B, want_timing=True, rol
     pl.close()
     return dict(scene=scene, X=X, OBS=OBS, wall=wall, gpu=gpu, lat=lat, same=same, launch=launch,
                 kernel_ms=kernel_ms, mix=mix, per_branch=per_branch, trees=tstat, n_live=n_live,
-                L=L, K=K, W=W, loop_warm=loop_warm)
+                L=L, K=K, W=W, loop_warm=loop_warm, dbscan_path=dbscan_path)
 
 
 def companion(name, seed, loop_warm, L, K, torch, B, label):
@@ -619,8 +627,9 @@ def main():
                           "config": {"workload": rb["workload"]}, **{k: v for k, v in rb.items()
                                                                      if k != "workload"}}))
         return
+    dmode = {"auto": 0, "window": 1, "bitmap": 2, "tiled": 3}[args.dbscan]
     res = run_workload(args.workload, args.seed, args.loop_warm, args.loop, W, K, torch, B,
-                       rollout_reps=args.rollout_reps)
+                       rollout_reps=args.rollout_reps, dbscan_mode=dmode)
     if args.calibrate_copy_mib:
         copy_calibration(torch, args.calibrate_copy_mib)
     spec = res["scene"].spec
@@ -689,6 +698,7 @@ def main():
             f"a step replays {L} closed-loop replans",
             "K": spec.num_samples, "N": spec.horizon, "n_obs": n_obs, "replans_per_step": L,
             "branch_mix": res["mix"],
+            "dbscan_path": res["dbscan_path"],
             "dbscan_trees": res["trees"],
             "launch": res["launch"],
         },
@@ -700,14 +710,26 @@ def main():
         "roofline": roofline,
     }
     if not args.no_probe and args.workload == "unicycle_dynamic":
-        pr = run_workload("unicycle_dynamic_ahead", args.seed, 0, 40, 1, max(K, 5), torch, B)
+        pr = run_workload("unicycle_dynamic_ahead", args.seed, 0, 40, 1, max(K, 5), torch, B,
+                          dbscan_mode=dmode)
         out["clustering_branch"] = {
             "workload": "unicycle_dynamic_ahead: same planner, obstacle ahead in the robot's path "
                         "(replays of a 40-replan loop)",
             "replans_per_s": round(pr["K"] * pr["L"] / pr["wall"], 2),
             "latency_ms": {"p50": _ms(np.percentile(pr["lat"], 50)), "p99": _ms(np.percentile(pr["lat"], 99))},
-            "branch_mix": pr["mix"], "per_branch": pr["per_branch"], "dbscan_trees": pr["trees"],
+            "branch_mix": pr["mix"], "per_branch": pr["per_branch"], "dbscan_path": pr["dbscan_path"],
+            "dbscan_trees": pr["trees"],
         }
+        # the same loop on the other single-planner DBSCAN paths (same bits)
+        ab = {}
+        for m in (1, 2, 3):
+            if DBSCAN_NAMES[m] == pr["dbscan_path"]:
+                continue
+            q = run_workload("unicycle_dynamic_ahead", args.seed, 0, 40, 1, max(K, 5), torch, B,
+                             want_timing=True, rollout_reps=20, dbscan_mode=m)
+            ab[q["dbscan_path"]] = {"replans_per_s": round(q["K"] * q["L"] / q["wall"], 2),
+                                    "device_us": q["per_branch"]["cluster"].get("device_us")}
+        out["clustering_branch"]["other_dbscan_paths"] = ab
     if not args.no_companions and args.workload == "unicycle_dynamic":
         cK = max(2, min(K, 3))
         out["static_2d"] = companion("unicycle_static", args.seed, 0, 200, cK, torch, B,

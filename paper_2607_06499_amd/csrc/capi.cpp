@@ -384,6 +384,8 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_wbmin = cv.take<int>(with_win ? kWinBins : 0);
   const size_t o_wkey = cv.take<int>(wk), o_wnc = cv.take<int>(wk);
   const size_t o_wuf = cv.take<int>(with_win ? 3 * (kWinMaxRuns + K) : 0);
+  // (one region of K indices per block of the count pass, 512 positions each)
+  const size_t o_wzone = cv.take<int>(with_win ? (K + 511) / 512 * K : 0);
   const size_t o_ccost = cv.take<float>((size_t)c.mcap), o_cdir = cv.take<float>((size_t)c.mcap * 4);
   const size_t o_csize = cv.take<int>((size_t)c.mcap), o_csmin = cv.take<float>((size_t)c.mcap);
   // update partials, then rows that stay zero so the final combination can
@@ -433,6 +435,7 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   b.wkey = with_win ? reinterpret_cast<int*>(base + o_wkey) : nullptr;
   b.wnc = with_win ? reinterpret_cast<int*>(base + o_wnc) : nullptr;
   b.wuf = with_win ? reinterpret_cast<int*>(base + o_wuf) : nullptr;
+  b.wzone = with_win ? reinterpret_cast<int*>(base + o_wzone) : nullptr;
   b.c_cost = reinterpret_cast<float*>(base + o_ccost);
   b.c_dir = reinterpret_cast<float*>(base + o_cdir);
   b.c_size = reinterpret_cast<int*>(base + o_csize);

@@ -195,7 +195,7 @@ __device__ __forceinline__ Totals decide(const Cfg& c, const float* tot, int bad
 // in ascending rollout order, features z (Eq. (13)) and the DBSCAN arrays.
 // Block 0 publishes the totals.
 // ---------------------------------------------------------------------------
-// Angular buckets of the windowed DBSCAN (k_wplace .. k_wcc below).  The
+// Angular buckets of the windowed DBSCAN (k_wcount, k_wcc below).  The
 // bucket coordinate of a feature is its angle mapped to [0, kWinBins]; a
 // ring point has a squared norm within [w_r2lo, w_r2hi]; every other point
 // goes to the extra bucket kWinBins ("off the ring").
@@ -1408,23 +1408,22 @@ __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const fl
 // end, and the points off the ring, are decided by the distance test: the
 // same FP32 expression as in every other DBSCAN pass, so the neighbour graph
 // is the same, and so are the counts, the core flags and the labels.
-//  W0 bin    (in the compaction) each feature's bucket and its slot there
-//  W1 place  bucket starts; the features sorted by bucket (zs, sid)
-//  W2 count  count = ring points of the inner window (two bucket starts) +
-//            hits among the boundary buckets and the off-ring points: exact;
-//            the lowest core index of every bucket (atomic minimum)
-//  W3 mcn    lowest-index core neighbour of every non-core point: a range
-//            minimum of the bucket minima over the inner window, then the
-//            boundary buckets and the off-ring points
-//  W4 cc     core buckets at most w_g apart hold core points that are
-//            neighbours for certain, so a run of such buckets is connected;
-//            two adjacent runs more than w_gout apart are not, and runs in
-//            between are linked if one core pair across the gap is; off-ring
-//            core points join through their own tests (union-find).
-//            Components are numbered by their lowest core index; labels and
-//            cluster statistics as in k_tree_cc.
+//  bin    (in the compaction) each feature's bucket and its slot there
+//  count  (k_wcount) the sorted order by bucket; count = ring points of the
+//         inner window (two bucket starts) + hits among the boundary buckets
+//         and the off-ring points: exact; the lowest core index of every bucket
+//  cc     (k_wcc, one block) core buckets at most w_g apart hold core points
+//         that are neighbours for certain, so a run of such buckets is
+//         connected; two adjacent runs more than w_gout apart are not, and
+//         runs in between are linked if one core pair across the gap is;
+//         off-ring core points join through their own tests (union-find).
+//         The lowest-index core neighbour of a non-core point is a range
+//         minimum of the bucket minima over its inner window, then its
+//         boundary buckets and the off-ring points.  Components are
+//         numbered by their lowest core index; labels and cluster
+//         statistics as in k_tree_cc.
 // Work: O(V) window lookups and O(V * points of the boundary buckets) tests,
-// against V^2 / 2 pair tests for the bitmap.
+// against V^2 / 2 pair tests for the bitmap; two launches instead of four.
 
 __device__ __forceinline__ int wmod(int j) { return j & (kWinBins - 1); }
 
@@ -1466,20 +1465,280 @@ __device__ __forceinline__ void win_pos(const int* __restrict__ ws, int j0, int 
   }
 }
 
-// number of neighbours of zk among the sorted positions [p0, p1)
-__device__ __forceinline__ int win_hits(float2 zk, const float2* __restrict__ zs, int p0, int p1, float r2) {
-  int n = 0;
-  int q = p0;
-  for (; q + 4 <= p1; q += 4) {
-    const float2 a = zs[q], b = zs[q + 1], d = zs[q + 2], e = zs[q + 3];
-    n += (ZVec<2>::d2(zk, a) <= r2 ? 1 : 0) + (ZVec<2>::d2(zk, b) <= r2 ? 1 : 0) +
-         (ZVec<2>::d2(zk, d) <= r2 ? 1 : 0) + (ZVec<2>::d2(zk, e) <= r2 ? 1 : 0);
+// the bucket of sorted position r (ring positions): the last bucket whose
+// start is at most r
+__device__ __forceinline__ int win_bucket_of(const int* s_start, int r) {
+  int lo = 0, hi = kWinBins - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_start[mid] <= r) lo = mid;
+    else hi = mid - 1;
   }
-  for (; q < p1; ++q) n += ZVec<2>::d2(zk, zs[q]) <= r2 ? 1 : 0;
-  return n;
+  return lo;
+}
+
+// unwrapped bucket range [lo, hi] (at most kWinBins buckets) holds bucket j
+__device__ __forceinline__ bool win_in(int j, int lo, int hi) { return hi >= lo && wmod(j - lo) <= hi - lo; }
+
+constexpr int kWinThreads = 512;  // count-and-place blocks
+constexpr int kWinZone = 4096;    // zone points a count block keeps in LDS
+
+// K1: counts and the sorted order.  Block i takes the sorted positions
+// [i NT, i NT + NT) (sorted by bucket, then slot; off-ring points last).
+//  - every block scans the bucket counts into LDS (block 0 publishes them);
+//  - the block's zone: the buckets any of its ring points may find beyond
+//    its inner window (the union of their boundary buckets) and the
+//    off-ring points;
+//  - one pass over every key places the block's own points and its zone
+//    points at their sorted positions in LDS, with their features;
+//  - count = ring points of the inner window (bucket starts) + distance
+//    tests against the boundary buckets and the off-ring points, from LDS.
+// A zone beyond kWinZone points keeps its indices in the block's region of
+// a global array instead, and its features are read from global memory.
+// The block's off-ring points are tested against every point by the whole
+// block.  Writes the counts, the sorted features, indices and counts, and
+// the lowest core index of every bucket (as kWinMaxK - index, an atomic
+// maximum over zero-initialised words).
+__global__ __launch_bounds__(kWinThreads) void k_wcount(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
+  constexpr int NT = kWinThreads, PER = kWinBins / NT;
+  __shared__ int s_start[kWinBins + 1];
+  __shared__ int s_own[NT];      // own point: compacted index | bucket << kWinShift
+  __shared__ float2 s_oz[NT];    // own point: feature
+  __shared__ union {
+    int k[kWinZone];
+    float2 z[kWinZone];
+  } s_zn;                        // zone: indices, then features
+  __shared__ int s_b01[2];
+  const int V = dbscan_V(b, zin, Vin);
+  const int R0 = (int)blockIdx.x * NT;
+  if (R0 >= V) return;
+  const float2* z = reinterpret_cast<const float2*>(zin ? zin : b.z);
+  const int t = (int)threadIdx.x;
+  const int R1 = min(R0 + NT, V);
+  // the first keys are requested with the bucket counts
+  constexpr int KB = 16;  // keys per thread and round
+  int key0[KB];
+#pragma unroll
+  for (int u = 0; u < KB; ++u) {
+    const int k = u * NT + t;
+    key0[u] = k < V ? b.wkey[k] : -1;
+  }
+  // bucket starts
+  int cnt[PER], sum = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    cnt[i] = b.wcnt[t * PER + i];
+    sum += cnt[i];
+  }
+  int nring;
+  int off = block_excl_scan<NT>(sum, &nring);
+  const int rr1 = min(R1, nring);
+  // the buckets of the block's first and last ring points: the non-empty
+  // buckets whose positions hold them
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int lo = off, hi = off + cnt[i];
+    s_start[t * PER + i] = lo;
+    if (lo <= R0 && R0 < hi) s_b01[0] = t * PER + i;
+    if (lo <= rr1 - 1 && rr1 - 1 < hi) s_b01[1] = t * PER + i;
+    off = hi;
+  }
+  if (t == 0) s_start[kWinBins] = nring;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) b.wstart[t * PER + i] = s_start[t * PER + i];
+    if (t == 0) {
+      b.wstart[kWinBins] = nring;
+      b.wstart[kWinBins + 1] = V;
+    }
+  }
+  // The zone, block-uniform: one or two unwrapped bucket ranges [lo_g,
+  // hi_g] (every boundary bucket of the block's ring points; the left
+  // boundaries lie in range 0, the right ones in the last), stored from LDS
+  // index base_g in unwrapped bucket order, then the off-ring points.
+  int zlo[2] = {0, 0}, zhi[2] = {-1, -1}, zs0[2] = {0, 0}, zbase[2] = {0, 0};
+  int nr = 0;
+  if (R0 < rr1) {
+    const int B0 = s_b01[0], B1 = s_b01[1];
+    const int wo = (int)ceilf(c.w_out), wi = (int)floorf(c.w_in);
+    zlo[0] = B0 - wo - 1;
+    zhi[0] = B1 - wi + 1;
+    zlo[1] = B0 + wi - 1;
+    zhi[1] = B1 + wo + 2;
+    nr = 2;
+    if (zhi[1] - zlo[0] + 1 >= kWinBins) {
+      zlo[0] = 0;
+      zhi[0] = kWinBins - 1;
+      nr = 1;
+    } else if (zlo[1] <= zhi[0] + 1) {
+      zhi[0] = zhi[1];
+      nr = 1;
+    }
+    if (nr == 1) {
+      zlo[1] = zlo[0];
+      zhi[1] = zhi[0];
+    }
+  }
+  // points of bucket range [lo, hi] (unwrapped, at most kWinBins buckets)
+  auto npts = [&](int lo, int hi) {
+    if (hi < lo) return 0;
+    const int m = wmod(lo), x = m + (hi - lo) + 1;
+    return x <= kWinBins ? s_start[x] - s_start[m] : nring - s_start[m] + s_start[x - kWinBins];
+  };
+  int zsize = 0;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    zs0[g] = s_start[wmod(zlo[g])];
+    zbase[g] = zsize;
+    if (g < nr) zsize += npts(zlo[g], zhi[g]);
+  }
+  if (nr == 1) zbase[1] = zbase[0];
+  const int zoff = zsize;  // the off-ring points
+  zsize += R0 < rr1 ? V - nring : 0;
+  const bool lds = zsize <= kWinZone;
+  int* gzone = b.wzone + (size_t)blockIdx.x * c.K;
+  // zone index of the first point of unwrapped bucket j of range g
+  auto zidx = [&](int g, int j) {
+    const int m = wmod(zlo[g]), x = m + (j - zlo[g]);
+    return zbase[g] + (x < kWinBins ? s_start[x] - zs0[g] : nring - zs0[g] + s_start[x - kWinBins]);
+  };
+  // own and zone points at their places: indices first, then every feature
+  // gathered in one round
+  for (int k0 = 0; k0 < V; k0 += NT * KB) {
+    int key[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int k = k0 + u * NT + t;
+      key[u] = k0 == 0 ? key0[u] : (k < V ? b.wkey[k] : -1);
+    }
+    // (straight-line per key: one LDS read, the rest arithmetic; the zone
+    // index of a bucket's points follows from its position: bucket j at
+    // offset d of range g starts at base_g + start(j) - start(lo_g), plus
+    // the ring points when the range passes the end of the circle)
+    int st[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) st[u] = s_start[key[u] < 0 ? 0 : min(key[u] >> kWinShift, kWinBins)];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int k = k0 + u * NT + t, bk = key[u] >> kWinShift, slot = key[u] & (kWinMaxK - 1);
+      const int pos = st[u] + slot;
+      const bool valid = key[u] >= 0;
+      if (valid && pos >= R0 && pos < R1) s_own[pos - R0] = k | (bk << kWinShift);
+      int zi = -1;
+      if (bk == kWinBins) zi = zoff + slot;
+#pragma unroll
+      for (int g = 1; g >= 0; --g) {
+        const int m = wmod(zlo[g]);
+        if (g < nr && bk < kWinBins && wmod(bk - zlo[g]) <= zhi[g] - zlo[g])
+          zi = zbase[g] - zs0[g] + pos + (bk < m ? nring : 0);
+      }
+      if (valid && R0 < rr1 && zi >= 0) {
+        if (lds) s_zn.k[zi] = k;
+        else gzone[zi] = k;
+      }
+    }
+  }
+  __syncthreads();
+  {
+    constexpr int ZPER = kWinZone / NT;
+    const int nz = lds ? zsize : 0;
+    int kz[ZPER];
+#pragma unroll
+    for (int j = 0; j < ZPER; ++j) kz[j] = j * NT + t < nz ? s_zn.k[j * NT + t] : -1;
+    const int ko = R0 + t < R1 ? s_own[t] & (kWinMaxK - 1) : -1;
+    float2 zz[ZPER];
+#pragma unroll
+    for (int j = 0; j < ZPER; ++j) zz[j] = kz[j] >= 0 ? z[kz[j]] : make_float2(0.f, 0.f);
+    const float2 zo = ko >= 0 ? z[ko] : make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ZPER; ++j)
+      if (kz[j] >= 0) s_zn.z[j * NT + t] = zz[j];
+    s_oz[t] = zo;
+  }
+  __syncthreads();
+  const int pos = R0 + t;
+  const bool own = pos < R1;
+  const int ok = own ? s_own[t] : 0;
+  const int k = ok & (kWinMaxK - 1), bk = ok >> kWinShift;
+  const float2 zk = own ? s_oz[t] : make_float2(0.f, 0.f);
+  const float r2 = c.eps2;
+  const bool ring = pos < nring;
+  // hits of zk among the zone entries [e0, e1)
+  auto hits = [&](int e0, int e1) {
+    int n = 0;
+    if (lds) {
+      int e = e0;
+      for (; e + 4 <= e1; e += 4) {
+        const float2 a0 = s_zn.z[e], a1 = s_zn.z[e + 1], a2 = s_zn.z[e + 2], a3 = s_zn.z[e + 3];
+        n += (ZVec<2>::d2(zk, a0) <= r2 ? 1 : 0) + (ZVec<2>::d2(zk, a1) <= r2 ? 1 : 0) +
+             (ZVec<2>::d2(zk, a2) <= r2 ? 1 : 0) + (ZVec<2>::d2(zk, a3) <= r2 ? 1 : 0);
+      }
+      for (; e < e1; ++e) n += ZVec<2>::d2(zk, s_zn.z[e]) <= r2 ? 1 : 0;
+    } else {
+      for (int e = e0; e < e1; e += 4) {
+        int kq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) kq[u] = e + u < e1 ? gzone[e + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (kq[u] >= 0) n += ZVec<2>::d2(zk, z[kq[u]]) <= r2 ? 1 : 0;
+      }
+    }
+    return n;
+  };
+  // hits among the len buckets from bucket j0 (any representative) of zone
+  // range g: one run of zone entries, or two where it passes the end of a
+  // range that covers the whole circle
+  auto range_hits = [&](int g, int j0, int len) {
+    if (len <= 0) return 0;
+    const int L = zhi[g] - zlo[g] + 1, d0 = wmod(j0 - zlo[g]);
+    if (d0 + len <= L) return hits(zidx(g, zlo[g] + d0), zidx(g, zlo[g] + d0 + len));
+    return hits(zidx(g, zlo[g] + d0), zidx(g, zlo[g] + L)) + hits(zidx(g, zlo[g]), zidx(g, zlo[g] + min(L, d0 + len - L)));
+  };
+  int n = 0;
+  if (own && ring) {
+    const WinRange r = win_range(c, win_u(c, zk));
+    if (r.all) {
+      n = nring;
+    } else {
+      n = npts(r.sl, r.sh);
+      // the left boundary lies in range 0 and the right one in the last
+      n += range_hits(0, r.lb0, r.lb1 - r.lb0 + 1) + range_hits(1, r.rb0, r.rb1 - r.rb0 + 1);
+    }
+    n += hits(zoff, zsize);
+  }
+  // off-ring points of the block: every point, the whole block on each
+  // (each thread tests a strided share of the features; a block sum)
+  const int off0 = max(R0, nring), noff_own = max(0, R1 - off0);
+  for (int i = 0; i < noff_own; ++i) {
+    const float2 zo = s_oz[off0 - R0 + i];
+    int h = 0;
+    for (int q0 = t; q0 < V; q0 += NT * 4) {
+      float2 zq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * NT;
+        zq[u] = q < V ? z[q] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) h += (q0 + u * NT < V && ZVec<2>::d2(zo, zq[u]) <= r2) ? 1 : 0;
+    }
+    int tot;
+    (void)block_excl_scan<NT>(h, &tot);
+    if (pos == off0 + i) n = tot;
+  }
+  if (!own) return;
+  b.ncount[k] = n;
+  b.wnc[pos] = n;
+  reinterpret_cast<float2*>(b.zs)[pos] = zk;
+  b.sid[pos] = k;
+  if (ring && n >= c.min_pts) atomicMax(&b.wbmin[bk], kWinMaxK - k);
 }
 
 // lowest index among the core neighbours of zk at sorted positions [p0, p1)
+// (global sorted arrays)
 __device__ __forceinline__ int win_core_min(float2 zk, const Bufs& b, int p0, int p1, float r2, int min_pts,
                                             int m) {
   const float2* zs = reinterpret_cast<const float2*>(b.zs);
@@ -1495,187 +1754,104 @@ __device__ __forceinline__ int win_core_min(float2 zk, const Bufs& b, int p0, in
   return m;
 }
 
-// W1.  Every block scans the bucket counts into LDS; block 0 publishes the
-// starts and clears the bucket minima of W2.
-__global__ __launch_bounds__(kFinThreads) void k_wplace(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
-  constexpr int PER = kWinBins / kFinThreads;
-  __shared__ int s_start[kWinBins + 1];
-  const int V = dbscan_V(b, zin, Vin);
-  const int base = (int)blockIdx.x * kFinThreads;
-  if (base >= V) return;
-  const float2* z = reinterpret_cast<const float2*>(zin ? zin : b.z);
-  const int t = (int)threadIdx.x, k = base + t;
-  const bool in = k < V;
-  const int key = in ? b.wkey[k] : 0;
-  const float2 zk = in ? z[k] : make_float2(0.f, 0.f);
-  int cnt[PER], sum = 0;
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    cnt[i] = b.wcnt[t * PER + i];
-    sum += cnt[i];
-  }
-  int tot;
-  int off = block_excl_scan<kFinThreads>(sum, &tot);
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    s_start[t * PER + i] = off;
-    off += cnt[i];
-  }
-  if (t == 0) s_start[kWinBins] = tot;
-  __syncthreads();
-  if (blockIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      b.wstart[t * PER + i] = s_start[t * PER + i];
-      b.wbmin[t * PER + i] = kInt32Max;
-    }
-    if (t == 0) {
-      b.wstart[kWinBins] = tot;
-      b.wstart[kWinBins + 1] = V;
-    }
-  }
-  const int pos = s_start[key >> kWinShift] + (key & (kWinMaxK - 1));
-  if (in && pos < V) {  // (always: the counts hold exactly the V keys)
-    reinterpret_cast<float2*>(b.zs)[pos] = zk;
-    b.sid[pos] = k;
-  }
-}
+constexpr short kNoCore = 0x7fff;  // above every index (V <= kWinMaxK)
 
-// W2.  One thread per sorted position.
-__global__ __launch_bounds__(256) void k_wcount(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
-  const int V = dbscan_V(b, zin, Vin);
-  const int pos = (int)blockIdx.x * 256 + (int)threadIdx.x;
-  if (pos >= V) return;
+// Lowest-index core neighbour of one non-core point at feature zk, by the
+// whole wave (zk and ring wave-uniform), as index | (bucket + 1) << kWinShift
+// when its bucket is known (0 in the high bits otherwise), or kInt32Max if
+// there is none.  Every core point of the inner window is a neighbour, so
+// the window's lowest bucket minimum is the answer unless a boundary bucket
+// holds a lower core index or there are off-ring points (LDS only); then
+// the core points of the boundary buckets and the off-ring points are
+// tested (every point for an off-ring zk).
+__device__ int win_mcn_wave(const Cfg& c, const Bufs& b, const short* s_bmin, const int* ws, float2 zk, bool ring,
+                            int nring, int V) {
+  const int lane = (int)(threadIdx.x & (kWave - 1));
   const float2* zs = reinterpret_cast<const float2*>(b.zs);
-  const int* ws = b.wstart;
-  const int nring = ws[kWinBins];
-  const float2 zk = zs[pos];
-  const int k = b.sid[pos];
   const float r2 = c.eps2;
-  int cnt;
-  if (pos < nring) {
-    const int key = b.wkey[k];
-    const WinRange r = win_range(c, win_u(c, zk));
+  int m = kNoCore, mb = -1, mbnd = kNoCore;
+  WinRange r{};
+  if (ring) {
+    r = win_range(c, win_u(c, zk));
+    auto take = [&](int j) {
+      const int v = s_bmin[wmod(j)];
+      if (v < m) {
+        m = v;
+        mb = wmod(j);
+      }
+    };
     if (r.all) {
-      cnt = nring;
+      for (int j = lane; j < kWinBins; j += kWave) take(j);
     } else {
-      int p0, p1, q0, q1;
-      win_pos(ws, r.sl, r.sh, p0, p1, q0, q1);
-      cnt = (p1 - p0) + (q1 - q0);
-      win_pos(ws, r.lb0, r.lb1, p0, p1, q0, q1);
-      cnt += win_hits(zk, zs, p0, p1, r2) + win_hits(zk, zs, q0, q1, r2);
-      win_pos(ws, r.rb0, r.rb1, p0, p1, q0, q1);
-      cnt += win_hits(zk, zs, p0, p1, r2) + win_hits(zk, zs, q0, q1, r2);
+      for (int j = r.sl + lane; j <= r.sh; j += kWave) take(j);
+      for (int j = r.lb0 + lane; j <= r.lb1; j += kWave) mbnd = min(mbnd, (int)s_bmin[wmod(j)]);
+      for (int j = r.rb0 + lane; j <= r.rb1; j += kWave) mbnd = min(mbnd, (int)s_bmin[wmod(j)]);
     }
-    cnt += win_hits(zk, zs, nring, V, r2);
-    if (cnt >= c.min_pts) atomicMin(&b.wbmin[key >> kWinShift], k);
+    // (minimum over the wave; the bucket follows its index, which is unique)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const int om = __shfl_xor(m, off, kWave), ob = __shfl_xor(mb, off, kWave);
+      if (om < m) {
+        m = om;
+        mb = ob;
+      }
+      mbnd = min(mbnd, __shfl_xor(mbnd, off, kWave));
+    }
+    if (mbnd >= m && nring == V) return m >= kNoCore ? kInt32Max : (m | ((mb + 1) << kWinShift));
+  }
+  // the position ranges to test (all bounds requested together): the two
+  // boundary sides (each up to two ranges) and the off-ring points, or every
+  // point
+  int p0[5] = {0, 0, 0, 0, 0}, p1[5] = {0, 0, 0, 0, 0};
+  if (ring) {
+    if (!r.all) {
+      win_pos(ws, r.lb0, r.lb1, p0[0], p1[0], p0[1], p1[1]);
+      win_pos(ws, r.rb0, r.rb1, p0[2], p1[2], p0[3], p1[3]);
+    }
+    p0[4] = nring;
+    p1[4] = V;
   } else {
-    cnt = win_hits(zk, zs, 0, V, r2);
+    p1[4] = V;
   }
-  b.ncount[k] = cnt;
-  b.wnc[pos] = cnt;
-}
-
-// Range minimum over the bucket minima: within-chunk prefix and suffix
-// minima (chunks of 64 buckets) and a sparse table over the chunk minima.
-struct WinRmq {
-  int pre[kWinBins], suf[kWinBins];
-  int sp[7][kWinBins / 64];
-};
-template <int NT>
-__device__ __forceinline__ void win_rmq_build(const Bufs& b, WinRmq& q) {
-  constexpr int NCH = kWinBins / 64, NW = NT / kWave, PER = NCH / NW;
-  const int lane = (int)(threadIdx.x & (kWave - 1)), wv = (int)(threadIdx.x / kWave);
-  int v[PER];
+  int mt = ring ? m : kNoCore;
+  // one strided pass over the ranges laid end to end, four loads per lane
+  // in flight
+  int len[5], tot = 0;
 #pragma unroll
-  for (int i = 0; i < PER; ++i) v[i] = b.wbmin[(wv + i * NW) * 64 + lane];
+  for (int i = 0; i < 5; ++i) {
+    len[i] = max(0, p1[i] - p0[i]);
+    tot += len[i];
+  }
+  auto at = [&](int e) {
+    int q = -1;
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int ch = wv + i * NW;
-    int pre = v[i], suf = v[i];
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int a = __shfl_up(pre, (unsigned)d, kWave);
-      const int s = __shfl_down(suf, (unsigned)d, kWave);
-      if (lane >= d) pre = min(pre, a);
-      if (lane + d < kWave) suf = min(suf, s);
+    for (int i = 0; i < 5; ++i) {
+      if (q < 0 && e < len[i]) q = p0[i] + e;
+      e -= len[i];
     }
-    q.pre[ch * 64 + lane] = pre;
-    q.suf[ch * 64 + lane] = suf;
-    if (lane == kWave - 1) q.sp[0][ch] = pre;
-  }
-  __syncthreads();
+    return q;
+  };
+  for (int e0 = lane; e0 < tot; e0 += 4 * kWave) {
+    int qq[4], nq[4];
+    float2 zq[4];
 #pragma unroll
-  for (int lev = 1; lev < 7; ++lev) {
-    const int t = (int)threadIdx.x;
-    if (t + (1 << lev) <= NCH) q.sp[lev][t] = min(q.sp[lev - 1][t], q.sp[lev - 1][t + (1 << (lev - 1))]);
-    __syncthreads();
-  }
-}
-// minimum over buckets l..r (0 <= l <= r < kWinBins)
-__device__ __forceinline__ int win_rmq(const WinRmq& q, const int* __restrict__ gmin, int l, int r) {
-  const int cl = l >> 6, cr = r >> 6;
-  if (cl == cr) {
-    int m = kInt32Max;
-    for (int i = l; i <= r; ++i) m = min(m, gmin[i]);
-    return m;
-  }
-  int m = min(q.suf[l], q.pre[r]);
-  if (cr - cl >= 2) {
-    const int a = cl + 1, e = cr - 1, lev = 31 - __clz(e - a + 1);
-    m = min(m, min(q.sp[lev][a], q.sp[lev][e - (1 << lev) + 1]));
-  }
-  return m;
-}
-// over the unwrapped buckets j0..j1 (at most kWinBins of them)
-__device__ __forceinline__ int win_rmq_range(const WinRmq& q, const int* __restrict__ gmin, int j0, int j1) {
-  if (j1 < j0) return kInt32Max;
-  const int n = j1 - j0 + 1, m0 = wmod(j0);
-  if (m0 + n <= kWinBins) return win_rmq(q, gmin, m0, m0 + n - 1);
-  return min(win_rmq(q, gmin, m0, kWinBins - 1), win_rmq(q, gmin, 0, m0 + n - 1 - kWinBins));
-}
-
-// W3.  One thread per sorted position; core points keep their label from
-// their component and are skipped.
-__global__ __launch_bounds__(256) void k_wmcn(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
-  __shared__ WinRmq s_q;
-  const int V = dbscan_V(b, zin, Vin);
-  if ((int)blockIdx.x * 256 >= V) return;
-  const int pos = (int)blockIdx.x * 256 + (int)threadIdx.x;
-  const bool in = pos < V;
-  const float2* zs = reinterpret_cast<const float2*>(b.zs);
-  const int* ws = b.wstart;
-  // the point's operands are requested before the table is built
-  const int nring = ws[kWinBins];
-  const float2 zk = in ? zs[pos] : make_float2(0.f, 0.f);
-  const int nk = in ? b.wnc[pos] : c.min_pts;
-  const int k = in ? b.sid[pos] : 0;
-  win_rmq_build<256>(b, s_q);
-  if (!in || nk >= c.min_pts) return;
-  const float r2 = c.eps2;
-  int m = kInt32Max;
-  if (pos < nring) {
-    const WinRange r = win_range(c, win_u(c, zk));
-    if (r.all) {
-      m = s_q.sp[6][0];
-    } else {
-      m = win_rmq_range(s_q, b.wbmin, r.sl, r.sh);
-      int p0, p1, q0, q1;
-      win_pos(ws, r.lb0, r.lb1, p0, p1, q0, q1);
-      m = win_core_min(zk, b, p0, p1, r2, c.min_pts, m);
-      m = win_core_min(zk, b, q0, q1, r2, c.min_pts, m);
-      win_pos(ws, r.rb0, r.rb1, p0, p1, q0, q1);
-      m = win_core_min(zk, b, p0, p1, r2, c.min_pts, m);
-      m = win_core_min(zk, b, q0, q1, r2, c.min_pts, m);
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * kWave;
+      qq[u] = e < tot ? at(e) : -1;
+      nq[u] = qq[u] >= 0 ? b.wnc[qq[u]] : 0;
+      zq[u] = qq[u] >= 0 ? zs[qq[u]] : make_float2(0.f, 0.f);
     }
-    m = win_core_min(zk, b, nring, V, r2, c.min_pts, m);
-  } else {
-    m = win_core_min(zk, b, 0, V, r2, c.min_pts, m);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (nq[u] >= c.min_pts && ZVec<2>::d2(zk, zq[u]) <= r2) mt = min(mt, b.sid[qq[u]]);
   }
-  b.mcn[k] = m;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mt = min(mt, __shfl_xor(mt, off, kWave));
+  if (mt >= kNoCore) return kInt32Max;
+  return mt == m && ring ? (m | ((mb + 1) << kWinShift)) : mt;
 }
 
-// union-find over the nodes of W4 (runs, then off-ring points), in global
+// union-find over the nodes of K2 (runs, then off-ring points), in global
 // memory, within one workgroup: parents always point to a lower node.  Words
 // that atomics update are read with atomic loads.
 __device__ __forceinline__ int ld_wg(const int* p) {
@@ -1705,20 +1881,50 @@ __device__ __forceinline__ void win_union(int* parent, int x, int y) {
   }
 }
 
-// W4.  One 1024-thread block.
+// Point data of one labelling chunk of the window path (points a0 + u *
+// kFinThreads + threadIdx.x): neighbour count and key; with stats the cost
+// and direction.
+__device__ __forceinline__ void win_label_keys(const Bufs& b, int a0, int V, int (&nc)[kLabBatch],
+                                               int (&key)[kLabBatch]) {
+#pragma unroll
+  for (int u = 0; u < kLabBatch; ++u) {
+    const int a = a0 + u * kFinThreads + threadIdx.x;
+    nc[u] = a < V ? b.ncount[a] : 0;
+    key[u] = a < V ? b.wkey[a] : -1;
+  }
+}
+__device__ __forceinline__ void win_label_stats(const Bufs& b, int a0, int V, bool stats, float (&Sa)[kLabBatch],
+                                                float2 (&ga)[kLabBatch]) {
+  const float2* gv = reinterpret_cast<const float2*>(b.gv);
+#pragma unroll
+  for (int u = 0; u < kLabBatch; ++u) {
+    const int a = a0 + u * kFinThreads + threadIdx.x;
+    Sa[u] = (stats && a < V) ? b.Sv[a] : 0.f;
+    ga[u] = (stats && a < V) ? gv[a] : float2{};
+  }
+}
+
+// K2: one 1024-thread block.  Runs of core buckets, the links across their
+// gaps and the off-ring core points give the components; the lowest-index
+// core neighbour of each non-core point (one wave per point) gives the
+// border rule; labels and cluster statistics as in k_tree_cc.  Clears the
+// bucket counts and minima for the next call.
 __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float* __restrict__ zin, int Vin,
                                                      int* mout, int* lab_out, int* cnt_out) {
   using ZT = float2;
   constexpr int PER = kWinBins / kFinThreads;  // buckets per thread
   constexpr int NBW = kWinMaxK / 32;           // words of the component-minimum bitmap
+  constexpr int NW = kFinThreads / kWave;
   static_assert(kWinMaxRuns <= kFinThreads, "one run per thread");
-  __shared__ int s_lab[kWinBins];              // bucket -> run, then cluster label (-1: no core point)
+  __shared__ short s_lab[kWinBins];            // bucket -> run, then cluster label (-1: no core point)
+  __shared__ short s_bmin[kWinBins];           // lowest core index of each bucket (kNoCore: none)
   __shared__ int s_run[kWinMaxRuns];           // run -> lowest core index, then cluster label
-  __shared__ int s_mj[kWinMaxRuns], s_mp[kWinMaxRuns];  // gaps that may link two runs
+  __shared__ short s_mj[kWinMaxRuns], s_mp[kWinMaxRuns];  // gaps that may link two runs
   __shared__ unsigned s_bits[NBW];
   __shared__ int s_boff[NBW];
   __shared__ int s_nmaybe;
-  __shared__ float s_red[kFinThreads / kWave][kStatClusters][6];
+  __shared__ int s_ncl[kFinThreads];          // non-core points of one labelling round, then their results
+  __shared__ float s_red[NW][kStatClusters][6];
   __shared__ float s_tot[kStatClusters][6];
   const int V = dbscan_V(b, zin, Vin);
   const int t = (int)threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
@@ -1732,23 +1938,27 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
     return;
   }
   const bool stats_pts = zin == nullptr;
+  const float2* zsrc = reinterpret_cast<const float2*>(zin ? zin : b.z);
   const float2* zs = reinterpret_cast<const float2*>(b.zs);
   const int* ws = b.wstart;
-  // the first labelling chunk's point data are requested first
-  int nc0[kLabBatch], x0[kLabBatch], key0[kLabBatch];
-  float S0[kLabBatch];
-  ZT g0[kLabBatch];
-  label_loads<2>(c, b, 0, V, stats_pts, nc0, x0, S0, g0);
+  const float r2 = c.eps2;
+  // every independent operand first: the bucket minima and the first
+  // labelling chunk's point data
+  const int nring = ws[kWinBins];
   int bm[PER];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) bm[i] = b.wbmin[t * PER + i];
-  const int nring = ws[kWinBins];
-#pragma unroll
-  for (int u = 0; u < kLabBatch; ++u) key0[u] = x0[u] >= 0 ? b.wkey[x0[u]] : -1;
+  for (int i = 0; i < PER; ++i) {
+    const int v = b.wbmin[t * PER + i];
+    bm[i] = v ? kWinMaxK - v : kInt32Max;
+  }
+  int nc[kLabBatch], key[kLabBatch];
+  win_label_keys(b, 0, V, nc, key);
   const int noff = V - nring;
   s_run[t] = kInt32Max;
   if (t < NBW) s_bits[t] = 0u;
   if (t == 0) s_nmaybe = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) s_bmin[t * PER + i] = (short)min(bm[i], (int)kNoCore);
   // the core bucket before each core bucket (cyclic) and the gap to it
   int mine = -1;
 #pragma unroll
@@ -1781,12 +1991,12 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
     if (bm[i] != kInt32Max) {
       cum += st[i];
       const int run = nst == 0 ? 0 : (cum > 0 ? cum - 1 : nst - 1);
-      s_lab[j] = run;
+      s_lab[j] = (short)run;
       atomicMin(&s_run[run], bm[i]);
       if (st[i] && nR >= 2 && j - prv[i] <= c.w_gout) {
         const int q = atomicAdd(&s_nmaybe, 1);
-        s_mj[q] = j;
-        s_mp[q] = prv[i];
+        s_mj[q] = (short)j;
+        s_mp[q] = (short)prv[i];
       }
     } else {
       s_lab[j] = -1;
@@ -1807,44 +2017,71 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
                        : (b.wnc[nring + i - nR] >= c.min_pts ? b.sid[nring + i - nR] : kInt32Max);
     }
     __syncthreads();
-    const float r2 = c.eps2;
     // a gap that may link two runs: core pairs across it, one wave per gap
-    for (int gi = wv; gi < nmaybe; gi += kFinThreads / kWave) {
+    for (int gi = wv; gi < nmaybe; gi += NW) {
       const int j = s_mj[gi], pj = s_mp[gi];
       int a0, a1, a2, a3, c0, c1, c2, c3;
       win_pos(ws, j - c.w_gout, pj, a0, a1, a2, a3);
       win_pos(ws, j, pj + c.w_gout, c0, c1, c2, c3);
       const int na = (a1 - a0) + (a3 - a2), nb = (c1 - c0) + (c3 - c2);
+      // 64 points of each side per round, one per lane; the A points are
+      // broadcast from their lanes
       bool hit = false;
-      for (int ia = 0; ia < na && !hit; ++ia) {
+      for (int ia0 = 0; ia0 < na && !hit; ia0 += kWave) {
+        const int ia = ia0 + lane;
         const int pa = ia < a1 - a0 ? a0 + ia : a2 + ia - (a1 - a0);
-        if (b.wnc[pa] < c.min_pts) continue;
-        const float2 za = zs[pa];
-        bool h = false;
-        for (int ib = lane; ib < nb; ib += kWave) {
+        const bool ca = ia < na && b.wnc[pa] >= c.min_pts;
+        const float2 za = ia < na ? zs[pa] : make_float2(0.f, 0.f);
+        const unsigned long long acore = __ballot(ca);
+        for (int ib0 = 0; ib0 < nb && !hit && acore; ib0 += kWave) {
+          const int ib = ib0 + lane;
           const int pb = ib < c1 - c0 ? c0 + ib : c2 + ib - (c1 - c0);
-          h |= b.wnc[pb] >= c.min_pts && ZVec<2>::d2(za, zs[pb]) <= r2;
+          const bool cb = ib < nb && b.wnc[pb] >= c.min_pts;
+          const float2 zb = ib < nb ? zs[pb] : make_float2(0.f, 0.f);
+          bool h = false;
+          unsigned long long am = acore;
+          while (am) {
+            const int L = __ffsll((long long)am) - 1;
+            am &= am - 1ull;
+            const float2 zl = make_float2(__shfl(za.x, L, kWave), __shfl(za.y, L, kWave));
+            h |= cb && ZVec<2>::d2(zl, zb) <= r2;
+          }
+          hit = __ballot(h) != 0ull;
         }
-        hit = __ballot(h) != 0ull;
       }
       if (hit && lane == 0) win_union(parent, s_lab[wmod(pj)], s_lab[j]);
     }
-    // off-ring core points: every core neighbour, one wave per point
-    for (int o = wv; o < noff; o += kFinThreads / kWave) {
+    // off-ring core points: every core neighbour, the whole block on each
+    // (a thread unions each node it meets once in a row)
+    for (int o = 0; o < noff; ++o) {
       const int po = nring + o;
       if (b.wnc[po] < c.min_pts) continue;
       const float2 zo = zs[po];
-      for (int q = lane; q < V; q += kWave) {
-        if (q == po || b.wnc[q] < c.min_pts || !(ZVec<2>::d2(zo, zs[q]) <= r2)) continue;
-        const int node = q < nring ? s_lab[b.wkey[b.sid[q]] >> kWinShift] : nR + (q - nring);
-        win_union(parent, nR + o, node);
+      int prev_node = -1;
+      for (int q0 = t; q0 < V; q0 += kFinThreads * 4) {
+        int nq[4];
+        float2 zq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u * kFinThreads;
+          nq[u] = q < V ? b.wnc[q] : 0;
+          zq[u] = q < V ? zs[q] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u * kFinThreads;
+          if (q >= V || q == po || nq[u] < c.min_pts || !(ZVec<2>::d2(zo, zq[u]) <= r2)) continue;
+          const int node = q < nring ? s_lab[b.wkey[b.sid[q]] >> kWinShift] : nR + (q - nring);
+          if (node != prev_node) win_union(parent, nR + o, node);
+          prev_node = node;
+        }
       }
     }
     __syncthreads();
     // (nodes that are not roots keep their own minimum; roots only decrease)
     for (int i = t; i < nn; i += kFinThreads) {
-      const int r = win_find(parent, i), m = ld_wg(&cmin[i]);
-      if (m != kInt32Max && r != i) atomicMin(&cmin[r], m);
+      const int rt = win_find(parent, i), m = ld_wg(&cmin[i]);
+      if (m != kInt32Max && rt != i) atomicMin(&cmin[rt], m);
     }
     __syncthreads();
     for (int i = t; i < nn; i += kFinThreads) {
@@ -1873,7 +2110,7 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = t * PER + i;
-    if (s_lab[j] >= 0) s_lab[j] = s_run[s_lab[j]];
+    if (s_lab[j] >= 0) s_lab[j] = (short)s_run[s_lab[j]];
   }
   if (t == 0) {
     b.ctrl->n_trees = nR;
@@ -1886,27 +2123,62 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
   // lowest-index core neighbour, noise -> -1; statistics as in k_tree_cc
   const bool stats = stats_pts && M > 0;
   for (int a0 = 0; a0 < V; a0 += kFinThreads * kLabBatch) {
-    int nc[kLabBatch], x[kLabBatch], key[kLabBatch], lab[kLabBatch];
+    int lab[kLabBatch];
+    if (a0 > 0) win_label_keys(b, a0, V, nc, key);
+    // (requested here, used by the statistics after the border rule)
     float Sa[kLabBatch];
     ZT ga[kLabBatch];
-    if (a0 == 0) {
+    win_label_stats(b, a0, V, stats_pts && M > 0, Sa, ga);
+    // non-core points: the key of their lowest-index core neighbour (none:
+    // noise).  They are listed in LDS, kFinThreads at a time, and every wave
+    // takes list entries in turn, one point per wave.
+    int mync = 0;
+#pragma unroll
+    for (int u = 0; u < kLabBatch; ++u) mync += (a0 + u * kFinThreads + t < V && nc[u] < c.min_pts) ? 1 : 0;
+    int nnc;
+    const int ncb = block_excl_scan<kFinThreads>(mync, &nnc);
+    for (int base = 0; base < nnc; base += kFinThreads) {
+      int r = ncb;
 #pragma unroll
       for (int u = 0; u < kLabBatch; ++u) {
-        nc[u] = nc0[u];
-        x[u] = x0[u];
-        key[u] = key0[u];
-        Sa[u] = S0[u];
-        ga[u] = g0[u];
+        const int a = a0 + u * kFinThreads + t;
+        if (a < V && nc[u] < c.min_pts) {
+          if (r >= base && r < base + kFinThreads) s_ncl[r - base] = a;
+          ++r;
+        }
       }
-    } else {
-      label_loads<2>(c, b, a0, V, stats_pts, nc, x, Sa, ga);
+      __syncthreads();
+      const int n_this = min(kFinThreads, nnc - base);
+      for (int i = wv; i < n_this; i += NW) {
+        const int a = s_ncl[i];
+        const int ka = b.wkey[a];
+        const int m = win_mcn_wave(c, b, s_bmin, ws, zsrc[a], (ka >> kWinShift) < kWinBins, nring, V);
+        if (lane == 0) {
+          b.mcn[a] = m == kInt32Max ? m : (m & (kWinMaxK - 1));
+          s_ncl[i] = m;
+        }
+      }
+      __syncthreads();
+      // each owner takes its points' results
+      r = ncb;
 #pragma unroll
-      for (int u = 0; u < kLabBatch; ++u) key[u] = x[u] >= 0 ? b.wkey[x[u]] : -1;
+      for (int u = 0; u < kLabBatch; ++u) {
+        const int a = a0 + u * kFinThreads + t;
+        if (a < V && nc[u] < c.min_pts) {
+          if (r >= base && r < base + kFinThreads) {
+            // (the neighbour's bucket when known, else its key)
+            const int m = s_ncl[r - base], mbk = (m >> kWinShift) - 1;
+            key[u] = m == kInt32Max ? -1 : (mbk >= 0 ? mbk << kWinShift : b.wkey[m]);
+          }
+          ++r;
+        }
+      }
+      __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < kLabBatch; ++u) {
       const int bk = key[u] >> kWinShift;
-      lab[u] = key[u] < 0 ? -1 : (bk < kWinBins ? s_lab[bk] : olab[key[u] & (kWinMaxK - 1)]);
+      lab[u] = key[u] < 0 ? -1 : (bk < kWinBins ? (int)s_lab[bk] : olab[key[u] & (kWinMaxK - 1)]);
     }
 #pragma unroll
     for (int u = 0; u < kLabBatch; ++u) {
@@ -1932,9 +2204,12 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
       b.c_dir[4 * cl + 2] = 0.f;
     }
   }
-  // the bucket counts start from zero at the next call
+  // the bucket counts and minima start from zero at the next call
 #pragma unroll
-  for (int i = 0; i < PER; ++i) b.wcnt[t * PER + i] = 0;
+  for (int i = 0; i < PER; ++i) {
+    b.wcnt[t * PER + i] = 0;
+    b.wbmin[t * PER + i] = 0;
+  }
   if (t == 0) b.wcnt[kWinBins] = 0;
 }
 
@@ -2452,9 +2727,7 @@ static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const floa
   if (P == 2 && use_window(c, b)) {
     // grids sized for every point the call may have (K for a replan)
     const int cap = ntile * kTile;
-    L(k_wplace, dim3((cap + kFinThreads - 1) / kFinThreads), dim3(kFinThreads), c, b, zin, Vin);
-    L(k_wcount, dim3((cap + 255) / 256), dim3(256), c, b, zin, Vin);
-    L(k_wmcn, dim3((cap + 255) / 256), dim3(256), c, b, zin, Vin);
+    L(k_wcount, dim3((cap + kWinThreads - 1) / kWinThreads), dim3(kWinThreads), c, b, zin, Vin);
     L(k_wcc, dim3(1), dim3(kFinThreads), c, b, zin, Vin, mout, lab_out, cnt_out);
     return;
   }

@@ -179,9 +179,10 @@ struct Bufs {
   int* wcnt;       // [kWinBins + 1] points per bucket (the last: off the ring); zero between calls
   int* wstart;     // [kWinBins + 2] first sorted position of each bucket; [kWinBins] = ring points
   int* wkey;       // [K] bucket << kWinShift | slot, by compacted index
-  int* wbmin;      // [kWinBins] lowest core index in each bucket (kInt32Max if none)
+  int* wbmin;      // [kWinBins] kWinMaxK - lowest core index in each bucket (0 if none); zero between calls
   int* wnc;        // [K] neighbour counts by sorted position
   int* wuf;        // [3][kWinMaxRuns + K] union-find parents, component minima, off-ring labels
+  int* wzone;      // [ceil(K / 512)][K] indices of a count block's zone when it exceeds LDS
   float* upart;    // [nblk_upd][NM + 1]
   float* Unew;     // [N][m] updated sequence before the shift
 };

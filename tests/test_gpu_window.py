@@ -64,6 +64,16 @@ def _cases():
     z[:60] = rng.normal(0, 0.3, (60, 2)).astype(np.float32)
     z[60:120] *= np.float32(0.5)
     cases.append(("off_ring", z, 0.25, 10))
+    # one feature just inside the ring tolerance among 8,191 on it (the
+    # terminal point nearest the reference point)
+    z = _ring(rng, rng.uniform(-math.pi, math.pi, 8192))
+    z[4321] *= np.float32(0.9984)
+    cases.append(("one_off_8192", z, 0.25, 20))
+    # a sparse stretch between two dense arcs: the block of sorted points
+    # that spans it needs more boundary points than its LDS holds
+    th = np.concatenate([rng.uniform(0.0, 0.4, 7000), rng.uniform(0.4, 3.0, 600),
+                         rng.uniform(3.0, 3.4, 7000)])
+    cases.append(("sparse_between_dense", _ring(rng, th), 0.25, 20))
     # more than 64 clusters
     ang = np.repeat(np.arange(90) * (2 * math.pi / 90), 20) + rng.normal(0, 0.002, 1800)
     cases.append(("90_groups", _ring(rng, ang), 0.03, 5))
