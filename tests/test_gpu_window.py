@@ -74,6 +74,10 @@ def _cases():
     th = np.concatenate([rng.uniform(0.0, 0.4, 7000), rng.uniform(0.4, 3.0, 600),
                          rng.uniform(3.0, 3.4, 7000)])
     cases.append(("sparse_between_dense", _ring(rng, th), 0.25, 20))
+    # one bucket with more points than the bucket-major tables hold (the
+    # count pass then scans the keys)
+    th = np.concatenate([np.full(300, 1.2345), rng.normal(1.0, 0.4, 2700)])
+    cases.append(("crowded_bucket", _ring(rng, th), 0.25, 20))
     # more than 64 clusters
     ang = np.repeat(np.arange(90) * (2 * math.pi / 90), 20) + rng.normal(0, 0.002, 1800)
     cases.append(("90_groups", _ring(rng, ang), 0.03, 5))
