@@ -63,6 +63,8 @@ def parse():
                     help="skip the clustering-branch companion measurement")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-form companion measurement")
+    ap.add_argument("--no-scaling", action="store_true",
+                    help="skip the clustering-branch replays at K = 16384 and 65536")
     ap.add_argument("--no-companions", action="store_true",
                     help="skip the static 2-D and arm workloads")
     ap.add_argument("--no-serve", action="store_true",
@@ -81,13 +83,18 @@ def parse():
 def scene_for(name, seed):
     from paper_2607_06499_amd import workloads as W
 
-    return {"unicycle_dynamic": W.unicycle_dynamic,
-            "unicycle_dynamic_ahead": W.unicycle_dynamic_ahead,
-            "unicycle_static": W.unicycle_static,
-            "unicycle_static_ahead": W.unicycle_static_ahead,
-            "arm6_dynamic": W.arm6_dynamic,
-            "unicycle_dynamic_cv": W.unicycle_dynamic_cv,
-            "arm6_pose": W.arm6_pose}[name](seed)
+    table = {"unicycle_dynamic": W.unicycle_dynamic,
+             "unicycle_dynamic_ahead": W.unicycle_dynamic_ahead,
+             "unicycle_static": W.unicycle_static,
+             "unicycle_static_ahead": W.unicycle_static_ahead,
+             "arm6_dynamic": W.arm6_dynamic,
+             "unicycle_dynamic_cv": W.unicycle_dynamic_cv,
+             "arm6_pose": W.arm6_pose}
+    if "@" in name:
+        # another rollout count: "<workload>@<K>"
+        base, k = name.split("@")
+        return table[base](seed, num_samples=int(k))
+    return table[name](seed)
 
 
 def record_loop(pl, scene, T, torch, snap_at=0):
@@ -730,6 +737,24 @@ def main():
             ab[q["dbscan_path"]] = {"replans_per_s": round(q["K"] * q["L"] / q["wall"], 2),
                                     "device_us": q["per_branch"]["cluster"].get("device_us")}
         out["clustering_branch"]["other_dbscan_paths"] = ab
+        # the same scene with more rollouts: the pairwise paths grow with
+        # V^2, the window path with V (the bitmap stops at K = 16384)
+        if not args.no_scaling:
+            scal = {}
+            for ks, modes in ((16384, (1, 2, 3)), (65536, (1, 3))):
+                sc = {}
+                for m in modes:
+                    q = run_workload(f"unicycle_dynamic_ahead@{ks}", args.seed, 0, 20, 1, 3, torch, B,
+                                     want_timing=True, rollout_reps=20, dbscan_mode=m)
+                    cb = q["per_branch"].get("cluster", {})
+                    sc[q["dbscan_path"]] = {"replans_per_s": round(q["K"] * q["L"] / q["wall"], 2),
+                                            "branch_mix": q["mix"],
+                                            "mean_feasible": cb.get("mean_feasible"),
+                                            "device_us": cb.get("device_us")}
+                scal[f"K{ks}"] = sc
+            out["clustering_branch"]["larger_K"] = dict(
+                workload="unicycle_dynamic_ahead with K=16384 and K=65536 rollouts (replays of a "
+                         "20-replan loop) on each single-planner DBSCAN path", **scal)
     if not args.no_companions and args.workload == "unicycle_dynamic":
         cK = max(2, min(K, 3))
         out["static_2d"] = companion("unicycle_static", args.seed, 0, 200, cK, torch, B,

@@ -291,7 +291,7 @@ ce_status ce_mppi_stage_dbscan(ce_mppi_planner* planner, const float* z, int32_t
  *                     between the windows, and features off the ring, are
  *                     tested pair by pair.  About O(V) window lookups plus
  *                     the boundary tests, where the others take V^2/2 pairs.
- *                     Needs p = 2, K <= 16384 and eps in roughly [0.01, 1.4].
+ *                     Needs p = 2 and eps in roughly [0.01, 1.4].
  *   CE_DBSCAN_BITMAP  one tiled pass over the V^2/2 pairs into an
  *                     eps-adjacency bitmap that the later passes read;
  *                     K <= 16384.

@@ -137,9 +137,9 @@ ce_status validate(const ce_mppi_config* c) {
 // angle surely not.  The windows lose the error of two computed angles
 // (atan2f, the shift by pi and the scaling to buckets: well under 1e-5 rad
 // each) and 1e-2 bucket for the rounding of u +- w.  Leaves w_g = 0 (path
-// off) where the windows do not fit: 3-D features, K beyond the key's slot
-// bits, an inner window under five buckets (eps below about 0.01) or an
-// outer window of a quarter turn or more (eps above about 1.4).
+// off) where the windows do not fit: 3-D features, an inner window under
+// five buckets (eps below about 0.01) or an outer window of a quarter turn
+// or more (eps above about 1.4).
 void set_windows(Cfg& c) {
   const double pi = 3.14159265358979323846, beta = 2.0 * pi / kWinBins;
   const double delta = 1e-3;
@@ -626,7 +626,7 @@ ce_status ce_mppi_set_dbscan_mode(ce_mppi_planner* P, int32_t mode) {
     case CE_DBSCAN_AUTO: path = P->b.wcnt ? 0 : (P->b.adj ? 1 : 2); break;
     case CE_DBSCAN_WINDOW:
       if (!P->b.wcnt)
-        return fail(CE_EUNSUPPORTED, "angular windows need 2-D features, K <= 16384 and eps in [0.01, 1.4]");
+        return fail(CE_EUNSUPPORTED, "angular windows need 2-D features and eps in [0.01, 1.4]");
       path = 0;
       break;
     case CE_DBSCAN_BITMAP:

@@ -1754,7 +1754,7 @@ __device__ __forceinline__ int win_core_min(float2 zk, const Bufs& b, int p0, in
   return m;
 }
 
-constexpr short kNoCore = 0x7fff;  // above every index (V <= kWinMaxK)
+constexpr int kNoCore = kWinMaxK;  // above every index (V <= kWinMaxK)
 
 // Lowest-index core neighbour of one non-core point at feature zk, by the
 // whole wave (zk and ring wave-uniform), as index | (bucket + 1) << kWinShift
@@ -1764,7 +1764,7 @@ constexpr short kNoCore = 0x7fff;  // above every index (V <= kWinMaxK)
 // holds a lower core index or there are off-ring points (LDS only); then
 // the core points of the boundary buckets and the off-ring points are
 // tested (every point for an off-ring zk).
-__device__ int win_mcn_wave(const Cfg& c, const Bufs& b, const short* s_bmin, const int* ws, float2 zk, bool ring,
+__device__ int win_mcn_wave(const Cfg& c, const Bufs& b, const int* s_bmin, const int* ws, float2 zk, bool ring,
                             int nring, int V) {
   const int lane = (int)(threadIdx.x & (kWave - 1));
   const float2* zs = reinterpret_cast<const float2*>(b.zs);
@@ -1914,10 +1914,11 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
   using ZT = float2;
   constexpr int PER = kWinBins / kFinThreads;  // buckets per thread
   constexpr int NBW = kWinMaxK / 32;           // words of the component-minimum bitmap
+  constexpr int BPT = (NBW + kFinThreads - 1) / kFinThreads;  // of them per thread
   constexpr int NW = kFinThreads / kWave;
   static_assert(kWinMaxRuns <= kFinThreads, "one run per thread");
-  __shared__ short s_lab[kWinBins];            // bucket -> run, then cluster label (-1: no core point)
-  __shared__ short s_bmin[kWinBins];           // lowest core index of each bucket (kNoCore: none)
+  __shared__ int s_lab[kWinBins];              // bucket -> run, then cluster label (-1: no core point)
+  __shared__ int s_bmin[kWinBins];             // lowest core index of each bucket (kNoCore: none)
   __shared__ int s_run[kWinMaxRuns];           // run -> lowest core index, then cluster label
   __shared__ short s_mj[kWinMaxRuns], s_mp[kWinMaxRuns];  // gaps that may link two runs
   __shared__ unsigned s_bits[NBW];
@@ -1955,10 +1956,12 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
   win_label_keys(b, 0, V, nc, key);
   const int noff = V - nring;
   s_run[t] = kInt32Max;
-  if (t < NBW) s_bits[t] = 0u;
+#pragma unroll
+  for (int i = 0; i < BPT; ++i)
+    if (t * BPT + i < NBW) s_bits[t * BPT + i] = 0u;
   if (t == 0) s_nmaybe = 0;
 #pragma unroll
-  for (int i = 0; i < PER; ++i) s_bmin[t * PER + i] = (short)min(bm[i], (int)kNoCore);
+  for (int i = 0; i < PER; ++i) s_bmin[t * PER + i] = min(bm[i], kNoCore);
   // the core bucket before each core bucket (cyclic) and the gap to it
   int mine = -1;
 #pragma unroll
@@ -1991,7 +1994,7 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
     if (bm[i] != kInt32Max) {
       cum += st[i];
       const int run = nst == 0 ? 0 : (cum > 0 ? cum - 1 : nst - 1);
-      s_lab[j] = (short)run;
+      s_lab[j] = run;
       atomicMin(&s_run[run], bm[i]);
       if (st[i] && nR >= 2 && j - prv[i] <= c.w_gout) {
         const int q = atomicAdd(&s_nmaybe, 1);
@@ -2093,10 +2096,17 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
   }
   __syncthreads();
   // clusters are the components ranked by their lowest core index
-  const unsigned wbits = t < NBW ? s_bits[t] : 0u;
+  int npop = 0;
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) npop += t * BPT + i < NBW ? __popc(s_bits[t * BPT + i]) : 0;
   int M;
-  const int boff = block_excl_scan<kFinThreads>(__popc(wbits), &M);
-  if (t < NBW) s_boff[t] = boff;
+  int boff = block_excl_scan<kFinThreads>(npop, &M);
+#pragma unroll
+  for (int i = 0; i < BPT; ++i)
+    if (t * BPT + i < NBW) {
+      s_boff[t * BPT + i] = boff;
+      boff += __popc(s_bits[t * BPT + i]);
+    }
   __syncthreads();
   auto rank_of = [&](int x) {
     const int w = x >> 5, bit = x & 31;
@@ -2110,7 +2120,7 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = t * PER + i;
-    if (s_lab[j] >= 0) s_lab[j] = (short)s_run[s_lab[j]];
+    if (s_lab[j] >= 0) s_lab[j] = s_run[s_lab[j]];
   }
   if (t == 0) {
     b.ctrl->n_trees = nR;
@@ -2178,7 +2188,7 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
 #pragma unroll
     for (int u = 0; u < kLabBatch; ++u) {
       const int bk = key[u] >> kWinShift;
-      lab[u] = key[u] < 0 ? -1 : (bk < kWinBins ? (int)s_lab[bk] : olab[key[u] & (kWinMaxK - 1)]);
+      lab[u] = key[u] < 0 ? -1 : (bk < kWinBins ? s_lab[bk] : olab[key[u] & (kWinMaxK - 1)]);
     }
 #pragma unroll
     for (int u = 0; u < kLabBatch; ++u) {

@@ -56,9 +56,10 @@ constexpr int kMcnLoads = (kAdjMaxK / kTile + kMcnSplit - 1) / kMcnSplit;  // ro
 // angular-window DBSCAN of single planners with 2-D features (the unit
 // directions of Eq. (13)): points on the unit ring are binned by angle into
 // kWinBins buckets; the compacted index of a point and its slot in its bucket
-// share one key (bucket << kWinShift | slot), so V <= 2^kWinShift
+// share one key (bucket << kWinShift | slot), so V <= 2^kWinShift, which
+// covers every planner size
 constexpr int kWinBins = 4096;
-constexpr int kWinShift = 14;
+constexpr int kWinShift = 16;
 constexpr int kWinMaxK = 1 << kWinShift;
 constexpr int kWinMaxRuns = 1024;  // runs of core buckets (at most kWinBins / (gap + 1) with gap >= 3)
 static_assert(kWinMaxK >= kAdjMaxK, "the windowed path covers every planner with a bitmap");

@@ -9,7 +9,8 @@ compared by that contract.  The feature sets put the windows' edge cases in
 reach: gaps between runs of core buckets swept across the critical angle in
 quarter-bucket steps (the boundary tests that link or split runs), clusters
 across the +-pi seam, features off the unit ring, duplicates, small and
-large eps, and a full 16,384-point arc."""
+large eps, a full 16,384-point arc, and planners of 32,768 and 65,536
+rollouts, beyond the bitmap's limit."""
 import math
 
 import numpy as np
@@ -85,6 +86,13 @@ def _cases():
     cases.append(("small_eps", _ring(rng, rng.normal(0, 0.05, 2000)), 0.02, 5))
     cases.append(("duplicates", _ring(rng, np.repeat(rng.uniform(-3, 3, 40), 25), 1.0, 1.0), 0.1, 10))
     cases.append(("two_points", _ring(rng, np.array([0.1, 0.1 + crit])), eps, 1))
+    # planners beyond the bitmap's limit (window against the distance passes)
+    cases.append(("arc_32768", _ring(rng, rng.normal(-2.0, 0.4, 32768)), 0.25, 20))
+    th = np.concatenate([rng.normal(1.0, 0.3, 40000), rng.normal(2.6, 0.2, 25000),
+                         rng.uniform(-math.pi, math.pi, 536)])
+    z = _ring(rng, th)
+    z[:300] = rng.normal(0, 0.4, (300, 2)).astype(np.float32)
+    cases.append(("two_arcs_65536", z, 0.25, 20))
     return cases
 
 
@@ -96,27 +104,46 @@ def test_window_matches_bitmap_tiled_and_definition(case):
     from paper_2607_06499_amd import binding as B
 
     name, z, eps, min_pts = CASES[case]
-    spec = W.PlannerSpec(num_samples=max(len(z), 64), dbscan_eps=eps, dbscan_min_pts=min_pts).rounded()
+    V = len(z)
+    spec = W.PlannerSpec(num_samples=max(V, 64), horizon=8 if V > 16384 else 50, dbscan_eps=eps,
+                         dbscan_min_pts=min_pts).rounded()
     pl = B.Planner(spec)
     assert pl.dbscan_path() == B.DBSCAN_WINDOW
+    modes = (B.DBSCAN_WINDOW, B.DBSCAN_TILED) + ((B.DBSCAN_BITMAP,) if V <= 16384 else ())
     res = {}
-    for mode in (B.DBSCAN_WINDOW, B.DBSCAN_BITMAP, B.DBSCAN_TILED):
+    for mode in modes:
         pl.set_dbscan_mode(mode)
         lab, cnt, M = pl.stage_dbscan(H.to_dev(z))
         res[mode] = (lab.cpu().numpy(), cnt.cpu().numpy(), int(M.cpu().item()))
         if mode == B.DBSCAN_WINDOW:
             runs = int(pl.debug(B.DBG_TREES, 2).cpu().numpy()[0])
+    pl.close()
     lw, cw, mw = res[B.DBSCAN_WINDOW]
-    lb, cb, mb = res[B.DBSCAN_BITMAP]
     lt, ct, mt = res[B.DBSCAN_TILED]
-    print(f"{name}: V={len(z)} M={mw} runs={runs}")
-    assert np.array_equal(cw, cb), name
-    assert np.array_equal(lw, lb) and np.array_equal(lw, lt), name
-    assert mw == mb == mt, name
+    print(f"{name}: V={V} M={mw} runs={runs}")
+    if B.DBSCAN_BITMAP in res:
+        lb, cb, mb = res[B.DBSCAN_BITMAP]
+        assert np.array_equal(cw, cb) and np.array_equal(lw, lb) and mw == mb, name
+    assert np.array_equal(lw, lt) and mw == mt, name
     assert H.counts_agree(ct, cw, min_pts), name
     eps32 = float(np.float32(eps))
     z64 = z.astype(np.float64)
+    if V > 40000:
+        # beyond what the brute-force check finishes in seconds: exact FP64
+        # counts of sampled points (one row of distances each), every
+        # difference explained by a pair within the band of eps
+        rng = np.random.default_rng(3)
+        lim = 0.5 * H.STAGE_BAND * eps32
+        for k in rng.choice(V, 256, replace=False):
+            d = np.sqrt(((z64 - z64[k]) ** 2).sum(1))
+            exact = int((d <= eps32).sum())
+            band = int((np.abs(d - eps32) <= 2 * lim).sum())
+            assert abs(int(cw[k]) - exact) <= band, (name, k, cw[k], exact, band)
+        return
     olab, _, ocnt, oM = oracle.dbscan(z64, eps32, min_pts)
+    if V > 16384 and np.array_equal(cw, ocnt) and np.array_equal(lw, olab):
+        print(f"{name}: counts and labels equal to the oracle's")
+        return
     st = H.dbscan_check(z64, eps32, min_pts, cw, lw, 0.5 * H.STAGE_BAND * eps32, exact_ref=olab, tag=name)
     print(f"{name}: {st}")
     if st["flagged_pairs"] == 0:
@@ -128,6 +155,8 @@ def _twins(spec):
 
     pls = {}
     for mode in (B.DBSCAN_WINDOW, B.DBSCAN_BITMAP, B.DBSCAN_TILED):
+        if mode == B.DBSCAN_BITMAP and spec.num_samples > 16384:
+            continue
         pl = B.Planner(spec)
         pl.set_dbscan_mode(mode)
         assert pl.dbscan_path() == mode
@@ -141,6 +170,7 @@ REPLANS = [
     ("crossing_8192", lambda: W.unicycle_crossing(1, side=1, num_samples=8192, distance=1.2), 4),
     ("random_2000", lambda: W.random_scene(11, num_samples=2000, horizon=40, n_obs=10), 3),
     ("paper_unicycle_1", lambda: W.paper_unicycle_preset(1), 4),
+    ("dynamic_ahead_32768", lambda: W.unicycle_dynamic_ahead(1, num_samples=32768), 3),
 ]
 
 
@@ -163,7 +193,8 @@ def test_window_replans_bitwise(name, make, steps):
     for t in range(steps):
         obs = fld.observation()
         r = {m: H.gpu_replan(pl, np.float32(x), obs) for m, pl in pls.items()}
-        w, bm, tl = r[B.DBSCAN_WINDOW], r[B.DBSCAN_BITMAP], r[B.DBSCAN_TILED]
+        w, tl = r[B.DBSCAN_WINDOW], r[B.DBSCAN_TILED]
+        bm = r.get(B.DBSCAN_BITMAP, w)
         for k in ("S", "col", "v_idx", "z", "label", "c_mean_cost", "c_dir", "c_size", "u_out", "U_new",
                   "U_next"):
             assert np.array_equal(w[k], bm[k]) and np.array_equal(w[k], tl[k]), (name, t, k)
@@ -189,11 +220,12 @@ def test_dbscan_mode_availability():
         arm.set_dbscan_mode(B.DBSCAN_WINDOW)
     assert arm.dbscan_path() == B.DBSCAN_BITMAP
     big = B.Planner(W.PlannerSpec(num_samples=20000, horizon=8).rounded())
-    assert big.dbscan_path() == B.DBSCAN_TILED
+    assert big.dbscan_path() == B.DBSCAN_WINDOW
     with pytest.raises(B.CeMppiError):
         big.set_dbscan_mode(B.DBSCAN_BITMAP)
-    with pytest.raises(B.CeMppiError):
-        big.set_dbscan_mode(B.DBSCAN_WINDOW)
+    assert big.dbscan_path() == B.DBSCAN_WINDOW
+    big.set_dbscan_mode(B.DBSCAN_TILED)
+    assert big.dbscan_path() == B.DBSCAN_TILED
     tiny_eps = B.Planner(W.PlannerSpec(num_samples=512, dbscan_eps=0.002).rounded())
     assert tiny_eps.dbscan_path() == B.DBSCAN_BITMAP
     pl = B.Planner(W.PlannerSpec(num_samples=512).rounded())
