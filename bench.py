@@ -52,10 +52,11 @@ def parse():
     ap.add_argument("--loop-warm", type=int, default=LOOP_WARM,
                     help="closed-loop replans recorded before the timed segment")
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--workload", default="unicycle_dynamic",
-                    choices=["unicycle_dynamic", "unicycle_dynamic_ahead", "unicycle_static",
-                             "unicycle_static_ahead", "arm6_dynamic", "unicycle_dynamic_cv",
-                             "arm6_pose", "batch_uneven", "served_sessions"])
+    ap.add_argument("--workload", default="unicycle_dynamic", type=_workload_name,
+                    help="unicycle_dynamic, unicycle_dynamic_ahead, unicycle_static, "
+                         "unicycle_static_ahead, arm6_dynamic, unicycle_dynamic_cv, arm6_pose, "
+                         "batch_uneven or served_sessions; a single-planner workload may take "
+                         "another rollout count as <name>@<K>")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="budget of each CPU-oracle baseline sample (one thread, then every core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -78,6 +79,19 @@ def parse():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (profiler calibration)")
     return ap.parse_args()
+
+
+SINGLE_WORKLOADS = ("unicycle_dynamic", "unicycle_dynamic_ahead", "unicycle_static",
+                    "unicycle_static_ahead", "arm6_dynamic", "unicycle_dynamic_cv", "arm6_pose")
+
+
+def _workload_name(s):
+    base, _, k = s.partition("@")
+    ok = (s in ("batch_uneven", "served_sessions") or
+          (base in SINGLE_WORKLOADS and (not k or (k.isdigit() and 1 <= int(k) <= 65536))))
+    if not ok:
+        raise argparse.ArgumentTypeError(f"unknown workload {s!r}")
+    return s
 
 
 def scene_for(name, seed):
