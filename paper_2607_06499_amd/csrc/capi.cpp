@@ -125,7 +125,7 @@ ce_status validate(const ce_mppi_config* c) {
   return CE_OK;
 }
 
-// Angular windows of the 2-D DBSCAN (cluster.hip, k_wplace .. k_wcc), in
+// Angular windows of the 2-D DBSCAN (cluster.hip, k_wdbscan), in
 // double precision.  Ring points have |z| in [s_lo, s_hi]: the features of
 // Eq. (13) are unit directions scaled by |d| / (|d| + eps_n), so this holds
 // for every feasible rollout whose terminal point is more than about 1 mm
@@ -385,7 +385,7 @@ ce_status ce_mppi_create(const ce_mppi_config* cfg, ce_mppi_planner** out) {
   const size_t o_wkey = cv.take<int>(wk), o_wnc = cv.take<int>(wk);
   const size_t o_wuf = cv.take<int>(with_win ? 3 * (kWinMaxRuns + K) : 0);
   // (one region of K indices per block of the count pass, 512 positions each)
-  const size_t o_wzone = cv.take<int>(with_win ? (K + 511) / 512 * K : 0);
+  const size_t o_wzone = cv.take<int>(with_win ? (K + kWinPos - 1) / kWinPos * K : 0);
   const size_t o_ccost = cv.take<float>((size_t)c.mcap), o_cdir = cv.take<float>((size_t)c.mcap * 4);
   const size_t o_csize = cv.take<int>((size_t)c.mcap), o_csmin = cv.take<float>((size_t)c.mcap);
   // update partials, then rows that stay zero so the final combination can

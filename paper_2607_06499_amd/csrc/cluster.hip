@@ -195,7 +195,7 @@ __device__ __forceinline__ Totals decide(const Cfg& c, const float* tot, int bad
 // in ascending rollout order, features z (Eq. (13)) and the DBSCAN arrays.
 // Block 0 publishes the totals.
 // ---------------------------------------------------------------------------
-// Angular buckets of the windowed DBSCAN (k_wcount, k_wcc below).  The
+// Angular buckets of the windowed DBSCAN (k_wdbscan below).  The
 // bucket coordinate of a feature is its angle mapped to [0, kWinBins]; a
 // ring point has a squared norm within [w_r2lo, w_r2hi]; every other point
 // goes to the extra bucket kWinBins ("off the ring").
@@ -1409,12 +1409,13 @@ __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const fl
 // same FP32 expression as in every other DBSCAN pass, so the neighbour graph
 // is the same, and so are the counts, the core flags and the labels.
 //  bin    (in the compaction) each feature's bucket and its slot there
-//  count  (k_wcount) the sorted order by bucket; count = ring points of the
-//         inner window (two bucket starts) + hits among the boundary buckets
-//         and the off-ring points: exact; the lowest core index of every bucket
-//  cc     (k_wcc, one block) core buckets at most w_g apart hold core points
-//         that are neighbours for certain, so a run of such buckets is
-//         connected; two adjacent runs more than w_gout apart are not, and
+//  count  (K1, every block of k_wdbscan) the sorted order by bucket; count
+//         = ring points of the inner window (two bucket starts) + hits among
+//         the boundary buckets and the off-ring points: exact; the lowest
+//         core index of every bucket
+//  cc     (K2, the last block of k_wdbscan to finish K1) core buckets at most
+//         w_g apart hold core points that are neighbours for certain, so a
+//         run of such buckets is connected; two adjacent runs more than w_gout apart are not, and
 //         runs in between are linked if one core pair across the gap is;
 //         off-ring core points join through their own tests (union-find).
 //         The lowest-index core neighbour of a non-core point is a range
@@ -1423,7 +1424,7 @@ __global__ __launch_bounds__(kFinThreads) void k_tree_cc(Cfg c, Bufs b, const fl
 //         numbered by their lowest core index; labels and cluster
 //         statistics as in k_tree_cc.
 // Work: O(V) window lookups and O(V * points of the boundary buckets) tests,
-// against V^2 / 2 pair tests for the bitmap; two launches instead of four.
+// against V^2 / 2 pair tests for the bitmap; one launch instead of four.
 
 __device__ __forceinline__ int wmod(int j) { return j & (kWinBins - 1); }
 
@@ -1480,11 +1481,11 @@ __device__ __forceinline__ int win_bucket_of(const int* s_start, int r) {
 // unwrapped bucket range [lo, hi] (at most kWinBins buckets) holds bucket j
 __device__ __forceinline__ bool win_in(int j, int lo, int hi) { return hi >= lo && wmod(j - lo) <= hi - lo; }
 
-constexpr int kWinThreads = 512;  // count-and-place blocks
 constexpr int kWinZone = 4096;    // zone points a count block keeps in LDS
 
 // K1: counts and the sorted order.  Block i takes the sorted positions
-// [i NT, i NT + NT) (sorted by bucket, then slot; off-ring points last).
+// [i POS, i POS + POS) (sorted by bucket, then slot; off-ring points last),
+// two threads per position.
 //  - every block scans the bucket counts into LDS (block 0 publishes them);
 //  - the block's zone: the buckets any of its ring points may find beyond
 //    its inner window (the union of their boundary buckets) and the
@@ -1498,23 +1499,24 @@ constexpr int kWinZone = 4096;    // zone points a count block keeps in LDS
 // The block's off-ring points are tested against every point by the whole
 // block.  Writes the counts, the sorted features, indices and counts, and
 // the lowest core index of every bucket (as kWinMaxK - index, an atomic
-// maximum over zero-initialised words).
-__global__ __launch_bounds__(kWinThreads) void k_wcount(Cfg c, Bufs b, const float* __restrict__ zin, int Vin) {
-  constexpr int NT = kWinThreads, PER = kWinBins / NT;
+// maximum over zero-initialised words).  Called only by blocks that hold
+// points (V > 0).
+__device__ __forceinline__ void wcount_body(const Cfg& c, const Bufs& b, const float* __restrict__ zin, int V) {
+  constexpr int NT = kFinThreads, POS = kWinPos, PER = kWinBins / NT;
+  static_assert(NT == 2 * POS, "two threads per sorted position");
   __shared__ int s_start[kWinBins + 1];
-  __shared__ int s_own[NT];      // own point: compacted index | bucket << kWinShift
-  __shared__ float2 s_oz[NT];    // own point: feature
+  __shared__ int s_own[POS];     // own point: compacted index | bucket << kWinShift
+  __shared__ float2 s_oz[POS];   // own point: feature
+  __shared__ int s_half[POS];    // second half of each own point's count
   __shared__ union {
     int k[kWinZone];
     float2 z[kWinZone];
   } s_zn;                        // zone: indices, then features
   __shared__ int s_b01[2];
-  const int V = dbscan_V(b, zin, Vin);
-  const int R0 = (int)blockIdx.x * NT;
-  if (R0 >= V) return;
+  const int R0 = (int)blockIdx.x * POS;
   const float2* z = reinterpret_cast<const float2*>(zin ? zin : b.z);
   const int t = (int)threadIdx.x;
-  const int R1 = min(R0 + NT, V);
+  const int R1 = min(R0 + POS, V);
   // the first keys are requested with the bucket counts
   constexpr int KB = 16;  // keys per thread and round
   int key0[KB];
@@ -1646,7 +1648,7 @@ __global__ __launch_bounds__(kWinThreads) void k_wcount(Cfg c, Bufs b, const flo
     int kz[ZPER];
 #pragma unroll
     for (int j = 0; j < ZPER; ++j) kz[j] = j * NT + t < nz ? s_zn.k[j * NT + t] : -1;
-    const int ko = R0 + t < R1 ? s_own[t] & (kWinMaxK - 1) : -1;
+    const int ko = t < POS && R0 + t < R1 ? s_own[t] & (kWinMaxK - 1) : -1;
     float2 zz[ZPER];
 #pragma unroll
     for (int j = 0; j < ZPER; ++j) zz[j] = kz[j] >= 0 ? z[kz[j]] : make_float2(0.f, 0.f);
@@ -1655,14 +1657,16 @@ __global__ __launch_bounds__(kWinThreads) void k_wcount(Cfg c, Bufs b, const flo
 #pragma unroll
     for (int j = 0; j < ZPER; ++j)
       if (kz[j] >= 0) s_zn.z[j * NT + t] = zz[j];
-    s_oz[t] = zo;
+    if (t < POS) s_oz[t] = zo;
   }
   __syncthreads();
-  const int pos = R0 + t;
+  // thread t works on position R0 + (t mod POS), half t / POS of its count
+  const int pp = t & (POS - 1), half = t / POS;
+  const int pos = R0 + pp;
   const bool own = pos < R1;
-  const int ok = own ? s_own[t] : 0;
+  const int ok = own ? s_own[pp] : 0;
   const int k = ok & (kWinMaxK - 1), bk = ok >> kWinShift;
-  const float2 zk = own ? s_oz[t] : make_float2(0.f, 0.f);
+  const float2 zk = own ? s_oz[pp] : make_float2(0.f, 0.f);
   const float r2 = c.eps2;
   const bool ring = pos < nring;
   // hits of zk among the zone entries [e0, e1)
@@ -1697,18 +1701,21 @@ __global__ __launch_bounds__(kWinThreads) void k_wcount(Cfg c, Bufs b, const flo
     if (d0 + len <= L) return hits(zidx(g, zlo[g] + d0), zidx(g, zlo[g] + d0 + len));
     return hits(zidx(g, zlo[g] + d0), zidx(g, zlo[g] + L)) + hits(zidx(g, zlo[g]), zidx(g, zlo[g] + min(L, d0 + len - L)));
   };
+  // half 0: the inner window and the left boundary (in zone range 0);
+  // half 1: the right boundary (in the last range) and the off-ring points
   int n = 0;
   if (own && ring) {
     const WinRange r = win_range(c, win_u(c, zk));
-    if (r.all) {
-      n = nring;
+    if (half == 0) {
+      n = r.all ? nring : npts(r.sl, r.sh) + range_hits(0, r.lb0, r.lb1 - r.lb0 + 1);
     } else {
-      n = npts(r.sl, r.sh);
-      // the left boundary lies in range 0 and the right one in the last
-      n += range_hits(0, r.lb0, r.lb1 - r.lb0 + 1) + range_hits(1, r.rb0, r.rb1 - r.rb0 + 1);
+      if (!r.all) n = range_hits(1, r.rb0, r.rb1 - r.rb0 + 1);
+      n += hits(zoff, zsize);
     }
-    n += hits(zoff, zsize);
   }
+  if (half == 1) s_half[pp] = n;
+  __syncthreads();
+  if (half == 0) n += s_half[pp];
   // off-ring points of the block: every point, the whole block on each
   // (each thread tests a strided share of the features; a block sum)
   const int off0 = max(R0, nring), noff_own = max(0, R1 - off0);
@@ -1727,14 +1734,15 @@ __global__ __launch_bounds__(kWinThreads) void k_wcount(Cfg c, Bufs b, const flo
     }
     int tot;
     (void)block_excl_scan<NT>(h, &tot);
-    if (pos == off0 + i) n = tot;
+    if (half == 0 && pos == off0 + i) n = tot;
   }
-  if (!own) return;
-  b.ncount[k] = n;
-  b.wnc[pos] = n;
-  reinterpret_cast<float2*>(b.zs)[pos] = zk;
-  b.sid[pos] = k;
-  if (ring && n >= c.min_pts) atomicMax(&b.wbmin[bk], kWinMaxK - k);
+  if (own && half == 0) {
+    b.ncount[k] = n;
+    b.wnc[pos] = n;
+    reinterpret_cast<float2*>(b.zs)[pos] = zk;
+    b.sid[pos] = k;
+    if (ring && n >= c.min_pts) atomicMax(&b.wbmin[bk], kWinMaxK - k);
+  }
 }
 
 // lowest index among the core neighbours of zk at sorted positions [p0, p1)
@@ -1909,8 +1917,8 @@ __device__ __forceinline__ void win_label_stats(const Bufs& b, int a0, int V, bo
 // core neighbour of each non-core point (one wave per point) gives the
 // border rule; labels and cluster statistics as in k_tree_cc.  Clears the
 // bucket counts and minima for the next call.
-__global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float* __restrict__ zin, int Vin,
-                                                     int* mout, int* lab_out, int* cnt_out) {
+__device__ __forceinline__ void wcc_body(const Cfg& c, const Bufs& b, const float* __restrict__ zin, int V,
+                                         int* mout, int* lab_out, int* cnt_out) {
   using ZT = float2;
   constexpr int PER = kWinBins / kFinThreads;  // buckets per thread
   constexpr int NBW = kWinMaxK / 32;           // words of the component-minimum bitmap
@@ -1927,7 +1935,6 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
   __shared__ int s_ncl[kFinThreads];          // non-core points of one labelling round, then their results
   __shared__ float s_red[NW][kStatClusters][6];
   __shared__ float s_tot[kStatClusters][6];
-  const int V = dbscan_V(b, zin, Vin);
   const int t = (int)threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
   if (V == 0) {
     if (t == 0) {
@@ -2221,6 +2228,40 @@ __global__ __launch_bounds__(kFinThreads) void k_wcc(Cfg c, Bufs b, const float*
     b.wbmin[t * PER + i] = 0;
   }
   if (t == 0) b.wcnt[kWinBins] = 0;
+}
+
+// The window path in one launch: every block counts and places its share of
+// the sorted positions (K1); the last block to finish, known from a
+// completion ticket taken after a device-scope fence, then runs K2 on what
+// every block wrote.  With no points only block 0 runs (K2's empty case).
+__global__ __launch_bounds__(kFinThreads) void k_wdbscan(Cfg c, Bufs b, const float* __restrict__ zin, int Vin,
+                                                         int* mout, int* lab_out, int* cnt_out) {
+  __shared__ int s_last;
+  const int V = dbscan_V(b, zin, Vin);
+  if (V == 0) {
+    if (blockIdx.x == 0) wcc_body(c, b, zin, 0, mout, lab_out, cnt_out);
+    return;
+  }
+  const int nblk = (V + kWinPos - 1) / kWinPos;
+  if ((int)blockIdx.x >= nblk) return;
+  wcount_body(c, b, zin, V);
+  // every wave waits for its stores and atomics to reach the L2 of its XCD;
+  // then one wave writes that L2 back (device-scope release) and takes a
+  // ticket.  The block that takes the last one invalidates its caches
+  // (device-scope acquire) and reads what every block wrote.
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    s_last = __hip_atomic_fetch_add(&b.ctrl->wticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nblk - 1;
+    if (s_last) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      b.ctrl->wticket = 0;  // for the next call
+    }
+  }
+  __syncthreads();
+  if (!s_last) return;
+  wcc_body(c, b, zin, V, mout, lab_out, cnt_out);
 }
 
 // bucket and slot of caller features (stage calls; replans bin in the compaction)
@@ -2735,10 +2776,10 @@ template <int P>
 static void launch_dbscan_p(Launcher& L, const Cfg& c, const Bufs& b, const float* zin, int Vin,
                             int ntile, int* lab_out, int* cnt_out, int* mout) {
   if (P == 2 && use_window(c, b)) {
-    // grids sized for every point the call may have (K for a replan)
+    // grid sized for every point the call may have (K for a replan)
     const int cap = ntile * kTile;
-    L(k_wcount, dim3((cap + kWinThreads - 1) / kWinThreads), dim3(kWinThreads), c, b, zin, Vin);
-    L(k_wcc, dim3(1), dim3(kFinThreads), c, b, zin, Vin, mout, lab_out, cnt_out);
+    L(k_wdbscan, dim3((cap + kWinPos - 1) / kWinPos), dim3(kFinThreads), c, b, zin, Vin, mout,
+      lab_out, cnt_out);
     return;
   }
   const int ngrp = (ntile + kColGroup - 1) / kColGroup;

@@ -62,6 +62,7 @@ constexpr int kWinBins = 4096;
 constexpr int kWinShift = 16;
 constexpr int kWinMaxK = 1 << kWinShift;
 constexpr int kWinMaxRuns = 1024;  // runs of core buckets (at most kWinBins / (gap + 1) with gap >= 3)
+constexpr int kWinPos = 512;  // sorted positions per count-and-place block
 static_assert(kWinMaxK >= kAdjMaxK, "the windowed path covers every planner with a bitmap");
 constexpr int kLabBatch = 8;   // points per thread per labelling pass
 constexpr int kRecBatch = 4;   // partial records per thread in flight at once
@@ -94,6 +95,7 @@ struct Ctrl {
   int32_t dyn_h, dyn_ok;  // Eq. (17) estimate of this replan: H' and whether the dynamic rule applies
   uint32_t status;
   uint32_t step_used;
+  int32_t wticket;  // completion ticket of the window DBSCAN launch (zero between calls)
 };
 
 // Scalar configuration (kernel argument).
@@ -183,7 +185,7 @@ struct Bufs {
   int* wbmin;      // [kWinBins] kWinMaxK - lowest core index in each bucket (0 if none); zero between calls
   int* wnc;        // [K] neighbour counts by sorted position
   int* wuf;        // [3][kWinMaxRuns + K] union-find parents, component minima, off-ring labels
-  int* wzone;      // [ceil(K / 512)][K] indices of a count block's zone when it exceeds LDS
+  int* wzone;      // [ceil(K / kWinPos)][K] indices of a count block's zone when it exceeds LDS
   float* upart;    // [nblk_upd][NM + 1]
   float* Unew;     // [N][m] updated sequence before the shift
 };
