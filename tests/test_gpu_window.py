@@ -150,6 +150,65 @@ def test_window_matches_bitmap_tiled_and_definition(case):
         assert np.array_equal(cw, ocnt) and mw == oM, name
 
 
+@pytest.mark.parametrize("V", [1, 3, 511, 512, 513, 1023, 1024, 1025, 2047])
+def test_window_block_edges(V):
+    """Feature counts around the count blocks' 512 positions (one block,
+    a block plus one point, exact multiples): window, bitmap and distance
+    passes agree bit for bit, and the window result is DBSCAN by the
+    definition."""
+    from paper_2607_06499_amd import binding as B
+
+    rng = np.random.default_rng(100 + V)
+    th = np.concatenate([rng.normal(0.3, 0.2, V - V // 5), rng.uniform(-math.pi, math.pi, V // 5)])
+    z = _ring(rng, th)
+    if V > 3:
+        z[-2:] = rng.normal(0, 0.3, (2, 2)).astype(np.float32)  # two off the ring, sorted last
+    eps, min_pts = 0.25, 6
+    spec = W.PlannerSpec(num_samples=max(V, 64), dbscan_eps=eps, dbscan_min_pts=min_pts).rounded()
+    pl = B.Planner(spec)
+    res = {}
+    for mode in (B.DBSCAN_WINDOW, B.DBSCAN_BITMAP, B.DBSCAN_TILED):
+        pl.set_dbscan_mode(mode)
+        lab, cnt, M = pl.stage_dbscan(H.to_dev(z))
+        res[mode] = (lab.cpu().numpy(), cnt.cpu().numpy(), int(M.cpu().item()))
+    pl.close()
+    lw, cw, mw = res[B.DBSCAN_WINDOW]
+    lb, cb, mb = res[B.DBSCAN_BITMAP]
+    lt, ct, mt = res[B.DBSCAN_TILED]
+    assert np.array_equal(cw, cb) and np.array_equal(lw, lb) and np.array_equal(lw, lt) and mw == mb == mt
+    assert H.counts_agree(ct, cw, min_pts)
+    eps32 = float(np.float32(eps))
+    olab = oracle.dbscan(z.astype(np.float64), eps32, min_pts)[0]
+    H.dbscan_check(z.astype(np.float64), eps32, min_pts, cw, lw, 0.5 * H.STAGE_BAND * eps32, exact_ref=olab,
+                   tag=f"V={V}")
+
+
+def test_window_repeated_calls_and_all_off_ring():
+    """Forty stage calls in a row of random sizes on one planner (the
+    bucket tables and the completion ticket start from zero at every call),
+    including sets with every point off the ring, each equal to the bitmap's
+    result on the same features."""
+    from paper_2607_06499_amd import binding as B
+
+    rng = np.random.default_rng(77)
+    spec = W.PlannerSpec(num_samples=4096, dbscan_eps=0.2, dbscan_min_pts=8).rounded()
+    pw, pb = B.Planner(spec), B.Planner(spec)
+    pb.set_dbscan_mode(B.DBSCAN_BITMAP)
+    for i in range(40):
+        V = int(rng.integers(0, 4097))
+        if i % 5 == 4:
+            z = (rng.uniform(-0.9, 0.9, (V, 2))).astype(np.float32)  # all off the ring
+        else:
+            z = _ring(rng, rng.normal(rng.uniform(-3, 3), 0.5, V))
+        lw, cw, mw = pw.stage_dbscan(H.to_dev(z))
+        lb, cb, mb = pb.stage_dbscan(H.to_dev(z))
+        assert np.array_equal(lw.cpu().numpy(), lb.cpu().numpy()), (i, V)
+        assert np.array_equal(cw.cpu().numpy(), cb.cpu().numpy()), (i, V)
+        assert int(mw.cpu().item()) == int(mb.cpu().item()), (i, V)
+    pw.close()
+    pb.close()
+
+
 def _twins(spec):
     from paper_2607_06499_amd import binding as B
 
