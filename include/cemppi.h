@@ -298,10 +298,11 @@ ce_status ce_mppi_stage_dbscan(ce_mppi_planner* planner, const float* z, int32_t
  *   CE_DBSCAN_TILED   tiled distance passes (any K, p = 2 or 3).
  *   CE_DBSCAN_AUTO    (default) the first of these that the planner supports.
  * The mode applies to replans and to ce_mppi_stage_dbscan; a change rebuilds
- * the replan graph at the next replan.  The batched form always uses its own
- * spatially sorted distance passes.  Errors: CE_EINVAL (NULL planner,
- * unknown mode), CE_EUNSUPPORTED (the path is not available for this
- * planner; the mode is unchanged). */
+ * the replan graph at the next replan.  A batch runs each 2-D member on the
+ * angular windows if that is the member's path when the batch is made, and
+ * every other member on the batch's spatially sorted distance passes.
+ * Errors: CE_EINVAL (NULL planner, unknown mode), CE_EUNSUPPORTED (the path
+ * is not available for this planner; the mode is unchanged). */
 enum { CE_DBSCAN_AUTO = 0, CE_DBSCAN_WINDOW = 1, CE_DBSCAN_BITMAP = 2, CE_DBSCAN_TILED = 3 };
 ce_status ce_mppi_set_dbscan_mode(ce_mppi_planner* planner, int32_t mode);
 /* The path replans and stage calls use now (CE_DBSCAN_WINDOW, _BITMAP or
@@ -395,11 +396,11 @@ ce_status ce_mppi_time_rollout(ce_mppi_planner* planner, const float* x_t, const
  * A batch runs one replan of each of its planners (Alg. 1 for every member,
  * each exactly as ce_mppi_replan would run it) as one graph launch.  Every
  * phase of the replan is one persistent kernel per planner kind (rollout
- * kind: unicycle on 32 or 64 lanes, arm; feature dimension p = 2 or 3) whose
- * fixed grid loops over the work items of all members; the DBSCAN work
- * tables are sized on the device from each member's feasible count.  The
- * results of a member are bitwise those of ce_mppi_replan on the same inputs
- * and state.
+ * kind: unicycle on 32 or 64 lanes, arm; DBSCAN kind: 2-D on the angular
+ * windows, 2-D on sorted distance passes, 3-D) whose fixed grid loops over
+ * the work items of all members; the DBSCAN work tables are sized on the
+ * device from each member's feasible count.  The results of a member are
+ * bitwise those of ce_mppi_replan on the same inputs and state.
  *
  * Ownership: the batch holds references to its planners, which must outlive
  * it, stay on the batch's device, and must not run a replan concurrently with

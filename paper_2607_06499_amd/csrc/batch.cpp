@@ -36,9 +36,9 @@ constexpr int kAreas = 4;  // area 0: the full member set; 1..3: subset ring
 
 // Offsets (in ints) of every table inside an area, for n member capacity.
 struct Layout {
-  size_t cnt_roll[3], cnt_p[2], cnt_all;          // table counts n
+  size_t cnt_roll[3], cnt_p[kPlanKinds], cnt_all;  // table counts n
   size_t roll_slot[3], roll_pref[3][4];
-  size_t p_slot[2], compact[2], cc[2], dyn_cnt[2], dyn_adj[2];
+  size_t p_slot[kPlanKinds], compact[kPlanKinds], cc[kPlanKinds], dyn_cnt[kPlanKinds], dyn_adj[kPlanKinds];
   size_t all_slot, update, finish;
   size_t ints = 0;
   void make(int n) {
@@ -49,13 +49,13 @@ struct Layout {
       return r;
     };
     for (int k = 0; k < 3; ++k) cnt_roll[k] = take(1);
-    for (int kd = 0; kd < 2; ++kd) cnt_p[kd] = take(1);
+    for (int kd = 0; kd < kPlanKinds; ++kd) cnt_p[kd] = take(1);
     cnt_all = take(1);
     for (int k = 0; k < 3; ++k) {
       roll_slot[k] = take(n);
       for (int ri = 0; ri < 4; ++ri) roll_pref[k][ri] = take(n + 1);
     }
-    for (int kd = 0; kd < 2; ++kd) {
+    for (int kd = 0; kd < kPlanKinds; ++kd) {
       p_slot[kd] = take(n);
       compact[kd] = take(n + 1);
       cc[kd] = take(n + 1);
@@ -102,7 +102,7 @@ struct ce_mppi_batch {
   hipEvent_t up_done = nullptr;
   // totals of the full member set (upper bounds of any subset): grid sizes
   int roll_total[3][4] = {};
-  int compact_total[2] = {0, 0}, update_total = 0, n_p[2] = {0, 0};
+  int compact_total[kPlanKinds] = {}, update_total = 0, n_p[kPlanKinds] = {}, win_total = 0;
   ce_mppi_batch_tuning tune{8, 8, 4, 4};
 };
 
@@ -140,7 +140,7 @@ void drop_graphs(ce_mppi_batch* B) {
 // Host tables of one member list (slot indices) in the area layout.
 void fill_tables(const ce_mppi_batch* B, const int* members, int count, int* h) {
   const Layout& L = B->lay;
-  std::vector<int> lr[3], lp[2];
+  std::vector<int> lr[3], lp[kPlanKinds];
   for (int q = 0; q < count; ++q) {
     const int s = members[q];
     lr[B->roll_kind[s]].push_back(s);
@@ -164,7 +164,7 @@ void fill_tables(const ce_mppi_batch* B, const int* members, int count, int* h) 
       });
     }
   }
-  for (int kd = 0; kd < 2; ++kd) {
+  for (int kd = 0; kd < kPlanKinds; ++kd) {
     h[L.cnt_p[kd]] = (int)lp[kd].size();
     copy(lp[kd], L.p_slot[kd]);
     prefix(lp[kd], L.compact[kd], [](const ce_mppi_planner* P) { return (P->c.K + 255) / 256; });
@@ -187,7 +187,7 @@ void area_tabs(const ce_mppi_batch* B, Area& a) {
       a.roll[k][ri] = Tab{d + L.roll_slot[k], d + L.roll_pref[k][ri], d + L.cnt_roll[k]};
   BatchTabs& T = a.T;
   const int cus = B->cus;
-  for (int kd = 0; kd < 2; ++kd) {
+  for (int kd = 0; kd < kPlanKinds; ++kd) {
     const int* sl = d + L.p_slot[kd];
     const int* nk = d + L.cnt_p[kd];
     T.compact[kd] = Tab{sl, d + L.compact[kd], nk};
@@ -205,6 +205,8 @@ void area_tabs(const ce_mppi_batch* B, Area& a) {
   T.update = Tab{d + L.all_slot, d + L.update, d + L.cnt_all};
   T.finish = Tab{d + L.all_slot, d + L.finish, d + L.cnt_all};
   T.grid_tile = B->tune.tile_blocks_per_cu * cus;
+  // count-and-place blocks of the angular windows: two per CU fit its LDS
+  T.grid_win = std::max(1, std::min(B->win_total, 2 * cus));
   T.grid_update = std::max(1, std::min(B->update_total, 4 * cus));
   T.grid_finish = std::max(1, std::min(B->n, cus));
   T.colg = B->tune.colg;
@@ -293,7 +295,10 @@ ce_status ce_mppi_batch_create(ce_mppi_planner* const* planners, int32_t n, ce_m
   for (int i = 0; i < n; ++i) {
     const ce_mppi_planner* P = planners[i];
     B->roll_kind[i] = rollout_kind(P);
-    B->p_kind[i] = P->c.p == 2 ? 0 : 1;
+    // 2-D members on the angular windows (their path when the batch is
+    // made) form a group of their own
+    B->p_kind[i] = P->c.p == 3 ? 1 : (P->c.dbpath == 0 && P->b.wcnt ? 2 : 0);
+    if (B->p_kind[i] == 2) B->win_total += (P->c.K + kWinPos - 1) / kWinPos;
     B->has_roll[B->roll_kind[i]] = true;
     B->n_p[B->p_kind[i]] += 1;
     for (int ri = 0; ri < 4; ++ri) {

@@ -1499,9 +1499,10 @@ constexpr int kWinZone = 4096;    // zone points a count block keeps in LDS
 // The block's off-ring points are tested against every point by the whole
 // block.  Writes the counts, the sorted features, indices and counts, and
 // the lowest core index of every bucket (as kWinMaxK - index, an atomic
-// maximum over zero-initialised words).  Called only by blocks that hold
-// points (V > 0).
-__device__ __forceinline__ void wcount_body(const Cfg& c, const Bufs& b, const float* __restrict__ zin, int V) {
+// maximum over zero-initialised words).  Called for count blocks bx that
+// hold points (bx < ceil(V / POS)).
+__device__ __forceinline__ void wcount_body(const Cfg& c, const Bufs& b, const float* __restrict__ zin, int V,
+                                            int bx) {
   constexpr int NT = kFinThreads, POS = kWinPos, PER = kWinBins / NT;
   static_assert(NT == 2 * POS, "two threads per sorted position");
   __shared__ int s_start[kWinBins + 1];
@@ -1513,7 +1514,7 @@ __device__ __forceinline__ void wcount_body(const Cfg& c, const Bufs& b, const f
     float2 z[kWinZone];
   } s_zn;                        // zone: indices, then features
   __shared__ int s_b01[2];
-  const int R0 = (int)blockIdx.x * POS;
+  const int R0 = bx * POS;
   const float2* z = reinterpret_cast<const float2*>(zin ? zin : b.z);
   const int t = (int)threadIdx.x;
   const int R1 = min(R0 + POS, V);
@@ -1547,7 +1548,7 @@ __device__ __forceinline__ void wcount_body(const Cfg& c, const Bufs& b, const f
   }
   if (t == 0) s_start[kWinBins] = nring;
   __syncthreads();
-  if (blockIdx.x == 0) {
+  if (bx == 0) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) b.wstart[t * PER + i] = s_start[t * PER + i];
     if (t == 0) {
@@ -1599,7 +1600,7 @@ __device__ __forceinline__ void wcount_body(const Cfg& c, const Bufs& b, const f
   const int zoff = zsize;  // the off-ring points
   zsize += R0 < rr1 ? V - nring : 0;
   const bool lds = zsize <= kWinZone;
-  int* gzone = b.wzone + (size_t)blockIdx.x * c.K;
+  int* gzone = b.wzone + (size_t)bx * c.K;
   // zone index of the first point of unwrapped bucket j of range g
   auto zidx = [&](int g, int j) {
     const int m = wmod(zlo[g]), x = m + (j - zlo[g]);
@@ -2244,7 +2245,7 @@ __global__ __launch_bounds__(kFinThreads) void k_wdbscan(Cfg c, Bufs b, const fl
   }
   const int nblk = (V + kWinPos - 1) / kWinPos;
   if ((int)blockIdx.x >= nblk) return;
-  wcount_body(c, b, zin, V);
+  wcount_body(c, b, zin, V, (int)blockIdx.x);
   // every wave waits for its stores and atomics to reach the L2 of its XCD;
   // then one wave writes that L2 back (device-scope release) and takes a
   // ticket.  The block that takes the last one invalidates its caches
@@ -2639,7 +2640,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(Cfg c, Bufs b, float* __
 // them on the device after the compaction.
 
 __global__ __launch_bounds__(kFinThreads) void kb_plan(CSlotStatic st, PlanOut o) {
-  for (int kd = 0; kd < 2; ++kd) {
+  for (int kd = 0; kd < kPlanKinds; ++kd) {
     const int n = *o.n[kd];
     if (n == 0) continue;
     const int q = threadIdx.x;
@@ -2648,9 +2649,14 @@ __global__ __launch_bounds__(kFinThreads) void kb_plan(CSlotStatic st, PlanOut o
       const SlotStatic& S = *(const SlotStatic*)(st + o.slot[kd][q]);
       const Ctrl* ct = S.b.ctrl;
       const int V = ct->branch == 0 ? ct->n_feas : 0;
-      const int nt = ntiles_of(V);
-      ncnt = nt * ((nt + o.colg - 1) / o.colg);
-      nadj = nt * ((nt + kColGroup - 1) / kColGroup);
+      if (kd == 2) {
+        // angular windows: the count-and-place blocks
+        ncnt = (V + kWinPos - 1) / kWinPos;
+      } else {
+        const int nt = ntiles_of(V);
+        ncnt = nt * ((nt + o.colg - 1) / o.colg);
+        nadj = nt * ((nt + kColGroup - 1) / kColGroup);
+      }
     }
     int t1, t2;
     const int e1 = block_excl_scan<kFinThreads>(ncnt, &t1);
@@ -2671,12 +2677,12 @@ __global__ __launch_bounds__(kFinThreads) void kb_plan(CSlotStatic st, PlanOut o
   const Cfg& c = S.c;                                         \
   const Bufs& b = S.b
 
-template <int P>
+template <int P, bool BIN = false>
 __global__ __launch_bounds__(256) void kb_compact(CSlotStatic st, Tab t) {
   __shared__ int s_pref[kMaxBatch + 1];
   for_each_item<256>(t, s_pref, [&](int slot, int local) {
     CEMPPI_SLOT(slot);
-    compact_body<P>(c, b, local, 0, 0);
+    compact_body<P, BIN>(c, b, local, 0, 0);
   });
 }
 
@@ -2720,6 +2726,25 @@ __global__ __launch_bounds__(kTile) void kb_tree_adj(CSlotStatic st, Tab t) {
     const int nt = ntiles_of(dbscan_V(b, nullptr, 0));
     const int ng = (nt + kColGroup - 1) / kColGroup;
     tree_adj_body<P, true>(c, b, local % ng, local / ng, 0, nullptr, 0);
+  });
+}
+
+// angular windows of the 2-D members: the count-and-place blocks of every
+// member, then one block per member for the components and labels (the two
+// phases of k_wdbscan as two launches)
+__global__ __launch_bounds__(kFinThreads) void kb_wcount(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item<kFinThreads>(t, s_pref, [&](int slot, int local) {
+    CEMPPI_SLOT(slot);
+    wcount_body(c, b, nullptr, dbscan_V(b, nullptr, 0), local);
+  });
+}
+
+__global__ __launch_bounds__(kFinThreads) void kb_wcc(CSlotStatic st, Tab t) {
+  __shared__ int s_pref[kMaxBatch + 1];
+  for_each_item<kFinThreads>(t, s_pref, [&](int slot, int) {
+    CEMPPI_SLOT(slot);
+    wcc_body(c, b, nullptr, dbscan_V(b, nullptr, 0), nullptr, nullptr, nullptr);
   });
 }
 
@@ -2888,12 +2913,17 @@ static void launch_batch_dbscan(Launcher& L, const CSlotStatic cst, const BatchT
 void launch_batch_post(Launcher& L, const SlotStatic* st, const SlotIO* io, const BatchTabs& T) {
   const CSlotStatic cst = (CSlotStatic)st;
   const CSlotIO cio = (CSlotIO)io;
-  for (int kd = 0; kd < 2; ++kd) {
+  for (int kd = 0; kd < kPlanKinds; ++kd) {
     if (!T.has[kd]) continue;
     if (kd == 0) L(kb_compact<2>, dim3(T.grid_compact[0]), dim3(256), cst, T.compact[0]);
-    else L(kb_compact<3>, dim3(T.grid_compact[1]), dim3(256), cst, T.compact[1]);
+    else if (kd == 1) L(kb_compact<3>, dim3(T.grid_compact[1]), dim3(256), cst, T.compact[1]);
+    else L(kb_compact<2, true>, dim3(T.grid_compact[2]), dim3(256), cst, T.compact[2]);
   }
   L(kb_plan, dim3(1), dim3(kFinThreads), cst, T.plan);
+  if (T.has[2]) {
+    L(kb_wcount, dim3(T.grid_win), dim3(kFinThreads), cst, T.cnt[2]);
+    L(kb_wcc, dim3(T.grid_cc[2]), dim3(kFinThreads), cst, T.cc[2]);
+  }
   for (int kd = 0; kd < 2; ++kd) {
     if (!T.has[kd]) continue;
     if (kd == 0) L(kb_sort<2>, dim3(T.grid_cc[0]), dim3(kFinThreads), cst, T.cc[0]);

@@ -248,26 +248,28 @@ __device__ __forceinline__ void for_each_item(const Tab& t, int* s_pref, F&& f) 
 }
 
 // Tables of the batched post-rollout phases.  Index kd is the group of
-// planners with p = 2 (0) or p = 3 (1): static tables for compaction, tree
-// closure and statistics; the DBSCAN tables are filled on the device from
-// each planner's feasible count (PlanOut).  Update and finish run over every
-// planner of the batch.
+// planners: p = 2 on the sorted distance passes (0), p = 3 (1), p = 2 on the
+// angular windows (2).  Static tables for compaction and for the tree
+// closure, components and statistics (one item per planner); the DBSCAN
+// tables are filled on the device from each planner's feasible count
+// (PlanOut).  Update and finish run over every planner of the batch.
+constexpr int kPlanKinds = 3;
 struct PlanOut {
-  const int* slot[2];   // planners with p = 2 and p = 3
-  const int* n[2];      // their counts (device memory)
-  int* pref_cnt[2];     // count and lowest-core-neighbour tiles
-  int* pref_adj[2];     // tree-adjacency tiles
-  int colg;             // column tiles per count/mcn item
+  const int* slot[kPlanKinds];  // planners of each group
+  const int* n[kPlanKinds];     // their counts (device memory)
+  int* pref_cnt[kPlanKinds];    // count and lowest-core-neighbour tiles (group 2: count blocks)
+  int* pref_adj[kPlanKinds];    // tree-adjacency tiles
+  int colg;                     // column tiles per count/mcn item
 };
 
 struct BatchTabs {
-  Tab compact[2], cnt[2], adj[2], cc[2];
+  Tab compact[kPlanKinds], cnt[kPlanKinds], adj[kPlanKinds], cc[kPlanKinds];
   Tab update, finish;
   PlanOut plan;
-  int grid_compact[2], grid_cc[2], grid_update, grid_finish;
-  int grid_tile;
+  int grid_compact[kPlanKinds], grid_cc[kPlanKinds], grid_update, grid_finish;
+  int grid_tile, grid_win;
   int colg;
-  int has[2];  // the batch has planners with p = 2 / p = 3 (their phases are launched)
+  int has[kPlanKinds];  // the batch has planners of the group (its phases are launched)
 };
 
 // ---------------------------------------------------------------------------

@@ -1,6 +1,7 @@
 """Batched form: every member of a batch gets bitwise the result of its own
 single-planner replan (same configuration, nominal, history and step), for
-members of uneven size and of every kind, over consecutive steps and under
+members of uneven size and of every kind (2-D members on the angular windows
+and on the sorted distance passes, arms), over consecutive steps and under
 every tuning the autotuner may pick; and every member matches the FP64
 oracle's replan on its inputs, stage by stage."""
 import numpy as np
@@ -37,6 +38,11 @@ MEMBERS = [
 
 TUNINGS = [None, (1, 2, 2, 1), (4, 16, 4, 8), (8, 4, 2, 2)]
 
+# 2-D members put on the distance passes before the batch is made: the batch
+# runs them on its spatially sorted passes, the other 2-D members on the
+# angular windows
+TILED = (1, 8)
+
 
 def _setup():
     from paper_2607_06499_amd import binding as B
@@ -44,9 +50,14 @@ def _setup():
     scenes = [m() for m in MEMBERS]
     batched = [B.Planner(s.spec) for s in scenes]
     single = [B.Planner(s.spec) for s in scenes]
-    for s, a, b in zip(scenes, batched, single):
+    for i, (s, a, b) in enumerate(zip(scenes, batched, single)):
         a.set_nominal(H.to_dev(s.U0))
         b.set_nominal(H.to_dev(s.U0))
+        if i in TILED:
+            a.set_dbscan_mode(B.DBSCAN_TILED)
+            b.set_dbscan_mode(B.DBSCAN_TILED)
+    paths = {a.dbscan_path() for a in batched}
+    assert {B.DBSCAN_WINDOW, B.DBSCAN_TILED, B.DBSCAN_BITMAP} <= paths  # 2-D both ways, and the arm
     xs = [H.to_dev(np.asarray(s.x0, np.float32)) for s in scenes]
     obs = [H.to_dev(np.asarray(s.obstacles, np.float32)) if len(s.obstacles) else None for s in scenes]
     batch = B.Batch(batched)
