@@ -2099,31 +2099,44 @@ __device__ __forceinline__ void wcc_body(const Cfg& c, const Bufs& b, const floa
       const int m = ld_wg(&cmin[i]);
       if (ld_wg(&parent[i]) == i && m != kInt32Max) atomicOr(&s_bits[m >> 5], 1u << (m & 31));
     }
-  } else if (t < nR) {
+  } else if (nR > kWave && t < nR) {
     atomicOr(&s_bits[s_run[t] >> 5], 1u << (s_run[t] & 31));
   }
   __syncthreads();
   // clusters are the components ranked by their lowest core index
-  int npop = 0;
-#pragma unroll
-  for (int i = 0; i < BPT; ++i) npop += t * BPT + i < NBW ? __popc(s_bits[t * BPT + i]) : 0;
   int M;
-  int boff = block_excl_scan<kFinThreads>(npop, &M);
-#pragma unroll
-  for (int i = 0; i < BPT; ++i)
-    if (t * BPT + i < NBW) {
-      s_boff[t * BPT + i] = boff;
-      boff += __popc(s_bits[t * BPT + i]);
+  if (!uf && nR <= kWave) {
+    // the runs are the components (at most one wave of them): a run's rank
+    // is the number of runs with a lower minimum (the minima are distinct)
+    M = nR;
+    int r = 0;
+    if (t < nR) {
+      const int mv = s_run[t];
+      for (int j = 0; j < nR; ++j) r += s_run[j] < mv ? 1 : 0;
     }
-  __syncthreads();
-  auto rank_of = [&](int x) {
-    const int w = x >> 5, bit = x & 31;
-    return s_boff[w] + __popc(s_bits[w] & (bit ? (0xffffffffu >> (32 - bit)) : 0u));
-  };
-  if (t < nR) s_run[t] = rank_of(uf ? ld_wg(&cmin[win_find(parent, t)]) : s_run[t]);
-  if (uf)
-    for (int o = t; o < noff; o += kFinThreads)
-      olab[o] = b.wnc[nring + o] >= c.min_pts ? rank_of(ld_wg(&cmin[win_find(parent, nR + o)])) : -1;
+    __syncthreads();
+    if (t < nR) s_run[t] = r;
+  } else {
+    int npop = 0;
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) npop += t * BPT + i < NBW ? __popc(s_bits[t * BPT + i]) : 0;
+    int boff = block_excl_scan<kFinThreads>(npop, &M);
+#pragma unroll
+    for (int i = 0; i < BPT; ++i)
+      if (t * BPT + i < NBW) {
+        s_boff[t * BPT + i] = boff;
+        boff += __popc(s_bits[t * BPT + i]);
+      }
+    __syncthreads();
+    auto rank_of = [&](int x) {
+      const int w = x >> 5, bit = x & 31;
+      return s_boff[w] + __popc(s_bits[w] & (bit ? (0xffffffffu >> (32 - bit)) : 0u));
+    };
+    if (t < nR) s_run[t] = rank_of(uf ? ld_wg(&cmin[win_find(parent, t)]) : s_run[t]);
+    if (uf)
+      for (int o = t; o < noff; o += kFinThreads)
+        olab[o] = b.wnc[nring + o] >= c.min_pts ? rank_of(ld_wg(&cmin[win_find(parent, nR + o)])) : -1;
+  }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
