@@ -194,3 +194,39 @@ def test_batch_rejects_bad_io():
     with pytest.raises(B.CeMppiError):
         B.Batch([pl, pl])
     batch.close()
+
+
+def test_batch_large_window_members_match_single():
+    """Members of up to 16,384 rollouts on the angular windows (many
+    count-and-place items per member, zones that may leave LDS) replan in a
+    batch bitwise as they do alone, over three closed-loop steps."""
+    from paper_2607_06499_amd import binding as B
+    from paper_2607_06499_amd.plant import unicycle_step
+
+    scenes = [W.unicycle_dynamic_ahead(1, num_samples=16384), W.unicycle_dynamic_ahead(3, num_samples=12000),
+              W.unicycle_static_ahead(3, num_samples=4096)]
+    batched = [B.Planner(s.spec) for s in scenes]
+    single = [B.Planner(s.spec) for s in scenes]
+    for s, a, b in zip(scenes, batched, single):
+        a.set_nominal(H.to_dev(s.U0))
+        b.set_nominal(H.to_dev(s.U0))
+        assert a.dbscan_path() == B.DBSCAN_WINDOW
+    fields = [s.field.copy() for s in scenes]
+    xs = [s.x0.astype(np.float64) for s in scenes]
+    batch = B.Batch(batched)
+    clustered = 0
+    for step in range(3):
+        xd = [H.to_dev(np.float32(x)) for x in xs]
+        od = [H.to_dev(np.asarray(f.observation(), np.float32)) for f in fields]
+        batch.set_io(xd, od)
+        batch.replan()
+        for b, x, o in zip(single, xd, od):
+            b.replan(x, o)
+        _compare(B, batched, single, f"large step {step}")
+        for i, a in enumerate(batched):
+            info = a.info()
+            clustered += info["branch"] == 0 and info["n_clusters"] >= 1
+            xs[i] = unicycle_step(xs[i], a.u_out.cpu().numpy(), scenes[i].spec.dt)
+            fields[i].step(scenes[i].spec.dt)
+    assert clustered >= 2
+    batch.close()
